@@ -1,0 +1,215 @@
+/*
+ * CPU oracle for score-only pairwise alignment (Gotoh affine-gap dynamic
+ * program) -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Only the test suite, the smoke check and the CPU-baseline leg of the
+ * benchmark may load this library.  The GPU library never links it, never
+ * calls it and shares no code with it.
+ *
+ * Everything here is the plain textbook definition, computed in 64-bit
+ * integers, one matrix row at a time (linear memory, quadratic time; the
+ * paper's "Traceback" paragraph of section 2.1 notes score-only needs only
+ * linear space).  No blocking, no vectorisation, no reordering.
+ *
+ * Notation (paper, section 2.1 "Sequence Alignment"):
+ *   Q = q_1..q_m  (rows, i),  S = s_1..s_n  (columns, j)
+ *   H(i,j) = max{ H(i-1,j-1) + sigma(q_i,s_j), E(i,j), F(i,j), nu }   Eq. (1)
+ *   E(i,j) = max{ E(i-1,j) - beta, H(i-1,j) - alpha }                 Eq. (4)
+ *   F(i,j) = max{ F(i,j-1) - beta, H(i,j-1) - alpha }                 Eq. (5)
+ *   A gap of length k costs alpha + (k-1)*beta; linear gaps are alpha == beta
+ *   (Eq. (2),(3) are the alpha == beta case, because H >= E and H >= F).
+ *
+ * Modes ("Local / Global / Semi-global Alignments" paragraphs, section 2.1):
+ *   global      nu = -inf; H(i,0) = -alpha - beta(i-1), H(0,j) likewise,
+ *               H(0,0) = 0; result H(m,n).
+ *   local       nu = 0; H(i,0) = H(0,j) = 0; result max over every cell.
+ *   semi-global initialisation as local, nu = -inf (reading: the paper
+ *               shares only the initialisation with local; nu = 0 would make
+ *               mismatching prefixes free, which is not a free end gap);
+ *               result = max over the last row and the last column,
+ *               including the boundary cells H(m,0) and H(0,n).
+ *   In every mode E(0,j) = F(i,0) = -inf; the paper's E(i,0), F(0,j) values
+ *   are never read by a cell with i,j >= 1.
+ *
+ * Banded variant (not in the paper; the learned-band extension): a cell
+ * (i,j), boundary cells included, exists only when L <= j-i <= U with
+ *   L = min(0, n-m) - w,  U = max(0, n-m) + w,  w >= 0;
+ * cells outside are -inf in H, E and F.  The result is taken as in the full
+ * mode over existing cells only.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <pthread.h>
+
+#define ORACLE_NEG_INF (-(((int64_t)1) << 60))
+
+enum { ORACLE_GLOBAL = 0, ORACLE_SEMIGLOBAL = 1, ORACLE_LOCAL = 2 };
+
+static int64_t max2(int64_t a, int64_t b) { return a > b ? a : b; }
+
+/* Initial value of the boundary cell H(i,0) (or H(0,j) with i := j). */
+static int64_t boundary_h(int64_t i, int32_t mode, int64_t alpha, int64_t beta) {
+    if (i == 0) return 0;
+    if (mode == ORACLE_GLOBAL) return -alpha - beta * (i - 1);
+    return 0;
+}
+
+/* Score of one pair, restricted to the band [lo, hi] of diagonals j-i.
+ * The full problem is lo = -m, hi = n. */
+static int64_t align_band(const uint8_t *q, int64_t m, const uint8_t *s, int64_t n,
+                          const int8_t *subst, int32_t asz, int64_t alpha, int64_t beta,
+                          int32_t mode, int64_t lo, int64_t hi) {
+    const int64_t nu = (mode == ORACLE_LOCAL) ? 0 : ORACLE_NEG_INF;
+    int64_t *H = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1)); /* row i-1, then row i */
+    int64_t *E = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1)); /* E(i-1,j), then E(i,j) */
+    int64_t best = ORACLE_NEG_INF;
+    int64_t j, i;
+
+    /* row 0 */
+    for (j = 0; j <= n; ++j) {
+        int in_band = (j - 0 >= lo) && (j - 0 <= hi);
+        H[j] = in_band ? boundary_h(j, mode, alpha, beta) : ORACLE_NEG_INF;
+        E[j] = ORACLE_NEG_INF;
+    }
+    if (mode == ORACLE_LOCAL) {
+        for (j = 0; j <= n; ++j) best = max2(best, H[j]);
+    }
+    if (mode == ORACLE_SEMIGLOBAL) {
+        best = max2(best, H[n]); /* H(0,n): last column, row 0 */
+        if (m == 0)
+            for (j = 0; j <= n; ++j) best = max2(best, H[j]); /* row 0 is the last row */
+    }
+
+    for (i = 1; i <= m; ++i) {
+        int64_t diag = H[0];                       /* H(i-1, 0) */
+        int64_t F = ORACLE_NEG_INF;                /* F(i, 0) */
+        int in_band0 = (0 - i >= lo) && (0 - i <= hi);
+        H[0] = in_band0 ? boundary_h(i, mode, alpha, beta) : ORACLE_NEG_INF;
+        for (j = 1; j <= n; ++j) {
+            int64_t up = H[j]; /* H(i-1, j) */
+            int64_t h;
+            if (j - i < lo || j - i > hi) {
+                E[j] = ORACLE_NEG_INF;
+                F = ORACLE_NEG_INF;
+                h = ORACLE_NEG_INF;
+            } else {
+                int64_t sigma = subst[(int32_t)q[i - 1] * asz + (int32_t)s[j - 1]];
+                int64_t e = max2(E[j] - beta, up - alpha);
+                int64_t f = max2(F - beta, H[j - 1] - alpha);
+                h = diag + sigma;
+                h = max2(h, e);
+                h = max2(h, f);
+                h = max2(h, nu);
+                /* keep -inf from drifting upwards out of the sentinel range */
+                if (e < ORACLE_NEG_INF) e = ORACLE_NEG_INF;
+                if (f < ORACLE_NEG_INF) f = ORACLE_NEG_INF;
+                if (h < ORACLE_NEG_INF) h = ORACLE_NEG_INF;
+                E[j] = e;
+                F = f;
+            }
+            diag = up;
+            H[j] = h;
+            if (mode == ORACLE_LOCAL) best = max2(best, h);
+        }
+        if (mode == ORACLE_LOCAL) best = max2(best, H[0]);
+        if (mode == ORACLE_SEMIGLOBAL) best = max2(best, H[n]); /* last column, row i */
+    }
+    if (mode == ORACLE_SEMIGLOBAL && m > 0)
+        for (j = 0; j <= n; ++j) best = max2(best, H[j]); /* last row */
+    if (mode == ORACLE_GLOBAL) best = H[n];
+    free(H);
+    free(E);
+    return best;
+}
+
+int64_t oracle_align_pair(const uint8_t *q, int64_t m, const uint8_t *s, int64_t n,
+                          const int8_t *subst, int32_t asz, int64_t alpha, int64_t beta,
+                          int32_t mode) {
+    return align_band(q, m, s, n, subst, asz, alpha, beta, mode, -m, n);
+}
+
+int64_t oracle_banded_pair(const uint8_t *q, int64_t m, const uint8_t *s, int64_t n,
+                           const int8_t *subst, int32_t asz, int64_t alpha, int64_t beta,
+                           int32_t mode, int64_t w) {
+    int64_t lo = (n - m < 0 ? n - m : 0) - w;
+    int64_t hi = (n - m > 0 ? n - m : 0) + w;
+    return align_band(q, m, s, n, subst, asz, alpha, beta, mode, lo, hi);
+}
+
+/* ---- threaded batch driver: pairs are independent, split them over threads ---- */
+
+typedef struct {
+    const uint8_t *sa, *sb;
+    const int64_t *oa, *ob;
+    const int64_t *band_w; /* NULL = full DP */
+    int64_t n_pairs;
+    const int8_t *subst;
+    int32_t asz, mode;
+    int64_t alpha, beta;
+    int64_t *out;
+    int64_t next; /* shared work counter */
+    pthread_mutex_t lock;
+} batch_job;
+
+static void *batch_worker(void *arg) {
+    batch_job *job = (batch_job *)arg;
+    for (;;) {
+        int64_t p0, p1, p;
+        pthread_mutex_lock(&job->lock);
+        p0 = job->next;
+        job->next += 16;
+        pthread_mutex_unlock(&job->lock);
+        if (p0 >= job->n_pairs) break;
+        p1 = p0 + 16 < job->n_pairs ? p0 + 16 : job->n_pairs;
+        for (p = p0; p < p1; ++p) {
+            const uint8_t *q = job->sa + job->oa[p];
+            const uint8_t *s = job->sb + job->ob[p];
+            int64_t m = job->oa[p + 1] - job->oa[p];
+            int64_t n = job->ob[p + 1] - job->ob[p];
+            if (job->band_w)
+                job->out[p] = oracle_banded_pair(q, m, s, n, job->subst, job->asz, job->alpha,
+                                                 job->beta, job->mode, job->band_w[p]);
+            else
+                job->out[p] = oracle_align_pair(q, m, s, n, job->subst, job->asz, job->alpha,
+                                                job->beta, job->mode);
+        }
+    }
+    return NULL;
+}
+
+static void run_batch(batch_job *job, int32_t nthreads) {
+    pthread_t *th;
+    int32_t t;
+    if (nthreads < 1) nthreads = 1;
+    th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)nthreads);
+    pthread_mutex_init(&job->lock, NULL);
+    job->next = 0;
+    for (t = 0; t < nthreads; ++t) pthread_create(&th[t], NULL, batch_worker, job);
+    for (t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
+    pthread_mutex_destroy(&job->lock);
+    free(th);
+}
+
+void oracle_align_batch(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t *seqs_b,
+                        const int64_t *offs_b, int64_t n_pairs, const int8_t *subst, int32_t asz,
+                        int64_t alpha, int64_t beta, int32_t mode, int32_t nthreads, int64_t *out) {
+    batch_job job;
+    memset(&job, 0, sizeof(job));
+    job.sa = seqs_a; job.sb = seqs_b; job.oa = offs_a; job.ob = offs_b;
+    job.band_w = NULL; job.n_pairs = n_pairs; job.subst = subst; job.asz = asz;
+    job.mode = mode; job.alpha = alpha; job.beta = beta; job.out = out;
+    run_batch(&job, nthreads);
+}
+
+void oracle_banded_batch(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t *seqs_b,
+                         const int64_t *offs_b, int64_t n_pairs, const int8_t *subst, int32_t asz,
+                         int64_t alpha, int64_t beta, int32_t mode, const int64_t *band_w,
+                         int32_t nthreads, int64_t *out) {
+    batch_job job;
+    memset(&job, 0, sizeof(job));
+    job.sa = seqs_a; job.sb = seqs_b; job.oa = offs_a; job.ob = offs_b;
+    job.band_w = band_w; job.n_pairs = n_pairs; job.subst = subst; job.asz = asz;
+    job.mode = mode; job.alpha = alpha; job.beta = beta; job.out = out;
+    run_batch(&job, nthreads);
+}

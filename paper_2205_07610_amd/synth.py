@@ -1,0 +1,279 @@
+"""Seeded synthetic inputs for the five workloads (no alignment arithmetic here).
+
+This module is the only code that both the GPU path's callers and the CPU
+oracle's callers share.  It draws residues, lengths and mutations and builds
+substitution matrices; it computes no alignment score, bound or feature.
+
+The paper's own data (Mason-simulated Illumina reads and PBSIM PacBio reads
+from GRCh38 chr10, section 4.1) is not available, so every workload is drawn
+from the recipes below, with the shapes of the paper's short-read, mixed-length
+and long-read experiments:
+
+* residues: uniform codes 0..3 (DNA, A C G T) or 0..19 (protein);
+* mutation model, applied per source residue: substitution (a uniformly
+  different residue) with p_sub, an insertion of L ~ Geometric(1/2) random
+  residues before it with p_ins, a deletion of L ~ Geometric(1/2) residues
+  starting at it with p_del (geometric lengths have mean 2);
+* "divergence d, half indels" means p_sub = d/2, p_ins = p_del = d/4.
+
+All penalties are magnitudes: a gap of length k costs alpha + (k-1)*beta
+(paper Eq. (4),(5)); "gap open -5, extend -2" is alpha = 5, beta = 2.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+MODE_GLOBAL, MODE_SEMIGLOBAL, MODE_LOCAL = 0, 1, 2
+
+
+@dataclasses.dataclass
+class Batch:
+    """A batch of pairs in CSR form: pair p is A[offs_a[p]:offs_a[p+1]] vs B[...]."""
+    name: str
+    seqs_a: np.ndarray   # uint8 codes
+    offs_a: np.ndarray   # int64 [n_pairs + 1]
+    seqs_b: np.ndarray
+    offs_b: np.ndarray
+    subst: np.ndarray    # int8 [asz, asz], subst[q, s] = sigma(q, s)
+    alpha: int           # cost of a gap's first residue
+    beta: int            # cost of each further residue of the gap
+    mode: int            # 0 global, 1 semi-global, 2 local
+
+    @property
+    def n_pairs(self) -> int:
+        return len(self.offs_a) - 1
+
+    @property
+    def lens_a(self) -> np.ndarray:
+        return np.diff(self.offs_a)
+
+    @property
+    def lens_b(self) -> np.ndarray:
+        return np.diff(self.offs_b)
+
+    def cells(self) -> int:
+        return int(np.sum(self.lens_a.astype(np.int64) * self.lens_b.astype(np.int64)))
+
+    def subset(self, idx) -> "Batch":
+        """Pairs idx (in that order) as a new, compact batch."""
+        idx = np.asarray(idx, dtype=np.int64)
+        sa, oa = _gather(self.seqs_a, self.offs_a, idx)
+        sb, ob = _gather(self.seqs_b, self.offs_b, idx)
+        return Batch(self.name, sa, oa, sb, ob, self.subst, self.alpha, self.beta, self.mode)
+
+    def pair(self, p: int) -> tuple[np.ndarray, np.ndarray]:
+        return (self.seqs_a[self.offs_a[p]:self.offs_a[p + 1]],
+                self.seqs_b[self.offs_b[p]:self.offs_b[p + 1]])
+
+
+def _gather(seqs, offs, idx):
+    lens = (offs[idx + 1] - offs[idx]).astype(np.int64)
+    new_offs = np.zeros(len(idx) + 1, dtype=np.int64)
+    np.cumsum(lens, out=new_offs[1:])
+    total = int(new_offs[-1])
+    if total == 0:
+        return np.zeros(0, dtype=np.uint8), new_offs
+    starts = np.repeat(offs[idx] - new_offs[:-1], lens)
+    return seqs[np.arange(total, dtype=np.int64) + starts], new_offs
+
+
+def from_pairs(name, pairs, subst, alpha, beta, mode) -> Batch:
+    """Build a batch from a list of (a, b) code arrays."""
+    la = np.array([len(a) for a, _ in pairs], dtype=np.int64)
+    lb = np.array([len(b) for _, b in pairs], dtype=np.int64)
+    oa = np.zeros(len(pairs) + 1, dtype=np.int64)
+    ob = np.zeros(len(pairs) + 1, dtype=np.int64)
+    np.cumsum(la, out=oa[1:])
+    np.cumsum(lb, out=ob[1:])
+    sa = (np.concatenate([np.asarray(a, dtype=np.uint8) for a, _ in pairs])
+          if int(oa[-1]) else np.zeros(0, np.uint8))
+    sb = (np.concatenate([np.asarray(b, dtype=np.uint8) for _, b in pairs])
+          if int(ob[-1]) else np.zeros(0, np.uint8))
+    return Batch(name, sa, oa, sb, ob, np.asarray(subst, dtype=np.int8), int(alpha), int(beta),
+                 int(mode))
+
+
+# ---------------------------------------------------------------- scoring ----
+
+def dna_subst(match: int = 2, mismatch: int = -3) -> np.ndarray:
+    s = np.full((4, 4), mismatch, dtype=np.int8)
+    np.fill_diagonal(s, match)
+    return s
+
+
+def protein_subst(rng: np.random.Generator) -> np.ndarray:
+    """Symmetric 20x20 int8: diagonal U[4,11], off-diagonal U[-4,3]."""
+    s = np.zeros((20, 20), dtype=np.int8)
+    iu = np.triu_indices(20, 1)
+    off = rng.integers(-4, 4, size=len(iu[0]))
+    s[iu] = off
+    s[(iu[1], iu[0])] = off
+    np.fill_diagonal(s, rng.integers(4, 12, size=20))
+    return s
+
+
+# --------------------------------------------------------------- residues ----
+
+def random_csr(rng: np.random.Generator, lens, asz: int):
+    lens = np.asarray(lens, dtype=np.int64)
+    offs = np.zeros(len(lens) + 1, dtype=np.int64)
+    np.cumsum(lens, out=offs[1:])
+    return rng.integers(0, asz, size=int(offs[-1]), dtype=np.uint8), offs
+
+
+def mutate(rng: np.random.Generator, seqs, offs, p_sub, p_ins, p_del, asz: int):
+    """Apply the per-residue mutation model to every sequence of a CSR batch.
+
+    p_sub / p_ins / p_del are scalars or per-sequence arrays.  Deletions never
+    run past the end of their own sequence.
+    """
+    seqs = np.asarray(seqs, dtype=np.uint8)
+    offs = np.asarray(offs, dtype=np.int64)
+    n_seq = len(offs) - 1
+    lens = np.diff(offs)
+    total = int(offs[-1])
+    owner = np.repeat(np.arange(n_seq, dtype=np.int64), lens)
+    ps = np.broadcast_to(np.asarray(p_sub, dtype=np.float64), (n_seq,))[owner]
+    pi = np.broadcast_to(np.asarray(p_ins, dtype=np.float64), (n_seq,))[owner]
+    pd = np.broadcast_to(np.asarray(p_del, dtype=np.float64), (n_seq,))[owner]
+    u = rng.random(total)
+    is_sub = u < ps
+    is_ins = (u >= ps) & (u < ps + pi)
+    is_del = (u >= ps + pi) & (u < ps + pi + pd)
+    shift = rng.integers(1, asz, size=total)
+    ins_len = rng.geometric(0.5, size=total)
+    del_len = rng.geometric(0.5, size=total)
+
+    pos = np.arange(total, dtype=np.int64)
+    ends = np.minimum(pos + del_len, offs[1:][owner])
+    delta = np.zeros(total + 1, dtype=np.int64)
+    np.add.at(delta, pos[is_del], 1)
+    np.add.at(delta, ends[is_del], -1)
+    deleted = np.cumsum(delta)[:-1] > 0
+
+    base = np.where(is_sub, (seqs.astype(np.int64) + shift) % asz, seqs).astype(np.uint8)
+    n_ins = np.where(is_ins, ins_len, 0)
+    keep = ~deleted
+    count = n_ins + keep.astype(np.int64)
+    slot_end = np.cumsum(count)
+    slot_start = slot_end - count
+    out = rng.integers(0, asz, size=int(slot_end[-1]) if total else 0, dtype=np.uint8)
+    out[slot_start[keep] + n_ins[keep]] = base[keep]
+    new_lens = np.bincount(owner, weights=count, minlength=n_seq).astype(np.int64)
+    new_offs = np.zeros(n_seq + 1, dtype=np.int64)
+    np.cumsum(new_lens, out=new_offs[1:])
+    return out, new_offs
+
+
+def _diverged(rng, seqs, offs, div, asz):
+    div = np.asarray(div, dtype=np.float64)
+    return mutate(rng, seqs, offs, div / 2, div / 4, div / 4, asz)
+
+
+# -------------------------------------------------------------- workloads ----
+
+def config0(n_pairs: int = 1000, seed: int = 1000) -> Batch:
+    """1,000 pairs, A uniform ACGT^150, B = A with 3% sub, 1% ins, 1% del;
+    global affine, match +2, mismatch -3, alpha 5, beta 2."""
+    rng = np.random.default_rng(seed)
+    sa, oa = random_csr(rng, np.full(n_pairs, 150), 4)
+    sb, ob = mutate(rng, sa, oa, 0.03, 0.01, 0.01, 4)
+    return Batch("c0: global affine DNA, 150 bp", sa, oa, sb, ob, dna_subst(), 5, 2, MODE_GLOBAL)
+
+
+def config1(n_pairs: int = 1 << 20, seed: int = 1001) -> Batch:
+    """150 bp reads vs 250 bp windows; each window holds its read, mutated with
+    5% sub, 1% ins, 1% del (truncated to 250), at a uniform offset; local affine."""
+    rng = np.random.default_rng(seed)
+    sa, oa = random_csr(rng, np.full(n_pairs, 150), 4)
+    rm, ro = mutate(rng, sa, oa, 0.05, 0.01, 0.01, 4)
+    rl = np.minimum(np.diff(ro), 250)
+    win = rng.integers(0, 4, size=n_pairs * 250, dtype=np.uint8)
+    start = rng.integers(0, 250 - rl + 1)
+    owner = np.repeat(np.arange(n_pairs, dtype=np.int64), rl)
+    within = np.arange(int(rl.sum()), dtype=np.int64) - np.repeat(np.cumsum(rl) - rl, rl)
+    win[owner * 250 + start[owner] + within] = rm[ro[:-1][owner] + within]
+    ob = np.arange(n_pairs + 1, dtype=np.int64) * 250
+    return Batch("c1: local affine DNA, 150 bp reads vs 250 bp windows", sa, oa, win, ob,
+                 dna_subst(), 5, 2, MODE_LOCAL)
+
+
+def config2(n_pairs: int = 100_000, seed: int = 1002, sigma_ln: float = 1.0,
+            max_len: int = 20_000) -> Batch:
+    """Log-normal lengths (median 1 kb, sigma 1.0, clipped to 50..20,000),
+    B from A at divergence U[0, 0.15] (half indels); semi-global affine."""
+    rng = np.random.default_rng(seed)
+    la = np.clip(np.round(np.exp(rng.normal(math.log(1000.0), sigma_ln, size=n_pairs))),
+                 50, max_len).astype(np.int64)
+    sa, oa = random_csr(rng, la, 4)
+    div = rng.uniform(0.0, 0.15, size=n_pairs)
+    sb, ob = _diverged(rng, sa, oa, div, 4)
+    return Batch("c2: semi-global affine DNA, log-normal lengths", sa, oa, sb, ob, dna_subst(),
+                 5, 2, MODE_SEMIGLOBAL)
+
+
+def config3(n_pairs: int = 1 << 16, n_long: int = 64, long_len: int = 65536,
+            seed: int = 1003) -> Batch:
+    """Protein local affine: query U[50,1000] vs target U[50,2000], uniform
+    residues, seeded symmetric matrix, alpha 11, beta 1; then n_long pairs of
+    long_len residues (first half unrelated, second half B = A at 10%)."""
+    rng = np.random.default_rng(seed)
+    subst = protein_subst(rng)
+    la = rng.integers(50, 1001, size=n_pairs)
+    lb = rng.integers(50, 2001, size=n_pairs)
+    sa, oa = random_csr(rng, la, 20)
+    sb, ob = random_csr(rng, lb, 20)
+    if n_long:
+        la2, oa2 = random_csr(rng, np.full(n_long, long_len), 20)
+        half = n_long // 2
+        lb_un, ob_un = random_csr(rng, np.full(half, long_len), 20)
+        rel_a = la2[oa2[half]:]
+        rel_o = oa2[half:] - oa2[half]
+        lb_rel, ob_rel = _diverged(rng, rel_a, rel_o, np.full(n_long - half, 0.10), 20)
+        long_b = np.concatenate([lb_un, lb_rel])
+        long_ob = np.concatenate([ob_un[:-1], ob_rel + ob_un[-1]])
+        sa = np.concatenate([sa, la2])
+        oa = np.concatenate([oa[:-1], oa2 + oa[-1]])
+        sb = np.concatenate([sb, long_b])
+        ob = np.concatenate([ob[:-1], long_ob + ob[-1]])
+    return Batch("c3: local affine protein", sa, oa, sb, ob, subst, 11, 1, MODE_LOCAL)
+
+
+def config4(n_pairs: int = 1_000_000, seed: int = 1004) -> Batch:
+    """Lengths U[1000,5000], divergence U[0, 0.10] (half indels); global affine."""
+    rng = np.random.default_rng(seed)
+    la = rng.integers(1000, 5001, size=n_pairs)
+    sa, oa = random_csr(rng, la, 4)
+    div = rng.uniform(0.0, 0.10, size=n_pairs)
+    sb, ob = _diverged(rng, sa, oa, div, 4)
+    return Batch("c4: global affine DNA, 1-5 kb", sa, oa, sb, ob, dna_subst(), 5, 2, MODE_GLOBAL)
+
+
+def config4_training(n_pairs: int = 200_000, seed: int = 2004) -> Batch:
+    """Training pairs for the band network: config 4's law, its own seed."""
+    b = config4(n_pairs, seed)
+    b.name = "c4 training set"
+    return b
+
+
+def random_small(rng: np.random.Generator, n_pairs: int, max_len: int, asz: int = 4,
+                 related: float = 0.5) -> tuple[np.ndarray, np.ndarray, np.ndarray, np.ndarray]:
+    """Mixed small pairs for edge-case tests: lengths U[0, max_len], about
+    `related` of them with B derived from A at divergence U[0, 0.3]."""
+    la = rng.integers(0, max_len + 1, size=n_pairs)
+    sa, oa = random_csr(rng, la, asz)
+    div = rng.uniform(0.0, 0.3, size=n_pairs)
+    sb_rel, ob_rel = _diverged(rng, sa, oa, div, asz)
+    lb = rng.integers(0, max_len + 1, size=n_pairs)
+    sb_un, ob_un = random_csr(rng, lb, asz)
+    pick = rng.random(n_pairs) < related
+    pairs_b = [sb_rel[ob_rel[p]:ob_rel[p + 1]] if pick[p] else sb_un[ob_un[p]:ob_un[p + 1]]
+               for p in range(n_pairs)]
+    lens_b = np.array([len(x) for x in pairs_b], dtype=np.int64)
+    ob = np.zeros(n_pairs + 1, dtype=np.int64)
+    np.cumsum(lens_b, out=ob[1:])
+    sb = np.concatenate(pairs_b) if ob[-1] else np.zeros(0, np.uint8)
+    return sa, oa, sb.astype(np.uint8), ob
