@@ -1,0 +1,199 @@
+#!/usr/bin/env python3
+"""Benchmark: score-only alignment throughput on one MI355X.
+
+A step is one as_align_batch call over the whole batch (validation and
+classification, the DP kernels, the 16-bit overflow re-run, the status
+read-back), with the inputs already resident in HBM.  The workload is the
+2^20-pair local affine DNA batch (150 bp reads against 250 bp windows that
+hold a mutated copy; match +2, mismatch -3, alpha 5, beta 2), seeded and
+synthetic.  Prints one JSON line.
+
+--gpus N with N > 1 exits: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GCUPS & pairs/s: full DP vs learned-band exact, 1 MI355X, 0 mismatches"
+# Algorithmic integer operations per cell (the paper's section 4.2 count for
+# global affine: 4 max + 3 add/sub; local adds the nu = 0 max and the running
+# maximum).
+OPS_PER_CELL = {0: 7, 1: 7, 2: 9}
+# MI355X VALU integer peak: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz lane-ops/s;
+# packed 16-bit forms do two lane-ops per lane and instruction.
+PEAK_I32_TOPS = 256 * 64 * 2.4e9 / 1e12
+PEAK_I16X2_TOPS = 2 * PEAK_I32_TOPS
+KERNEL_SOURCES = {
+    "full32": "paper_2205_07610_amd/csrc/full_dp_i32.hip",
+}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def source_sha(path: str) -> str:
+    with open(os.path.join(ROOT, path), "rb") as f:
+        return hashlib.sha1(f.read()).hexdigest()[:12]
+
+
+def traffic_for(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 PMC summary, if it
+    was taken on the current kernel source; otherwise None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_sha") != source_sha(KERNEL_SOURCES[kernel]):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(batch, seconds: float, gpu_scores):
+    """Time the CPU oracle on a bounded sample of the same batch; also count
+    GPU/oracle mismatches on that sample."""
+    import numpy as np
+    import oracle
+    threads = oracle.default_threads()
+    rng = np.random.default_rng(12345)
+    order = rng.permutation(batch.n_pairs)
+    chunk = 4096
+    done_cells = 0
+    done_pairs = 0
+    mismatches = 0
+    elapsed = 0.0          # oracle time only (sample gathering excluded)
+    pos = 0
+    while pos < batch.n_pairs and elapsed < seconds:
+        idx = np.sort(order[pos:pos + chunk])
+        pos += chunk
+        sub = batch.subset(idx)
+        t1 = time.perf_counter()
+        want = oracle.align_batch(sub.seqs_a, sub.offs_a, sub.seqs_b, sub.offs_b, sub.subst,
+                                  sub.alpha, sub.beta, sub.mode, threads)
+        elapsed += time.perf_counter() - t1
+        done_cells += sub.cells()
+        done_pairs += len(idx)
+        mismatches += int(np.count_nonzero(gpu_scores[idx].astype(np.int64) != want))
+    return {
+        "value": round(done_cells / elapsed / 1e9, 4),
+        "unit": "GCUPS",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"{done_pairs} random pairs of the same batch ({done_cells:.3e} cells, "
+                  f"{elapsed:.1f} s, scalar int64 C, {threads} threads)",
+    }, mismatches, done_pairs
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--pairs", type=int, default=1 << 20)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(pairs are independent; see the sharding note in the design document)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2205_07610_amd import binding, synth
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    binding.lib()
+    log(f"generating workload: {args.pairs} pairs")
+    batch = synth.config1(n_pairs=args.pairs)
+    cells = batch.cells()
+    sa, oa, sb, ob = binding.to_device(batch)
+    out = torch.empty(batch.n_pairs, dtype=torch.int32, device="cuda")
+
+    def step():
+        binding.align_batch(sa, oa, sb, ob, batch.subst, batch.alpha, batch.beta, batch.mode,
+                            scores_out=out)
+
+    log(f"warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    binding.enable_timing(True)
+    kernel_ms = []
+    phases = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+        tm = binding.last_timing()
+        phases.append(tm)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    binding.enable_timing(False)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step")
+
+    # dominant kernel: the phase with the largest time
+    ph_names = ["full32_ms", "full16_ms", "rerun32_ms", "classify_ms"]
+    avg = {k: sum(p[k] for p in phases) / len(phases) for k in ph_names}
+    dom = max(ph_names, key=lambda k: avg[k])
+    kernel_ms = avg[dom]
+    kernel_name = dom.replace("_ms", "")
+    pairs_dom = phases[-1].get(f"pairs_{kernel_name}", batch.n_pairs)
+    packed = kernel_name == "full16"
+    ops = cells * OPS_PER_CELL[batch.mode]
+    achieved = ops / (kernel_ms * 1e-3) / 1e12
+    peak = PEAK_I16X2_TOPS if packed else PEAK_I32_TOPS
+
+    gpu_scores = out.cpu().numpy()
+    result = {
+        "metric": METRIC,
+        "value": round(cells / (ms_per_step * 1e-3) / 1e9, 2),
+        "unit": "GCUPS",
+        "pairs_per_s": round(batch.n_pairs / (ms_per_step * 1e-3), 1),
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i16x2" if packed else "i32",
+        "data": "synthetic",
+        "config": {"workload": "2^20 pairs, 150 bp reads vs 250 bp windows, local affine DNA "
+                               "(+2/-3, alpha 5, beta 2)",
+                   "n_pairs": batch.n_pairs, "cells": cells, "mode": "local"},
+        "phases_ms": {k: round(v, 4) for k, v in avg.items()},
+        "roofline": {
+            "bound": "alu",
+            "kernel": kernel_name,
+            "achieved": round(achieved, 3),
+            "peak": round(peak, 2),
+            "unit": "Tops/s",
+            "frac": round(achieved / peak, 4),
+            "kernel_ms": round(kernel_ms, 4),
+            "ops_per_cell": OPS_PER_CELL[batch.mode],
+            "traffic": traffic_for(kernel_name) if kernel_name in KERNEL_SOURCES else None,
+        },
+    }
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline (~{args.cpu_seconds} s)")
+        cb, mism, checked = cpu_baseline(batch, args.cpu_seconds, gpu_scores)
+        result["cpu_baseline"] = cb
+        result["mismatches"] = {"checked_pairs": checked, "mismatches": mism}
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

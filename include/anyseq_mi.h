@@ -1,0 +1,123 @@
+/*
+ * anyseq_mi -- score-only pairwise alignment of large batches of sequence
+ * pairs on AMD Instinct MI355X (gfx950).
+ *
+ * The problem follows the statement of AnySeq/GPU (arXiv 2205.07610),
+ * section 2.1: pairs (Q, S) of sequences over an alphabet, a substitution
+ * function sigma over alphabet x alphabet, gap penalties alpha (first gap
+ * residue) and beta (each further residue), so a gap of length k costs
+ * alpha + (k-1)*beta (Eq. (4),(5); linear gaps are alpha == beta, Eq. (2),(3)),
+ * and an alignment type: global, semi-global or local (the mode paragraphs
+ * of section 2.1).  Batches of pairs go in, one optimal score per pair comes
+ * out (the paper's Listing 1 signature; score-only, "Traceback" paragraph).
+ *
+ * Conventions shared by every entry point
+ *  - Sequences are residue codes 0..alphabet_size-1, one byte per residue,
+ *    concatenated: pair p is A[offs_a[p] .. offs_a[p+1]) against
+ *    B[offs_b[p] .. offs_b[p+1]).  Offsets are int64, non-decreasing,
+ *    offs[0] >= 0; the caller guarantees the sequence buffers hold
+ *    offs[n_pairs] bytes.  Empty sequences are allowed.
+ *  - Rows of the dynamic program run over A (q_i, i = 1..m), columns over
+ *    B (s_j, j = 1..n), sigma(q_i, s_j) = subst[q_i * alphabet_size + s_j].
+ *    The library may transpose a pair internally; results are unchanged.
+ *  - Device pointers are HIP device memory on the current device; the caller
+ *    owns every buffer.  `stream` is a hipStream_t (NULL = default stream).
+ *    Calls are stream-ordered; the return code is known when the call
+ *    returns (the call waits for its own status word).
+ *  - Errors: a negative return code; scores_out contents are then
+ *    unspecified.  A call never returns 0 with a wrong score.  No C++
+ *    exception crosses this interface.
+ *  - Scratch memory is owned by the library, cached per device and grown on
+ *    demand; as_release_workspace() frees it.  Calls on one device are
+ *    serialised by the library (a process-wide lock).
+ */
+#ifndef ANYSEQ_MI_H
+#define ANYSEQ_MI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Alignment type (paper section 2.1). */
+typedef enum {
+    AS_GLOBAL = 0,     /* nu = -inf, penalised end gaps, result H(m,n) */
+    AS_SEMIGLOBAL = 1, /* free end gaps: result = max over last row and column */
+    AS_LOCAL = 2       /* Smith-Waterman: nu = 0, result = max over all cells */
+} as_mode;
+
+/* Scoring scheme.  All penalties are magnitudes that are subtracted. */
+typedef struct {
+    int32_t alphabet_size; /* 2..32 */
+    const int8_t *subst;   /* HOST pointer, alphabet_size^2 entries, row-major */
+    int32_t gap_open;      /* alpha: cost of a gap's first residue, 0..10000 */
+    int32_t gap_extend;    /* beta: cost of each further residue, 0 <= beta <= alpha */
+} as_scoring;
+
+/* Return codes. */
+#define AS_OK 0
+#define AS_ERR_NULL (-1)      /* a required pointer is NULL */
+#define AS_ERR_OFFSETS (-2)   /* offsets decrease or offs[0] < 0 */
+#define AS_ERR_RESIDUE (-3)   /* a residue code >= alphabet_size */
+#define AS_ERR_SCORING (-4)   /* alphabet size, alpha, beta or mode invalid */
+#define AS_ERR_RANGE (-5)     /* a score could leave the int32 range */
+#define AS_ERR_HIP (-6)       /* a HIP runtime call failed */
+#define AS_ERR_ARG (-7)       /* another argument is out of range */
+
+/*
+ * Optimal alignment score of every pair of the batch (paper section 2.1,
+ * Eq. (1),(4),(5), mode as given).
+ *   seqs_a, seqs_b : device, uint8 residue codes
+ *   offs_a, offs_b : device, int64 [n_pairs + 1]
+ *   n_pairs        : >= 0 (0 returns AS_OK and touches nothing)
+ *   scoring        : host struct, read during the call only
+ *   mode           : as_mode
+ *   scores_out     : device, int32 [n_pairs]
+ *   stream         : hipStream_t or NULL
+ * Pairs whose scores fit 16-bit cells (a priori bound, or no saturation at
+ * run time) take the packed 16-bit path; all others, and every 16-bit pair
+ * that saturates, are computed with 32-bit cells.  Results are exact in
+ * every case.
+ */
+int as_align_batch(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t *seqs_b,
+                   const int64_t *offs_b, int64_t n_pairs, const as_scoring *scoring,
+                   int32_t mode, int32_t *scores_out, void *stream);
+
+/* Human-readable text for a return code (static storage). */
+const char *as_strerror(int code);
+
+/* Free the library's cached scratch memory on every device.  Returns AS_OK. */
+int as_release_workspace(void);
+
+/* Build information: the offload target and the kernel variants compiled in. */
+const char *as_build_info(void);
+
+/*
+ * Per-phase GPU times of the most recent as_align_batch call on this
+ * process, measured with HIP events recorded on the call's stream around
+ * each phase (only while timing is enabled; disabled by default because the
+ * events cost a few microseconds per call).  Times are milliseconds; a phase
+ * that did not run reports 0.  Counts describe the same call.
+ */
+typedef struct {
+    float classify_ms;  /* validation, orientation, work lists */
+    float full32_ms;    /* full DP, 32-bit cells */
+    float full16_ms;    /* full DP, packed 16-bit cells */
+    float rerun32_ms;   /* 32-bit re-run of saturated 16-bit pairs */
+    int64_t pairs_full32;
+    int64_t pairs_full16;
+    int64_t pairs_rerun32;
+    int64_t cells;      /* sum of m*n over the batch */
+} as_timing;
+
+/* Enable (1) or disable (0) phase timing.  Returns the previous setting. */
+int as_enable_timing(int on);
+/* Copy the last call's phase times into *out (host).  AS_ERR_NULL if out is NULL. */
+int as_last_timing(as_timing *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ANYSEQ_MI_H */

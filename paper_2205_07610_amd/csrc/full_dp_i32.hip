@@ -1,0 +1,296 @@
+// Full Gotoh DP with 32-bit cells, one 16-lane DPP row per alignment.
+//
+// Method: paper section 3.1 ("Mapping Matrix Cells and Sequences to
+// Threads"): lane t of a group owns K adjacent columns; in wavefront step
+// `it` it computes its K cells of row it + 1 - t from registers only, takes
+// the rightmost H (and F) of lane t-1 with a one-lane shift, and looks the
+// substitution scores up in a per-lane scoring profile.  On gfx950 the shift
+// is a DPP row_shr:1 (a VALU source modifier, no LDS traffic), the group is
+// one 16-lane DPP row, and the profile is int8 in LDS.  Columns wider than
+// 16*K are processed in stripes left to right with the stripe's right-hand
+// H/F column written to a global boundary buffer and read back by the next
+// stripe (the paper's multi-stage scheme for long subjects).
+//
+// Cell recurrences (paper Eq. (1),(4),(5)) are evaluated in two frames:
+//
+//  * global and semi-global use the shifted frame X^(i,j) = X(i,j) + beta*(i+j)
+//    for X in {H, E, F}.  In it the extension penalty disappears:
+//        E^(i,j)   = max(E^(i-1,j), H'(i-1,j))
+//        F^(i,j+1) = max(F^(i,j),   H'(i,j))
+//        H^(i,j)   = max(H'(i-1,j-1) + sigma + alpha + beta, E^(i,j), F^(i,j))
+//        H'(i,j)   = H^(i,j) - (alpha - beta)
+//    five VALU operations per cell (max, add, max3, sub, max) instead of the
+//    paper's seven; the frame is exact integer arithmetic, undone on output.
+//  * local keeps the plain frame, with E and F clamped at 0 so that the
+//    nu = 0 term folds into their max3:  E'(i,j) = max(E'(i-1,j) - beta,
+//    H(i-1,j) - alpha, 0), likewise F'; H = max3(H(i-1,j-1) + sigma, E', F')
+//    equals max(..., E, F, 0) because E' = max(E, 0).  Seven operations per
+//    cell plus the running maximum.
+//
+// Padding: global pads the last stripe on the right (result cell H(m,n) is
+// picked out at the end).  Semi-global and local pad the first stripe on the
+// left with columns whose sigma is 0: such columns keep H = 0 in every row,
+// exactly the boundary column H(i,0) = 0 of these modes, and F flowing out of
+// them equals H(i,0) - alpha.  Column n then sits in the last register of the
+// last lane, which makes the semi-global last-column maximum one max per step.
+#include "internal.h"
+
+namespace asmi {
+namespace {
+
+constexpr int kK = 16;                 // columns per lane
+constexpr int kW = kGroup * kK;        // columns per stripe
+
+__device__ __forceinline__ int dpp_shr1(int old, int src) {
+  // row_shr:1 -- lane t reads lane t-1 of its 16-lane row; lane 0 keeps `old`.
+  return __builtin_amdgcn_update_dpp(old, src, 0x111, 0xF, 0xF, false);
+}
+__device__ __forceinline__ int dpp_shl1(int old, int src) {
+  // row_shl:1 -- lane t reads lane t+1 of its row; lane 15 keeps `old`.
+  return __builtin_amdgcn_update_dpp(old, src, 0x101, 0xF, 0xF, false);
+}
+__device__ __forceinline__ int imax3(int a, int b, int c) { return max(max(a, b), c); }
+
+__device__ __forceinline__ int group_max(int v) {
+  v = max(v, __shfl_xor(v, 8, 16));
+  v = max(v, __shfl_xor(v, 4, 16));
+  v = max(v, __shfl_xor(v, 2, 16));
+  v = max(v, __shfl_xor(v, 1, 16));
+  return v;
+}
+__device__ __forceinline__ int wave_max_groups(int v) {
+  // v is uniform inside each group: combine the four groups.
+  v = max(v, __shfl_xor(v, 16));
+  v = max(v, __shfl_xor(v, 32));
+  return v;
+}
+
+template <int MODE, int K>
+__global__ void __launch_bounds__(kWave) full_dp_i32_kernel(FullDpArgs a) {
+  constexpr int W = kGroup * K;
+  extern __shared__ __align__(16) int8_t lds[];
+  const int lane = threadIdx.x;
+  const int g = lane >> 4;
+  const int t = lane & 15;
+  const int asz = a.asz;
+  int8_t *prof = lds + g * asz * W;
+  const int alpha = a.alpha, beta = a.beta;
+  const int n_items = a.ctr->n_full32;
+  int2 *slot = a.bnd + ((int64_t)blockIdx.x * kGroupsPerWave + g) * 2 * a.bnd_rows;
+
+  // Profile bias: the value added to the stored diagonal (see header).
+  const int bias = (MODE == kLocal) ? alpha : alpha + beta;
+  const int amb = alpha - beta;
+
+  for (;;) {
+    int base = 0;
+    if (lane == 0) base = atomicAdd(&a.ctr->next_full32, kGroupsPerWave);
+    base = __shfl(base, 0);
+    if (base >= n_items) break;
+    const int item = base + g;
+    const bool has = item < n_items;
+    PairDesc d{0, 0, 0, 0, -1, 0};
+    if (has) d = a.items[item];
+    const int m = has ? d.m : 0;
+    const int n = has ? d.n : 0;
+    const int S = has ? (n + W - 1) / W : 0;
+    const int pad = (MODE == kGlobal) ? 0 : S * W - n;
+    const bool tr = (d.flags & kTransposed) != 0;
+    const uint8_t *rows = (tr ? a.seqs_b : a.seqs_a) + d.row_off;
+    const uint8_t *cols = (tr ? a.seqs_a : a.seqs_b) + d.col_off;
+    const int S_max = wave_max_groups(S);
+    int result = 0;       // semi-global / local: boundary cells and the empty alignment give 0
+    int bad = 0;          // residue codes out of range seen by this lane
+
+    for (int s = 0; s < S_max; ++s) {
+      const bool on = s < S;
+      const int m_s = on ? m : 0;
+      const int jp0 = s * W + t * K;   // padded column of x = 0 is jp0 + 1
+      // ---- scoring profile for this lane's K columns (paper: init_profile) ----
+      if (on) {
+#pragma unroll
+        for (int x = 0; x < K; ++x) {
+          const int j = jp0 + x + 1 - pad;  // real column, 1-based
+          int c = -1;
+          if (j >= 1 && j <= n) {
+            c = cols[j - 1];
+            if (c >= asz) { bad = 1; c = 0; }
+          }
+          for (int r = 0; r < asz; ++r) {
+            int sv = 0;  // padding columns score 0 (see header)
+            if (c >= 0) sv = tr ? a.subst[c * asz + r] : a.subst[r * asz + c];
+            prof[r * W + t * K + x] = (int8_t)(sv + bias);
+          }
+        }
+      }
+      // ---- row-0 state ----
+      int Ha[K], Ee[K];
+#pragma unroll
+      for (int x = 0; x < K; ++x) {
+        const int jp = jp0 + x + 1;
+        if (MODE == kGlobal) { Ha[x] = 2 * beta - 2 * alpha; Ee[x] = kNegInf32; }
+        else if (MODE == kSemiGlobal) { Ha[x] = beta * jp + beta - alpha; Ee[x] = kNegInf32; }
+        else { Ha[x] = -alpha; Ee[x] = 0; }
+      }
+      int hl_prev;
+      if (MODE == kGlobal) hl_prev = (jp0 == 0) ? beta - alpha : 2 * beta - 2 * alpha;
+      else if (MODE == kSemiGlobal) hl_prev = beta * jp0 + beta - alpha;
+      else hl_prev = -alpha;
+      int hout = Ha[K - 1];
+      int fout = (MODE == kLocal) ? 0 : kNegInf32;
+      int rm = 0;                 // local running max / semi-global last-column max
+      if (MODE == kSemiGlobal) rm = kNegInf32;
+      int rowoff = 0;             // beta * row, semi-global only
+
+      const bool import = s > 0;
+      const bool export_ = on && (s + 1 < S);
+      const int2 *bin = slot + (int64_t)(s & 1) * a.bnd_rows;
+      int2 *bout = slot + (int64_t)((s + 1) & 1) * a.bnd_rows;
+
+      const int its = m_s > 0 ? m_s + kGroup - 1 : 0;
+      const int its_max = wave_max_groups(its);
+
+      // left boundary of stripe 0 for lane 0 (rows advance by one per step)
+      int hb, fb;
+      if (MODE == kGlobal) { hb = 2 * beta - 2 * alpha; fb = hb; }
+      else if (MODE == kSemiGlobal) { hb = 2 * beta - alpha; fb = hb; }  // row 1
+      else { hb = -alpha; fb = 0; }
+
+      // feeds: query residues (and imported boundary) for 16 steps, lane t = step t
+      int qfeed = 0, hfeed = 0, ffeed = 0, qc = 0;
+      {
+        const int qi = t;
+        if (qi < m_s) { qfeed = rows[qi]; if (qfeed >= asz) { bad = 1; qfeed = 0; } }
+        if (import && t + 1 <= m_s) { const int2 v = bin[t + 1]; hfeed = v.x; ffeed = v.y; }
+      }
+      if (MODE == kSemiGlobal) rowoff = beta * (1 - t);
+
+      for (int it0 = 0; it0 < its_max; it0 += kGroup) {
+        int qnext = 0, hnext = 0, fnext = 0;
+        {
+          const int qi = it0 + kGroup + t;
+          if (qi < m_s) { qnext = rows[qi]; if (qnext >= asz) { bad = 1; qnext = 0; } }
+          const int bi = it0 + kGroup + 1 + t;
+          if (import && bi <= m_s) { const int2 v = bin[bi]; hnext = v.x; fnext = v.y; }
+        }
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) {
+          const int row = it0 + u + 1 - t;
+          qc = dpp_shr1(qfeed, qc);
+          const int hsrc = import ? hfeed : hb;
+          const int fsrc = import ? ffeed : fb;
+          const int hl = dpp_shr1(hsrc, hout);
+          const int fl = dpp_shr1(fsrc, fout);
+          if ((unsigned)(row - 1) < (unsigned)m_s) {
+            const int8_t *pp = prof + qc * W + t * K;
+            int4 pw[K / 16];
+#pragma unroll
+            for (int v = 0; v < K / 16; ++v) pw[v] = *(const int4 *)(pp + 16 * v);
+            int dg = hl_prev;
+            int f = fl;
+#pragma unroll
+            for (int x = 0; x < K; ++x) {
+              const int word = (x & 15) >> 2;
+              const int w32 = word == 0 ? pw[x >> 4].x : word == 1 ? pw[x >> 4].y
+                            : word == 2 ? pw[x >> 4].z : pw[x >> 4].w;
+              const int sc = (int)(int8_t)(w32 >> (8 * (x & 3)));
+              if (MODE == kLocal) {
+                const int e = imax3(Ee[x] - beta, Ha[x], 0);
+                const int h = imax3(dg + sc, e, f);
+                rm = max(rm, h);
+                dg = Ha[x];
+                Ha[x] = h - alpha;
+                Ee[x] = e;
+                f = imax3(f - beta, Ha[x], 0);
+              } else {
+                const int e = max(Ee[x], Ha[x]);
+                const int h = imax3(dg + sc, e, f);
+                dg = Ha[x];
+                Ha[x] = h - amb;
+                Ee[x] = e;
+                f = max(f, Ha[x]);
+              }
+            }
+            hout = Ha[K - 1];
+            fout = f;
+            if (MODE == kSemiGlobal) rm = max(rm, hout - rowoff);
+            if (export_ && t == kGroup - 1) bout[row] = make_int2(hout, fout);
+          }
+          hl_prev = hl;
+          if (MODE == kSemiGlobal) { hb += beta; fb = hb; rowoff += beta; }
+          qfeed = dpp_shl1(qfeed, qfeed);
+          if (import) { hfeed = dpp_shl1(hfeed, hfeed); ffeed = dpp_shl1(ffeed, ffeed); }
+        }
+        qfeed = qnext;
+        hfeed = hnext;
+        ffeed = fnext;
+      }
+
+      // ---- per-stripe results ----
+      if (MODE == kLocal) {
+        result = max(result, group_max(rm));
+      } else if (MODE == kSemiGlobal) {
+        // last row: H(m, jp) = H'(m, jp) + alpha - beta - beta*(m + jp)
+        int lr = kNegInf32;
+#pragma unroll
+        for (int x = 0; x < K; ++x) lr = max(lr, Ha[x] - beta * (jp0 + x + 1));
+        int cand = m_s > 0 ? lr + amb - beta * m_s : kNegInf32;
+        if (on && s + 1 == S && t == kGroup - 1 && m_s > 0)   // last column (jp = S*W)
+          cand = max(cand, rm + amb - beta * (S * W));
+        const int gm = group_max(cand);
+        if (on) result = max(result, gm);
+      } else {
+        // H(m, n) sits in stripe (n-1)/W, lane ((n-1)%W)/K, register (n-1)%K
+        const int c = n - 1 - s * W;
+        int v = kNegInf32;
+        if (on && c >= 0 && c < W && c / K == t) {
+          const int xr = c % K;
+#pragma unroll
+          for (int x = 0; x < K; ++x) if (x == xr) v = Ha[x];
+          v = v + amb - beta * (m + n);
+        }
+        v = group_max(v);
+        if (on && c >= 0 && c < W) result = v;
+      }
+      if (s + 1 < S_max) __threadfence();  // boundary writes visible to the next stripe's loads
+    }
+    if (bad) atomicOr(&a.ctr->status, kStatusBadResidue);
+    if (has && t == 0) a.scores[d.pair] = result;
+  }
+}
+
+template <int MODE>
+hipError_t launch_mode(const FullDpArgs &args, int grid, hipStream_t stream) {
+  const size_t lds = full_dp_i32_lds_bytes(args.asz);
+  hipLaunchKernelGGL((full_dp_i32_kernel<MODE, kK>), dim3(grid), dim3(kWave), lds, stream, args);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+size_t full_dp_i32_lds_bytes(int asz) { return (size_t)kGroupsPerWave * asz * kW; }
+int full_dp_i32_stripe_width() { return kW; }
+
+int full_dp_i32_blocks_per_cu(int mode, int asz) {
+  int nb = 0;
+  const size_t lds = full_dp_i32_lds_bytes(asz);
+  hipError_t e;
+  if (mode == kGlobal)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, full_dp_i32_kernel<kGlobal, kK>, kWave, lds);
+  else if (mode == kSemiGlobal)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, full_dp_i32_kernel<kSemiGlobal, kK>, kWave, lds);
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, full_dp_i32_kernel<kLocal, kK>, kWave, lds);
+  if (e != hipSuccess || nb < 1) nb = 1;
+  return nb;
+}
+
+hipError_t launch_full_dp_i32(int mode, const FullDpArgs &args, int grid, hipStream_t stream) {
+  switch (mode) {
+    case kGlobal: return launch_mode<kGlobal>(args, grid, stream);
+    case kSemiGlobal: return launch_mode<kSemiGlobal>(args, grid, stream);
+    default: return launch_mode<kLocal>(args, grid, stream);
+  }
+}
+
+}  // namespace asmi

@@ -1,0 +1,73 @@
+// Internal declarations shared by the library's HIP translation units.
+// Nothing here is part of the public C ABI (include/anyseq_mi.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace asmi {
+
+// One DPP row (16 lanes) cooperates on one alignment: lane t owns K adjacent
+// DP columns and, in wavefront step `it`, computes row it + 1 - t
+// (the paper's section 3.1 mapping with p = 16 lanes).  A wave64 therefore
+// carries four independent alignments.
+constexpr int kGroup = 16;
+constexpr int kWave = 64;
+constexpr int kGroupsPerWave = kWave / kGroup;
+
+// Finite stand-in for -infinity in 32-bit cells.  Every reachable value stays
+// far above it (scores are bounded a priori, see RangeBound in runtime.hip).
+constexpr int32_t kNegInf32 = -(1 << 29);
+
+enum Mode : int32_t { kGlobal = 0, kSemiGlobal = 1, kLocal = 2 };
+
+// One queued alignment as the DP kernels see it.  "rows" is the sequence
+// streamed down the DP rows, "cols" the one held in the per-lane profile.
+struct PairDesc {
+  int64_t row_off;  // offset of the row sequence in its buffer
+  int64_t col_off;  // offset of the column sequence in its buffer
+  int32_t m;        // number of rows (>= 1)
+  int32_t n;        // number of columns (>= 1)
+  int32_t pair;     // index of the score in scores_out
+  int32_t flags;    // kTransposed: rows come from B, columns from A
+};
+constexpr int32_t kTransposed = 1;
+
+// Status word bits, OR-ed by kernels; read back once per call.
+constexpr int32_t kStatusBadOffsets = 1;
+constexpr int32_t kStatusBadResidue = 2;
+constexpr int32_t kStatusRange = 4;
+
+// Work-list counters written by the classify kernel.
+struct Counters {
+  int32_t n_full32;      // items queued for the 32-bit full DP
+  int32_t next_full32;   // work pointer of the persistent 32-bit kernel
+  int32_t max_rows_multi;// largest m among multi-stripe items
+  int32_t status;        // OR of kStatus* bits
+  unsigned long long cells;  // sum of m*n over the batch
+};
+
+struct FullDpArgs {
+  const uint8_t *seqs_a;
+  const uint8_t *seqs_b;
+  const PairDesc *items;
+  Counters *ctr;
+  const int8_t *subst;  // device copy, sigma(a, b) = subst[a * asz + b]
+  int32_t asz;
+  int32_t alpha;
+  int32_t beta;
+  int32_t *scores;
+  int2 *bnd;            // boundary columns, one slot per group: 2 * bnd_rows int2
+  int64_t bnd_rows;     // rows per boundary buffer (>= max_rows_multi + 1)
+};
+
+// Launch the persistent 32-bit full-DP kernel for `mode` on `grid` blocks
+// of one wave each.  Returns hipSuccess or the launch error.
+hipError_t launch_full_dp_i32(int mode, const FullDpArgs &args, int grid, hipStream_t stream);
+// Resident one-wave blocks per CU for the kernel (occupancy query).
+int full_dp_i32_blocks_per_cu(int mode, int asz);
+// Columns per stripe (16 lanes x K).
+int full_dp_i32_stripe_width();
+size_t full_dp_i32_lds_bytes(int asz);
+
+}  // namespace asmi

@@ -1,0 +1,74 @@
+"""Host-side checks of the C-ABI library that need no GPU: it loads, it
+exports every function the header declares, and argument validation that
+happens before any device work returns the documented codes."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_2205_07610_amd import binding
+
+AS_ERR_NULL, AS_ERR_SCORING, AS_ERR_ARG = -1, -4, -7
+
+
+@pytest.fixture(scope="module")
+def L():
+    return binding.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = binding.declared_functions()
+    assert "as_align_batch" in names and len(names) >= 4
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_strerror_and_build_info(L):
+    for code in range(0, -8, -1):
+        assert binding.strerror(code)
+    assert binding.strerror(-99) == "unknown error"
+    assert b"gfx950" in L.as_build_info()
+
+
+def _call(L, *, n_pairs=1, asz=4, alpha=5, beta=2, mode=0, null=None, subst=None):
+    sub = np.full((asz, asz), -3, np.int8) if subst is None else subst
+    sc = binding.Scoring(asz, sub.ctypes.data_as(ctypes.c_void_p), alpha, beta)
+    dummy = ctypes.c_void_p(0x1000)   # never dereferenced: validation fails first
+    ptrs = [dummy] * 5
+    if null is not None:
+        ptrs[null] = ctypes.c_void_p(0)
+    return L.as_align_batch(ptrs[0], ptrs[1], ptrs[2], ptrs[3], n_pairs, ctypes.byref(sc), mode,
+                            ptrs[4], None)
+
+
+@pytest.mark.parametrize("which", range(5))
+def test_null_pointers(L, which):
+    assert _call(L, null=which) == AS_ERR_NULL
+
+
+def test_null_scoring(L):
+    d = ctypes.c_void_p(0x1000)
+    assert L.as_align_batch(d, d, d, d, 1, None, 0, d, None) == AS_ERR_NULL
+
+
+@pytest.mark.parametrize("kw", [dict(asz=1), dict(asz=33), dict(alpha=2, beta=3), dict(beta=-1),
+                                dict(mode=3), dict(mode=-1), dict(alpha=20000, beta=0)])
+def test_bad_scoring(L, kw):
+    assert _call(L, **kw) == AS_ERR_SCORING
+
+
+def test_bad_n_pairs(L):
+    assert _call(L, n_pairs=-1) == AS_ERR_ARG
+
+
+def test_zero_pairs_is_ok_without_device(L):
+    assert _call(L, n_pairs=0) == 0
+
+
+def test_python_binding_rejects_host_tensors():
+    torch = pytest.importorskip("torch")
+    t = torch.zeros(4, dtype=torch.uint8)
+    o = torch.zeros(2, dtype=torch.int64)
+    with pytest.raises(TypeError):
+        binding.align_batch(t, o, t, o, np.eye(4, dtype=np.int8), 5, 2, 0,
+                            scores_out=torch.zeros(1, dtype=torch.int32), stream=0)

@@ -1,0 +1,152 @@
+"""GPU parity: every score from the HIP library equals the CPU oracle's,
+bit for bit, on the same seeded inputs.  Runs on an MI355X only."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2205_07610_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+DNA = synth.dna_subst()
+
+
+def _say(msg):
+    print(f"[parity] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2205_07610_amd import binding
+    binding.lib()
+    return binding
+
+
+def _check(gpu, oracle_mod, batch, label, nthreads=None):
+    _say(f"{label}: {batch.n_pairs} pairs, {batch.cells():.3g} cells, mode {batch.mode}")
+    got = gpu.align(batch)
+    want = oracle_mod.align_batch(batch.seqs_a, batch.offs_a, batch.seqs_b, batch.offs_b,
+                                  batch.subst, batch.alpha, batch.beta, batch.mode, nthreads)
+    bad = np.nonzero(got.astype(np.int64) != want)[0]
+    if len(bad):
+        p = int(bad[0])
+        raise AssertionError(f"{label}: {len(bad)} mismatches; first pair {p}: gpu {got[p]} oracle "
+                             f"{want[p]} (m={batch.lens_a[p]}, n={batch.lens_b[p]})")
+    return got
+
+
+def test_config0_all_pairs(gpu, oracle_mod):
+    _check(gpu, oracle_mod, synth.config0(), "c0")
+
+
+def test_config1_subset(gpu, oracle_mod):
+    _check(gpu, oracle_mod, synth.config1(n_pairs=8192), "c1[8192]")
+
+
+def test_config2_subset(gpu, oracle_mod):
+    _check(gpu, oracle_mod, synth.config2(n_pairs=300), "c2[300]")
+
+
+def test_config3_subset(gpu, oracle_mod):
+    b = synth.config3(n_pairs=400, n_long=2, long_len=3000)
+    _check(gpu, oracle_mod, b, "c3[400+2x3000]")
+
+
+def test_config4_subset(gpu, oracle_mod):
+    _check(gpu, oracle_mod, synth.config4(n_pairs=60), "c4[60]")
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_small_random_with_empty(gpu, oracle_mod, mode):
+    rng = np.random.default_rng(100 + mode)
+    sa, oa, sb, ob = synth.random_small(rng, 3000, 40)
+    b = synth.Batch("small", sa, oa, sb, ob, DNA, 5, 2, mode)
+    _check(gpu, oracle_mod, b, f"small mode {mode}")
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_stripe_and_tile_boundaries(gpu, oracle_mod, mode):
+    rng = np.random.default_rng(200 + mode)
+    pairs = []
+    for n in (1, 2, 15, 16, 17, 255, 256, 257, 511, 512, 513, 767, 769, 1000):
+        for m in (1, 2, 16, 17, 300):
+            a = rng.integers(0, 4, size=m).astype(np.uint8)
+            s = rng.integers(0, 4, size=n).astype(np.uint8)
+            if rng.random() < 0.5:   # related pair: B contains a mutated copy of A
+                k = min(m, n)
+                s[:k] = np.where(rng.random(k) < 0.1, rng.integers(0, 4, size=k), a[:k])
+            pairs.append((a, s))
+            pairs.append((s, a))
+    b = synth.from_pairs("bounds", pairs, DNA, 5, 2, mode)
+    _check(gpu, oracle_mod, b, f"boundaries mode {mode}")
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_asymmetric_sigma_and_gap_variants(gpu, oracle_mod, mode):
+    rng = np.random.default_rng(300 + mode)
+    sub = rng.integers(-6, 7, size=(5, 5)).astype(np.int8)
+    for alpha, beta in [(5, 2), (3, 3), (0, 0), (9, 1), (1, 0)]:
+        sa, oa, sb, ob = synth.random_small(rng, 400, 300, asz=5)
+        b = synth.Batch("asym", sa, oa, sb, ob, sub, alpha, beta, mode)
+        _check(gpu, oracle_mod, b, f"asym sigma a={alpha} b={beta} mode {mode}")
+
+
+def test_protein_alphabet_and_long_pairs(gpu, oracle_mod):
+    rng = np.random.default_rng(400)
+    sub = synth.protein_subst(rng)
+    pairs = []
+    for m, n in [(5000, 4000), (2500, 7000), (64, 9000), (9000, 40)]:
+        a = rng.integers(0, 20, size=m).astype(np.uint8)
+        s = rng.integers(0, 20, size=n).astype(np.uint8)
+        pairs.append((a, s))
+    a = rng.integers(0, 20, size=6000).astype(np.uint8)
+    pairs.append((a, a.copy()))               # identical: local score = sum of the diagonal
+    for mode in (0, 1, 2):
+        b = synth.from_pairs("protein long", pairs, sub, 11, 1, mode)
+        _check(gpu, oracle_mod, b, f"protein long mode {mode}")
+
+
+def test_error_codes(gpu):
+    import torch
+    from paper_2205_07610_amd.binding import AlignError
+    sa = torch.zeros(10, dtype=torch.uint8, device="cuda")
+    ok = torch.tensor([0, 5, 10], dtype=torch.int64, device="cuda")
+    bad = torch.tensor([0, 6, 5], dtype=torch.int64, device="cuda")
+    with pytest.raises(AlignError) as e:
+        gpu.align_batch(sa, bad, sa, ok, DNA, 5, 2, 0)
+    assert e.value.code == -2
+    sb = sa.clone()
+    sb[7] = 4                                 # code 4 with a 4-letter alphabet
+    with pytest.raises(AlignError) as e:
+        gpu.align_batch(sa, ok, sb, ok, DNA, 5, 2, 2)
+    assert e.value.code == -3
+    out = gpu.align_batch(sa, ok, sa, ok, DNA, 5, 2, 2)
+    assert out.cpu().tolist() == [10, 10]
+
+
+def test_deterministic(gpu):
+    b = synth.config1(n_pairs=4096, seed=77)
+    r1 = gpu.align(b)
+    r2 = gpu.align(b)
+    assert np.array_equal(r1, r2)
+
+
+def test_config1_full_size_sampled(gpu, oracle_mod):
+    """All 2^20 pairs in the benchmark's configuration; 3000 sampled pairs
+    are checked against the oracle, every score against its bounds."""
+    b = synth.config1()
+    _say(f"c1 full: {b.n_pairs} pairs")
+    got = gpu.align(b)
+    assert got.min() >= 0 and got.max() <= 2 * 150
+    rng = np.random.default_rng(5)
+    idx = np.sort(rng.choice(b.n_pairs, size=3000, replace=False))
+    sub = b.subset(idx)
+    want = oracle_mod.align_batch(sub.seqs_a, sub.offs_a, sub.seqs_b, sub.offs_b, sub.subst,
+                                  sub.alpha, sub.beta, sub.mode)
+    assert np.array_equal(got[idx].astype(np.int64), want)
