@@ -111,6 +111,16 @@ typedef struct {
     int64_t cells;      /* sum of m*n over the batch */
 } as_timing;
 
+/*
+ * Saturation threshold of the packed 16-bit local path: a pair whose 16-bit
+ * maximum reaches `limit` is treated as saturated and recomputed with 32-bit
+ * cells.  The default, 32767, is the int16 saturation value itself; a lower
+ * value only sends more pairs to the exact 32-bit re-run, which lets tests
+ * force that path from the host.  limit <= 0 restores the default.
+ * Returns the previous threshold.
+ */
+int as_set_i16_limit(int32_t limit);
+
 /* Enable (1) or disable (0) phase timing.  Returns the previous setting. */
 int as_enable_timing(int on);
 /* Copy the last call's phase times into *out (host).  AS_ERR_NULL if out is NULL. */

@@ -62,6 +62,8 @@ def lib() -> ctypes.CDLL:
     L.as_release_workspace.argtypes = []
     L.as_build_info.restype = ctypes.c_char_p
     L.as_build_info.argtypes = []
+    L.as_set_i16_limit.restype = ctypes.c_int
+    L.as_set_i16_limit.argtypes = [ctypes.c_int32]
     L.as_enable_timing.restype = ctypes.c_int
     L.as_enable_timing.argtypes = [ctypes.c_int]
     L.as_last_timing.restype = ctypes.c_int
@@ -131,6 +133,11 @@ def align_batch(seqs_a, offs_a, seqs_b, offs_b, subst, alpha: int, beta: int, mo
     del keep
     _check(rc)
     return scores_out
+
+
+def set_i16_limit(limit: int) -> int:
+    """Saturation threshold of the 16-bit local path (test hook; <= 0 resets)."""
+    return int(lib().as_set_i16_limit(int(limit)))
 
 
 def enable_timing(on: bool = True) -> bool:

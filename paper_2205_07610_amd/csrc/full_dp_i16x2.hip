@@ -1,0 +1,346 @@
+// Full Gotoh DP with packed 16-bit cells: two alignments per 16-lane group,
+// one in the low and one in the high half of every 32-bit register, so each
+// packed VALU instruction updates two DP cells (the paper's section 3.2
+// "two independent alignments in one register" idea, with exact int16
+// arithmetic instead of half floats).
+//
+// Mapping, frames and per-cell recurrences are those of the 32-bit kernel
+// (full_dp_i32.hip): lane t owns K adjacent columns, step `it` computes row
+// it + 1 - t, the rightmost H/F of lane t-1 arrives through DPP row_shr:1,
+// global and semi-global run in the shifted frame X + beta*(i+j) (no beta
+// anywhere in the cell update), local in the plain frame with E and F
+// clamped at 0.  Differences:
+//
+//  * Profile: the alphabet has at most 4 letters here, so each lane keeps,
+//    per owned column and per half, one 32-bit word whose byte c holds
+//    sigma(c, s_j) + bias.  One v_perm_b32 per cell pair selects the byte of
+//    the current row's residue for each half and zero-extends both into a
+//    packed pair -- no LDS traffic at all.  Row residues travel down the
+//    lanes as the v_perm selector itself.
+//  * Padding: every mode pads on the LEFT so that column n of both halves is
+//    the last register of lane 15.  Local/semi-global padding columns score
+//    0 (they reproduce the boundary column H = 0); global padding columns
+//    use the profile value alpha - beta, which keeps the shifted frame flat
+//    at its boundary value: in the shifted frame the global boundary
+//    H(i,0) = -alpha - beta(i-1) is the constant beta - alpha.
+//  * Rows past a half's own length use selector 0 (score -bias), which can
+//    only lower cells; local and semi-global maxima are unaffected, global
+//    results are snapshot at the half's last row.
+//  * Range: global and semi-global pairs are queued here only when an a
+//    priori bound keeps every shifted cell inside int16; local cells are
+//    bounded below by -alpha and are added with signed saturation, so a
+//    pair whose maximum reaches 32767 is re-queued for the 32-bit kernel.
+#include "internal.h"
+
+namespace asmi {
+namespace {
+
+constexpr int kK16 = 16;
+constexpr int kW16 = kGroup * kK16;
+constexpr short kNeg16 = -16384;
+
+typedef short s2 __attribute__((ext_vector_type(2)));
+typedef unsigned short u2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ int as_i(s2 v) { return __builtin_bit_cast(int, v); }
+__device__ __forceinline__ s2 as_s2(int v) { return __builtin_bit_cast(s2, v); }
+__device__ __forceinline__ s2 pk(int lo, int hi) {
+  s2 r;
+  r.x = (short)lo;
+  r.y = (short)hi;
+  return r;
+}
+__device__ __forceinline__ s2 vmax(s2 a, s2 b) { return __builtin_elementwise_max(a, b); }
+__device__ __forceinline__ s2 sat_sub_u(s2 a, s2 b) {
+  return __builtin_bit_cast(s2, __builtin_elementwise_sub_sat(__builtin_bit_cast(u2, a),
+                                                              __builtin_bit_cast(u2, b)));
+}
+__device__ __forceinline__ int dpp_shr1(int old, int src) {
+  return __builtin_amdgcn_update_dpp(old, src, 0x111, 0xF, 0xF, false);
+}
+__device__ __forceinline__ int dpp_shl1(int old, int src) {
+  return __builtin_amdgcn_update_dpp(old, src, 0x101, 0xF, 0xF, false);
+}
+__device__ __forceinline__ s2 group_max2(s2 v) {
+  v = vmax(v, as_s2(__shfl_xor(as_i(v), 8, 16)));
+  v = vmax(v, as_s2(__shfl_xor(as_i(v), 4, 16)));
+  v = vmax(v, as_s2(__shfl_xor(as_i(v), 2, 16)));
+  v = vmax(v, as_s2(__shfl_xor(as_i(v), 1, 16)));
+  return v;
+}
+__device__ __forceinline__ int wave_max_groups(int v) {
+  v = max(v, __shfl_xor(v, 16));
+  v = max(v, __shfl_xor(v, 32));
+  return v;
+}
+
+// v_perm selector for the row residues of both halves: byte 0 picks letter
+// c0 of the low half's word (source bytes 0..3), byte 2 letter c1 of the
+// high half's word (source bytes 4..7), bytes 1 and 3 are zero.  A residue
+// code of 12 ("no row") selects the constant 0 byte.
+__device__ __forceinline__ uint32_t make_sel(int c0, int c1) {
+  const uint32_t s0 = (c0 == 12) ? 0x0Cu : (uint32_t)c0;
+  const uint32_t s1 = (c1 == 12) ? 0x0Cu : (uint32_t)(4 + c1);
+  return s0 | 0x0C00u | (s1 << 16) | 0x0C000000u;
+}
+
+template <int MODE>
+__device__ __forceinline__ uint32_t profile_word(const FullDp16Args &a, const uint8_t *cols, int n,
+                                                 bool tr, int j, int bias, int pad_val, int &bad) {
+  if (j < 1 || j > n) return (uint32_t)(pad_val & 0xFF) * 0x01010101u;
+  int s = cols[j - 1];
+  if (s >= a.asz) { bad = 1; s = 0; }
+  uint32_t w = 0;
+  for (int c = 0; c < a.asz; ++c) {
+    const int sv = tr ? a.subst[s * a.asz + c] : a.subst[c * a.asz + s];
+    w |= (uint32_t)((sv + bias) & 0xFF) << (8 * c);
+  }
+  return w;
+}
+
+template <int MODE, int K>
+__global__ void __launch_bounds__(kWave) full_dp_i16_kernel(FullDp16Args a) {
+  constexpr int W = kGroup * K;
+  const int lane = threadIdx.x;
+  const int g = lane >> 4;
+  const int t = lane & 15;
+  const int n_list = a.ctr->n_full16;
+  const int alpha = a.alpha, beta = a.beta, amb = alpha - beta;
+  const int asz = a.asz;
+  const int bias = (MODE == kLocal) ? alpha : alpha + beta;
+  const int pad_val = (MODE == kLocal) ? alpha : (MODE == kGlobal ? alpha - beta : alpha + beta);
+  const s2 beta2 = pk(beta, beta);
+  const s2 alpha2 = pk(alpha, alpha);
+  const s2 amb2 = pk(amb, amb);
+
+  for (;;) {
+    int base = 0;
+    if (lane == 0) base = atomicAdd(&a.ctr->next_full16, 2 * kGroupsPerWave);
+    base = __shfl(base, 0);
+    if (base >= n_list) break;
+    const int i0 = base + 2 * g, i1 = i0 + 1;
+    const bool has0 = i0 < n_list, has1 = i1 < n_list;
+    PairDesc d0{0, 0, 0, 0, -1, 0}, d1{0, 0, 0, 0, -1, 0};
+    if (has0) d0 = a.items[i0];
+    if (has1) d1 = a.items[i1];
+    const int m0 = d0.m, m1 = d1.m, n0 = d0.n, n1 = d1.n;
+    const int P0 = W - n0, P1 = W - n1;     // left padding of each half
+    const bool tr0 = (d0.flags & kTransposed) != 0, tr1 = (d1.flags & kTransposed) != 0;
+    const uint8_t *rows0 = (tr0 ? a.seqs_b : a.seqs_a) + d0.row_off;
+    const uint8_t *cols0 = (tr0 ? a.seqs_a : a.seqs_b) + d0.col_off;
+    const uint8_t *rows1 = (tr1 ? a.seqs_b : a.seqs_a) + d1.row_off;
+    const uint8_t *cols1 = (tr1 ? a.seqs_a : a.seqs_b) + d1.col_off;
+    const int mmax = max(m0, m1);
+    const int msmall = min(m0, m1);
+    const bool unequal = m0 != m1;
+    const int its = mmax > 0 ? mmax + kGroup - 1 : 0;
+    const int its_max = wave_max_groups(its);
+    int bad = 0;
+
+    // ---- register profile (paper: init_profile), both halves ----
+    uint32_t Plo[K], Phi[K];
+#pragma unroll
+    for (int x = 0; x < K; ++x) {
+      const int jp = t * K + x + 1;
+      Plo[x] = profile_word<MODE>(a, cols0, n0, tr0, jp - P0, bias, pad_val, bad);
+      Phi[x] = profile_word<MODE>(a, cols1, n1, tr1, jp - P1, bias, pad_val, bad);
+    }
+
+    // ---- row-0 state ----
+    s2 Ha[K], Ee[K];
+#pragma unroll
+    for (int x = 0; x < K; ++x) {
+      const int j0 = t * K + x + 1 - P0, j1 = t * K + x + 1 - P1;
+      if (MODE == kGlobal) {
+        Ha[x] = pk(j0 == 0 ? beta - alpha : 2 * beta - 2 * alpha,
+                   j1 == 0 ? beta - alpha : 2 * beta - 2 * alpha);
+        Ee[x] = pk(kNeg16, kNeg16);
+      } else if (MODE == kSemiGlobal) {
+        Ha[x] = pk(beta * j0 + beta - alpha, beta * j1 + beta - alpha);
+        Ee[x] = pk(kNeg16, kNeg16);
+      } else {
+        Ha[x] = pk(-alpha, -alpha);
+        Ee[x] = pk(0, 0);   // E'(1, j) = max(E(1,j), 0) = 0
+      }
+    }
+    s2 hl_prev;
+    {
+      const int j0 = t * K - P0, j1 = t * K - P1;
+      if (MODE == kGlobal)
+        hl_prev = pk(j0 == 0 ? beta - alpha : 2 * beta - 2 * alpha,
+                     j1 == 0 ? beta - alpha : 2 * beta - 2 * alpha);
+      else if (MODE == kSemiGlobal)
+        hl_prev = pk(beta * j0 + beta - alpha, beta * j1 + beta - alpha);
+      else
+        hl_prev = pk(-alpha, -alpha);
+    }
+    int fout = (MODE == kLocal) ? 0 : as_i(pk(kNeg16, kNeg16));
+    // left feed for lane 0 (row 1 first)
+    s2 hb, fb;
+    if (MODE == kGlobal) { hb = pk(2 * beta - 2 * alpha, 2 * beta - 2 * alpha); fb = hb; }
+    else if (MODE == kSemiGlobal) {
+      hb = pk(beta * (1 - P0) + beta - alpha, beta * (1 - P1) + beta - alpha);
+      fb = hb;
+    } else { hb = pk(-alpha, -alpha); fb = pk(0, 0); }
+    s2 rowoff = pk(beta * (1 - t), beta * (1 - t));
+    s2 rm = pk(0, 0);                       // local: running max of H
+    s2 cm = pk(kNeg16, kNeg16);             // semi-global: max of H'(i,n) - beta*i
+    s2 snap = pk(kNeg16, kNeg16);           // value of the shorter half at its last row
+
+    auto load_sel = [&](int idx) -> int {
+      int c0 = 12, c1 = 12;
+      if (idx < m0) { c0 = rows0[idx]; if (c0 >= asz) { bad = 1; c0 = 0; } }
+      if (idx < m1) { c1 = rows1[idx]; if (c1 >= asz) { bad = 1; c1 = 0; } }
+      return (int)make_sel(c0, c1);
+    };
+    int selfeed = load_sel(t);
+    int sel = (int)make_sel(12, 12);
+
+    for (int it0 = 0; it0 < its_max; it0 += kGroup) {
+      const int selnext = load_sel(it0 + kGroup + t);
+#pragma unroll
+      for (int u = 0; u < kGroup; ++u) {
+        const int row = it0 + u + 1 - t;
+        sel = dpp_shr1(selfeed, sel);
+        const s2 hl = as_s2(dpp_shr1(as_i(hb), as_i(Ha[K - 1])));
+        const s2 fl = as_s2(dpp_shr1(as_i(fb), fout));
+        if ((unsigned)(row - 1) < (unsigned)mmax) {
+          // Phase A, independent per column: diagonal sums from the previous
+          // row's values (and, shifted frame, E), so that phase B can overwrite
+          // every state register in place.
+          s2 tt[K];
+#pragma unroll
+          for (int x = 0; x < K; ++x) {
+            const s2 p = as_s2((int)__builtin_amdgcn_perm(Phi[x], Plo[x], (uint32_t)sel));
+            const s2 dg = (x == 0) ? hl_prev : Ha[x - 1];
+            if (MODE == kLocal) {
+              tt[x] = __builtin_elementwise_add_sat(dg, p);
+            } else {
+              tt[x] = dg + p;
+              Ee[x] = vmax(Ee[x], Ha[x]);
+            }
+          }
+          // Phase B, the F chain along the row.
+          s2 f = fl;
+#pragma unroll
+          for (int x = 0; x < K; ++x) {
+            if (MODE == kLocal) {
+              const s2 h = vmax(vmax(tt[x], Ee[x]), f);
+              rm = vmax(rm, h);
+              Ha[x] = h - alpha2;
+              Ee[x] = vmax(sat_sub_u(Ee[x], beta2), Ha[x]);
+              f = vmax(sat_sub_u(f, beta2), Ha[x]);
+            } else {
+              const s2 h = vmax(vmax(tt[x], Ee[x]), f);
+              Ha[x] = h - amb2;
+              f = vmax(f, Ha[x]);
+            }
+          }
+          fout = as_i(f);
+          if (MODE == kSemiGlobal) cm = vmax(cm, Ha[K - 1] - rowoff);
+          if (MODE != kLocal && unequal && row == msmall) {
+            if (MODE == kGlobal) {
+              if (t == kGroup - 1) snap = Ha[K - 1];
+            } else {
+              s2 lr = pk(kNeg16, kNeg16);
+#pragma unroll
+              for (int x = 0; x < K; ++x) {
+                const int jp = t * K + x + 1;
+                lr = vmax(lr, Ha[x] - pk(beta * (jp - P0), beta * (jp - P1)));
+              }
+              snap = lr;
+            }
+          }
+        }
+        hl_prev = hl;
+        if (MODE == kSemiGlobal) {
+          hb = hb + beta2;
+          fb = hb;
+        }
+        rowoff = rowoff + beta2;
+        selfeed = dpp_shl1(selfeed, selfeed);
+      }
+      selfeed = selnext;
+    }
+
+    // ---- results of both halves ----
+    int r0 = 0, r1 = 0;
+    bool over0 = false, over1 = false;
+    if (MODE == kLocal) {
+      const s2 gm = group_max2(rm);
+      r0 = gm.x;
+      r1 = gm.y;
+      over0 = r0 >= a.sat_limit;
+      over1 = r1 >= a.sat_limit;
+    } else if (MODE == kGlobal) {
+      // lane 15, register K-1 holds column n of both halves
+      const int src = (lane & ~(kGroup - 1)) + kGroup - 1;
+      const s2 fin = as_s2(__shfl(as_i(Ha[K - 1]), src));
+      const s2 sn = as_s2(__shfl(as_i(snap), src));
+      const int v0 = (unequal && m0 < m1) ? sn.x : fin.x;
+      const int v1 = (unequal && m1 < m0) ? sn.y : fin.y;
+      r0 = v0 + amb - beta * (m0 + n0);
+      r1 = v1 + amb - beta * (m1 + n1);
+    } else {
+      s2 lr = pk(kNeg16, kNeg16);
+#pragma unroll
+      for (int x = 0; x < K; ++x) {
+        const int jp = t * K + x + 1;
+        lr = vmax(lr, Ha[x] - pk(beta * (jp - P0), beta * (jp - P1)));
+      }
+      if (unequal) {
+        if (m0 < m1) lr.x = snap.x;
+        else lr.y = snap.y;
+      }
+      const s2 gl = group_max2(lr);
+      const int src = (lane & ~(kGroup - 1)) + kGroup - 1;
+      const s2 gc = as_s2(__shfl(as_i(cm), src));
+      r0 = max(0, max(gl.x + amb - beta * m0, gc.x + amb - beta * n0));
+      r1 = max(0, max(gl.y + amb - beta * m1, gc.y + amb - beta * n1));
+    }
+    if (bad) atomicOr(&a.ctr->status, kStatusBadResidue);
+    if (t == 0) {
+      if (has0) {
+        if (over0) a.rerun[atomicAdd(&a.ctr->n_rerun32, 1)] = d0;
+        else a.scores[d0.pair] = r0;
+      }
+      if (has1) {
+        if (over1) a.rerun[atomicAdd(&a.ctr->n_rerun32, 1)] = d1;
+        else a.scores[d1.pair] = r1;
+      }
+    }
+  }
+}
+
+template <int MODE>
+hipError_t launch_mode(const FullDp16Args &args, int grid, hipStream_t stream) {
+  hipLaunchKernelGGL((full_dp_i16_kernel<MODE, kK16>), dim3(grid), dim3(kWave), 0, stream, args);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int full_dp_i16_stripe_width() { return kW16; }
+
+int full_dp_i16_blocks_per_cu(int mode) {
+  int nb = 0;
+  hipError_t e;
+  if (mode == kGlobal)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, full_dp_i16_kernel<kGlobal, kK16>, kWave, 0);
+  else if (mode == kSemiGlobal)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, full_dp_i16_kernel<kSemiGlobal, kK16>, kWave, 0);
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, full_dp_i16_kernel<kLocal, kK16>, kWave, 0);
+  if (e != hipSuccess || nb < 1) nb = 1;
+  return nb;
+}
+
+hipError_t launch_full_dp_i16(int mode, const FullDp16Args &args, int grid, hipStream_t stream) {
+  switch (mode) {
+    case kGlobal: return launch_mode<kGlobal>(args, grid, stream);
+    case kSemiGlobal: return launch_mode<kSemiGlobal>(args, grid, stream);
+    default: return launch_mode<kLocal>(args, grid, stream);
+  }
+}
+
+}  // namespace asmi

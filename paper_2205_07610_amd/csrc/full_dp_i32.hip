@@ -75,7 +75,7 @@ __global__ void __launch_bounds__(kWave) full_dp_i32_kernel(FullDpArgs a) {
   const int asz = a.asz;
   int8_t *prof = lds + g * asz * W;
   const int alpha = a.alpha, beta = a.beta;
-  const int n_items = a.ctr->n_full32;
+  const int n_items = *a.n_items;
   int2 *slot = a.bnd + ((int64_t)blockIdx.x * kGroupsPerWave + g) * 2 * a.bnd_rows;
 
   // Profile bias: the value added to the stored diagonal (see header).
@@ -84,7 +84,7 @@ __global__ void __launch_bounds__(kWave) full_dp_i32_kernel(FullDpArgs a) {
 
   for (;;) {
     int base = 0;
-    if (lane == 0) base = atomicAdd(&a.ctr->next_full32, kGroupsPerWave);
+    if (lane == 0) base = atomicAdd(a.next, kGroupsPerWave);
     base = __shfl(base, 0);
     if (base >= n_items) break;
     const int item = base + g;

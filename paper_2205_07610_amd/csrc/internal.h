@@ -45,12 +45,18 @@ struct Counters {
   int32_t max_rows_multi;// largest m among multi-stripe items
   int32_t status;        // OR of kStatus* bits
   unsigned long long cells;  // sum of m*n over the batch
+  int32_t n_full16;      // pairs queued for the packed 16-bit full DP
+  int32_t next_full16;   // work pointer of the 16-bit kernel (in pairs)
+  int32_t n_rerun32;     // 16-bit pairs that saturated, queued for 32 bits
+  int32_t next_rerun32;  // work pointer of the re-run
 };
 
 struct FullDpArgs {
   const uint8_t *seqs_a;
   const uint8_t *seqs_b;
   const PairDesc *items;
+  const int32_t *n_items;  // device: number of items in the list
+  int32_t *next;           // device: work pointer (starts at 0)
   Counters *ctr;
   const int8_t *subst;  // device copy, sigma(a, b) = subst[a * asz + b]
   int32_t asz;
@@ -60,6 +66,26 @@ struct FullDpArgs {
   int2 *bnd;            // boundary columns, one slot per group: 2 * bnd_rows int2
   int64_t bnd_rows;     // rows per boundary buffer (>= max_rows_multi + 1)
 };
+
+// Arguments of the packed 16-bit kernel: two pairs per 16-lane group, one in
+// each half of every 32-bit register.
+struct FullDp16Args {
+  const uint8_t *seqs_a;
+  const uint8_t *seqs_b;
+  const PairDesc *items;   // 16-bit work list (pairs; consecutive pairs share a group)
+  Counters *ctr;
+  PairDesc *rerun;         // saturated pairs are appended here for the 32-bit kernel
+  const int8_t *subst;
+  int32_t asz;             // <= 4 (profile held in registers, one byte per residue)
+  int32_t alpha;
+  int32_t beta;
+  int32_t sat_limit;       // local: a 16-bit maximum >= this is re-run with 32 bits
+  int32_t *scores;
+};
+
+hipError_t launch_full_dp_i16(int mode, const FullDp16Args &args, int grid, hipStream_t stream);
+int full_dp_i16_blocks_per_cu(int mode);
+int full_dp_i16_stripe_width();
 
 // Launch the persistent 32-bit full-DP kernel for `mode` on `grid` blocks
 // of one wave each.  Returns hipSuccess or the launch error.

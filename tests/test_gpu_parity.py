@@ -150,3 +150,35 @@ def test_config1_full_size_sampled(gpu, oracle_mod):
     want = oracle_mod.align_batch(sub.seqs_a, sub.offs_a, sub.seqs_b, sub.offs_b, sub.subst,
                                   sub.alpha, sub.beta, sub.mode)
     assert np.array_equal(got[idx].astype(np.int64), want)
+
+
+def test_packed16_rerun_forced(gpu, oracle_mod):
+    """Lowering the 16-bit saturation threshold from the host sends pairs
+    through the 32-bit re-run; scores stay exact and the re-run is used."""
+    b = synth.config1(n_pairs=5000, seed=91)
+    prev = gpu.set_i16_limit(200)
+    try:
+        gpu.enable_timing(True)
+        got = _check(gpu, oracle_mod, b, "c1 rerun forced")
+        tm = gpu.last_timing()
+    finally:
+        gpu.set_i16_limit(prev)
+        gpu.enable_timing(False)
+    assert tm["pairs_full16"] == b.n_pairs
+    assert tm["pairs_rerun32"] == int(np.count_nonzero(got >= 200)) > 0
+
+
+def test_packed16_routing(gpu, oracle_mod):
+    """Short DNA pairs take the packed path in every mode; unequal row counts
+    inside one packed group are handled."""
+    rng = np.random.default_rng(92)
+    for mode in (0, 1, 2):
+        sa, oa, sb, ob = synth.random_small(rng, 4000, 250)
+        b = synth.Batch("pk", sa, oa, sb, ob, DNA, 5, 2, mode)
+        gpu.enable_timing(True)
+        try:
+            _check(gpu, oracle_mod, b, f"packed routing mode {mode}")
+            tm = gpu.last_timing()
+        finally:
+            gpu.enable_timing(False)
+        assert tm["pairs_full16"] > 0.9 * b.n_pairs
