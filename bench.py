@@ -33,7 +33,38 @@ PEAK_I32_TOPS = 256 * 64 * 2.4e9 / 1e12
 PEAK_I16X2_TOPS = 2 * PEAK_I32_TOPS
 KERNEL_SOURCES = {
     "full32": "paper_2205_07610_amd/csrc/full_dp_i32.hip",
+    "full16": "paper_2205_07610_amd/csrc/full_dp_i16x2.hip",
+    "rerun32": "paper_2205_07610_amd/csrc/full_dp_i32.hip",
+    "long": "paper_2205_07610_amd/csrc/long_dp_i32.hip",
 }
+MODE_NAMES = {0: "global", 1: "semi-global", 2: "local"}
+
+
+def workload(name: str, pairs: int | None):
+    """Seeded batch and its description for a named workload."""
+    from paper_2205_07610_amd import synth
+    if name == "c1":
+        b = synth.config1(n_pairs=pairs or (1 << 20))
+        desc = (f"{b.n_pairs} pairs, 150 bp reads vs 250 bp windows, local affine DNA "
+                "(+2/-3, alpha 5, beta 2)")
+    elif name == "c0":
+        b = synth.config0(n_pairs=pairs or 1000)
+        desc = f"{b.n_pairs} pairs, 150 bp, global affine DNA (+2/-3, alpha 5, beta 2)"
+    elif name == "c2":
+        b = synth.config2(n_pairs=pairs or 100_000)
+        desc = f"{b.n_pairs} pairs, log-normal lengths (median 1 kb), semi-global affine DNA"
+    elif name == "c3":
+        b = synth.config3(n_pairs=pairs or (1 << 16), n_long=0)
+        desc = f"{b.n_pairs} protein pairs, 50-1000 vs 50-2000 residues, local affine (alpha 11, beta 1)"
+    elif name == "c3long":
+        b = synth.config3(n_pairs=0, n_long=pairs or 64, long_len=65536)
+        desc = f"{b.n_pairs} protein pairs of 65,536 residues, local affine (alpha 11, beta 1)"
+    elif name == "c4":
+        b = synth.config4(n_pairs=pairs or 1_000_000)
+        desc = f"{b.n_pairs} pairs, 1-5 kb, global affine DNA (+2/-3, alpha 5, beta 2)"
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return b, desc
 
 
 def log(msg):
@@ -98,7 +129,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--pairs", type=int, default=1 << 20)
+    ap.add_argument("--pairs", type=int, default=None)
+    ap.add_argument("--workload", default="c1", help="c1 (default), c0, c2, c3, c3long, c4")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -108,16 +140,15 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
-    from paper_2205_07610_amd import binding, synth
+    from paper_2205_07610_amd import binding
 
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     binding.lib()
-    log(f"generating workload: {args.pairs} pairs")
-    batch = synth.config1(n_pairs=args.pairs)
+    log(f"generating workload {args.workload}")
+    batch, desc = workload(args.workload, args.pairs)
     cells = batch.cells()
     sa, oa, sb, ob = binding.to_device(batch)
     out = torch.empty(batch.n_pairs, dtype=torch.int32, device="cuda")
@@ -130,7 +161,6 @@ def main():
     for _ in range(args.warmup):
         step()
     binding.enable_timing(True)
-    kernel_ms = []
     phases = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -145,12 +175,11 @@ def main():
     log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step")
 
     # dominant kernel: the phase with the largest time
-    ph_names = ["full32_ms", "full16_ms", "rerun32_ms", "classify_ms"]
+    ph_names = ["full32_ms", "full16_ms", "rerun32_ms", "long_ms", "classify_ms"]
     avg = {k: sum(p[k] for p in phases) / len(phases) for k in ph_names}
     dom = max(ph_names, key=lambda k: avg[k])
     kernel_ms = avg[dom]
     kernel_name = dom.replace("_ms", "")
-    pairs_dom = phases[-1].get(f"pairs_{kernel_name}", batch.n_pairs)
     packed = kernel_name == "full16"
     ops = cells * OPS_PER_CELL[batch.mode]
     achieved = ops / (kernel_ms * 1e-3) / 1e12
@@ -171,9 +200,8 @@ def main():
         "vs_baseline": None,
         "dtype": "i16x2" if packed else "i32",
         "data": "synthetic",
-        "config": {"workload": "2^20 pairs, 150 bp reads vs 250 bp windows, local affine DNA "
-                               "(+2/-3, alpha 5, beta 2)",
-                   "n_pairs": batch.n_pairs, "cells": cells, "mode": "local"},
+        "config": {"workload": desc, "name": args.workload,
+                   "n_pairs": batch.n_pairs, "cells": cells, "mode": MODE_NAMES[batch.mode]},
         "phases_ms": {k: round(v, 4) for k, v in avg.items()},
         "roofline": {
             "bound": "alu",

@@ -62,7 +62,7 @@ typedef struct {
 #define AS_ERR_RESIDUE (-3)   /* a residue code >= alphabet_size */
 #define AS_ERR_SCORING (-4)   /* alphabet size, alpha, beta or mode invalid */
 #define AS_ERR_RANGE (-5)     /* a score could leave the int32 range */
-#define AS_ERR_HIP (-6)       /* a HIP runtime call failed */
+#define AS_ERR_HIP (-6)       /* a HIP runtime call failed, or a device-side wait stalled */
 #define AS_ERR_ARG (-7)       /* another argument is out of range */
 
 /*
@@ -105,9 +105,12 @@ typedef struct {
     float full32_ms;    /* full DP, 32-bit cells */
     float full16_ms;    /* full DP, packed 16-bit cells */
     float rerun32_ms;   /* 32-bit re-run of saturated 16-bit pairs */
+    float long_ms;      /* multi-wave wavefront for long pairs, 32-bit cells */
+    float reserved_ms[3];
     int64_t pairs_full32;
     int64_t pairs_full16;
     int64_t pairs_rerun32;
+    int64_t pairs_long;
     int64_t cells;      /* sum of m*n over the batch */
 } as_timing;
 

@@ -32,11 +32,13 @@ class Scoring(ctypes.Structure):
 class Timing(ctypes.Structure):
     _fields_ = [("classify_ms", ctypes.c_float), ("full32_ms", ctypes.c_float),
                 ("full16_ms", ctypes.c_float), ("rerun32_ms", ctypes.c_float),
+                ("long_ms", ctypes.c_float), ("reserved_ms", ctypes.c_float * 3),
                 ("pairs_full32", ctypes.c_int64), ("pairs_full16", ctypes.c_int64),
-                ("pairs_rerun32", ctypes.c_int64), ("cells", ctypes.c_int64)]
+                ("pairs_rerun32", ctypes.c_int64), ("pairs_long", ctypes.c_int64),
+                ("cells", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
-        return {name: getattr(self, name) for name, _ in self._fields_}
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved_ms"}
 
 
 class AlignError(RuntimeError):

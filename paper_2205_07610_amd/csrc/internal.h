@@ -37,6 +37,7 @@ constexpr int32_t kTransposed = 1;
 constexpr int32_t kStatusBadOffsets = 1;
 constexpr int32_t kStatusBadResidue = 2;
 constexpr int32_t kStatusRange = 4;
+constexpr int32_t kStatusStall = 8;   // a wavefront wait exceeded its spin limit
 
 // Work-list counters written by the classify kernel.
 struct Counters {
@@ -49,7 +50,39 @@ struct Counters {
   int32_t next_full16;   // work pointer of the 16-bit kernel (in pairs)
   int32_t n_rerun32;     // 16-bit pairs that saturated, queued for 32 bits
   int32_t next_rerun32;  // work pointer of the re-run
+  int32_t n_long;        // pairs queued for the multi-wave wavefront
+  int32_t n_long_tasks;  // their stripes (one task per stripe)
+  int32_t next_long;     // ticket counter of the wavefront kernel
+  int32_t pad_;
+  long long long_bnd_total;  // int2 entries of all wavefront boundary columns
 };
+
+// A long pair and where its stripes and boundary columns live.
+struct LongItem {
+  PairDesc d;
+  int32_t task0;     // ticket of its first stripe
+  int32_t stripes;   // number of stripes (tasks)
+  int64_t bnd_off;   // first boundary entry (int2) of its (stripes-1) columns
+};
+
+struct LongDpArgs {
+  const uint8_t *seqs_a;
+  const uint8_t *seqs_b;
+  const LongItem *items;
+  Counters *ctr;
+  const int8_t *subst;
+  int32_t asz;
+  int32_t alpha;
+  int32_t beta;
+  int32_t *scores;
+  int2 *bnd;       // boundary columns, (m+1) rows per stripe edge
+  int32_t *flags;  // rows published per stripe, zeroed before launch
+};
+
+hipError_t launch_long_dp_i32(int mode, const LongDpArgs &args, int grid, hipStream_t stream);
+int long_dp_i32_blocks_per_cu(int mode, int asz);
+int long_dp_i32_stripe_width();
+size_t long_dp_i32_lds_bytes(int asz);
 
 struct FullDpArgs {
   const uint8_t *seqs_a;

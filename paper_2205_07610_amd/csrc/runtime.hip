@@ -28,6 +28,9 @@ struct ClassifyParams {
   int64_t n_pairs;
   int32_t mode, alpha, beta, smax_abs, smax_pos;
   int32_t stripe_w, allow16, stripe_w16;
+  int32_t long_w;         // stripe width of the wavefront kernel
+  int32_t long_min_rows;  // pairs with at least this many rows and more than
+                          // one wavefront stripe of columns go to the wavefront
 };
 
 // Route of one pair: 0 none (error or empty pair, scored here), 1 the 32-bit
@@ -76,6 +79,7 @@ __device__ int route_pair(const ClassifyParams &c, int64_t p, Counters *ctr,
                        (int64_t)c.beta * c.stripe_w16 + c.alpha + 2 * c.beta + 256;
     if (ub < 32000) return 2;
   }
+  if (d.n > c.long_w && d.m >= c.long_min_rows) return 3;
   if (first_pass && d.n > c.stripe_w) atomicMax(&ctr->max_rows_multi, d.m);
   return 1;
 }
@@ -103,14 +107,15 @@ __device__ int block_prefix(bool flag, int *lds4, int *total) {
 // its slice of each work list with one atomic per list, then scatters.  Items
 // of a block stay in pair order inside the lists.
 __global__ void __launch_bounds__(256) classify_kernel(ClassifyParams c, PairDesc *__restrict__ items32,
-                                                       PairDesc *__restrict__ items16, Counters *ctr,
-                                                       int32_t *__restrict__ scores) {
+                                                       PairDesc *__restrict__ items16,
+                                                       LongItem *__restrict__ items_long,
+                                                       Counters *ctr, int32_t *__restrict__ scores) {
   __shared__ int lds4[4];
-  __shared__ int base_sh[2];
+  __shared__ int base_sh[3];
   const int64_t chunk = (c.n_pairs + gridDim.x - 1) / gridDim.x;
   const int64_t lo = (int64_t)blockIdx.x * chunk;
   const int64_t hi = lo + chunk < c.n_pairs ? lo + chunk : c.n_pairs;
-  int cnt32 = 0, cnt16 = 0;
+  int cnt32 = 0, cnt16 = 0, cntl = 0;
   unsigned long long cells = 0;
   for (int64_t t0 = lo; t0 < hi; t0 += 256) {
     const int64_t p = t0 + threadIdx.x;
@@ -123,17 +128,19 @@ __global__ void __launch_bounds__(256) classify_kernel(ClassifyParams c, PairDes
     }
     cnt32 += (r == 1);
     cnt16 += (r == 2);
+    cntl += (r == 3);
   }
   // block totals: one atomic per list and one for the cell count
   for (int off = 32; off > 0; off >>= 1) {
     cnt32 += __shfl_xor(cnt32, off);
     cnt16 += __shfl_xor(cnt16, off);
+    cntl += __shfl_xor(cntl, off);
     cells += __shfl_xor(cells, off);
   }
-  __shared__ int s32[4], s16[4];
+  __shared__ int s32[4], s16[4], sl[4];
   __shared__ unsigned long long sc[4];
   const int wave = threadIdx.x >> 6;
-  if (__lane_id() == 0) { s32[wave] = cnt32; s16[wave] = cnt16; sc[wave] = cells; }
+  if (__lane_id() == 0) { s32[wave] = cnt32; s16[wave] = cnt16; sl[wave] = cntl; sc[wave] = cells; }
   __syncthreads();
   if (threadIdx.x == 0) {
     const int t32 = s32[0] + s32[1] + s32[2] + s32[3];
@@ -141,10 +148,12 @@ __global__ void __launch_bounds__(256) classify_kernel(ClassifyParams c, PairDes
     const unsigned long long tc = sc[0] + sc[1] + sc[2] + sc[3];
     base_sh[0] = t32 ? atomicAdd(&ctr->n_full32, t32) : 0;
     base_sh[1] = t16 ? atomicAdd(&ctr->n_full16, t16) : 0;
+    const int tl = sl[0] + sl[1] + sl[2] + sl[3];
+    base_sh[2] = tl ? atomicAdd(&ctr->n_long, tl) : 0;
     if (tc) atomicAdd(&ctr->cells, tc);
   }
   __syncthreads();
-  int cur32 = base_sh[0], cur16 = base_sh[1];
+  int cur32 = base_sh[0], cur16 = base_sh[1], curl = base_sh[2];
   for (int64_t t0 = lo; t0 < hi; t0 += 256) {
     const int64_t p = t0 + threadIdx.x;
     int r = 0;
@@ -153,13 +162,65 @@ __global__ void __launch_bounds__(256) classify_kernel(ClassifyParams c, PairDes
       unsigned long long cl = 0;
       r = route_pair(c, p, ctr, scores, false, d, cl);
     }
-    int n32, n16;
+    int n32, n16, nl;
     const int i32 = block_prefix(r == 1, lds4, &n32);
     const int i16 = block_prefix(r == 2, lds4, &n16);
+    const int il = block_prefix(r == 3, lds4, &nl);
     if (r == 1) items32[cur32 + i32] = d;
     if (r == 2) items16[cur16 + i16] = d;
+    if (r == 3) items_long[curl + il].d = d;
     cur32 += n32;
     cur16 += n16;
+    curl += nl;
+  }
+}
+
+// One block: prefix sums over the wavefront list (first ticket and boundary
+// offset of every long pair), and the score seed that the stripes' atomic
+// maxima start from (0 = the empty alignment / boundary cells).
+__global__ void __launch_bounds__(256) long_prep_kernel(LongItem *items, Counters *ctr, int32_t long_w,
+                                                        int32_t mode, int32_t *scores) {
+  __shared__ int lds4[4];
+  const int n = ctr->n_long;
+  int task = 0;
+  long long bnd = 0;
+  for (int b = 0; b < n; b += 256) {
+    const int i = b + threadIdx.x;
+    int st = 0;
+    long long be = 0;
+    if (i < n) {
+      const PairDesc d = items[i].d;
+      st = (d.n + long_w - 1) / long_w;
+      be = (long long)(st - 1) * (d.m + 1);
+      if (mode != kGlobal) scores[d.pair] = 0;
+    }
+    // block-wide inclusive scans of st and be (256 threads, simple two-level)
+    __shared__ int sst[256];
+    __shared__ long long sbe[256];
+    sst[threadIdx.x] = st;
+    sbe[threadIdx.x] = be;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+      const int vs = threadIdx.x >= off ? sst[threadIdx.x - off] : 0;
+      const long long vb = threadIdx.x >= off ? sbe[threadIdx.x - off] : 0;
+      __syncthreads();
+      sst[threadIdx.x] += vs;
+      sbe[threadIdx.x] += vb;
+      __syncthreads();
+    }
+    if (i < n) {
+      items[i].task0 = task + sst[threadIdx.x] - st;
+      items[i].stripes = st;
+      items[i].bnd_off = bnd + sbe[threadIdx.x] - be;
+    }
+    task += sst[255];
+    bnd += sbe[255];
+    __syncthreads();
+  }
+  (void)lds4;
+  if (threadIdx.x == 0) {
+    ctr->n_long_tasks = task;
+    ctr->long_bnd_total = bnd;
   }
 }
 
@@ -172,12 +233,18 @@ struct Workspace {
   int64_t items16_cap = 0;
   PairDesc *rerun = nullptr;    // saturated 16-bit pairs
   int64_t rerun_cap = 0;
+  LongItem *items_long = nullptr;  // wavefront list
+  int64_t items_long_cap = 0;
+  int2 *bnd_long = nullptr;        // wavefront boundary columns
+  int64_t bnd_long_cap = 0;
+  int32_t *flags = nullptr;        // wavefront progress counters
+  int64_t flags_cap = 0;
   Counters *ctr = nullptr;
   Counters *host_ctr = nullptr;  // pinned
   int8_t *subst = nullptr;       // 32*32 bytes
   int2 *bnd = nullptr;
   int64_t bnd_cap = 0;           // int2 elements
-  hipEvent_t ev[8] = {};
+  hipEvent_t ev[10] = {};
 };
 
 bool g_timing = false;
@@ -223,6 +290,7 @@ int grow(void **ptr, int64_t *cap, int64_t need, size_t elem) {
 }
 
 int status_to_code(int32_t st) {
+  if (st & kStatusStall) return AS_ERR_HIP;
   if (st & kStatusBadOffsets) return AS_ERR_OFFSETS;
   if (st & kStatusBadResidue) return AS_ERR_RESIDUE;
   if (st & kStatusRange) return AS_ERR_RANGE;
@@ -267,6 +335,7 @@ extern "C" int as_align_batch(const uint8_t *seqs_a, const int64_t *offs_a, cons
   if ((rc = grow((void **)&w->items, &w->items_cap, n_pairs, sizeof(PairDesc)))) return rc;
   if ((rc = grow((void **)&w->items16, &w->items16_cap, n_pairs, sizeof(PairDesc)))) return rc;
   if ((rc = grow((void **)&w->rerun, &w->rerun_cap, n_pairs, sizeof(PairDesc)))) return rc;
+  if ((rc = grow((void **)&w->items_long, &w->items_long_cap, n_pairs, sizeof(LongItem)))) return rc;
 
   AS_HIP(hipMemcpyAsync(w->subst, scoring->subst, (size_t)asz * asz, hipMemcpyHostToDevice, stream));
   AS_HIP(hipMemsetAsync(w->ctr, 0, sizeof(Counters), stream));
@@ -288,10 +357,15 @@ extern "C" int as_align_batch(const uint8_t *seqs_a, const int64_t *offs_a, cons
     cp.stripe_w = stripe_w;
     cp.allow16 = allow16;
     cp.stripe_w16 = stripe_w16;
+    cp.long_w = long_dp_i32_stripe_width();
+    cp.long_min_rows = 2048;
     int64_t blocks = (n_pairs + 1023) / 1024;
     if (blocks > 1024) blocks = 1024;
     hipLaunchKernelGGL(classify_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, cp, w->items,
-                       w->items16, w->ctr, scores_out);
+                       w->items16, w->items_long, w->ctr, scores_out);
+    AS_HIP(hipGetLastError());
+    hipLaunchKernelGGL(long_prep_kernel, dim3(1), dim3(256), 0, stream, w->items_long, w->ctr,
+                       cp.long_w, mode, scores_out);
     AS_HIP(hipGetLastError());
   }
   if (timing) AS_HIP(hipEventRecord(w->ev[1], stream));
@@ -353,9 +427,37 @@ extern "C" int as_align_batch(const uint8_t *seqs_a, const int64_t *offs_a, cons
     AS_HIP(launch_full_dp_i32(mode, args, (int)grid, stream));
     if (timing) AS_HIP(hipEventRecord(w->ev[5], stream));
   }
+  if (c.n_long > 0) {
+    if ((rc = grow((void **)&w->bnd_long, &w->bnd_long_cap, c.long_bnd_total > 0 ? c.long_bnd_total : 1,
+                   sizeof(int2))))
+      return rc;
+    if ((rc = grow((void **)&w->flags, &w->flags_cap, c.n_long_tasks, sizeof(int32_t)))) return rc;
+    AS_HIP(hipMemsetAsync(w->flags, 0, sizeof(int32_t) * (size_t)c.n_long_tasks, stream));
+    const int bpc = long_dp_i32_blocks_per_cu(mode, asz);
+    int64_t grid = (int64_t)bpc * w->num_cu;
+    if (grid > c.n_long_tasks) grid = c.n_long_tasks;
+    LongDpArgs la;
+    la.seqs_a = seqs_a;
+    la.seqs_b = seqs_b;
+    la.items = w->items_long;
+    la.ctr = w->ctr;
+    la.subst = w->subst;
+    la.asz = asz;
+    la.alpha = alpha;
+    la.beta = beta;
+    la.scores = scores_out;
+    la.bnd = w->bnd_long;
+    la.flags = w->flags;
+    if (timing) AS_HIP(hipEventRecord(w->ev[8], stream));
+    AS_HIP(launch_long_dp_i32(mode, la, (int)grid, stream));
+    if (timing) AS_HIP(hipEventRecord(w->ev[9], stream));
+  }
   AS_HIP(hipMemcpyAsync(w->host_ctr, w->ctr, sizeof(Counters), hipMemcpyDeviceToHost, stream));
   AS_HIP(hipStreamSynchronize(stream));
   const Counters c2 = *w->host_ctr;
+  g_last_timing.pairs_long = c.n_long;
+  if (timing && c.n_long > 0)
+    AS_HIP(hipEventElapsedTime(&g_last_timing.long_ms, w->ev[8], w->ev[9]));
   if (timing && c.n_full16 > 0)
     AS_HIP(hipEventElapsedTime(&g_last_timing.full16_ms, w->ev[2], w->ev[3]));
   if (timing && c.n_full32 > 0)
@@ -434,6 +536,9 @@ extern "C" int as_release_workspace(void) {
     if (w.items) (void)hipFree(w.items);
     if (w.items16) (void)hipFree(w.items16);
     if (w.rerun) (void)hipFree(w.rerun);
+    if (w.items_long) (void)hipFree(w.items_long);
+    if (w.bnd_long) (void)hipFree(w.bnd_long);
+    if (w.flags) (void)hipFree(w.flags);
     if (w.ctr) (void)hipFree(w.ctr);
     if (w.host_ctr) (void)hipHostFree(w.host_ctr);
     if (w.subst) (void)hipFree(w.subst);

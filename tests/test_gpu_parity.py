@@ -182,3 +182,48 @@ def test_packed16_routing(gpu, oracle_mod):
         finally:
             gpu.enable_timing(False)
         assert tm["pairs_full16"] > 0.9 * b.n_pairs
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_wavefront_long_pairs(gpu, oracle_mod, mode):
+    """Pairs long enough for the multi-wave wavefront: many stripes, ragged
+    last stripe, both orientations, related and unrelated."""
+    rng = np.random.default_rng(500 + mode)
+    pairs = []
+    for m, n in [(2048, 1025), (3000, 5000), (7000, 2100), (4097, 4097), (2500, 9999)]:
+        a = rng.integers(0, 4, size=m).astype(np.uint8)
+        if rng.random() < 0.5:
+            s, _ = synth.mutate(rng, a, np.array([0, m]), 0.05, 0.02, 0.02, 4)
+            s = s[:n] if len(s) >= n else np.concatenate([s, rng.integers(0, 4, n - len(s)).astype(np.uint8)])
+        else:
+            s = rng.integers(0, 4, size=n).astype(np.uint8)
+        pairs.append((a, s))
+    b = synth.from_pairs("wavefront", pairs, DNA, 5, 2, mode)
+    gpu.enable_timing(True)
+    try:
+        _check(gpu, oracle_mod, b, f"wavefront mode {mode}")
+        tm = gpu.last_timing()
+    finally:
+        gpu.enable_timing(False)
+    # (2048, 1025) is oriented with 1025 rows and stays on the 16-lane path
+    assert tm["pairs_long"] == len(pairs) - 1
+
+
+def test_config3_long_pairs_full_size_sampled(gpu, oracle_mod):
+    """The 64 pairs of 65,536 residues in the benchmark configuration; four of
+    them (two unrelated, two related) are checked against the oracle."""
+    b = synth.config3(n_pairs=0, n_long=64, long_len=65536)
+    _say(f"c3 long: {b.n_pairs} pairs, {b.cells():.3g} cells")
+    gpu.enable_timing(True)
+    try:
+        got = gpu.align(b)
+        tm = gpu.last_timing()
+    finally:
+        gpu.enable_timing(False)
+    _say(f"c3 long: wavefront {tm['long_ms']:.1f} ms, {b.cells() / tm['long_ms'] / 1e9:.1f} TCUPS")
+    idx = np.array([0, 1, 32, 33])
+    sub = b.subset(idx)
+    want = oracle_mod.align_batch(sub.seqs_a, sub.offs_a, sub.seqs_b, sub.offs_b, sub.subst,
+                                  sub.alpha, sub.beta, sub.mode, nthreads=4)
+    assert np.array_equal(got[idx].astype(np.int64), want)
+    assert got.min() >= 0
