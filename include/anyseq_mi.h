@@ -106,13 +106,58 @@ typedef struct {
     float full16_ms;    /* full DP, packed 16-bit cells */
     float rerun32_ms;   /* 32-bit re-run of saturated 16-bit pairs */
     float long_ms;      /* multi-wave wavefront for long pairs, 32-bit cells */
-    float reserved_ms[3];
+    float band_ms;      /* banded rounds (as_align_batch_band) */
+    float reserved_ms[2];
     int64_t pairs_full32;
     int64_t pairs_full16;
     int64_t pairs_rerun32;
     int64_t pairs_long;
+    int64_t pairs_fallback; /* banded pairs that went to the full DP */
     int64_t cells;      /* sum of m*n over the batch */
 } as_timing;
+
+/*
+ * Banded path with a certificate (the learned-band extension; not in the
+ * paper).  For global and semi-global alignment of alphabets of at most four
+ * letters.  Pair p is first aligned inside the band of diagonals
+ *   min(0, n-m) - w <= j - i <= max(0, n-m) + w,   w = band_w0[p]
+ * widened to the kernel's lane width (a band of 64..1024 diagonals, centred
+ * on the requested one).  The banded score is accepted when it is at least
+ * an upper bound on every alignment path that leaves the computed band
+ * (closed form from the path structure of Eq. (1),(4),(5)); then it is the
+ * optimal score.  Otherwise w doubles, for at most max_rounds rounds (1..8),
+ * and a pair whose band would exceed the widest lane width or half its
+ * matrix is aligned with the full DP.  Every returned score is exact.
+ *   band_w0    : device, int32 [n_pairs], initial half-widths (< 0 read as 0)
+ *   stats      : HOST, optional (NULL), filled on return
+ * Local mode returns AS_ERR_ARG; alphabets above four letters, or scores
+ * sigma + alpha + beta outside 0..255, return AS_ERR_SCORING.
+ */
+typedef struct {
+    int32_t rounds;        /* banded rounds that ran */
+    int32_t reserved;
+    int64_t accepted[8];   /* pairs accepted in round r */
+    int64_t fallback;      /* pairs aligned with the full DP */
+    int64_t band_cells;    /* DP cells computed by the banded kernel */
+    int64_t cells;         /* sum of m*n over the batch */
+} as_band_stats;
+
+int as_align_batch_band(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t *seqs_b,
+                        const int64_t *offs_b, int64_t n_pairs, const as_scoring *scoring,
+                        int32_t mode, const int32_t *band_w0, int32_t max_rounds,
+                        int32_t *scores_out, as_band_stats *stats, void *stream);
+
+/*
+ * Raw banded scores: the optimal score of pair p restricted to the band the
+ * kernel computes for half-width band_w[p] (see above), with no acceptance
+ * test.  lo_out/hi_out (device int32 [n_pairs], both or neither) receive the
+ * diagonal limits actually computed, in A-rows/B-columns orientation
+ * (j - i, j over B).  A band wider than 1024 diagonals returns AS_ERR_ARG.
+ */
+int as_band_scores(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t *seqs_b,
+                   const int64_t *offs_b, int64_t n_pairs, const as_scoring *scoring, int32_t mode,
+                   const int32_t *band_w, int32_t *scores_out, int32_t *lo_out, int32_t *hi_out,
+                   void *stream);
 
 /*
  * Saturation threshold of the packed 16-bit local path: a pair whose 16-bit

@@ -55,6 +55,10 @@ def _load():
     lib.oracle_banded_pair.argtypes = [p, i64, p, i64, p, i32, i64, i64, i32, i64]
     lib.oracle_align_batch.restype = None
     lib.oracle_align_batch.argtypes = [p, p, p, p, i64, p, i32, i64, i64, i32, i32, p]
+    lib.oracle_diag_band_pair.restype = i64
+    lib.oracle_diag_band_pair.argtypes = [p, i64, p, i64, p, i32, i64, i64, i32, i64, i64]
+    lib.oracle_diag_band_batch.restype = None
+    lib.oracle_diag_band_batch.argtypes = [p, p, p, p, i64, p, i32, i64, i64, i32, p, p, i32, p]
     lib.oracle_banded_batch.restype = None
     lib.oracle_banded_batch.argtypes = [p, p, p, p, i64, p, i32, i64, i64, i32, p, i32, p]
     _lib = lib
@@ -126,4 +130,29 @@ def banded_batch(seqs_a, offs_a, seqs_b, offs_b, subst, alpha: int, beta: int, m
     _load().oracle_banded_batch(_ptr(sa), _ptr(oa), _ptr(sb), _ptr(ob), n, _ptr(sub), asz,
                                 int(alpha), int(beta), int(mode), _ptr(w),
                                 nthreads or default_threads(), _ptr(out))
+    return out
+
+
+def diag_band_pair(q, s, subst, alpha: int, beta: int, mode: int, lo: int, hi: int) -> int:
+    """Score restricted to diagonals lo <= j-i <= hi (boundary cells included)."""
+    q, s = _u8(q), _u8(s)
+    sub, asz = _subst(subst)
+    return int(_load().oracle_diag_band_pair(_ptr(q), len(q), _ptr(s), len(s), _ptr(sub), asz,
+                                              int(alpha), int(beta), int(mode), int(lo), int(hi)))
+
+
+def diag_band_batch(seqs_a, offs_a, seqs_b, offs_b, subst, alpha: int, beta: int, mode: int,
+                    lo, hi, nthreads: int | None = None) -> np.ndarray:
+    """Scores of every pair restricted to its own diagonal limits lo[p] <= j-i <= hi[p]."""
+    sa, sb = _u8(seqs_a), _u8(seqs_b)
+    oa = np.ascontiguousarray(offs_a, dtype=np.int64)
+    ob = np.ascontiguousarray(offs_b, dtype=np.int64)
+    n = len(oa) - 1
+    lo = np.ascontiguousarray(lo, dtype=np.int64)
+    hi = np.ascontiguousarray(hi, dtype=np.int64)
+    sub, asz = _subst(subst)
+    out = np.zeros(n, dtype=np.int64)
+    _load().oracle_diag_band_batch(_ptr(sa), _ptr(oa), _ptr(sb), _ptr(ob), n, _ptr(sub), asz,
+                                   int(alpha), int(beta), int(mode), _ptr(lo), _ptr(hi),
+                                   nthreads or default_threads(), _ptr(out))
     return out

@@ -34,6 +34,13 @@ def band_limits(m: int, n: int, w: int) -> tuple[int, int]:
 
 def ub_outside(m: int, n: int, w: int, sigma_max: int, alpha: int, beta: int, mode: int):
     lo, hi = band_limits(m, n, w)
+    return ub_outside_diag(m, n, lo, hi, sigma_max, alpha, beta, mode)
+
+
+def ub_outside_diag(m: int, n: int, lo: int, hi: int, sigma_max: int, alpha: int, beta: int,
+                    mode: int):
+    """Upper bound on every path that visits a diagonal outside [lo, hi]
+    (lo <= min(0, n-m) and hi >= max(0, n-m) assumed); None if no path can."""
     if mode == GLOBAL:
         cands = []
         if hi + 1 <= n:                      # a path can reach diagonal U+1

@@ -137,12 +137,20 @@ int64_t oracle_banded_pair(const uint8_t *q, int64_t m, const uint8_t *s, int64_
     return align_band(q, m, s, n, subst, asz, alpha, beta, mode, lo, hi);
 }
 
+/* Score restricted to the diagonals lo <= j-i <= hi (explicit limits). */
+int64_t oracle_diag_band_pair(const uint8_t *q, int64_t m, const uint8_t *s, int64_t n,
+                              const int8_t *subst, int32_t asz, int64_t alpha, int64_t beta,
+                              int32_t mode, int64_t lo, int64_t hi) {
+    return align_band(q, m, s, n, subst, asz, alpha, beta, mode, lo, hi);
+}
+
 /* ---- threaded batch driver: pairs are independent, split them over threads ---- */
 
 typedef struct {
     const uint8_t *sa, *sb;
     const int64_t *oa, *ob;
     const int64_t *band_w; /* NULL = full DP */
+    const int64_t *band_lo, *band_hi; /* explicit diagonal limits (overrides band_w) */
     int64_t n_pairs;
     const int8_t *subst;
     int32_t asz, mode;
@@ -167,7 +175,11 @@ static void *batch_worker(void *arg) {
             const uint8_t *s = job->sb + job->ob[p];
             int64_t m = job->oa[p + 1] - job->oa[p];
             int64_t n = job->ob[p + 1] - job->ob[p];
-            if (job->band_w)
+            if (job->band_lo)
+                job->out[p] = oracle_diag_band_pair(q, m, s, n, job->subst, job->asz, job->alpha,
+                                                    job->beta, job->mode, job->band_lo[p],
+                                                    job->band_hi[p]);
+            else if (job->band_w)
                 job->out[p] = oracle_banded_pair(q, m, s, n, job->subst, job->asz, job->alpha,
                                                  job->beta, job->mode, job->band_w[p]);
             else
@@ -210,6 +222,18 @@ void oracle_banded_batch(const uint8_t *seqs_a, const int64_t *offs_a, const uin
     memset(&job, 0, sizeof(job));
     job.sa = seqs_a; job.sb = seqs_b; job.oa = offs_a; job.ob = offs_b;
     job.band_w = band_w; job.n_pairs = n_pairs; job.subst = subst; job.asz = asz;
+    job.mode = mode; job.alpha = alpha; job.beta = beta; job.out = out;
+    run_batch(&job, nthreads);
+}
+
+void oracle_diag_band_batch(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t *seqs_b,
+                            const int64_t *offs_b, int64_t n_pairs, const int8_t *subst,
+                            int32_t asz, int64_t alpha, int64_t beta, int32_t mode,
+                            const int64_t *lo, const int64_t *hi, int32_t nthreads, int64_t *out) {
+    batch_job job;
+    memset(&job, 0, sizeof(job));
+    job.sa = seqs_a; job.sb = seqs_b; job.oa = offs_a; job.ob = offs_b;
+    job.band_lo = lo; job.band_hi = hi; job.n_pairs = n_pairs; job.subst = subst; job.asz = asz;
     job.mode = mode; job.alpha = alpha; job.beta = beta; job.out = out;
     run_batch(&job, nthreads);
 }

@@ -32,13 +32,24 @@ class Scoring(ctypes.Structure):
 class Timing(ctypes.Structure):
     _fields_ = [("classify_ms", ctypes.c_float), ("full32_ms", ctypes.c_float),
                 ("full16_ms", ctypes.c_float), ("rerun32_ms", ctypes.c_float),
-                ("long_ms", ctypes.c_float), ("reserved_ms", ctypes.c_float * 3),
+                ("long_ms", ctypes.c_float), ("band_ms", ctypes.c_float),
+                ("reserved_ms", ctypes.c_float * 2),
                 ("pairs_full32", ctypes.c_int64), ("pairs_full16", ctypes.c_int64),
                 ("pairs_rerun32", ctypes.c_int64), ("pairs_long", ctypes.c_int64),
-                ("cells", ctypes.c_int64)]
+                ("pairs_fallback", ctypes.c_int64), ("cells", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved_ms"}
+
+
+class BandStats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("accepted", ctypes.c_int64 * 8), ("fallback", ctypes.c_int64),
+                ("band_cells", ctypes.c_int64), ("cells", ctypes.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {"rounds": self.rounds, "accepted": list(self.accepted)[:max(self.rounds, 1)],
+                "fallback": self.fallback, "band_cells": self.band_cells, "cells": self.cells}
 
 
 class AlignError(RuntimeError):
@@ -64,6 +75,11 @@ def lib() -> ctypes.CDLL:
     L.as_release_workspace.argtypes = []
     L.as_build_info.restype = ctypes.c_char_p
     L.as_build_info.argtypes = []
+    L.as_align_batch_band.restype = ctypes.c_int
+    L.as_align_batch_band.argtypes = [p, p, p, p, i64, ctypes.POINTER(Scoring), i32, p, i32, p,
+                                      ctypes.POINTER(BandStats), p]
+    L.as_band_scores.restype = ctypes.c_int
+    L.as_band_scores.argtypes = [p, p, p, p, i64, ctypes.POINTER(Scoring), i32, p, p, p, p, p]
     L.as_set_i16_limit.restype = ctypes.c_int
     L.as_set_i16_limit.argtypes = [ctypes.c_int32]
     L.as_enable_timing.restype = ctypes.c_int
@@ -140,6 +156,56 @@ def align_batch(seqs_a, offs_a, seqs_b, offs_b, subst, alpha: int, beta: int, mo
 def set_i16_limit(limit: int) -> int:
     """Saturation threshold of the 16-bit local path (test hook; <= 0 resets)."""
     return int(lib().as_set_i16_limit(int(limit)))
+
+
+def _seq_ptrs(seqs_a, offs_a, seqs_b, offs_b):
+    import torch
+    pa = _dev_ptr(seqs_a, torch.uint8, "seqs_a") if seqs_a.numel() else ctypes.c_void_p(offs_a.data_ptr())
+    pb = _dev_ptr(seqs_b, torch.uint8, "seqs_b") if seqs_b.numel() else ctypes.c_void_p(offs_b.data_ptr())
+    return (pa, _dev_ptr(offs_a, torch.int64, "offs_a"), pb, _dev_ptr(offs_b, torch.int64, "offs_b"))
+
+
+def align_batch_band(seqs_a, offs_a, seqs_b, offs_b, subst, alpha: int, beta: int, mode: int,
+                     band_w0, max_rounds: int = 6, scores_out=None, stream=None):
+    """Certified banded alignment (exact scores); returns (scores, stats dict)."""
+    import torch
+    n_pairs = offs_a.numel() - 1
+    if scores_out is None:
+        scores_out = torch.empty(max(n_pairs, 1), dtype=torch.int32, device=offs_a.device)
+    sc, keep = make_scoring(subst, alpha, beta)
+    if stream is None:
+        stream = torch.cuda.current_stream(offs_a.device).cuda_stream
+    st = BandStats()
+    rc = lib().as_align_batch_band(*_seq_ptrs(seqs_a, offs_a, seqs_b, offs_b), n_pairs,
+                                   ctypes.byref(sc), int(mode),
+                                   _dev_ptr(band_w0, torch.int32, "band_w0"), int(max_rounds),
+                                   _dev_ptr(scores_out, torch.int32, "scores_out"),
+                                   ctypes.byref(st), ctypes.c_void_p(stream))
+    del keep
+    _check(rc)
+    return scores_out[:n_pairs], st.as_dict()
+
+
+def band_scores(seqs_a, offs_a, seqs_b, offs_b, subst, alpha: int, beta: int, mode: int, band_w,
+                stream=None):
+    """Raw banded scores and the diagonal limits computed (lo, hi), device tensors."""
+    import torch
+    n_pairs = offs_a.numel() - 1
+    dev = offs_a.device
+    out = torch.empty(max(n_pairs, 1), dtype=torch.int32, device=dev)
+    lo = torch.empty(max(n_pairs, 1), dtype=torch.int32, device=dev)
+    hi = torch.empty(max(n_pairs, 1), dtype=torch.int32, device=dev)
+    sc, keep = make_scoring(subst, alpha, beta)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev).cuda_stream
+    rc = lib().as_band_scores(*_seq_ptrs(seqs_a, offs_a, seqs_b, offs_b), n_pairs,
+                              ctypes.byref(sc), int(mode), _dev_ptr(band_w, torch.int32, "band_w"),
+                              _dev_ptr(out, torch.int32, "scores_out"),
+                              _dev_ptr(lo, torch.int32, "lo_out"), _dev_ptr(hi, torch.int32, "hi_out"),
+                              ctypes.c_void_p(stream))
+    del keep
+    _check(rc)
+    return out[:n_pairs], lo[:n_pairs], hi[:n_pairs]
 
 
 def enable_timing(on: bool = True) -> bool:

@@ -53,9 +53,102 @@ struct Counters {
   int32_t n_long;        // pairs queued for the multi-wave wavefront
   int32_t n_long_tasks;  // their stripes (one task per stripe)
   int32_t next_long;     // ticket counter of the wavefront kernel
-  int32_t pad_;
+  int32_t n_fallback;    // banded pairs sent to the full DP
   long long long_bnd_total;  // int2 entries of all wavefront boundary columns
+  // banded path: lists per round parity and lane-width class
+  int32_t n_band[2][5];
+  int32_t next_band[5];
+  int32_t band_accepted[8];  // pairs accepted in round r
+  unsigned long long band_cells;  // cells computed by the banded kernel
 };
+
+// ---- banded path ----
+constexpr int kBandClasses = 5;     // lane widths K = 4, 8, 16, 32, 64 (W = 64 .. 1024)
+constexpr int kMaxBandRounds = 8;
+
+// Band width (diagonals) of lane-width class kc: 16 lanes x K = 4 << kc.
+__host__ __device__ inline int band_class_width(int kc) { return kGroup * (4 << kc); }
+
+// Smallest class whose band width 16*K holds B diagonals, or -1.
+__host__ __device__ inline int band_class_for(int B) {
+  for (int kc = 0; kc < kBandClasses; ++kc)
+    if (kGroup * (4 << kc) >= B) return kc;
+  return -1;
+}
+
+// Upper bound on the score of every path that visits a diagonal outside
+// [lo, hi] (lo <= min(0, n-m), hi >= max(0, n-m), 0 <= beta <= alpha).
+// Returns false when no path can leave the band.
+//  global: a path reaching diagonal hi+1 takes >= hi+1 horizontal and
+//    >= hi+1-(n-m) vertical gap columns (it must return to n-m); one reaching
+//    lo-1 takes >= 1-lo vertical and >= n-m-lo+1 horizontal ones.  With g
+//    diagonal steps it has m+n-2g gap columns in >= 2 runs, so it scores at
+//    most sigma_max*g - 2 alpha - beta*(m+n-2g-2), g <= (m+n-G)/2.
+//  semi-global: a path through a cell of diagonal d has at most len(d)
+//    diagonal steps and gaps cost >= 0: at most max(sigma_max,0)*len(d), and
+//    len is largest on the nearest outside diagonals hi+1 and lo-1.
+__host__ __device__ inline bool band_leave_bound(int m, int n, int lo, int hi, int sigma_max,
+                                                 int alpha, int beta, int mode, int64_t *ub) {
+  bool any = false;
+  int64_t best = 0;
+  if (mode == kGlobal) {
+    int64_t G[2];
+    int ng = 0;
+    if (hi + 1 <= n) G[ng++] = 2LL * (hi + 1) - (n - m);
+    if (lo - 1 >= -m) G[ng++] = (int64_t)(n - m) - 2LL * (lo - 1);
+    for (int s = 0; s < ng; ++s) {
+      const int64_t gmax = ((int64_t)m + n - G[s]) / 2;
+      if ((int64_t)m + n - G[s] < 0) continue;
+      const int64_t g = (sigma_max + 2 * beta >= 0) ? gmax : 0;
+      const int64_t v = (int64_t)sigma_max * g - 2LL * alpha - (int64_t)beta * ((int64_t)m + n - 2 * g - 2);
+      best = any ? (v > best ? v : best) : v;
+      any = true;
+    }
+  } else {
+    int64_t len = -1;
+    if (hi + 1 <= n) {
+      const int d = hi + 1;
+      const int64_t l = d >= 0 ? (m < n - d ? m : n - d) : (m + d < n ? m + d : n);
+      len = l > len ? l : len;
+    }
+    if (lo - 1 >= -m) {
+      const int d = lo - 1;
+      const int64_t l = d >= 0 ? (m < n - d ? m : n - d) : (m + d < n ? m + d : n);
+      len = l > len ? l : len;
+    }
+    if (len >= 0) {
+      any = true;
+      best = (int64_t)(sigma_max > 0 ? sigma_max : 0) * len;
+    }
+  }
+  *ub = best;
+  return any;
+}
+
+// One banded pair: the orientation-fixed descriptor and its half-width.
+struct BandItem {
+  PairDesc d;
+  int32_t w;
+  int32_t pad_;
+};
+
+struct BandArgs {
+  const uint8_t *seqs_a;
+  const uint8_t *seqs_b;
+  BandItem *lists;          // [2 parities][kBandClasses][list_cap]
+  int64_t list_cap;
+  Counters *ctr;
+  const uint32_t *qwords;   // [2][32]: byte c of word r = sigma(r, c) + alpha + beta (row/col order)
+  int32_t asz, alpha, beta, sigma_max;
+  int32_t round, max_rounds;
+  int32_t raw;              // 1: write the banded score, no acceptance test
+  int32_t *scores;
+  int32_t *lo_out, *hi_out; // optional: diagonal limits computed (A/B orientation)
+  PairDesc *fallback;       // rejected pairs for the full DP
+};
+
+hipError_t launch_band_dp_i32(int mode, int kc, const BandArgs &args, int grid, hipStream_t stream);
+int band_dp_i32_blocks_per_cu(int mode, int kc);
 
 // A long pair and where its stripes and boundary columns live.
 struct LongItem {

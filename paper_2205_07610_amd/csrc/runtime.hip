@@ -1,14 +1,20 @@
 // Host runtime and C ABI of the library (include/anyseq_mi.h).
 //
-// Per call: argument checks on the host, then on the caller's stream
+// Full DP (as_align_batch), on the caller's stream:
 //   1. classify: per pair, offsets are validated, empty pairs are scored by
 //      their closed form (mode paragraphs of the paper's section 2.1), every
-//      other pair gets an orientation (which sequence is streamed down the
-//      rows) and is appended to the work list; the a priori score range is
-//      checked against the 32-bit cell budget;
+//      other pair gets an orientation (which sequence runs down the rows) and
+//      a route -- packed 16-bit list, 32-bit list or multi-wave wavefront --
+//      after the a priori range checks;
 //   2. the counters are read back (one small device-to-host copy);
-//   3. the persistent full-DP kernel drains the work list;
+//   3. the persistent kernels drain the lists; 16-bit pairs that saturate are
+//      re-queued and recomputed with 32-bit cells;
 //   4. the status word is read back and turned into the return code.
+// Banded path (as_align_batch_band): the band classify step queues every pair
+// with its initial half-width by lane-width class; each round the banded
+// kernel either accepts a pair (certificate), re-queues it with the band
+// doubled, or sends it to the full-DP fallback list, which then goes through
+// the full-DP routing of step 1 and steps 3-4.
 #include <mutex>
 #include <string.h>
 #include <vector>
@@ -21,10 +27,9 @@ namespace {
 
 constexpr int64_t kMaxLen = (int64_t)1 << 30;
 constexpr int64_t kCellBudget32 = (int64_t)1 << 28;  // |shifted cell| must stay below
+constexpr int32_t kStatusArg = 16;                    // band wider than the widest class
 
-struct ClassifyParams {
-  const int64_t *offs_a;
-  const int64_t *offs_b;
+struct RouteParams {
   int64_t n_pairs;
   int32_t mode, alpha, beta, smax_abs, smax_pos;
   int32_t stripe_w, allow16, stripe_w16;
@@ -33,35 +38,15 @@ struct ClassifyParams {
                           // one wavefront stripe of columns go to the wavefront
 };
 
-// Route of one pair: 0 none (error or empty pair, scored here), 1 the 32-bit
-// list, 2 the packed 16-bit list.  Fills d for routes 1 and 2.
-__device__ int route_pair(const ClassifyParams &c, int64_t p, Counters *ctr,
-                          int32_t *__restrict__ scores, bool first_pass, PairDesc &d,
-                          unsigned long long &cells) {
-  const int64_t a0 = c.offs_a[p], a1 = c.offs_a[p + 1];
-  const int64_t b0 = c.offs_b[p], b1 = c.offs_b[p + 1];
-  if (a0 < 0 || b0 < 0 || a1 < a0 || b1 < b0) {
-    if (first_pass) atomicOr(&ctr->status, kStatusBadOffsets);
-    return 0;
-  }
-  const int64_t m = a1 - a0, n = b1 - b0;
-  cells = (unsigned long long)(m * n);
-  // Every cell value, in either frame the kernels use, is bounded in
-  // magnitude by (|sigma|max + alpha + 2 beta) * (m + n + 2).
-  if (m >= kMaxLen || n >= kMaxLen ||
-      (int64_t)(c.smax_abs + c.alpha + 2 * c.beta) * (m + n + 2) >= kCellBudget32) {
-    if (first_pass) atomicOr(&ctr->status, kStatusRange);
-    return 0;
-  }
-  if (m == 0 || n == 0) {
-    // one gap of length m + n (global) or the empty alignment (others)
-    const int64_t len = m + n;
-    if (first_pass)
-      scores[p] = (c.mode == kGlobal && len > 0) ? (int32_t)(-c.alpha - c.beta * (len - 1)) : 0;
-    return 0;
-  }
-  // Orientation: a stripe pass costs (rows + 15) steps over 16*K columns;
-  // take the cheaper of A-as-rows and B-as-rows.
+enum Route { kRouteNone = 0, kRoute32 = 1, kRoute16 = 2, kRouteLong = 3 };
+constexpr int kFullRoutes = 4;
+
+// Orientation and full-DP route of a non-empty pair (A at a0, length m; B at
+// b0, length n).
+__device__ int route_full(const RouteParams &c, int64_t a0, int64_t m, int64_t b0, int64_t n,
+                          int64_t p, PairDesc &d) {
+  // A stripe pass costs (rows + 15) steps over 16*K columns; take the cheaper
+  // of A-as-rows and B-as-rows.
   const int64_t sa = (n + c.stripe_w - 1) / c.stripe_w, sb = (m + c.stripe_w - 1) / c.stripe_w;
   const int64_t cost_a = sa * (m + kGroup - 1), cost_b = sb * (n + kGroup - 1);
   const bool tr = cost_b < cost_a;
@@ -72,106 +57,217 @@ __device__ int route_pair(const ClassifyParams &c, int64_t p, Counters *ctr,
   d.pair = (int32_t)p;
   d.flags = tr ? kTransposed : 0;
   if (c.allow16 && d.n <= c.stripe_w16) {
-    if (c.mode == kLocal) return 2;  // saturation is detected at run time
+    if (c.mode == kLocal) return kRoute16;  // saturation is detected at run time
     // shifted-frame cells stay below sigma_max*min(m,n) + beta*(m+n), plus
     // the profile byte and the padding offset beta*W16
     const int64_t ub = (int64_t)c.smax_pos * (m < n ? m : n) + (int64_t)c.beta * (m + n) +
                        (int64_t)c.beta * c.stripe_w16 + c.alpha + 2 * c.beta + 256;
-    if (ub < 32000) return 2;
+    if (ub < 32000) return kRoute16;
   }
-  if (d.n > c.long_w && d.m >= c.long_min_rows) return 3;
-  if (first_pass && d.n > c.stripe_w) atomicMax(&ctr->max_rows_multi, d.m);
-  return 1;
+  if (d.n > c.long_w && d.m >= c.long_min_rows) return kRouteLong;
+  return kRoute32;
 }
 
-// Block-wide exclusive prefix of a per-thread 0/1 flag (256 threads).
-// Returns the prefix; *total gets the block's count.
-__device__ int block_prefix(bool flag, int *lds4, int *total) {
-  const unsigned long long mask = __ballot(flag);
-  const int lane = (int)__lane_id(), wave = threadIdx.x >> 6;
-  const int in_wave = __popcll(mask & ((1ull << lane) - 1ull));
-  if (lane == 0) lds4[wave] = __popcll(mask);
-  __syncthreads();
-  int before = 0, sum = 0;
-  for (int w = 0; w < 4; ++w) {
-    const int v = lds4[w];
-    before += (w < wave) ? v : 0;
-    sum += v;
+// Validation shared by the classify kernels.  Returns false for pairs that
+// need no DP (errors, empty sequences -- scored here).
+__device__ bool check_pair(const RouteParams &c, const int64_t *offs_a, const int64_t *offs_b,
+                           int64_t p, Counters *ctr, int32_t *scores, bool first_pass, int64_t &a0,
+                           int64_t &m, int64_t &b0, int64_t &n) {
+  a0 = offs_a[p];
+  b0 = offs_b[p];
+  const int64_t a1 = offs_a[p + 1], b1 = offs_b[p + 1];
+  m = a1 - a0;
+  n = b1 - b0;
+  if (a0 < 0 || b0 < 0 || a1 < a0 || b1 < b0) {
+    if (first_pass) atomicOr(&ctr->status, kStatusBadOffsets);
+    return false;
   }
-  __syncthreads();
-  *total = sum;
-  return before + in_wave;
+  // Every cell value, in either frame the kernels use, is bounded in
+  // magnitude by (|sigma|max + alpha + 2 beta) * (m + n + 2).
+  if (m >= kMaxLen || n >= kMaxLen ||
+      (int64_t)(c.smax_abs + c.alpha + 2 * c.beta) * (m + n + 2) >= kCellBudget32) {
+    if (first_pass) atomicOr(&ctr->status, kStatusRange);
+    return false;
+  }
+  if (m == 0 || n == 0) {
+    // one gap of length m + n (global) or the empty alignment (others)
+    const int64_t len = m + n;
+    if (first_pass)
+      scores[p] = (c.mode == kGlobal && len > 0) ? (int32_t)(-c.alpha - c.beta * (len - 1)) : 0;
+    return false;
+  }
+  return true;
 }
 
-// Each block owns a contiguous range of pairs: it counts its routes, reserves
-// its slice of each work list with one atomic per list, then scatters.  Items
-// of a block stay in pair order inside the lists.
-__global__ void __launch_bounds__(256) classify_kernel(ClassifyParams c, PairDesc *__restrict__ items32,
-                                                       PairDesc *__restrict__ items16,
-                                                       LongItem *__restrict__ items_long,
-                                                       Counters *ctr, int32_t *__restrict__ scores) {
-  __shared__ int lds4[4];
-  __shared__ int base_sh[3];
+// Block-level list reservation: pass 1 counts the routes of the block's
+// pairs in LDS, one global atomic per route reserves the block's slices, pass
+// 2 recomputes the routes and scatters through LDS cursors.
+template <int R>
+struct BlockLists {
+  int cnt[R];
+  int base[R];
+  unsigned long long cells;
+};
+
+__device__ inline unsigned long long valid_cells(int64_t a0, int64_t m, int64_t b0, int64_t n) {
+  return (a0 >= 0 && b0 >= 0 && m > 0 && n > 0) ? (unsigned long long)(m * n) : 0ull;
+}
+
+__global__ void __launch_bounds__(256) classify_kernel(RouteParams c, const int64_t *offs_a,
+                                                       const int64_t *offs_b, PairDesc *items32,
+                                                       PairDesc *items16, LongItem *items_long,
+                                                       Counters *ctr, int32_t *scores) {
+  __shared__ BlockLists<kFullRoutes> bl;
   const int64_t chunk = (c.n_pairs + gridDim.x - 1) / gridDim.x;
   const int64_t lo = (int64_t)blockIdx.x * chunk;
   const int64_t hi = lo + chunk < c.n_pairs ? lo + chunk : c.n_pairs;
-  int cnt32 = 0, cnt16 = 0, cntl = 0;
+  if (threadIdx.x < kFullRoutes) bl.cnt[threadIdx.x] = 0;
+  if (threadIdx.x == 0) bl.cells = 0;
+  __syncthreads();
   unsigned long long cells = 0;
-  for (int64_t t0 = lo; t0 < hi; t0 += 256) {
-    const int64_t p = t0 + threadIdx.x;
-    int r = 0;
-    if (p < hi) {
-      PairDesc d;
-      unsigned long long cl = 0;
-      r = route_pair(c, p, ctr, scores, true, d, cl);
-      cells += cl;
-    }
-    cnt32 += (r == 1);
-    cnt16 += (r == 2);
-    cntl += (r == 3);
+  for (int64_t p = lo + threadIdx.x; p < hi; p += blockDim.x) {
+    int64_t a0, m, b0, n;
+    const bool dp = check_pair(c, offs_a, offs_b, p, ctr, scores, true, a0, m, b0, n);
+    cells += valid_cells(a0, m, b0, n);
+    if (!dp) continue;
+    PairDesc d;
+    const int r = route_full(c, a0, m, b0, n, p, d);
+    if (r == kRoute32 && d.n > c.stripe_w) atomicMax(&ctr->max_rows_multi, d.m);
+    atomicAdd(&bl.cnt[r], 1);
   }
-  // block totals: one atomic per list and one for the cell count
-  for (int off = 32; off > 0; off >>= 1) {
-    cnt32 += __shfl_xor(cnt32, off);
-    cnt16 += __shfl_xor(cnt16, off);
-    cntl += __shfl_xor(cntl, off);
-    cells += __shfl_xor(cells, off);
-  }
-  __shared__ int s32[4], s16[4], sl[4];
-  __shared__ unsigned long long sc[4];
-  const int wave = threadIdx.x >> 6;
-  if (__lane_id() == 0) { s32[wave] = cnt32; s16[wave] = cnt16; sl[wave] = cntl; sc[wave] = cells; }
+  atomicAdd(&bl.cells, cells);
   __syncthreads();
   if (threadIdx.x == 0) {
-    const int t32 = s32[0] + s32[1] + s32[2] + s32[3];
-    const int t16 = s16[0] + s16[1] + s16[2] + s16[3];
-    const unsigned long long tc = sc[0] + sc[1] + sc[2] + sc[3];
-    base_sh[0] = t32 ? atomicAdd(&ctr->n_full32, t32) : 0;
-    base_sh[1] = t16 ? atomicAdd(&ctr->n_full16, t16) : 0;
-    const int tl = sl[0] + sl[1] + sl[2] + sl[3];
-    base_sh[2] = tl ? atomicAdd(&ctr->n_long, tl) : 0;
-    if (tc) atomicAdd(&ctr->cells, tc);
+    bl.base[kRoute32] = bl.cnt[kRoute32] ? atomicAdd(&ctr->n_full32, bl.cnt[kRoute32]) : 0;
+    bl.base[kRoute16] = bl.cnt[kRoute16] ? atomicAdd(&ctr->n_full16, bl.cnt[kRoute16]) : 0;
+    bl.base[kRouteLong] = bl.cnt[kRouteLong] ? atomicAdd(&ctr->n_long, bl.cnt[kRouteLong]) : 0;
+    if (bl.cells) atomicAdd(&ctr->cells, bl.cells);
+    for (int r = 0; r < kFullRoutes; ++r) bl.cnt[r] = 0;
   }
   __syncthreads();
-  int cur32 = base_sh[0], cur16 = base_sh[1], curl = base_sh[2];
-  for (int64_t t0 = lo; t0 < hi; t0 += 256) {
-    const int64_t p = t0 + threadIdx.x;
-    int r = 0;
+  for (int64_t p = lo + threadIdx.x; p < hi; p += blockDim.x) {
+    int64_t a0, m, b0, n;
+    if (!check_pair(c, offs_a, offs_b, p, ctr, scores, false, a0, m, b0, n)) continue;
     PairDesc d;
-    if (p < hi) {
-      unsigned long long cl = 0;
-      r = route_pair(c, p, ctr, scores, false, d, cl);
+    const int r = route_full(c, a0, m, b0, n, p, d);
+    const int slot = bl.base[r] + atomicAdd(&bl.cnt[r], 1);
+    if (r == kRoute32) items32[slot] = d;
+    else if (r == kRoute16) items16[slot] = d;
+    else items_long[slot].d = d;
+  }
+}
+
+// Full-DP routing of the banded path's fallback pairs.
+__global__ void __launch_bounds__(256) route_fallback_kernel(RouteParams c, const PairDesc *fallback,
+                                                             PairDesc *items32, PairDesc *items16,
+                                                             LongItem *items_long, Counters *ctr) {
+  __shared__ BlockLists<kFullRoutes> bl;
+  const int64_t total = ctr->n_fallback;
+  const int64_t chunk = (total + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = (int64_t)blockIdx.x * chunk;
+  const int64_t hi = lo + chunk < total ? lo + chunk : total;
+  if (threadIdx.x < kFullRoutes) bl.cnt[threadIdx.x] = 0;
+  __syncthreads();
+  auto route = [&](int64_t i, PairDesc &d) {
+    const PairDesc f = fallback[i];
+    const bool tr = (f.flags & kTransposed) != 0;
+    const int64_t a0 = tr ? f.col_off : f.row_off, b0 = tr ? f.row_off : f.col_off;
+    const int64_t m = tr ? f.n : f.m, n = tr ? f.m : f.n;
+    return route_full(c, a0, m, b0, n, f.pair, d);
+  };
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    PairDesc d;
+    const int r = route(i, d);
+    if (r == kRoute32 && d.n > c.stripe_w) atomicMax(&ctr->max_rows_multi, d.m);
+    atomicAdd(&bl.cnt[r], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    bl.base[kRoute32] = bl.cnt[kRoute32] ? atomicAdd(&ctr->n_full32, bl.cnt[kRoute32]) : 0;
+    bl.base[kRoute16] = bl.cnt[kRoute16] ? atomicAdd(&ctr->n_full16, bl.cnt[kRoute16]) : 0;
+    bl.base[kRouteLong] = bl.cnt[kRouteLong] ? atomicAdd(&ctr->n_long, bl.cnt[kRouteLong]) : 0;
+    for (int r = 0; r < kFullRoutes; ++r) bl.cnt[r] = 0;
+  }
+  __syncthreads();
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    PairDesc d;
+    const int r = route(i, d);
+    const int slot = bl.base[r] + atomicAdd(&bl.cnt[r], 1);
+    if (r == kRoute32) items32[slot] = d;
+    else if (r == kRoute16) items16[slot] = d;
+    else items_long[slot].d = d;
+  }
+}
+
+// Banded path entry: orientation (rows = the shorter sequence), initial
+// half-width, lane-width class; pairs whose first band is already wider than
+// the widest class, or than half the matrix, go straight to the fallback list.
+// raw = 1 queues every pair (too wide a band is an error).
+__global__ void __launch_bounds__(256) band_classify_kernel(RouteParams c, const int64_t *offs_a,
+                                                            const int64_t *offs_b, const int32_t *w0,
+                                                            int32_t raw, BandItem *lists,
+                                                            int64_t list_cap, PairDesc *fallback,
+                                                            Counters *ctr, int32_t *scores) {
+  constexpr int R = kBandClasses + 1;  // classes, then the fallback list
+  __shared__ BlockLists<R> bl;
+  const int64_t chunk = (c.n_pairs + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = (int64_t)blockIdx.x * chunk;
+  const int64_t hi = lo + chunk < c.n_pairs ? lo + chunk : c.n_pairs;
+  if (threadIdx.x < R) bl.cnt[threadIdx.x] = 0;
+  if (threadIdx.x == 0) bl.cells = 0;
+  __syncthreads();
+  unsigned long long cells = 0;
+  auto classify = [&](int64_t p, bool first, BandItem &bi) -> int {
+    int64_t a0, m, b0, n;
+    const bool dp = check_pair(c, offs_a, offs_b, p, ctr, scores, first, a0, m, b0, n);
+    if (first) cells += valid_cells(a0, m, b0, n);
+    if (!dp) return -1;
+    const bool tr = n < m;
+    bi.d.row_off = tr ? b0 : a0;
+    bi.d.col_off = tr ? a0 : b0;
+    bi.d.m = (int32_t)(tr ? n : m);
+    bi.d.n = (int32_t)(tr ? m : n);
+    bi.d.pair = (int32_t)p;
+    bi.d.flags = tr ? kTransposed : 0;
+    int w = w0[p];
+    w = w < 0 ? 0 : (w > (1 << 20) ? (1 << 20) : w);
+    bi.w = w;
+    bi.pad_ = 0;
+    const int B = bi.d.n - bi.d.m + 2 * w + 1;
+    const int kc = band_class_for(B);
+    if (raw) {
+      if (kc < 0) {
+        if (first) atomicOr(&ctr->status, kStatusArg);
+        return -1;
+      }
+      return kc;
     }
-    int n32, n16, nl;
-    const int i32 = block_prefix(r == 1, lds4, &n32);
-    const int i16 = block_prefix(r == 2, lds4, &n16);
-    const int il = block_prefix(r == 3, lds4, &nl);
-    if (r == 1) items32[cur32 + i32] = d;
-    if (r == 2) items16[cur16 + i16] = d;
-    if (r == 3) items_long[curl + il].d = d;
-    cur32 += n32;
-    cur16 += n16;
-    curl += nl;
+    if (kc < 0 || 2 * band_class_width(kc) >= bi.d.n) return kBandClasses;
+    return kc;
+  };
+  for (int64_t p = lo + threadIdx.x; p < hi; p += blockDim.x) {
+    BandItem bi;
+    const int r = classify(p, true, bi);
+    if (r >= 0) atomicAdd(&bl.cnt[r], 1);
+  }
+  atomicAdd(&bl.cells, cells);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int kc = 0; kc < kBandClasses; ++kc)
+      bl.base[kc] = bl.cnt[kc] ? atomicAdd(&ctr->n_band[0][kc], bl.cnt[kc]) : 0;
+    bl.base[kBandClasses] =
+        bl.cnt[kBandClasses] ? atomicAdd(&ctr->n_fallback, bl.cnt[kBandClasses]) : 0;
+    if (bl.cells) atomicAdd(&ctr->cells, bl.cells);
+    for (int r = 0; r < R; ++r) bl.cnt[r] = 0;
+  }
+  __syncthreads();
+  for (int64_t p = lo + threadIdx.x; p < hi; p += blockDim.x) {
+    BandItem bi;
+    const int r = classify(p, false, bi);
+    if (r < 0) continue;
+    const int slot = bl.base[r] + atomicAdd(&bl.cnt[r], 1);
+    if (r == kBandClasses) fallback[slot] = bi.d;
+    else lists[(int64_t)r * list_cap + slot] = bi;
   }
 }
 
@@ -180,7 +276,8 @@ __global__ void __launch_bounds__(256) classify_kernel(ClassifyParams c, PairDes
 // maxima start from (0 = the empty alignment / boundary cells).
 __global__ void __launch_bounds__(256) long_prep_kernel(LongItem *items, Counters *ctr, int32_t long_w,
                                                         int32_t mode, int32_t *scores) {
-  __shared__ int lds4[4];
+  __shared__ int sst[256];
+  __shared__ long long sbe[256];
   const int n = ctr->n_long;
   int task = 0;
   long long bnd = 0;
@@ -194,9 +291,6 @@ __global__ void __launch_bounds__(256) long_prep_kernel(LongItem *items, Counter
       be = (long long)(st - 1) * (d.m + 1);
       if (mode != kGlobal) scores[d.pair] = 0;
     }
-    // block-wide inclusive scans of st and be (256 threads, simple two-level)
-    __shared__ int sst[256];
-    __shared__ long long sbe[256];
     sst[threadIdx.x] = st;
     sbe[threadIdx.x] = be;
     __syncthreads();
@@ -217,7 +311,6 @@ __global__ void __launch_bounds__(256) long_prep_kernel(LongItem *items, Counter
     bnd += sbe[255];
     __syncthreads();
   }
-  (void)lds4;
   if (threadIdx.x == 0) {
     ctr->n_long_tasks = task;
     ctr->long_bnd_total = bnd;
@@ -239,12 +332,17 @@ struct Workspace {
   int64_t bnd_long_cap = 0;
   int32_t *flags = nullptr;        // wavefront progress counters
   int64_t flags_cap = 0;
+  BandItem *band_lists = nullptr;  // [2][kBandClasses][cap]
+  int64_t band_cap = 0;
+  PairDesc *fallback = nullptr;
+  int64_t fallback_cap = 0;
+  uint32_t *qwords = nullptr;      // [2][32]
   Counters *ctr = nullptr;
   Counters *host_ctr = nullptr;  // pinned
   int8_t *subst = nullptr;       // 32*32 bytes
   int2 *bnd = nullptr;
   int64_t bnd_cap = 0;           // int2 elements
-  hipEvent_t ev[10] = {};
+  hipEvent_t ev[16] = {};
 };
 
 bool g_timing = false;
@@ -271,6 +369,7 @@ int get_workspace(Workspace **out) {
     AS_HIP(hipMalloc(&w.ctr, sizeof(Counters)));
     AS_HIP(hipHostMalloc(&w.host_ctr, sizeof(Counters), hipHostMallocDefault));
     AS_HIP(hipMalloc(&w.subst, 32 * 32));
+    AS_HIP(hipMalloc(&w.qwords, 2 * 32 * sizeof(uint32_t)));
     for (auto &e : w.ev) AS_HIP(hipEventCreate(&e));
     w.device = dev;
   }
@@ -294,20 +393,29 @@ int status_to_code(int32_t st) {
   if (st & kStatusBadOffsets) return AS_ERR_OFFSETS;
   if (st & kStatusBadResidue) return AS_ERR_RESIDUE;
   if (st & kStatusRange) return AS_ERR_RANGE;
+  if (st & kStatusArg) return AS_ERR_ARG;
   return AS_OK;
 }
 
-}  // namespace
-}  // namespace asmi
+int read_counters(Workspace *w, hipStream_t stream, Counters *c) {
+  AS_HIP(hipMemcpyAsync(w->host_ctr, w->ctr, sizeof(Counters), hipMemcpyDeviceToHost, stream));
+  AS_HIP(hipStreamSynchronize(stream));
+  *c = *w->host_ctr;
+  return AS_OK;
+}
 
-using namespace asmi;
+float elapsed(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) ms = 0.f;
+  return ms;
+}
 
-extern "C" int as_align_batch(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t *seqs_b,
-                              const int64_t *offs_b, int64_t n_pairs, const as_scoring *scoring,
-                              int32_t mode, int32_t *scores_out, void *stream_ptr) {
-  if (!scoring || !offs_a || !offs_b || !seqs_a || !seqs_b || !scores_out || !scoring->subst)
-    return AS_ERR_NULL;
-  if (n_pairs < 0 || n_pairs >= ((int64_t)1 << 31) - 1) return AS_ERR_ARG;
+struct CallScoring {
+  int asz, alpha, beta, mode, smin, smax, smax_abs, allow16;
+};
+
+// Host-side checks of the scoring scheme; fills cs.
+int check_scoring(const as_scoring *scoring, int32_t mode, CallScoring *cs) {
   const int asz = scoring->alphabet_size;
   const int alpha = scoring->gap_open, beta = scoring->gap_extend;
   if (asz < 2 || asz > 32 || beta < 0 || alpha < beta || alpha > 10000 || mode < 0 || mode > 2)
@@ -317,68 +425,62 @@ extern "C" int as_align_batch(const uint8_t *seqs_a, const int64_t *offs_a, cons
     smin = scoring->subst[i] < smin ? scoring->subst[i] : smin;
     smax = scoring->subst[i] > smax ? scoring->subst[i] : smax;
   }
-  // The 32-bit kernel stores sigma + bias as int8 (bias = alpha + beta, or
+  // The 32-bit kernels store sigma + bias as int8 (bias = alpha + beta, or
   // alpha for local; padding columns store the bias itself).
   const int bias = (mode == kLocal) ? alpha : alpha + beta;
   if (smax + bias > 127 || smin + bias < -128 || bias > 127) return AS_ERR_SCORING;
-  if (n_pairs == 0) return AS_OK;
-  const int smax_abs = (smax > -smin) ? smax : -smin;
+  cs->asz = asz;
+  cs->alpha = alpha;
+  cs->beta = beta;
+  cs->mode = mode;
+  cs->smin = smin;
+  cs->smax = smax;
+  cs->smax_abs = (smax > -smin) ? smax : -smin;
   // The packed kernel keeps sigma + bias as unsigned bytes in registers, one
   // byte per letter of an alphabet of at most four.
-  const int allow16 = (asz <= 4 && smin + bias >= 0 && smax + bias <= 255) ? 1 : 0;
+  cs->allow16 = (asz <= 4 && smin + bias >= 0 && smax + bias <= 255) ? 1 : 0;
+  return AS_OK;
+}
 
-  std::lock_guard<std::mutex> guard(g_lock);
-  Workspace *w = nullptr;
-  int rc = get_workspace(&w);
-  if (rc) return rc;
-  hipStream_t stream = (hipStream_t)stream_ptr;
+RouteParams route_params(const CallScoring &cs, int64_t n_pairs) {
+  RouteParams rp;
+  rp.n_pairs = n_pairs;
+  rp.mode = cs.mode;
+  rp.alpha = cs.alpha;
+  rp.beta = cs.beta;
+  rp.smax_abs = cs.smax_abs;
+  rp.smax_pos = cs.smax > 0 ? cs.smax : 0;
+  rp.stripe_w = full_dp_i32_stripe_width();
+  rp.allow16 = cs.allow16;
+  rp.stripe_w16 = full_dp_i16_stripe_width();
+  rp.long_w = long_dp_i32_stripe_width();
+  rp.long_min_rows = 2048;
+  return rp;
+}
+
+int lists_capacity(Workspace *w, int64_t n_pairs) {
+  int rc;
   if ((rc = grow((void **)&w->items, &w->items_cap, n_pairs, sizeof(PairDesc)))) return rc;
   if ((rc = grow((void **)&w->items16, &w->items16_cap, n_pairs, sizeof(PairDesc)))) return rc;
   if ((rc = grow((void **)&w->rerun, &w->rerun_cap, n_pairs, sizeof(PairDesc)))) return rc;
   if ((rc = grow((void **)&w->items_long, &w->items_long_cap, n_pairs, sizeof(LongItem)))) return rc;
+  return AS_OK;
+}
 
-  AS_HIP(hipMemcpyAsync(w->subst, scoring->subst, (size_t)asz * asz, hipMemcpyHostToDevice, stream));
-  AS_HIP(hipMemsetAsync(w->ctr, 0, sizeof(Counters), stream));
-  const bool timing = g_timing;
-  memset(&g_last_timing, 0, sizeof(g_last_timing));
-  if (timing) AS_HIP(hipEventRecord(w->ev[0], stream));
-  const int stripe_w = full_dp_i32_stripe_width();
-  const int stripe_w16 = full_dp_i16_stripe_width();
-  {
-    ClassifyParams cp;
-    cp.offs_a = offs_a;
-    cp.offs_b = offs_b;
-    cp.n_pairs = n_pairs;
-    cp.mode = mode;
-    cp.alpha = alpha;
-    cp.beta = beta;
-    cp.smax_abs = smax_abs;
-    cp.smax_pos = smax > 0 ? smax : 0;
-    cp.stripe_w = stripe_w;
-    cp.allow16 = allow16;
-    cp.stripe_w16 = stripe_w16;
-    cp.long_w = long_dp_i32_stripe_width();
-    cp.long_min_rows = 2048;
-    int64_t blocks = (n_pairs + 1023) / 1024;
-    if (blocks > 1024) blocks = 1024;
-    hipLaunchKernelGGL(classify_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, cp, w->items,
-                       w->items16, w->items_long, w->ctr, scores_out);
-    AS_HIP(hipGetLastError());
+// Steps 3-4 for whatever the lists hold (counters c read after they were
+// filled): wavefront prefix, 16-bit, 32-bit and wavefront kernels, then the
+// 32-bit re-run of saturated 16-bit pairs.
+int run_full_lists(Workspace *w, const CallScoring &cs, const uint8_t *seqs_a,
+                   const uint8_t *seqs_b, int32_t *scores_out, hipStream_t stream, bool timing,
+                   Counters c) {
+  const int mode = cs.mode, asz = cs.asz;
+  int rc;
+  if (c.n_long > 0) {
     hipLaunchKernelGGL(long_prep_kernel, dim3(1), dim3(256), 0, stream, w->items_long, w->ctr,
-                       cp.long_w, mode, scores_out);
+                       long_dp_i32_stripe_width(), mode, scores_out);
     AS_HIP(hipGetLastError());
+    if ((rc = read_counters(w, stream, &c))) return rc;
   }
-  if (timing) AS_HIP(hipEventRecord(w->ev[1], stream));
-  AS_HIP(hipMemcpyAsync(w->host_ctr, w->ctr, sizeof(Counters), hipMemcpyDeviceToHost, stream));
-  AS_HIP(hipStreamSynchronize(stream));
-  const Counters c = *w->host_ctr;
-  g_last_timing.cells = (int64_t)c.cells;
-  g_last_timing.pairs_full32 = c.n_full32;
-  g_last_timing.pairs_full16 = c.n_full16;
-  if (timing) AS_HIP(hipEventElapsedTime(&g_last_timing.classify_ms, w->ev[0], w->ev[1]));
-  rc = status_to_code(c.status);
-  if (rc) return rc;
-
   if (c.n_full16 > 0) {
     const int bpc = full_dp_i16_blocks_per_cu(mode);
     int64_t grid = (int64_t)bpc * w->num_cu;
@@ -392,23 +494,22 @@ extern "C" int as_align_batch(const uint8_t *seqs_a, const int64_t *offs_a, cons
     a16.rerun = w->rerun;
     a16.subst = w->subst;
     a16.asz = asz;
-    a16.alpha = alpha;
-    a16.beta = beta;
+    a16.alpha = cs.alpha;
+    a16.beta = cs.beta;
     a16.sat_limit = g_i16_limit;
     a16.scores = scores_out;
     if (timing) AS_HIP(hipEventRecord(w->ev[2], stream));
     AS_HIP(launch_full_dp_i16(mode, a16, (int)grid, stream));
     if (timing) AS_HIP(hipEventRecord(w->ev[3], stream));
   }
-
   FullDpArgs args;
   args.seqs_a = seqs_a;
   args.seqs_b = seqs_b;
   args.ctr = w->ctr;
   args.subst = w->subst;
   args.asz = asz;
-  args.alpha = alpha;
-  args.beta = beta;
+  args.alpha = cs.alpha;
+  args.beta = cs.beta;
   args.scores = scores_out;
   if (c.n_full32 > 0) {
     const int bpc = full_dp_i32_blocks_per_cu(mode, asz);
@@ -416,8 +517,8 @@ extern "C" int as_align_batch(const uint8_t *seqs_a, const int64_t *offs_a, cons
     const int64_t need_waves = ((int64_t)c.n_full32 + kGroupsPerWave - 1) / kGroupsPerWave;
     if (grid > need_waves) grid = need_waves;
     const int64_t bnd_rows = c.max_rows_multi > 0 ? (int64_t)c.max_rows_multi + 1 : 1;
-    rc = grow((void **)&w->bnd, &w->bnd_cap, grid * kGroupsPerWave * 2 * bnd_rows, sizeof(int2));
-    if (rc) return rc;
+    if ((rc = grow((void **)&w->bnd, &w->bnd_cap, grid * kGroupsPerWave * 2 * bnd_rows, sizeof(int2))))
+      return rc;
     args.items = w->items;
     args.n_items = &w->ctr->n_full32;
     args.next = &w->ctr->next_full32;
@@ -443,8 +544,8 @@ extern "C" int as_align_batch(const uint8_t *seqs_a, const int64_t *offs_a, cons
     la.ctr = w->ctr;
     la.subst = w->subst;
     la.asz = asz;
-    la.alpha = alpha;
-    la.beta = beta;
+    la.alpha = cs.alpha;
+    la.beta = cs.beta;
     la.scores = scores_out;
     la.bnd = w->bnd_long;
     la.flags = w->flags;
@@ -452,21 +553,18 @@ extern "C" int as_align_batch(const uint8_t *seqs_a, const int64_t *offs_a, cons
     AS_HIP(launch_long_dp_i32(mode, la, (int)grid, stream));
     if (timing) AS_HIP(hipEventRecord(w->ev[9], stream));
   }
-  AS_HIP(hipMemcpyAsync(w->host_ctr, w->ctr, sizeof(Counters), hipMemcpyDeviceToHost, stream));
-  AS_HIP(hipStreamSynchronize(stream));
-  const Counters c2 = *w->host_ctr;
-  g_last_timing.pairs_long = c.n_long;
-  if (timing && c.n_long > 0)
-    AS_HIP(hipEventElapsedTime(&g_last_timing.long_ms, w->ev[8], w->ev[9]));
-  if (timing && c.n_full16 > 0)
-    AS_HIP(hipEventElapsedTime(&g_last_timing.full16_ms, w->ev[2], w->ev[3]));
-  if (timing && c.n_full32 > 0)
-    AS_HIP(hipEventElapsedTime(&g_last_timing.full32_ms, w->ev[4], w->ev[5]));
-  rc = status_to_code(c2.status);
-  if (rc) return rc;
+  Counters c2;
+  if ((rc = read_counters(w, stream, &c2))) return rc;
+  g_last_timing.pairs_full32 += c.n_full32;
+  g_last_timing.pairs_full16 += c.n_full16;
+  g_last_timing.pairs_long += c.n_long;
+  if (timing && c.n_full16 > 0) g_last_timing.full16_ms += elapsed(w->ev[2], w->ev[3]);
+  if (timing && c.n_full32 > 0) g_last_timing.full32_ms += elapsed(w->ev[4], w->ev[5]);
+  if (timing && c.n_long > 0) g_last_timing.long_ms += elapsed(w->ev[8], w->ev[9]);
+  if ((rc = status_to_code(c2.status))) return rc;
 
   // 32-bit re-run of the 16-bit pairs whose maximum saturated
-  g_last_timing.pairs_rerun32 = c2.n_rerun32;
+  g_last_timing.pairs_rerun32 += c2.n_rerun32;
   if (c2.n_rerun32 > 0) {
     const int bpc = full_dp_i32_blocks_per_cu(mode, asz);
     int64_t grid = (int64_t)bpc * w->num_cu;
@@ -482,11 +580,243 @@ extern "C" int as_align_batch(const uint8_t *seqs_a, const int64_t *offs_a, cons
     if (timing) AS_HIP(hipEventRecord(w->ev[6], stream));
     AS_HIP(launch_full_dp_i32(mode, args, (int)grid, stream));
     if (timing) AS_HIP(hipEventRecord(w->ev[7], stream));
-    AS_HIP(hipMemcpyAsync(w->host_ctr, w->ctr, sizeof(Counters), hipMemcpyDeviceToHost, stream));
-    AS_HIP(hipStreamSynchronize(stream));
-    if (timing) AS_HIP(hipEventElapsedTime(&g_last_timing.rerun32_ms, w->ev[6], w->ev[7]));
-    rc = status_to_code(w->host_ctr->status);
-    if (rc) return rc;
+    Counters c3;
+    if ((rc = read_counters(w, stream, &c3))) return rc;
+    if (timing) g_last_timing.rerun32_ms += elapsed(w->ev[6], w->ev[7]);
+    if ((rc = status_to_code(c3.status))) return rc;
+  }
+  return AS_OK;
+}
+
+int classify_blocks(int64_t n) {
+  int64_t blocks = (n + 1023) / 1024;
+  if (blocks > 1024) blocks = 1024;
+  return blocks < 1 ? 1 : (int)blocks;
+}
+
+// Score words of the banded kernel: byte c of word r is sigma(r, c) + alpha +
+// beta with rows from A (table 0) or from B (table 1).
+int upload_qwords(Workspace *w, const as_scoring *scoring, const CallScoring &cs, hipStream_t stream,
+                  uint32_t *host_words) {
+  for (int t = 0; t < 2; ++t)
+    for (int r = 0; r < 32; ++r) {
+      uint32_t word = 0;
+      if (r < cs.asz)
+        for (int c = 0; c < cs.asz; ++c) {
+          const int sv = t == 0 ? scoring->subst[r * cs.asz + c] : scoring->subst[c * cs.asz + r];
+          word |= (uint32_t)((sv + cs.alpha + cs.beta) & 0xFF) << (8 * c);
+        }
+      host_words[t * 32 + r] = word;
+    }
+  AS_HIP(hipMemcpyAsync(w->qwords, host_words, 64 * sizeof(uint32_t), hipMemcpyHostToDevice, stream));
+  AS_HIP(hipStreamSynchronize(stream));  // host_words lives on the caller's stack
+  return AS_OK;
+}
+
+// Checks of the banded path on top of check_scoring.
+int check_band_scoring(const CallScoring &cs) {
+  if (cs.mode == kLocal) return AS_ERR_ARG;
+  // one byte per letter, four letters, unsigned
+  if (cs.asz > 4 || cs.smin + cs.alpha + cs.beta < 0 || cs.smax + cs.alpha + cs.beta > 255 ||
+      cs.alpha + cs.beta > 255)
+    return AS_ERR_SCORING;
+  return AS_OK;
+}
+
+}  // namespace
+}  // namespace asmi
+
+using namespace asmi;
+
+extern "C" int as_align_batch(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t *seqs_b,
+                              const int64_t *offs_b, int64_t n_pairs, const as_scoring *scoring,
+                              int32_t mode, int32_t *scores_out, void *stream_ptr) {
+  if (!scoring || !offs_a || !offs_b || !seqs_a || !seqs_b || !scores_out || !scoring->subst)
+    return AS_ERR_NULL;
+  if (n_pairs < 0 || n_pairs >= ((int64_t)1 << 31) - 1) return AS_ERR_ARG;
+  CallScoring cs;
+  int rc = check_scoring(scoring, mode, &cs);
+  if (rc) return rc;
+  if (n_pairs == 0) return AS_OK;
+
+  std::lock_guard<std::mutex> guard(g_lock);
+  Workspace *w = nullptr;
+  if ((rc = get_workspace(&w))) return rc;
+  hipStream_t stream = (hipStream_t)stream_ptr;
+  if ((rc = lists_capacity(w, n_pairs))) return rc;
+
+  AS_HIP(hipMemcpyAsync(w->subst, scoring->subst, (size_t)cs.asz * cs.asz, hipMemcpyHostToDevice, stream));
+  AS_HIP(hipMemsetAsync(w->ctr, 0, sizeof(Counters), stream));
+  const bool timing = g_timing;
+  memset(&g_last_timing, 0, sizeof(g_last_timing));
+  if (timing) AS_HIP(hipEventRecord(w->ev[0], stream));
+  const RouteParams rp = route_params(cs, n_pairs);
+  hipLaunchKernelGGL(classify_kernel, dim3(classify_blocks(n_pairs)), dim3(256), 0, stream, rp, offs_a,
+                     offs_b, w->items, w->items16, w->items_long, w->ctr, scores_out);
+  AS_HIP(hipGetLastError());
+  if (timing) AS_HIP(hipEventRecord(w->ev[1], stream));
+  Counters c;
+  if ((rc = read_counters(w, stream, &c))) return rc;
+  g_last_timing.cells = (int64_t)c.cells;
+  if (timing) g_last_timing.classify_ms = elapsed(w->ev[0], w->ev[1]);
+  if ((rc = status_to_code(c.status))) return rc;
+  return run_full_lists(w, cs, seqs_a, seqs_b, scores_out, stream, timing, c);
+}
+
+// Banded entry points share everything up to the rounds.
+static int band_call(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t *seqs_b,
+                     const int64_t *offs_b, int64_t n_pairs, const as_scoring *scoring, int32_t mode,
+                     const int32_t *band_w, int32_t max_rounds, int32_t raw, int32_t *scores_out,
+                     int32_t *lo_out, int32_t *hi_out, as_band_stats *stats, void *stream_ptr) {
+  if (!scoring || !offs_a || !offs_b || !seqs_a || !seqs_b || !scores_out || !scoring->subst || !band_w)
+    return AS_ERR_NULL;
+  if ((lo_out == nullptr) != (hi_out == nullptr)) return AS_ERR_NULL;
+  if (n_pairs < 0 || n_pairs >= ((int64_t)1 << 31) - 1) return AS_ERR_ARG;
+  if (!raw && (max_rounds < 1 || max_rounds > kMaxBandRounds)) return AS_ERR_ARG;
+  CallScoring cs;
+  int rc = check_scoring(scoring, mode, &cs);
+  if (rc) return rc;
+  if ((rc = check_band_scoring(cs))) return rc;
+  if (stats) memset(stats, 0, sizeof(*stats));
+  if (n_pairs == 0) return AS_OK;
+
+  std::lock_guard<std::mutex> guard(g_lock);
+  Workspace *w = nullptr;
+  if ((rc = get_workspace(&w))) return rc;
+  hipStream_t stream = (hipStream_t)stream_ptr;
+  if ((rc = lists_capacity(w, n_pairs))) return rc;
+  if ((rc = grow((void **)&w->band_lists, &w->band_cap, 2 * kBandClasses * n_pairs, sizeof(BandItem))))
+    return rc;
+  const int64_t list_cap = w->band_cap / (2 * kBandClasses);
+  if ((rc = grow((void **)&w->fallback, &w->fallback_cap, n_pairs, sizeof(PairDesc)))) return rc;
+  uint32_t host_words[64];
+  AS_HIP(hipMemcpyAsync(w->subst, scoring->subst, (size_t)cs.asz * cs.asz, hipMemcpyHostToDevice, stream));
+  if ((rc = upload_qwords(w, scoring, cs, stream, host_words))) return rc;
+  AS_HIP(hipMemsetAsync(w->ctr, 0, sizeof(Counters), stream));
+  const bool timing = g_timing;
+  memset(&g_last_timing, 0, sizeof(g_last_timing));
+  if (timing) AS_HIP(hipEventRecord(w->ev[0], stream));
+  const RouteParams rp = route_params(cs, n_pairs);
+  hipLaunchKernelGGL(band_classify_kernel, dim3(classify_blocks(n_pairs)), dim3(256), 0, stream, rp,
+                     offs_a, offs_b, band_w, raw, w->band_lists, list_cap, w->fallback, w->ctr,
+                     scores_out);
+  AS_HIP(hipGetLastError());
+  if (timing) AS_HIP(hipEventRecord(w->ev[1], stream));
+  Counters c;
+  if ((rc = read_counters(w, stream, &c))) return rc;
+  g_last_timing.cells = (int64_t)c.cells;
+  if (timing) g_last_timing.classify_ms = elapsed(w->ev[0], w->ev[1]);
+  if ((rc = status_to_code(c.status))) return rc;
+
+  BandArgs ba;
+  ba.seqs_a = seqs_a;
+  ba.seqs_b = seqs_b;
+  ba.lists = w->band_lists;
+  ba.list_cap = list_cap;
+  ba.ctr = w->ctr;
+  ba.qwords = w->qwords;
+  ba.asz = cs.asz;
+  ba.alpha = cs.alpha;
+  ba.beta = cs.beta;
+  ba.sigma_max = cs.smax;
+  ba.max_rounds = raw ? 1 : max_rounds;
+  ba.raw = raw;
+  ba.scores = scores_out;
+  ba.lo_out = lo_out;
+  ba.hi_out = hi_out;
+  ba.fallback = w->fallback;
+  int rounds = 0;
+  float band_ms = 0.f;
+  for (int r = 0; r < ba.max_rounds; ++r) {
+    const int cur = r & 1;
+    int any = 0;
+    for (int kc = 0; kc < kBandClasses; ++kc) any += c.n_band[cur][kc];
+    if (!any) break;
+    ba.round = r;
+    if (timing) AS_HIP(hipEventRecord(w->ev[10], stream));
+    for (int kc = 0; kc < kBandClasses; ++kc) {
+      const int cnt = c.n_band[cur][kc];
+      if (!cnt) continue;
+      int64_t grid = (int64_t)band_dp_i32_blocks_per_cu(mode, kc) * w->num_cu;
+      const int64_t need = ((int64_t)cnt + kGroupsPerWave - 1) / kGroupsPerWave;
+      if (grid > need) grid = need;
+      AS_HIP(launch_band_dp_i32(mode, kc, ba, (int)grid, stream));
+    }
+    if (timing) AS_HIP(hipEventRecord(w->ev[11], stream));
+    // this round's lists are consumed: clear their counters and work pointers
+    AS_HIP(hipMemsetAsync(&w->ctr->n_band[cur][0], 0, sizeof(int32_t) * kBandClasses, stream));
+    AS_HIP(hipMemsetAsync(&w->ctr->next_band[0], 0, sizeof(int32_t) * kBandClasses, stream));
+    if ((rc = read_counters(w, stream, &c))) return rc;
+    if (timing) band_ms += elapsed(w->ev[10], w->ev[11]);
+    if ((rc = status_to_code(c.status))) return rc;
+    rounds = r + 1;
+  }
+  g_last_timing.band_ms = band_ms;
+  g_last_timing.pairs_fallback = c.n_fallback;
+  if (stats) {
+    stats->rounds = rounds;
+    for (int r = 0; r < kMaxBandRounds; ++r) stats->accepted[r] = c.band_accepted[r];
+    stats->fallback = c.n_fallback;
+    stats->band_cells = (int64_t)c.band_cells;
+    stats->cells = (int64_t)c.cells;
+  }
+  if (raw || c.n_fallback == 0) return AS_OK;
+
+  // full DP for the fallback pairs
+  hipLaunchKernelGGL(route_fallback_kernel, dim3(classify_blocks(c.n_fallback)), dim3(256), 0, stream,
+                     rp, w->fallback, w->items, w->items16, w->items_long, w->ctr);
+  AS_HIP(hipGetLastError());
+  if ((rc = read_counters(w, stream, &c))) return rc;
+  if ((rc = status_to_code(c.status))) return rc;
+  return run_full_lists(w, cs, seqs_a, seqs_b, scores_out, stream, timing, c);
+}
+
+extern "C" int as_align_batch_band(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t *seqs_b,
+                                   const int64_t *offs_b, int64_t n_pairs, const as_scoring *scoring,
+                                   int32_t mode, const int32_t *band_w0, int32_t max_rounds,
+                                   int32_t *scores_out, as_band_stats *stats, void *stream) {
+  return band_call(seqs_a, offs_a, seqs_b, offs_b, n_pairs, scoring, mode, band_w0, max_rounds, 0,
+                   scores_out, nullptr, nullptr, stats, stream);
+}
+
+extern "C" int as_band_scores(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t *seqs_b,
+                              const int64_t *offs_b, int64_t n_pairs, const as_scoring *scoring,
+                              int32_t mode, const int32_t *band_w, int32_t *scores_out,
+                              int32_t *lo_out, int32_t *hi_out, void *stream) {
+  return band_call(seqs_a, offs_a, seqs_b, offs_b, n_pairs, scoring, mode, band_w, 1, 1, scores_out,
+                   lo_out, hi_out, nullptr, stream);
+}
+
+extern "C" const char *as_strerror(int code) {
+  switch (code) {
+    case AS_OK: return "success";
+    case AS_ERR_NULL: return "a required pointer is NULL";
+    case AS_ERR_OFFSETS: return "offsets decrease or are negative";
+    case AS_ERR_RESIDUE: return "a residue code is >= alphabet_size";
+    case AS_ERR_SCORING: return "invalid scoring (alphabet size, alpha, beta, mode or sigma range)";
+    case AS_ERR_RANGE: return "a score could leave the 32-bit range";
+    case AS_ERR_HIP: return "a HIP runtime call failed or a device-side wait stalled";
+    case AS_ERR_ARG: return "an argument is out of range";
+    default: return "unknown error";
+  }
+}
+
+extern "C" int as_release_workspace(void) {
+  std::lock_guard<std::mutex> guard(g_lock);
+  for (Workspace &w : g_ws) {
+    if (w.device < 0) continue;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(w.device);
+    void *bufs[] = {w.items, w.items16, w.rerun, w.items_long, w.bnd_long, w.flags, w.band_lists,
+                    w.fallback, w.qwords, w.ctr, w.subst, w.bnd};
+    for (void *b : bufs)
+      if (b) (void)hipFree(b);
+    if (w.host_ctr) (void)hipHostFree(w.host_ctr);
+    for (auto &e : w.ev)
+      if (e) (void)hipEventDestroy(e);
+    (void)hipSetDevice(cur);
+    w = Workspace();
   }
   return AS_OK;
 }
@@ -512,45 +842,9 @@ extern "C" int as_last_timing(as_timing *out) {
   return AS_OK;
 }
 
-extern "C" const char *as_strerror(int code) {
-  switch (code) {
-    case AS_OK: return "success";
-    case AS_ERR_NULL: return "a required pointer is NULL";
-    case AS_ERR_OFFSETS: return "offsets decrease or are negative";
-    case AS_ERR_RESIDUE: return "a residue code is >= alphabet_size";
-    case AS_ERR_SCORING: return "invalid scoring (alphabet size, alpha, beta, mode or sigma range)";
-    case AS_ERR_RANGE: return "a score could leave the 32-bit range";
-    case AS_ERR_HIP: return "a HIP runtime call failed";
-    case AS_ERR_ARG: return "an argument is out of range";
-    default: return "unknown error";
-  }
-}
-
-extern "C" int as_release_workspace(void) {
-  std::lock_guard<std::mutex> guard(g_lock);
-  for (Workspace &w : g_ws) {
-    if (w.device < 0) continue;
-    int cur = 0;
-    (void)hipGetDevice(&cur);
-    (void)hipSetDevice(w.device);
-    if (w.items) (void)hipFree(w.items);
-    if (w.items16) (void)hipFree(w.items16);
-    if (w.rerun) (void)hipFree(w.rerun);
-    if (w.items_long) (void)hipFree(w.items_long);
-    if (w.bnd_long) (void)hipFree(w.bnd_long);
-    if (w.flags) (void)hipFree(w.flags);
-    if (w.ctr) (void)hipFree(w.ctr);
-    if (w.host_ctr) (void)hipHostFree(w.host_ctr);
-    if (w.subst) (void)hipFree(w.subst);
-    if (w.bnd) (void)hipFree(w.bnd);
-    for (auto &e : w.ev) if (e) (void)hipEventDestroy(e);
-    (void)hipSetDevice(cur);
-    w = Workspace();
-  }
-  return AS_OK;
-}
-
 extern "C" const char *as_build_info(void) {
   return "anyseq_mi gfx950: full DP int32 (16-lane DPP groups, K=16, int8 LDS profile); "
-         "full DP packed int16x2 (2 pairs per group, K=16, v_perm register profile, alphabet <= 4)";
+         "full DP packed int16x2 (2 pairs per group, K=16, v_perm register profile, alphabet <= 4); "
+         "long-pair wavefront int32 (wave64 pipelines, 1024-column stripes); "
+         "banded int32 (sheared band, K=4..64, v_perm scores, certificate + doubling)";
 }

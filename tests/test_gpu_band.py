@@ -1,0 +1,121 @@
+"""GPU parity of the banded path: raw banded scores against the oracle's DP
+restricted to the same diagonals (the limits the kernel reports), and the
+certified path's final scores against the oracle's full DP."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2205_07610_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+DNA = synth.dna_subst()
+
+
+def _say(msg):
+    print(f"[band] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2205_07610_amd import binding
+    binding.lib()
+    return binding
+
+
+def _dev(b):
+    from paper_2205_07610_amd import binding
+    return binding.to_device(b)
+
+
+def _w(torch, w):
+    return torch.as_tensor(np.asarray(w, dtype=np.int32)).to("cuda")
+
+
+def _pairs_mixed(rng, n_pairs, max_len, related=0.7):
+    sa, oa, sb, ob = synth.random_small(rng, n_pairs, max_len, related=related)
+    return sa, oa, sb, ob
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_raw_band_scores_match_oracle(gpu, oracle_mod, mode):
+    import torch
+    rng = np.random.default_rng(700 + mode)
+    sa, oa, sb, ob = _pairs_mixed(rng, 1500, 700)
+    b = synth.Batch("band raw", sa, oa, sb, ob, DNA, 5, 2, mode)
+    m, n = b.lens_a, b.lens_b
+    # half-widths of every class, kept within the widest band (1024 diagonals)
+    w = rng.integers(0, 60, size=b.n_pairs)
+    w[::7] = 0
+    w[::11] = rng.integers(100, 300, size=len(w[::11]))
+    w = np.minimum(w, np.maximum(0, (1024 - 1 - np.abs(n - m)) // 2))
+    keep = np.abs(n - m) + 2 * w + 1 <= 1024
+    b = b.subset(np.nonzero(keep)[0])
+    w = w[keep]
+    _say(f"raw mode {mode}: {b.n_pairs} pairs")
+    got, lo, hi = gpu.band_scores(*_dev(b), b.subst, b.alpha, b.beta, b.mode, _w(torch, w))
+    got, lo, hi = got.cpu().numpy(), lo.cpu().numpy(), hi.cpu().numpy()
+    ne = (b.lens_a > 0) & (b.lens_b > 0)
+    # every computed band contains the requested one and is at most 1024 wide
+    L = np.minimum(0, b.lens_b - b.lens_a) - w
+    U = np.maximum(0, b.lens_b - b.lens_a) + w
+    assert np.all(lo[ne] <= L[ne]) and np.all(hi[ne] >= U[ne]) and np.all(hi[ne] - lo[ne] < 1024)
+    idx = np.nonzero(ne)[0]
+    sub = b.subset(idx)
+    want = oracle_mod.diag_band_batch(sub.seqs_a, sub.offs_a, sub.seqs_b, sub.offs_b, sub.subst,
+                                      sub.alpha, sub.beta, sub.mode, lo[idx], hi[idx])
+    bad = np.nonzero(got[idx].astype(np.int64) != want)[0]
+    assert len(bad) == 0, (f"{len(bad)} mismatches, first pair {idx[bad[0]]}: gpu {got[idx[bad[0]]]} "
+                           f"oracle {want[bad[0]]} m={sub.lens_a[bad[0]]} n={sub.lens_b[bad[0]]} "
+                           f"lo={lo[idx[bad[0]]]} hi={hi[idx[bad[0]]]}")
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("w0,rounds", [(0, 6), (8, 6), (40, 1), (3, 2)])
+def test_certified_band_equals_full(gpu, oracle_mod, mode, w0, rounds):
+    import torch
+    rng = np.random.default_rng(800 + 10 * mode + w0 + rounds)
+    b = synth.config4(n_pairs=150, seed=int(rng.integers(1 << 30)))
+    b.mode = mode
+    extra = synth.random_small(rng, 300, 400, related=0.8)
+    b2 = synth.Batch("mixed", *extra, DNA, 5, 2, mode)
+    idx_all = [b, b2]
+    pairs = []
+    for bb in idx_all:
+        for p in range(bb.n_pairs):
+            pairs.append(bb.pair(p))
+    batch = synth.from_pairs("band cert", pairs, DNA, 5, 2, mode)
+    _say(f"certified mode {mode} w0={w0} rounds={rounds}: {batch.n_pairs} pairs")
+    got, stats = gpu.align_batch_band(*_dev(batch), batch.subst, batch.alpha, batch.beta,
+                                      batch.mode, _w(torch, np.full(batch.n_pairs, w0)),
+                                      max_rounds=rounds)
+    want = oracle_mod.align_batch(batch.seqs_a, batch.offs_a, batch.seqs_b, batch.offs_b,
+                                  batch.subst, batch.alpha, batch.beta, batch.mode)
+    got = got.cpu().numpy().astype(np.int64)
+    bad = np.nonzero(got != want)[0]
+    assert len(bad) == 0, f"{len(bad)} mismatches, first {bad[0]}: {got[bad[0]]} vs {want[bad[0]]}"
+    nonempty = int(np.count_nonzero((batch.lens_a > 0) & (batch.lens_b > 0)))
+    assert sum(stats["accepted"]) + stats["fallback"] == nonempty
+    _say(f"  stats {stats}")
+
+
+def test_band_api_errors(gpu):
+    import torch
+    from paper_2205_07610_amd.binding import AlignError
+    b = synth.config0(n_pairs=10)
+    with pytest.raises(AlignError) as e:                 # local mode has no band path
+        gpu.align_batch_band(*_dev(b), b.subst, 5, 2, 2, _w(torch, np.zeros(10)))
+    assert e.value.code == -7
+    with pytest.raises(AlignError) as e:                 # band wider than 1024 diagonals
+        gpu.band_scores(*_dev(b), b.subst, 5, 2, 0, _w(torch, np.full(10, 600)))
+    assert e.value.code == -7
+    prot = synth.protein_subst(np.random.default_rng(1))
+    pb = synth.config3(n_pairs=4, n_long=0)
+    with pytest.raises(AlignError) as e:                 # 20-letter alphabet
+        gpu.align_batch_band(*_dev(pb), prot, 11, 1, 0, _w(torch, np.zeros(4)))
+    assert e.value.code == -4

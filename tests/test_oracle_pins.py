@@ -318,3 +318,33 @@ def test_band_widths(oracle_mod):
             assert oracle_mod.banded_pair(a, b, DNA, 5, 2, md, we) == full
             if we > 0:
                 assert oracle_mod.banded_pair(a, b, DNA, 5, 2, md, we - 1) < full
+
+
+def test_diag_band_matches_w_band_and_brute(oracle_mod):
+    """Explicit diagonal limits reproduce the half-width band and brute force
+    restricted to those diagonals (asymmetric limits included)."""
+    from oracle import band
+    rng = np.random.default_rng(61)
+    for _ in range(60):
+        sub, alpha, beta = _random_scoring(rng, 3)
+        q = rng.integers(0, 3, size=int(rng.integers(0, 6))).tolist()
+        s = rng.integers(0, 3, size=int(rng.integers(0, 6))).tolist()
+        m, n = len(q), len(s)
+        for mode in (GLOBAL, SEMIGLOBAL):
+            w = int(rng.integers(0, 3))
+            lo, hi = band.band_limits(m, n, w)
+            assert (oracle_mod.diag_band_pair(q, s, sub, alpha, beta, mode, lo, hi)
+                    == oracle_mod.banded_pair(q, s, sub, alpha, beta, mode, w))
+            hi2 = hi + int(rng.integers(0, 4))
+            lo2 = lo - int(rng.integers(0, 4))
+            want = brute.SCORERS[mode](q, s, sub, alpha, beta,
+                                       cell_ok=lambda i, j: lo2 <= j - i <= hi2)
+            got = oracle_mod.diag_band_pair(q, s, sub, alpha, beta, mode, lo2, hi2)
+            assert got == want or (want == float("-inf") and got <= -(1 << 59))
+            ub = band.ub_outside_diag(m, n, lo2, hi2, int(sub.max()), alpha, beta, mode)
+            out = brute.SCORERS[mode](q, s, sub, alpha, beta,
+                                      cell_ok=lambda i, j: lo2 <= j - i <= hi2, escape=True)
+            if ub is None:
+                assert out == float("-inf")
+            else:
+                assert out <= ub
