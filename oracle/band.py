@@ -110,3 +110,20 @@ def exact_width(q, s, subst, alpha, beta, mode) -> int:
         else:
             lo = mid
     return hi
+
+
+# Widest band the banded kernels compute (in diagonals); a pair whose
+# accepted band would be wider gets this value as its label.
+MAX_BAND = 1024
+
+
+def band_label(q, s, subst, alpha, beta, mode, max_band: int = MAX_BAND) -> int:
+    """Training label of a pair: the smallest accepted half-width w when its
+    band (|n - m| + 2w + 1 diagonals) fits in max_band diagonals, else
+    max_band (an ordinal 'wider than any band' value)."""
+    m, n = len(q), len(s)
+    w_cap = (max_band - 1 - abs(n - m)) // 2
+    if w_cap < 0:
+        return max_band
+    wa = accepted_width(q, s, subst, alpha, beta, mode)
+    return wa if wa <= w_cap else max_band
