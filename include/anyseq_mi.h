@@ -107,7 +107,8 @@ typedef struct {
     float rerun32_ms;   /* 32-bit re-run of saturated 16-bit pairs */
     float long_ms;      /* multi-wave wavefront for long pairs, 32-bit cells */
     float band_ms;      /* banded rounds (as_align_batch_band) */
-    float reserved_ms[2];
+    float features_ms;  /* k-mer features (as_align_batch_learned) */
+    float mlp_ms;       /* band network inference (as_align_batch_learned) */
     int64_t pairs_full32;
     int64_t pairs_full16;
     int64_t pairs_rerun32;
@@ -140,6 +141,7 @@ typedef struct {
     int64_t fallback;      /* pairs aligned with the full DP */
     int64_t band_cells;    /* DP cells computed by the banded kernel */
     int64_t cells;         /* sum of m*n over the batch */
+    int64_t fallback_cells; /* sum of m*n over the pairs aligned with the full DP */
 } as_band_stats;
 
 int as_align_batch_band(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t *seqs_b,
@@ -158,6 +160,114 @@ int as_band_scores(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t *
                    const int64_t *offs_b, int64_t n_pairs, const as_scoring *scoring, int32_t mode,
                    const int32_t *band_w, int32_t *scores_out, int32_t *lo_out, int32_t *hi_out,
                    void *stream);
+
+/*
+ * Certified score of one exact band: the optimal score of pair p restricted
+ * to the diagonals min(0, n-m) - w <= j - i <= max(0, n-m) + w themselves,
+ * w = band_w[p] (no widening; |n - m| + 2w + 1 <= 1024 or AS_ERR_ARG), and
+ * accept_out[p] = 1 when that score is at least the upper bound on every
+ * path leaving those diagonals (then it is the optimal score), else 0.
+ * A pair with band_w[p] < 0 is skipped: its outputs are left unchanged.
+ * Pairs with an empty sequence are scored by their closed form and their
+ * accept_out entry is left unchanged.
+ *   band_w, scores_out, accept_out : device, int32 [n_pairs]
+ * Same modes, alphabets and errors as as_align_batch_band.
+ */
+int as_band_certify(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t *seqs_b,
+                    const int64_t *offs_b, int64_t n_pairs, const as_scoring *scoring, int32_t mode,
+                    const int32_t *band_w, int32_t *scores_out, int32_t *accept_out, void *stream);
+
+/*
+ * Learned band (the learned-band extension; not in the paper).  A small
+ * network reads cheap per-pair features and predicts the initial half-width
+ * of the certified banded path above, so every score stays exact whatever it
+ * predicts; a good prediction only saves work.
+ *
+ * Network: 32 -> 64 -> 64 -> 1 with ReLU, y = log2(w + 1), float32
+ * parameters in one device array of AS_MLP_PARAMS floats laid out as
+ *   w1[32][64] (input-major), b1[64], w2[64][64], b2[64], w3[64], b3[1].
+ * Products run on the matrix cores with operands rounded to bfloat16
+ * (nearest even) and float32 accumulation; biases, ReLU, loss and optimiser
+ * are float32.  The predicted half-width is ceil(2^y - 1) clamped to
+ * [0, 2^20].
+ */
+#define AS_FEATURES 32
+#define AS_MLP_PARAMS 6337
+#define AS_BAND_WIDE 1024 /* label: no band of at most 1024 diagonals is accepted */
+
+/*
+ * Features of every pair (residues 0..3 only, else AS_ERR_RESIDUE):
+ * 7-mers of A are looked up among the 7-mers of B that occur exactly once
+ * (and start before position 65535); each hit at (i, j) adds one to signed
+ * log2 bin b = min(14, floor(log2(1 + |d|))) of d = (j - i) -
+ * trunc(i (n - m) / m): bin 15 + b for d >= 0, 14 - b otherwise.
+ *   features_out[p][0..29] = bin counts / max(1, hits)
+ *   features_out[p][30]    = log2(1 + |n - m|) / 16
+ *   features_out[p][31]    = hits / max(1, m - 6)
+ * features_out: device float [n_pairs][32], 16-byte aligned.
+ */
+int as_pair_features(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t *seqs_b,
+                     const int64_t *offs_b, int64_t n_pairs, float *features_out, void *stream);
+
+/*
+ * Network inference: band_w_out[p] = ceil(2^y_p - 1) clamped to [0, 2^20];
+ * y_out (optional, NULL) receives y_p.  params, features (16-byte aligned),
+ * band_w_out, y_out: device.
+ */
+int as_band_predict(const float *params, const float *features, int64_t n, int32_t *band_w_out,
+                    float *y_out, void *stream);
+
+/*
+ * Band labels from the full DP: label_p is the smallest w >= 0 whose exact
+ * band (as in as_band_certify) is accepted, when |n - m| + 2w + 1 <= 1024;
+ * otherwise AS_BAND_WIDE.  The full-DP score S gives the search its lower
+ * end (no band below the smallest w whose leave bound is <= S can be
+ * accepted); exact bands are then tried with doubling and bisection.
+ * Pairs with an empty sequence get 0.  Global and semi-global only.
+ *   labels_out : device int32 [n_pairs]
+ */
+int as_band_labels(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t *seqs_b,
+                   const int64_t *offs_b, int64_t n_pairs, const as_scoring *scoring, int32_t mode,
+                   int32_t *labels_out, void *stream);
+
+/*
+ * Adam training of the network, n_steps minibatches of `batch` samples:
+ * step s uses samples order[s * batch .. s * batch + batch - 1] (indices
+ * into features/labels, 0 <= index < n), target log2(label + 1), pinball
+ * loss with quantile tau (0 < tau < 1), averaged over the minibatch, and
+ * Adam (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) with step
+ * counter t0 + s for the bias corrections.
+ *   params, adam_m, adam_v : device float [AS_MLP_PARAMS], updated in place
+ *                            (adam_m, adam_v zero before the first step)
+ *   features : device float [n][32] (16-byte aligned); labels : device int32 [n] (>= 0)
+ *   order    : device int32 [n_steps * batch]
+ *   grads_out: optional device float [AS_MLP_PARAMS]: the first step's gradient
+ * Out-of-range indices or negative labels return AS_ERR_ARG before any step.
+ */
+int as_band_train(float *params, float *adam_m, float *adam_v, const float *features,
+                  const int32_t *labels, int64_t n, const int32_t *order, int32_t n_steps,
+                  int32_t batch, int32_t t0, float lr, float tau, float *grads_out, void *stream);
+
+/*
+ * Features, labels and training in one call: params (device, AS_MLP_PARAMS
+ * floats) hold the initial weights on entry and the trained ones on return;
+ * order as in as_band_train (indices into this batch of pairs).
+ */
+int as_train_band_model(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t *seqs_b,
+                        const int64_t *offs_b, int64_t n_pairs, const as_scoring *scoring,
+                        int32_t mode, float *params, const int32_t *order, int32_t n_steps,
+                        int32_t batch, float lr, float tau, void *stream);
+
+/*
+ * Learned-band alignment: features, network inference, then
+ * as_align_batch_band with the predicted half-widths.  Every score is exact.
+ * Same modes, alphabets and errors as as_align_batch_band, plus residues
+ * above 3 (AS_ERR_RESIDUE).
+ */
+int as_align_batch_learned(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t *seqs_b,
+                           const int64_t *offs_b, int64_t n_pairs, const as_scoring *scoring,
+                           int32_t mode, const float *params, int32_t max_rounds,
+                           int32_t *scores_out, as_band_stats *stats, void *stream);
 
 /*
  * Saturation threshold of the packed 16-bit local path: a pair whose 16-bit

@@ -18,6 +18,9 @@ LIB_PATH = os.path.join(HERE, "libanyseq_mi.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "anyseq_mi.h")
 
 GLOBAL, SEMIGLOBAL, LOCAL = 0, 1, 2
+N_FEATURES = 32
+MLP_PARAMS = 6337
+BAND_WIDE = 1024
 
 _lib = None
 
@@ -33,23 +36,26 @@ class Timing(ctypes.Structure):
     _fields_ = [("classify_ms", ctypes.c_float), ("full32_ms", ctypes.c_float),
                 ("full16_ms", ctypes.c_float), ("rerun32_ms", ctypes.c_float),
                 ("long_ms", ctypes.c_float), ("band_ms", ctypes.c_float),
-                ("reserved_ms", ctypes.c_float * 2),
+                ("features_ms", ctypes.c_float), ("mlp_ms", ctypes.c_float),
                 ("pairs_full32", ctypes.c_int64), ("pairs_full16", ctypes.c_int64),
                 ("pairs_rerun32", ctypes.c_int64), ("pairs_long", ctypes.c_int64),
                 ("pairs_fallback", ctypes.c_int64), ("cells", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
-        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved_ms"}
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class BandStats(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("accepted", ctypes.c_int64 * 8), ("fallback", ctypes.c_int64),
-                ("band_cells", ctypes.c_int64), ("cells", ctypes.c_int64)]
+                ("band_cells", ctypes.c_int64), ("cells", ctypes.c_int64),
+                ("fallback_cells", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {"rounds": self.rounds, "accepted": list(self.accepted)[:max(self.rounds, 1)],
-                "fallback": self.fallback, "band_cells": self.band_cells, "cells": self.cells}
+                "fallback": self.fallback, "band_cells": self.band_cells, "cells": self.cells,
+                "fallback_cells": self.fallback_cells,
+                "dp_cells": self.band_cells + self.fallback_cells}
 
 
 class AlignError(RuntimeError):
@@ -80,6 +86,23 @@ def lib() -> ctypes.CDLL:
                                       ctypes.POINTER(BandStats), p]
     L.as_band_scores.restype = ctypes.c_int
     L.as_band_scores.argtypes = [p, p, p, p, i64, ctypes.POINTER(Scoring), i32, p, p, p, p, p]
+    L.as_band_certify.restype = ctypes.c_int
+    L.as_band_certify.argtypes = [p, p, p, p, i64, ctypes.POINTER(Scoring), i32, p, p, p, p]
+    L.as_pair_features.restype = ctypes.c_int
+    L.as_pair_features.argtypes = [p, p, p, p, i64, p, p]
+    L.as_band_predict.restype = ctypes.c_int
+    L.as_band_predict.argtypes = [p, p, i64, p, p, p]
+    L.as_band_labels.restype = ctypes.c_int
+    L.as_band_labels.argtypes = [p, p, p, p, i64, ctypes.POINTER(Scoring), i32, p, p]
+    L.as_band_train.restype = ctypes.c_int
+    L.as_band_train.argtypes = [p, p, p, p, p, i64, p, i32, i32, i32, ctypes.c_float,
+                                ctypes.c_float, p, p]
+    L.as_train_band_model.restype = ctypes.c_int
+    L.as_train_band_model.argtypes = [p, p, p, p, i64, ctypes.POINTER(Scoring), i32, p, p, i32,
+                                      i32, ctypes.c_float, ctypes.c_float, p]
+    L.as_align_batch_learned.restype = ctypes.c_int
+    L.as_align_batch_learned.argtypes = [p, p, p, p, i64, ctypes.POINTER(Scoring), i32, p, i32, p,
+                                         ctypes.POINTER(BandStats), p]
     L.as_set_i16_limit.restype = ctypes.c_int
     L.as_set_i16_limit.argtypes = [ctypes.c_int32]
     L.as_enable_timing.restype = ctypes.c_int
@@ -206,6 +229,130 @@ def band_scores(seqs_a, offs_a, seqs_b, offs_b, subst, alpha: int, beta: int, mo
     del keep
     _check(rc)
     return out[:n_pairs], lo[:n_pairs], hi[:n_pairs]
+
+
+def _stream(dev, stream):
+    import torch
+    return torch.cuda.current_stream(dev).cuda_stream if stream is None else stream
+
+
+def band_certify(seqs_a, offs_a, seqs_b, offs_b, subst, alpha: int, beta: int, mode: int, band_w,
+                 stream=None):
+    """Exact-band scores and certificate flags (device int32 tensors)."""
+    import torch
+    n_pairs = offs_a.numel() - 1
+    dev = offs_a.device
+    out = torch.zeros(max(n_pairs, 1), dtype=torch.int32, device=dev)
+    acc = torch.zeros(max(n_pairs, 1), dtype=torch.int32, device=dev)
+    sc, keep = make_scoring(subst, alpha, beta)
+    rc = lib().as_band_certify(*_seq_ptrs(seqs_a, offs_a, seqs_b, offs_b), n_pairs,
+                               ctypes.byref(sc), int(mode), _dev_ptr(band_w, torch.int32, "band_w"),
+                               _dev_ptr(out, torch.int32, "scores_out"),
+                               _dev_ptr(acc, torch.int32, "accept_out"),
+                               ctypes.c_void_p(_stream(dev, stream)))
+    del keep
+    _check(rc)
+    return out[:n_pairs], acc[:n_pairs]
+
+
+def pair_features(seqs_a, offs_a, seqs_b, offs_b, out=None, stream=None):
+    """k-mer diagonal features, float32 device tensor [n_pairs, 32]."""
+    import torch
+    n_pairs = offs_a.numel() - 1
+    dev = offs_a.device
+    if out is None:
+        out = torch.empty((max(n_pairs, 1), N_FEATURES), dtype=torch.float32, device=dev)
+    _check(lib().as_pair_features(*_seq_ptrs(seqs_a, offs_a, seqs_b, offs_b), n_pairs,
+                                  _dev_ptr(out, torch.float32, "features_out"),
+                                  ctypes.c_void_p(_stream(dev, stream))))
+    return out[:n_pairs]
+
+
+def band_predict(params, features, with_y: bool = False, stream=None):
+    """Predicted half-widths (int32) and optionally the network outputs y (float32)."""
+    import torch
+    n = features.shape[0]
+    dev = features.device
+    w = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    y = torch.empty(max(n, 1), dtype=torch.float32, device=dev) if with_y else None
+    _check(lib().as_band_predict(_dev_ptr(params, torch.float32, "params"),
+                                 _dev_ptr(features, torch.float32, "features"), n,
+                                 _dev_ptr(w, torch.int32, "band_w_out"),
+                                 _dev_ptr(y, torch.float32, "y_out") if with_y else None,
+                                 ctypes.c_void_p(_stream(dev, stream))))
+    return (w[:n], y[:n]) if with_y else w[:n]
+
+
+def band_labels(seqs_a, offs_a, seqs_b, offs_b, subst, alpha: int, beta: int, mode: int,
+                stream=None):
+    """Band labels from the full DP (int32 device tensor)."""
+    import torch
+    n_pairs = offs_a.numel() - 1
+    dev = offs_a.device
+    out = torch.empty(max(n_pairs, 1), dtype=torch.int32, device=dev)
+    sc, keep = make_scoring(subst, alpha, beta)
+    rc = lib().as_band_labels(*_seq_ptrs(seqs_a, offs_a, seqs_b, offs_b), n_pairs,
+                              ctypes.byref(sc), int(mode), _dev_ptr(out, torch.int32, "labels_out"),
+                              ctypes.c_void_p(_stream(dev, stream)))
+    del keep
+    _check(rc)
+    return out[:n_pairs]
+
+
+def band_train(params, adam_m, adam_v, features, labels, order, n_steps: int, batch: int,
+               t0: int = 1, lr: float = 1e-3, tau: float = 0.85, grads_out=None, stream=None):
+    """Adam steps on the network (params, adam_m, adam_v updated in place)."""
+    import torch
+    dev = params.device
+    _check(lib().as_band_train(_dev_ptr(params, torch.float32, "params"),
+                               _dev_ptr(adam_m, torch.float32, "adam_m"),
+                               _dev_ptr(adam_v, torch.float32, "adam_v"),
+                               _dev_ptr(features, torch.float32, "features"),
+                               _dev_ptr(labels, torch.int32, "labels"), labels.numel(),
+                               _dev_ptr(order, torch.int32, "order"), int(n_steps), int(batch),
+                               int(t0), float(lr), float(tau),
+                               _dev_ptr(grads_out, torch.float32, "grads_out")
+                               if grads_out is not None else None,
+                               ctypes.c_void_p(_stream(dev, stream))))
+    return params
+
+
+def train_band_model(seqs_a, offs_a, seqs_b, offs_b, subst, alpha: int, beta: int, mode: int,
+                     params, order, n_steps: int, batch: int, lr: float = 1e-3, tau: float = 0.85,
+                     stream=None):
+    """Features, labels and training in one library call (params updated in place)."""
+    import torch
+    n_pairs = offs_a.numel() - 1
+    dev = offs_a.device
+    sc, keep = make_scoring(subst, alpha, beta)
+    rc = lib().as_train_band_model(*_seq_ptrs(seqs_a, offs_a, seqs_b, offs_b), n_pairs,
+                                   ctypes.byref(sc), int(mode),
+                                   _dev_ptr(params, torch.float32, "params"),
+                                   _dev_ptr(order, torch.int32, "order"), int(n_steps), int(batch),
+                                   float(lr), float(tau), ctypes.c_void_p(_stream(dev, stream)))
+    del keep
+    _check(rc)
+    return params
+
+
+def align_batch_learned(seqs_a, offs_a, seqs_b, offs_b, subst, alpha: int, beta: int, mode: int,
+                        params, max_rounds: int = 6, scores_out=None, stream=None):
+    """Learned-band alignment (exact scores); returns (scores, stats dict)."""
+    import torch
+    n_pairs = offs_a.numel() - 1
+    dev = offs_a.device
+    if scores_out is None:
+        scores_out = torch.empty(max(n_pairs, 1), dtype=torch.int32, device=dev)
+    sc, keep = make_scoring(subst, alpha, beta)
+    st = BandStats()
+    rc = lib().as_align_batch_learned(*_seq_ptrs(seqs_a, offs_a, seqs_b, offs_b), n_pairs,
+                                      ctypes.byref(sc), int(mode),
+                                      _dev_ptr(params, torch.float32, "params"), int(max_rounds),
+                                      _dev_ptr(scores_out, torch.int32, "scores_out"),
+                                      ctypes.byref(st), ctypes.c_void_p(_stream(dev, stream)))
+    del keep
+    _check(rc)
+    return scores_out[:n_pairs], st.as_dict()
 
 
 def enable_timing(on: bool = True) -> bool:

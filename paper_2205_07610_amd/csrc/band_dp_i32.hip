@@ -28,6 +28,15 @@
 // The band actually computed is [lo, lo + W - 1] with W the smallest lane
 // width that holds the requested band, centred on it; it contains the
 // requested band, so the acceptance bound computed for it is valid.
+//
+// Exact mode (EXACT = true) restricts the DP to the requested diagonals
+// L <= j - i <= U themselves: a register whose diagonal lies outside is set
+// to -infinity after every update (and at row 0), so no value crosses the
+// band edge -- E only enters a cell from the diagonal above, F from the one
+// below, and both come from masked registers there.  Columns j < 0 inside
+// the band keep reproducing the boundary column along their own diagonal,
+// which the mask never cuts.  The acceptance bound is then taken for [L, U].
+// This mode produces the band labels (smallest accepted half-width).
 #include "internal.h"
 
 namespace asmi {
@@ -62,7 +71,7 @@ __device__ __forceinline__ uint32_t col_code(const uint8_t *cols, int n, int j, 
   return (uint32_t)c;
 }
 
-template <int MODE, int K>
+template <int MODE, int K, bool EXACT>
 __global__ void __launch_bounds__(kWave) band_dp_i32_kernel(BandArgs a, int kc) {
   constexpr int W = kGroup * K;
   constexpr int NV = K / 4;  // selector words per lane
@@ -98,6 +107,9 @@ __global__ void __launch_bounds__(kWave) band_dp_i32_kernel(BandArgs a, int kc) 
     const int lo = L - (W - (U - L + 1)) / 2;
     const int hi = lo + W - 1;
     const int kb = t * K;
+    // registers of this lane inside [L, U] (exact mode)
+    const int xa = L - lo - kb, xb = U - lo - kb;
+    auto outside = [&](int x) -> bool { return EXACT && (x < xa || x > xb); };
     int bad = 0;
 
     // ---- state at row 0 (and the sheared column codes of row -t) ----
@@ -106,6 +118,7 @@ __global__ void __launch_bounds__(kWave) band_dp_i32_kernel(BandArgs a, int kc) 
     // lane's results are taken when its row reaches m.  No step is masked.
     auto init_h = [&](int x) -> int {
       const int j = lo + kb + x;  // column of register x at row 0
+      if (outside(x)) return kNegInf32;
       if (MODE == kGlobal) return (j == 0) ? beta - alpha : 2 * beta - 2 * alpha;
       return beta * j + beta - alpha;
     };
@@ -169,7 +182,7 @@ __global__ void __launch_bounds__(kWave) band_dp_i32_kernel(BandArgs a, int kc) 
         int f = fl;
         {
           const int h = imax3(tt[0], K > 1 ? ee[0] : kNegInf32, f);
-          Ha[0] = h - amb;
+          Ha[0] = outside(0) ? kNegInf32 : h - amb;
           Ee[0] = K > 1 ? ee[0] : kNegInf32;
           f = max(f, Ha[0]);
           if (MODE == kSemiGlobal) D[0] = max(K > 1 ? D[1] : kNegInf32, Ha[0] - rowoff);
@@ -187,7 +200,7 @@ __global__ void __launch_bounds__(kWave) band_dp_i32_kernel(BandArgs a, int kc) 
         for (int x = 1; x < K; ++x) {
           const int e = (x + 1 < K) ? ee[x] : eR;
           const int h = imax3(tt[x], e, f);
-          Ha[x] = h - amb;
+          Ha[x] = outside(x) ? kNegInf32 : h - amb;
           Ee[x] = e;
           f = max(f, Ha[x]);
           if (MODE == kSemiGlobal) D[x] = max((x + 1 < K) ? D[x + 1] : dR, Ha[x] - rowoff);
@@ -239,18 +252,24 @@ __global__ void __launch_bounds__(kWave) band_dp_i32_kernel(BandArgs a, int kc) 
     int score = group_max(res);
     // H(0, n) = 0 counts when that boundary cell lies in the band (H(m, 0) is
     // the last row's column 0, already among the registers when in the band)
-    if (MODE == kSemiGlobal && n <= hi) score = max(0, score);
+    const int blo = EXACT ? L : lo, bhi = EXACT ? U : hi;  // the band scored
+    if (MODE == kSemiGlobal && n <= bhi) score = max(0, score);
     if (bad) atomicOr(&a.ctr->status, kStatusBadResidue);
     if (!has || t != 0) continue;
 
     // ---- acceptance (certificate), next band or full-DP fallback ----
-    const int lo_ab = tr ? -hi : lo, hi_ab = tr ? -lo : hi;  // limits in A/B orientation
+    const int lo_ab = tr ? -bhi : blo, hi_ab = tr ? -blo : bhi;  // limits in A/B orientation
     if (a.lo_out) { a.lo_out[d.pair] = lo_ab; a.hi_out[d.pair] = hi_ab; }
-    if (a.raw) { a.scores[d.pair] = score; continue; }
     int64_t ub = 0;
-    const bool leave = band_leave_bound(m, n, lo, hi, a.sigma_max, alpha, beta, MODE, &ub);
+    const bool leave = band_leave_bound(m, n, blo, bhi, a.sigma_max, alpha, beta, MODE, &ub);
+    const bool accept = !leave || (int64_t)score >= ub;
+    if (a.raw) {
+      a.scores[d.pair] = score;
+      if (a.accept_out) a.accept_out[d.pair] = accept ? 1 : 0;
+      continue;
+    }
     atomicAdd(&a.ctr->band_cells, (unsigned long long)((long long)m * W));
-    if (!leave || (int64_t)score >= ub) {
+    if (accept) {
       a.scores[d.pair] = score;
       atomicAdd(&a.ctr->band_accepted[a.round < kMaxBandRounds ? a.round : kMaxBandRounds - 1], 1);
       continue;
@@ -271,14 +290,14 @@ __global__ void __launch_bounds__(kWave) band_dp_i32_kernel(BandArgs a, int kc) 
   }
 }
 
-template <int MODE>
+template <int MODE, bool EXACT>
 hipError_t launch_mode(const BandArgs &args, int kc, int grid, hipStream_t stream) {
   switch (kc) {
-    case 0: hipLaunchKernelGGL((band_dp_i32_kernel<MODE, 4>), dim3(grid), dim3(kWave), 0, stream, args, kc); break;
-    case 1: hipLaunchKernelGGL((band_dp_i32_kernel<MODE, 8>), dim3(grid), dim3(kWave), 0, stream, args, kc); break;
-    case 2: hipLaunchKernelGGL((band_dp_i32_kernel<MODE, 16>), dim3(grid), dim3(kWave), 0, stream, args, kc); break;
-    case 3: hipLaunchKernelGGL((band_dp_i32_kernel<MODE, 32>), dim3(grid), dim3(kWave), 0, stream, args, kc); break;
-    default: hipLaunchKernelGGL((band_dp_i32_kernel<MODE, 64>), dim3(grid), dim3(kWave), 0, stream, args, kc); break;
+    case 0: hipLaunchKernelGGL((band_dp_i32_kernel<MODE, 4, EXACT>), dim3(grid), dim3(kWave), 0, stream, args, kc); break;
+    case 1: hipLaunchKernelGGL((band_dp_i32_kernel<MODE, 8, EXACT>), dim3(grid), dim3(kWave), 0, stream, args, kc); break;
+    case 2: hipLaunchKernelGGL((band_dp_i32_kernel<MODE, 16, EXACT>), dim3(grid), dim3(kWave), 0, stream, args, kc); break;
+    case 3: hipLaunchKernelGGL((band_dp_i32_kernel<MODE, 32, EXACT>), dim3(grid), dim3(kWave), 0, stream, args, kc); break;
+    default: hipLaunchKernelGGL((band_dp_i32_kernel<MODE, 64, EXACT>), dim3(grid), dim3(kWave), 0, stream, args, kc); break;
   }
   return hipGetLastError();
 }
@@ -286,7 +305,7 @@ hipError_t launch_mode(const BandArgs &args, int kc, int grid, hipStream_t strea
 template <int MODE, int K>
 int occupancy() {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, band_dp_i32_kernel<MODE, K>, kWave, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, band_dp_i32_kernel<MODE, K, false>, kWave, 0) !=
           hipSuccess || nb < 1)
     nb = 1;
   return nb;
@@ -295,8 +314,11 @@ int occupancy() {
 }  // namespace
 
 hipError_t launch_band_dp_i32(int mode, int kc, const BandArgs &args, int grid, hipStream_t stream) {
-  return mode == kGlobal ? launch_mode<kGlobal>(args, kc, grid, stream)
-                         : launch_mode<kSemiGlobal>(args, kc, grid, stream);
+  if (args.exact)
+    return mode == kGlobal ? launch_mode<kGlobal, true>(args, kc, grid, stream)
+                           : launch_mode<kSemiGlobal, true>(args, kc, grid, stream);
+  return mode == kGlobal ? launch_mode<kGlobal, false>(args, kc, grid, stream)
+                         : launch_mode<kSemiGlobal, false>(args, kc, grid, stream);
 }
 
 int band_dp_i32_blocks_per_cu(int mode, int kc) {

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "anyseq_mi.h"
+
 namespace asmi {
 
 // One DPP row (16 lanes) cooperates on one alignment: lane t owns K adjacent
@@ -60,6 +62,7 @@ struct Counters {
   int32_t next_band[5];
   int32_t band_accepted[8];  // pairs accepted in round r
   unsigned long long band_cells;  // cells computed by the banded kernel
+  unsigned long long fallback_cells;  // sum of m*n over the fallback pairs
 };
 
 // ---- banded path ----
@@ -141,14 +144,45 @@ struct BandArgs {
   const uint32_t *qwords;   // [2][32]: byte c of word r = sigma(r, c) + alpha + beta (row/col order)
   int32_t asz, alpha, beta, sigma_max;
   int32_t round, max_rounds;
-  int32_t raw;              // 1: write the banded score, no acceptance test
+  int32_t raw;              // 1: write the banded score, no rounds or fallback
+  int32_t exact;            // 1: score exactly the diagonals of the requested half-width
   int32_t *scores;
-  int32_t *lo_out, *hi_out; // optional: diagonal limits computed (A/B orientation)
+  int32_t *lo_out, *hi_out; // optional: diagonal limits scored (A/B orientation)
+  int32_t *accept_out;      // optional (raw): 1 if the certificate accepts the score
   PairDesc *fallback;       // rejected pairs for the full DP
 };
 
 hipError_t launch_band_dp_i32(int mode, int kc, const BandArgs &args, int grid, hipStream_t stream);
 int band_dp_i32_blocks_per_cu(int mode, int kc);
+
+// ---- learned band ----
+constexpr int kMlpInputs = 32;
+constexpr int kMlpHidden = 64;
+constexpr int kMlpParams = kMlpInputs * kMlpHidden + kMlpHidden + kMlpHidden * kMlpHidden + kMlpHidden +
+                           kMlpHidden + 1;  // 6337
+constexpr int kMlpPartialStride = 6400;     // floats per gradient partial
+constexpr int kMlpMaxParts = 256;           // gradient partials (one per wave) per step
+
+hipError_t launch_features(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t *seqs_b,
+                           const int64_t *offs_b, int64_t n_pairs, float *out, int32_t *status,
+                           int num_cu, hipStream_t stream);
+hipError_t launch_mlp_predict(const float *params, const float *features, int64_t n, int32_t *w_out,
+                              float *y_out, int num_cu, hipStream_t stream);
+int mlp_grad_parts(int batch);
+
+// Banded driver shared by the banded entry points (runtime.hip): raw = 1
+// scores one band per pair (no rounds, no fallback), exact = 1 scores the
+// requested diagonals themselves and skips pairs with a negative half-width.
+int band_call(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t *seqs_b, const int64_t *offs_b,
+              int64_t n_pairs, const as_scoring *scoring, int32_t mode, const int32_t *band_w,
+              int32_t max_rounds, int32_t raw, int32_t exact, int32_t *scores_out, int32_t *lo_out,
+              int32_t *hi_out, int32_t *accept_out, as_band_stats *stats, void *stream_ptr);
+bool timing_enabled();
+void record_learned_timing(float features_ms, float mlp_ms);
+hipError_t launch_mlp_train_step(const float *features, const int32_t *labels, const int32_t *order,
+                                 int32_t batch, float tau, float *params, float *m1, float *m2,
+                                 float *partials, float *grads_out, float lr, float c1, float c2,
+                                 hipStream_t stream);
 
 // A long pair and where its stripes and boundary columns live.
 struct LongItem {

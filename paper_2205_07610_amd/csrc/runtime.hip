@@ -167,7 +167,9 @@ __global__ void __launch_bounds__(256) route_fallback_kernel(RouteParams c, cons
   const int64_t lo = (int64_t)blockIdx.x * chunk;
   const int64_t hi = lo + chunk < total ? lo + chunk : total;
   if (threadIdx.x < kFullRoutes) bl.cnt[threadIdx.x] = 0;
+  if (threadIdx.x == 0) bl.cells = 0;
   __syncthreads();
+  unsigned long long cells = 0;
   auto route = [&](int64_t i, PairDesc &d) {
     const PairDesc f = fallback[i];
     const bool tr = (f.flags & kTransposed) != 0;
@@ -180,9 +182,12 @@ __global__ void __launch_bounds__(256) route_fallback_kernel(RouteParams c, cons
     const int r = route(i, d);
     if (r == kRoute32 && d.n > c.stripe_w) atomicMax(&ctr->max_rows_multi, d.m);
     atomicAdd(&bl.cnt[r], 1);
+    cells += (unsigned long long)((int64_t)d.m * d.n);
   }
+  atomicAdd(&bl.cells, cells);
   __syncthreads();
   if (threadIdx.x == 0) {
+    if (bl.cells) atomicAdd(&ctr->fallback_cells, bl.cells);
     bl.base[kRoute32] = bl.cnt[kRoute32] ? atomicAdd(&ctr->n_full32, bl.cnt[kRoute32]) : 0;
     bl.base[kRoute16] = bl.cnt[kRoute16] ? atomicAdd(&ctr->n_full16, bl.cnt[kRoute16]) : 0;
     bl.base[kRouteLong] = bl.cnt[kRouteLong] ? atomicAdd(&ctr->n_long, bl.cnt[kRouteLong]) : 0;
@@ -202,10 +207,11 @@ __global__ void __launch_bounds__(256) route_fallback_kernel(RouteParams c, cons
 // Banded path entry: orientation (rows = the shorter sequence), initial
 // half-width, lane-width class; pairs whose first band is already wider than
 // the widest class, or than half the matrix, go straight to the fallback list.
-// raw = 1 queues every pair (too wide a band is an error).
+// raw = 1 queues every pair (too wide a band is an error); with exact = 1 a
+// negative half-width leaves the pair out.
 __global__ void __launch_bounds__(256) band_classify_kernel(RouteParams c, const int64_t *offs_a,
                                                             const int64_t *offs_b, const int32_t *w0,
-                                                            int32_t raw, BandItem *lists,
+                                                            int32_t raw, int32_t exact, BandItem *lists,
                                                             int64_t list_cap, PairDesc *fallback,
                                                             Counters *ctr, int32_t *scores) {
   constexpr int R = kBandClasses + 1;  // classes, then the fallback list
@@ -230,6 +236,7 @@ __global__ void __launch_bounds__(256) band_classify_kernel(RouteParams c, const
     bi.d.pair = (int32_t)p;
     bi.d.flags = tr ? kTransposed : 0;
     int w = w0[p];
+    if (exact && w < 0) return -1;
     w = w < 0 ? 0 : (w > (1 << 20) ? (1 << 20) : w);
     bi.w = w;
     bi.pad_ = 0;
@@ -664,10 +671,11 @@ extern "C" int as_align_batch(const uint8_t *seqs_a, const int64_t *offs_a, cons
 }
 
 // Banded entry points share everything up to the rounds.
-static int band_call(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t *seqs_b,
-                     const int64_t *offs_b, int64_t n_pairs, const as_scoring *scoring, int32_t mode,
-                     const int32_t *band_w, int32_t max_rounds, int32_t raw, int32_t *scores_out,
-                     int32_t *lo_out, int32_t *hi_out, as_band_stats *stats, void *stream_ptr) {
+int asmi::band_call(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t *seqs_b,
+                    const int64_t *offs_b, int64_t n_pairs, const as_scoring *scoring, int32_t mode,
+                    const int32_t *band_w, int32_t max_rounds, int32_t raw, int32_t exact,
+                    int32_t *scores_out, int32_t *lo_out, int32_t *hi_out, int32_t *accept_out,
+                    as_band_stats *stats, void *stream_ptr) {
   if (!scoring || !offs_a || !offs_b || !seqs_a || !seqs_b || !scores_out || !scoring->subst || !band_w)
     return AS_ERR_NULL;
   if ((lo_out == nullptr) != (hi_out == nullptr)) return AS_ERR_NULL;
@@ -698,7 +706,7 @@ static int band_call(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t
   if (timing) AS_HIP(hipEventRecord(w->ev[0], stream));
   const RouteParams rp = route_params(cs, n_pairs);
   hipLaunchKernelGGL(band_classify_kernel, dim3(classify_blocks(n_pairs)), dim3(256), 0, stream, rp,
-                     offs_a, offs_b, band_w, raw, w->band_lists, list_cap, w->fallback, w->ctr,
+                     offs_a, offs_b, band_w, raw, exact, w->band_lists, list_cap, w->fallback, w->ctr,
                      scores_out);
   AS_HIP(hipGetLastError());
   if (timing) AS_HIP(hipEventRecord(w->ev[1], stream));
@@ -721,9 +729,11 @@ static int band_call(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t
   ba.sigma_max = cs.smax;
   ba.max_rounds = raw ? 1 : max_rounds;
   ba.raw = raw;
+  ba.exact = exact;
   ba.scores = scores_out;
   ba.lo_out = lo_out;
   ba.hi_out = hi_out;
+  ba.accept_out = accept_out;
   ba.fallback = w->fallback;
   int rounds = 0;
   float band_ms = 0.f;
@@ -768,6 +778,7 @@ static int band_call(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t
   AS_HIP(hipGetLastError());
   if ((rc = read_counters(w, stream, &c))) return rc;
   if ((rc = status_to_code(c.status))) return rc;
+  if (stats) stats->fallback_cells = (int64_t)c.fallback_cells;
   return run_full_lists(w, cs, seqs_a, seqs_b, scores_out, stream, timing, c);
 }
 
@@ -775,16 +786,32 @@ extern "C" int as_align_batch_band(const uint8_t *seqs_a, const int64_t *offs_a,
                                    const int64_t *offs_b, int64_t n_pairs, const as_scoring *scoring,
                                    int32_t mode, const int32_t *band_w0, int32_t max_rounds,
                                    int32_t *scores_out, as_band_stats *stats, void *stream) {
-  return band_call(seqs_a, offs_a, seqs_b, offs_b, n_pairs, scoring, mode, band_w0, max_rounds, 0,
-                   scores_out, nullptr, nullptr, stats, stream);
+  return band_call(seqs_a, offs_a, seqs_b, offs_b, n_pairs, scoring, mode, band_w0, max_rounds, 0, 0,
+                   scores_out, nullptr, nullptr, nullptr, stats, stream);
 }
 
 extern "C" int as_band_scores(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t *seqs_b,
                               const int64_t *offs_b, int64_t n_pairs, const as_scoring *scoring,
                               int32_t mode, const int32_t *band_w, int32_t *scores_out,
                               int32_t *lo_out, int32_t *hi_out, void *stream) {
-  return band_call(seqs_a, offs_a, seqs_b, offs_b, n_pairs, scoring, mode, band_w, 1, 1, scores_out,
-                   lo_out, hi_out, nullptr, stream);
+  return band_call(seqs_a, offs_a, seqs_b, offs_b, n_pairs, scoring, mode, band_w, 1, 1, 0, scores_out,
+                   lo_out, hi_out, nullptr, nullptr, stream);
+}
+
+extern "C" int as_band_certify(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t *seqs_b,
+                               const int64_t *offs_b, int64_t n_pairs, const as_scoring *scoring,
+                               int32_t mode, const int32_t *band_w, int32_t *scores_out,
+                               int32_t *accept_out, void *stream) {
+  if (!accept_out) return AS_ERR_NULL;
+  return band_call(seqs_a, offs_a, seqs_b, offs_b, n_pairs, scoring, mode, band_w, 1, 1, 1, scores_out,
+                   nullptr, nullptr, accept_out, nullptr, stream);
+}
+
+bool asmi::timing_enabled() { return g_timing; }
+
+void asmi::record_learned_timing(float features_ms, float mlp_ms) {
+  g_last_timing.features_ms = features_ms;
+  g_last_timing.mlp_ms = mlp_ms;
 }
 
 extern "C" const char *as_strerror(int code) {

@@ -277,3 +277,55 @@ def random_small(rng: np.random.Generator, n_pairs: int, max_len: int, asz: int 
     np.cumsum(lens_b, out=ob[1:])
     sb = np.concatenate(pairs_b) if ob[-1] else np.zeros(0, np.uint8)
     return sa, oa, sb.astype(np.uint8), ob
+
+
+def config4_like(n_pairs: int, seed: int, min_len: int = 1000, max_len: int = 5000,
+                 max_div: float = 0.10) -> Batch:
+    """Config 4's law at another size or length range (tests)."""
+    rng = np.random.default_rng(seed)
+    la = rng.integers(min_len, max_len + 1, size=n_pairs)
+    sa, oa = random_csr(rng, la, 4)
+    div = rng.uniform(0.0, max_div, size=n_pairs)
+    sb, ob = _diverged(rng, sa, oa, div, 4)
+    return Batch(f"config-4 law, {min_len}-{max_len} bp", sa, oa, sb, ob, dna_subst(), 5, 2,
+                 MODE_GLOBAL)
+
+
+# ---- random draws of the band network's training (passed to the library as inputs)
+
+# float32 parameter layout of the band network: name -> (offset, shape)
+BAND_PARAM_LAYOUT = {"w1": (0, (32, 64)), "b1": (2048, (64,)), "w2": (2112, (64, 64)),
+                     "b2": (6208, (64,)), "w3": (6272, (64,)), "b3": (6336, (1,))}
+BAND_PARAMS = 6337
+
+
+def band_params_init(seed: int, b3: float = 0.0) -> np.ndarray:
+    """Initial weights: normal with variance 2/fan_in (last layer 1/fan_in),
+    zero biases except b3; float32 [6337] in the library's layout."""
+    rng = np.random.default_rng(seed)
+    p = np.zeros(BAND_PARAMS, dtype=np.float32)
+    for name, fan_in, var in (("w1", 32, 2 / 32), ("w2", 64, 2 / 64), ("w3", 64, 1 / 64)):
+        off, shape = BAND_PARAM_LAYOUT[name]
+        size = int(np.prod(shape))
+        p[off:off + size] = rng.normal(0.0, math.sqrt(var), size)
+    p[BAND_PARAM_LAYOUT["b3"][0]] = b3
+    return p
+
+
+def band_params_split(flat) -> dict:
+    """The flat array as named float32 arrays (views of a copy)."""
+    flat = np.asarray(flat, dtype=np.float32).copy()
+    return {k: flat[off:off + int(np.prod(shape))].reshape(shape)
+            for k, (off, shape) in BAND_PARAM_LAYOUT.items()}
+
+
+def minibatch_order(seed: int, n: int, n_steps: int, batch: int) -> np.ndarray:
+    """Sample indices of n_steps minibatches: consecutive random permutations
+    of 0..n-1 (epochs), cut into minibatches of `batch`; int32."""
+    rng = np.random.default_rng(seed)
+    need = n_steps * batch
+    parts, have = [], 0
+    while have < need:
+        parts.append(rng.permutation(n))
+        have += n
+    return np.concatenate(parts)[:need].astype(np.int32) if need else np.zeros(0, np.int32)

@@ -1,0 +1,263 @@
+"""GPU parity of the learned band: features, exact-band certificate, labels,
+network inference, gradients and Adam against the oracle, then the trained
+network's gain over the best fixed initial half-width (scores stay exact)."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2205_07610_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+DNA = synth.dna_subst()
+
+
+def _say(msg):
+    print(f"[learned] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2205_07610_amd import binding
+    binding.lib()
+    return binding
+
+
+def _t(x, dtype=None):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x) if dtype is None
+                           else np.ascontiguousarray(x, dtype=dtype)).to("cuda")
+
+
+def _feature_cases(rng):
+    """Hand-shaped pairs (empty, short, identical, duplicated k-mers, a B
+    beyond the position cap) plus related and unrelated random pairs."""
+    pairs = [([], []), ([0, 1, 2], [0, 1, 2]), ([1] * 50, []), ([2] * 7, [2] * 7)]
+    a = rng.integers(0, 4, 300).tolist()
+    pairs += [(a, a), (a, a + a), (a, a[40:]), (a[:100], rng.integers(0, 4, 20).tolist() + a)]
+    far = ([0, 1] * 40_000)[:70_000]
+    far[65_534:65_541] = [2] * 7
+    pairs.append(([2] * 7, far))
+    far2 = list(far)
+    far2[65_534:65_541] = [0, 1] * 3 + [0]
+    far2[65_535:65_542] = [2] * 7
+    pairs.append(([2] * 7, far2))
+    sa, oa, sb, ob = synth.random_small(rng, 400, 600, related=0.8)
+    for p in range(400):
+        pairs.append((sa[oa[p]:oa[p + 1]].tolist(), sb[ob[p]:ob[p + 1]].tolist()))
+    return synth.from_pairs("features", pairs, DNA, 5, 2, 0)
+
+
+def test_features_match_oracle(gpu):
+    from oracle import features as F
+    b = _feature_cases(np.random.default_rng(800))
+    _say(f"features: {b.n_pairs} pairs")
+    got = gpu.pair_features(*gpu.to_device(b)).cpu().numpy()
+    want = F.batch_features(b)
+    # bins and hit fraction are ratios of integers rounded once: exact;
+    # feature 30 is a log2 in double precision rounded to float: within 1 ulp
+    np.testing.assert_array_equal(got[:, :30], want[:, :30])
+    np.testing.assert_array_equal(got[:, 31], want[:, 31])
+    ulp = np.abs(got[:, 30].view(np.int32).astype(np.int64) - want[:, 30].view(np.int32))
+    assert ulp.max() <= 1
+
+
+def test_features_errors(gpu):
+    import torch
+    b = synth.from_pairs("bad", [([0, 1, 2, 3, 4, 0, 1, 2], [0, 1, 2, 3, 0, 0, 1, 2])], DNA, 5, 2, 0)
+    with pytest.raises(gpu.AlignError) as e:
+        gpu.pair_features(*gpu.to_device(b))
+    assert e.value.code == -3
+    sa, oa, sb, ob = gpu.to_device(synth.from_pairs("ok", [([0] * 9, [1] * 9)], DNA, 5, 2, 0))
+    bad = torch.tensor([5, 0], dtype=torch.int64, device="cuda")
+    with pytest.raises(gpu.AlignError) as e:
+        gpu.pair_features(sa, bad, sb, ob)
+    assert e.value.code == -2
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_certify_matches_oracle(gpu, oracle_mod, mode):
+    from oracle import band
+    rng = np.random.default_rng(810 + mode)
+    sa, oa, sb, ob = synth.random_small(rng, 1200, 500, related=0.8)
+    b = synth.Batch("certify", sa, oa, sb, ob, DNA, 5, 2, mode)
+    m, n = b.lens_a, b.lens_b
+    w = rng.integers(0, 80, size=b.n_pairs)
+    w[::5] = rng.integers(0, 4, size=len(w[::5]))
+    w = np.minimum(w, np.maximum(0, (1023 - np.abs(n - m)) // 2))
+    keep = np.abs(n - m) + 2 * w + 1 <= 1024
+    b, w = b.subset(np.nonzero(keep)[0]), w[keep]
+    w[::13] = -1  # skipped pairs keep their outputs
+    _say(f"certify mode {mode}: {b.n_pairs} pairs")
+    sc, acc = gpu.band_certify(*gpu.to_device(b), DNA, 5, 2, mode, _t(w, np.int32))
+    sc, acc = sc.cpu().numpy(), acc.cpu().numpy()
+    m, n = b.lens_a, b.lens_b
+    L = np.minimum(0, n - m) - w
+    U = np.maximum(0, n - m) + w
+    live = (w >= 0) & (m > 0) & (n > 0)
+    want = oracle_mod.diag_band_batch(b.seqs_a, b.offs_a, b.seqs_b, b.offs_b, DNA, 5, 2, mode,
+                                      np.where(live, L, 0), np.where(live, U, 0))
+    np.testing.assert_array_equal(sc[live], want[live])
+    for p in np.nonzero(live)[0]:
+        ub = band.ub_outside(int(m[p]), int(n[p]), int(w[p]), 2, 5, 2, mode)
+        assert acc[p] == int(band.accepts(int(want[p]), ub)), p
+    assert np.all(acc[~live] == 0)
+    assert 0 < acc[live].sum() < live.sum()
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_labels_match_oracle(gpu, oracle_mod, mode):
+    from oracle import band
+    b = synth.config4_like(160, 821 + mode, min_len=80, max_len=500, max_div=0.2)
+    extra = [([], [0, 1, 2]), ([0] * 5, [1] * 1200), ([3] * 40, [0] * 40)]
+    pairs = [b.pair(p) for p in range(b.n_pairs)] + [(np.array(x, np.uint8), np.array(y, np.uint8))
+                                                    for x, y in extra]
+    b = synth.from_pairs("labels", pairs, DNA, 5, 2, mode)
+    _say(f"labels mode {mode}: {b.n_pairs} pairs")
+    got = gpu.band_labels(*gpu.to_device(b), DNA, 5, 2, mode).cpu().numpy()
+    want = np.array([0 if (len(q) == 0 or len(s) == 0) else band.band_label(q, s, DNA, 5, 2, mode)
+                     for q, s in (b.pair(p) for p in range(b.n_pairs))])
+    np.testing.assert_array_equal(got, want)
+    assert got[-2] == 1024 and got[-3] == 0
+    _say(f"  label range {got.min()}..{got.max()}, median {np.median(got)}")
+
+
+def _oracle_params(flat):
+    return synth.band_params_split(flat)
+
+
+def _rand_flat(seed):
+    rng = np.random.default_rng(seed)
+    p = synth.band_params_init(seed, b3=3.0)
+    for k in ("b1", "b2"):
+        off, shape = synth.BAND_PARAM_LAYOUT[k]
+        p[off:off + shape[0]] = rng.normal(0, 0.1, shape[0])
+    return p
+
+
+def test_predict_matches_oracle(gpu):
+    from oracle import mlp
+    rng = np.random.default_rng(830)
+    flat = _rand_flat(831)
+    x = rng.uniform(0, 1, (1000, 32)).astype(np.float32)  # 62.5 tiles: ragged tail
+    x[:, 30] *= 0.7
+    w, y = gpu.band_predict(_t(flat), _t(x), with_y=True)
+    w, y = w.cpu().numpy(), y.cpu().numpy()
+    yo, _ = mlp.forward(_oracle_params(flat), x)
+    # one bfloat16 rounding of a hidden activation can flip with the
+    # summation order (float32 on the GPU, float64 here): a 2^-8 relative
+    # change of one of 64 terms, so |dy| stays well below 1e-2 * (1 + |y|)
+    err = np.abs(y - yo)
+    _say(f"predict: max |dy| {err.max():.3g}, median {np.median(err):.3g}")
+    assert np.all(err <= 1e-2 * (1 + np.abs(yo)))
+    assert np.median(err) < 1e-5
+    wo = mlp.predict_width(yo)
+    # the width is ceil(2^y - 1): equal unless 2^y - 1 sits within the y error of an integer
+    t = np.exp2(yo) - 1
+    near = np.abs(t - np.round(t)) < 1e-2 * (1 + np.abs(t))
+    np.testing.assert_array_equal(w[~near], wo[~near])
+
+
+def test_grad_and_adam_match_oracle(gpu):
+    import torch
+    from oracle import mlp
+    rng = np.random.default_rng(840)
+    flat = _rand_flat(841)
+    n, batch = 700, 300
+    x = rng.uniform(0, 1, (n, 32)).astype(np.float32)
+    labels = rng.integers(0, 400, n).astype(np.int32)
+    order = rng.permutation(n)[:batch].astype(np.int32)
+    params = _t(flat)
+    m1 = torch.zeros_like(params)
+    m2 = torch.zeros_like(params)
+    g = torch.zeros_like(params)
+    tau, lr = 0.85, 1e-3
+    gpu.band_train(params, m1, m2, _t(x), _t(labels), _t(order), 1, batch, 1, lr, tau, grads_out=g)
+    g = g.cpu().numpy()
+    P = _oracle_params(flat)
+    xs = x[order]
+    target = np.log2(labels[order].astype(np.float64) + 1).astype(np.float32)
+    y, cache = mlp.forward(P, xs)
+    go = mlp.backward(cache, mlp.dloss_dy(y, target, tau))
+    gsplit = synth.band_params_split(g)
+    for k in mlp.PARAM_NAMES:
+        a, b_ = gsplit[k].astype(np.float64), np.asarray(go[k], np.float64).reshape(gsplit[k].shape)
+        scale = np.abs(b_).max()
+        err = np.abs(a - b_)
+        _say(f"grad {k}: max |err| / max |g| = {err.max() / max(scale, 1e-30):.3g}")
+        assert np.all(err <= 1e-3 * scale + 1e-2 * np.abs(b_)), k
+    # one Adam step from zero state, applied to the GPU's own gradient
+    newp, _ = mlp.adam_step({k: np.asarray(v, np.float64) for k, v in P.items()},
+                            {k: gsplit[k].astype(np.float64) for k in mlp.PARAM_NAMES}, {}, 1, lr)
+    got = synth.band_params_split(params.cpu().numpy())
+    for k in mlp.PARAM_NAMES:
+        np.testing.assert_allclose(got[k], newp[k].reshape(got[k].shape), rtol=1e-5, atol=1e-7)
+
+
+def test_training_reduces_loss(gpu):
+    import torch
+    from oracle import mlp
+    rng = np.random.default_rng(850)
+    n = 4096
+    x = rng.uniform(0, 1, (n, 32)).astype(np.float32)
+    # a learnable target: the label grows with features 0 and 31
+    labels = np.floor(np.exp2(1 + 6 * x[:, 0] * x[:, 31])).astype(np.int32)
+    target = np.log2(labels + 1.0)
+    params = _t(synth.band_params_init(851))
+    P0 = params.cpu().numpy()
+    m1, m2 = torch.zeros_like(params), torch.zeros_like(params)
+    steps, batch = 300, 256
+    order = synth.minibatch_order(852, n, steps, batch)
+    gpu.band_train(params, m1, m2, _t(x), _t(labels), _t(order), steps, batch, 1, 3e-3, 0.5)
+    loss0 = mlp.pinball(mlp.forward(_oracle_params(P0), x)[0], target, 0.5)
+    _, y1 = gpu.band_predict(params, _t(x), with_y=True)
+    loss1 = mlp.pinball(y1.cpu().numpy().astype(np.float64), target, 0.5)
+    _say(f"training: pinball {loss0:.3f} -> {loss1:.3f}")
+    assert loss1 < 0.25 * loss0
+
+
+def test_learned_band_exact_and_beats_fixed_width(gpu, oracle_mod):
+    """Train on a config-4-law training set (own seed), then align a held-out
+    set: every score equals the oracle's full DP, and the learned initial
+    widths need fewer DP cells (banded cells plus the full matrices of the
+    fallback pairs) than the best fixed initial width chosen on the training
+    set."""
+    import torch
+    train = synth.config4_like(12000, 860, min_len=1000, max_len=3000)
+    test = synth.config4_like(600, 861, min_len=1000, max_len=3000)
+    _say(f"train {train.n_pairs} pairs ({train.cells() / 1e9:.1f} Gcells), test {test.n_pairs}")
+    dtr = gpu.to_device(train)
+    dte = gpu.to_device(test)
+    steps, batch = 1500, 512
+    params = _t(synth.band_params_init(862, b3=5.0))
+    order = _t(synth.minibatch_order(863, train.n_pairs, steps, batch))
+    gpu.train_band_model(*dtr, DNA, 5, 2, 0, params, order, steps, batch, lr=2e-3, tau=0.85)
+    torch.cuda.synchronize()
+
+    def run(dev, b, w0=None):
+        if w0 is None:
+            sc, st = gpu.align_batch_learned(*dev, DNA, 5, 2, 0, params, max_rounds=6)
+        else:
+            sc, st = gpu.align_batch_band(*dev, DNA, 5, 2, 0, _t(np.full(b.n_pairs, w0, np.int32)),
+                                          max_rounds=6)
+        return sc.cpu().numpy(), st
+
+    fixed = {w0: run(dtr, train, w0)[1]["dp_cells"] for w0 in (4, 8, 16, 32, 64, 128, 256)}
+    best = min(fixed, key=fixed.get)
+    _say(f"fixed widths on the training set (DP cells / full): "
+         f"{ {k: round(v / train.cells(), 4) for k, v in fixed.items()} }, best {best}")
+    want = oracle_mod.align_batch(test.seqs_a, test.offs_a, test.seqs_b, test.offs_b, DNA, 5, 2, 0)
+    got_l, st_l = run(dte, test)
+    got_f, st_f = run(dte, test, best)
+    np.testing.assert_array_equal(got_l, want)
+    np.testing.assert_array_equal(got_f, want)
+    _say(f"test set: learned {st_l['dp_cells'] / test.cells():.4f} of full "
+         f"(rounds {st_l['rounds']}, accepted {st_l['accepted']}, fallback {st_l['fallback']}); "
+         f"fixed w0={best}: {st_f['dp_cells'] / test.cells():.4f} "
+         f"(accepted {st_f['accepted']}, fallback {st_f['fallback']})")
+    assert st_l["dp_cells"] < st_f["dp_cells"]
