@@ -1,14 +1,20 @@
 #!/usr/bin/env python3
 """Benchmark: score-only alignment throughput on one MI355X.
 
-A step is one as_align_batch call over the whole batch (validation and
-classification, the DP kernels, the 16-bit overflow re-run, the status
-read-back), with the inputs already resident in HBM.  The workload is the
-2^20-pair local affine DNA batch (150 bp reads against 250 bp windows that
-hold a mutated copy; match +2, mismatch -3, alpha 5, beta 2), seeded and
-synthetic.  Prints one JSON line.
+Default workload: 10^6 global affine DNA pairs of 1-5 kb (divergence
+U[0, 10%], half indels; match +2, mismatch -3, alpha 5, beta 2), seeded and
+synthetic, inputs resident in HBM.  A step is one as_align_batch_learned
+call over the whole batch: k-mer features, network inference, certified
+banded rounds and the full-DP fallback, with the status read-back.  The band
+network is trained first (untimed) on 2*10^5 pairs of the same law with
+their own seed, by the library's own labelling and training kernels.  The
+same batch is then timed with the plain full DP (as_align_batch), and every
+learned-band score is compared with the full-DP score (0 mismatches
+required).  value = effective GCUPS of the learned step (sum of m*n over the
+batch / step time); the full DP's figures are reported beside it.
 
---gpus N with N > 1 exits: this build runs on one GPU.
+Other workloads (--workload c0, c1, c2, c3, c3long) time as_align_batch.
+Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
 """
 from __future__ import annotations
 
@@ -36,7 +42,11 @@ KERNEL_SOURCES = {
     "full16": "paper_2205_07610_amd/csrc/full_dp_i16x2.hip",
     "rerun32": "paper_2205_07610_amd/csrc/full_dp_i32.hip",
     "long": "paper_2205_07610_amd/csrc/long_dp_i32.hip",
+    "band": "paper_2205_07610_amd/csrc/band_dp_i32.hip",
 }
+# band network training of the learned workload (library kernels, untimed)
+TRAIN = {"pairs": 200_000, "seed": 2004, "steps": 4000, "batch": 1024, "lr": 2e-3, "tau": 0.85,
+         "init_seed": 2005, "order_seed": 2006, "b3": 5.0}
 MODE_NAMES = {0: "global", 1: "semi-global", 2: "local"}
 
 
@@ -61,7 +71,8 @@ def workload(name: str, pairs: int | None):
         desc = f"{b.n_pairs} protein pairs of 65,536 residues, local affine (alpha 11, beta 1)"
     elif name == "c4":
         b = synth.config4(n_pairs=pairs or 1_000_000)
-        desc = f"{b.n_pairs} pairs, 1-5 kb, global affine DNA (+2/-3, alpha 5, beta 2)"
+        desc = (f"{b.n_pairs} pairs, 1-5 kb, divergence U[0,10%] half indels, global affine DNA "
+                "(+2/-3, alpha 5, beta 2); learned band vs full DP")
     else:
         raise SystemExit(f"unknown workload {name}")
     return b, desc
@@ -124,13 +135,74 @@ def cpu_baseline(batch, seconds: float, gpu_scores):
     }, mismatches, done_pairs
 
 
+def roofline(kernel_name, kernel_ms, ops, packed):
+    achieved = ops / (kernel_ms * 1e-3) / 1e12 if kernel_ms > 0 else 0.0
+    peak = PEAK_I16X2_TOPS if packed else PEAK_I32_TOPS
+    return {
+        "bound": "alu",
+        "kernel": kernel_name,
+        "achieved": round(achieved, 3),
+        "peak": round(peak, 2),
+        "unit": "Tops/s",
+        "frac": round(achieved / peak, 4),
+        "kernel_ms": round(kernel_ms, 4),
+        "traffic": traffic_for(kernel_name) if kernel_name in KERNEL_SOURCES else None,
+    }
+
+
+def timed(step, steps, warmup, binding, torch):
+    """Warm up, then time exactly `steps` steps between synchronisations;
+    returns ms per step and the per-step phase timings."""
+    for _ in range(warmup):
+        step()
+    binding.enable_timing(True)
+    phases = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st = step()
+        tm = binding.last_timing()
+        if isinstance(st, dict):
+            tm.update({"stats": st})
+        phases.append(tm)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    binding.enable_timing(False)
+    return (t1 - t0) * 1e3 / steps, phases
+
+
+def mean_phases(phases, names):
+    return {k: sum(p[k] for p in phases) / len(phases) for k in names}
+
+
+def train_band_model(binding, torch, synth):
+    """Labels and training on the training set; returns params and a summary."""
+    t0 = time.perf_counter()
+    train = synth.config4(n_pairs=TRAIN["pairs"], seed=TRAIN["seed"])
+    t_gen = time.perf_counter() - t0
+    dev = binding.to_device(train)
+    params = torch.from_numpy(synth.band_params_init(TRAIN["init_seed"], b3=TRAIN["b3"])).cuda()
+    order = torch.from_numpy(synth.minibatch_order(TRAIN["order_seed"], train.n_pairs,
+                                                   TRAIN["steps"], TRAIN["batch"])).cuda()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    binding.train_band_model(*dev, train.subst, train.alpha, train.beta, train.mode, params, order,
+                             TRAIN["steps"], TRAIN["batch"], lr=TRAIN["lr"], tau=TRAIN["tau"])
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    del dev
+    return params, {"pairs": train.n_pairs, "steps": TRAIN["steps"], "batch": TRAIN["batch"],
+                    "lr": TRAIN["lr"], "tau": TRAIN["tau"], "gen_s": round(t_gen, 2),
+                    "labels_and_training_s": round(t_train, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--pairs", type=int, default=None)
-    ap.add_argument("--workload", default="c1", help="c1 (default), c0, c2, c3, c3long, c4")
+    ap.add_argument("--workload", default="c4", help="c4 (default), c0, c1, c2, c3, c3long")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -140,52 +212,75 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
-    from paper_2205_07610_amd import binding
+    from paper_2205_07610_amd import binding, synth
 
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     binding.lib()
+    learned = args.workload == "c4"
+    train_info = None
+    if learned:
+        log("training the band network")
+        params, train_info = train_band_model(binding, torch, synth)
+        log(f"trained: {train_info}")
     log(f"generating workload {args.workload}")
     batch, desc = workload(args.workload, args.pairs)
     cells = batch.cells()
     sa, oa, sb, ob = binding.to_device(batch)
     out = torch.empty(batch.n_pairs, dtype=torch.int32, device="cuda")
+    args_sc = (batch.subst, batch.alpha, batch.beta, batch.mode)
 
-    def step():
-        binding.align_batch(sa, oa, sb, ob, batch.subst, batch.alpha, batch.beta, batch.mode,
-                            scores_out=out)
+    def full_step():
+        binding.align_batch(sa, oa, sb, ob, *args_sc, scores_out=out)
 
-    log(f"warmup {args.warmup}")
-    for _ in range(args.warmup):
-        step()
-    binding.enable_timing(True)
-    phases = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-        tm = binding.last_timing()
-        phases.append(tm)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    binding.enable_timing(False)
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step")
+    full_names = ["full32_ms", "full16_ms", "rerun32_ms", "long_ms", "classify_ms"]
+    log(f"full DP: warmup {args.warmup}, {args.steps} steps")
+    full_ms, full_phases = timed(full_step, args.steps, args.warmup, binding, torch)
+    full_avg = mean_phases(full_phases, full_names)
+    log(f"full DP: {full_ms:.3f} ms/step")
+    full_scores = out.cpu().numpy()
 
-    # dominant kernel: the phase with the largest time
-    ph_names = ["full32_ms", "full16_ms", "rerun32_ms", "long_ms", "classify_ms"]
-    avg = {k: sum(p[k] for p in phases) / len(phases) for k in ph_names}
-    dom = max(ph_names, key=lambda k: avg[k])
-    kernel_ms = avg[dom]
-    kernel_name = dom.replace("_ms", "")
-    packed = kernel_name == "full16"
-    ops = cells * OPS_PER_CELL[batch.mode]
-    achieved = ops / (kernel_ms * 1e-3) / 1e12
-    peak = PEAK_I16X2_TOPS if packed else PEAK_I32_TOPS
+    if learned:
+        out_l = torch.empty(batch.n_pairs, dtype=torch.int32, device="cuda")
 
-    gpu_scores = out.cpu().numpy()
+        def learned_step():
+            return binding.align_batch_learned(sa, oa, sb, ob, *args_sc, params, max_rounds=6,
+                                               scores_out=out_l)[1]
+
+        log(f"learned band: warmup {args.warmup}, {args.steps} steps")
+        ms_per_step, phases = timed(learned_step, args.steps, args.warmup, binding, torch)
+        names = ["features_ms", "mlp_ms", "classify_ms", "band_ms", "full32_ms", "full16_ms",
+                 "rerun32_ms", "long_ms"]
+        avg = mean_phases(phases, names)
+        stats = phases[-1]["stats"]
+        gpu_scores = out_l.cpu().numpy()
+        mism_full = int(np.count_nonzero(gpu_scores != full_scores))
+        log(f"learned band: {ms_per_step:.3f} ms/step, mismatches vs full DP {mism_full}")
+        dom = max(["band_ms", "full32_ms", "long_ms", "features_ms"], key=lambda k: avg[k])
+        kernel_name = {"band_ms": "band", "full32_ms": "full32", "long_ms": "long",
+                       "features_ms": "features"}[dom]
+        if kernel_name == "band":
+            ops = stats["band_cells"] * OPS_PER_CELL[batch.mode]
+        elif kernel_name == "features":
+            ops = 0
+        else:
+            ops = stats["fallback_cells"] * OPS_PER_CELL[batch.mode]
+        roof = roofline(kernel_name, avg[dom], ops, False)
+        roof["ops_per_cell"] = OPS_PER_CELL[batch.mode]
+        roof["cells_note"] = "cells the banded kernel computed (m x band width per round)"
+        dtype = "i32"
+    else:
+        ms_per_step, avg, gpu_scores = full_ms, full_avg, full_scores
+        dom = max(full_names, key=lambda k: avg[k])
+        kernel_name = dom.replace("_ms", "")
+        packed = kernel_name == "full16"
+        roof = roofline(kernel_name, avg[dom], cells * OPS_PER_CELL[batch.mode], packed)
+        roof["ops_per_cell"] = OPS_PER_CELL[batch.mode]
+        dtype = "i16x2" if packed else "i32"
+
     result = {
         "metric": METRIC,
         "value": round(cells / (ms_per_step * 1e-3) / 1e9, 2),
@@ -198,23 +293,31 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "i16x2" if packed else "i32",
+        "dtype": dtype,
         "data": "synthetic",
-        "config": {"workload": desc, "name": args.workload,
-                   "n_pairs": batch.n_pairs, "cells": cells, "mode": MODE_NAMES[batch.mode]},
+        "config": {"workload": desc, "name": args.workload, "n_pairs": batch.n_pairs,
+                   "cells": cells, "mode": MODE_NAMES[batch.mode],
+                   "method": "learned band (certified, exact)" if learned else "full DP"},
         "phases_ms": {k: round(v, 4) for k, v in avg.items()},
-        "roofline": {
-            "bound": "alu",
-            "kernel": kernel_name,
-            "achieved": round(achieved, 3),
-            "peak": round(peak, 2),
-            "unit": "Tops/s",
-            "frac": round(achieved / peak, 4),
-            "kernel_ms": round(kernel_ms, 4),
-            "ops_per_cell": OPS_PER_CELL[batch.mode],
-            "traffic": traffic_for(kernel_name) if kernel_name in KERNEL_SOURCES else None,
-        },
+        "roofline": roof,
     }
+    if learned:
+        result["value_note"] = "effective GCUPS: sum of m*n over the batch / learned step time"
+        fr = roofline(max(full_names, key=lambda k: full_avg[k]).replace("_ms", ""),
+                      max(full_avg.values()), cells * OPS_PER_CELL[batch.mode], False)
+        result["full_dp"] = {
+            "ms_per_step": round(full_ms, 4),
+            "GCUPS": round(cells / (full_ms * 1e-3) / 1e9, 2),
+            "pairs_per_s": round(batch.n_pairs / (full_ms * 1e-3), 1),
+            "phases_ms": {k: round(v, 4) for k, v in full_avg.items()},
+            "roofline": fr,
+        }
+        result["speedup_vs_full_dp"] = round(full_ms / ms_per_step, 3)
+        result["mismatches_vs_full_dp"] = mism_full
+        result["band_stats"] = {k: stats[k] for k in ("rounds", "accepted", "fallback", "band_cells",
+                                                      "fallback_cells", "dp_cells")}
+        result["band_stats"]["dp_cells_frac"] = round(stats["dp_cells"] / cells, 4)
+        result["training"] = train_info
     if not args.no_cpu_baseline:
         log(f"cpu baseline (~{args.cpu_seconds} s)")
         cb, mism, checked = cpu_baseline(batch, args.cpu_seconds, gpu_scores)
