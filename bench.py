@@ -175,6 +175,20 @@ def mean_phases(phases, names):
     return {k: sum(p[k] for p in phases) / len(phases) for k in names}
 
 
+# cells each full-DP phase processed, from the library's per-route counts
+PHASE_CELLS = {"full32_ms": "cells_full32", "full16_ms": "cells_full16", "long_ms": "cells_long"}
+
+
+def phase_roofline(phases, name, ops_per_cell):
+    """Roofline of one full-DP phase: its own cells x ops per cell / its time."""
+    ms = sum(p[name] for p in phases) / len(phases)
+    cells = phases[-1][PHASE_CELLS[name]] if name in PHASE_CELLS else 0
+    r = roofline(name.replace("_ms", ""), ms, cells * ops_per_cell, name == "full16_ms")
+    r["cells"] = cells
+    r["ops_per_cell"] = ops_per_cell
+    return r
+
+
 def train_band_model(binding, torch, synth):
     """Labels and training on the training set; returns params and a summary."""
     t0 = time.perf_counter()
@@ -205,6 +219,9 @@ def main():
     ap.add_argument("--workload", default="c4", help="c4 (default), c0, c1, c2, c3, c3long")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-reference", action="store_true",
+                    help="first copy 1 GiB device-to-device three times (untimed): the known-size "
+                         "reference that scales HBM byte counters in a profiler run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -220,6 +237,13 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     binding.lib()
+    if args.copy_reference:
+        src = torch.ones(1 << 30, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     learned = args.workload == "c4"
     train_info = None
     if learned:
@@ -259,27 +283,20 @@ def main():
         gpu_scores = out_l.cpu().numpy()
         mism_full = int(np.count_nonzero(gpu_scores != full_scores))
         log(f"learned band: {ms_per_step:.3f} ms/step, mismatches vs full DP {mism_full}")
-        dom = max(["band_ms", "full32_ms", "long_ms", "features_ms"], key=lambda k: avg[k])
-        kernel_name = {"band_ms": "band", "full32_ms": "full32", "long_ms": "long",
-                       "features_ms": "features"}[dom]
-        if kernel_name == "band":
-            ops = stats["band_cells"] * OPS_PER_CELL[batch.mode]
-        elif kernel_name == "features":
-            ops = 0
+        dom = max(["band_ms", "full32_ms", "long_ms"], key=lambda k: avg[k])
+        if dom == "band_ms":
+            roof = roofline("band", avg[dom], stats["band_cells"] * OPS_PER_CELL[batch.mode], False)
+            roof["cells"] = stats["band_cells"]
+            roof["ops_per_cell"] = OPS_PER_CELL[batch.mode]
+            roof["cells_note"] = "cells the banded kernel computed (m x band width, every round)"
         else:
-            ops = stats["fallback_cells"] * OPS_PER_CELL[batch.mode]
-        roof = roofline(kernel_name, avg[dom], ops, False)
-        roof["ops_per_cell"] = OPS_PER_CELL[batch.mode]
-        roof["cells_note"] = "cells the banded kernel computed (m x band width per round)"
+            roof = phase_roofline(phases, dom, OPS_PER_CELL[batch.mode])
         dtype = "i32"
     else:
         ms_per_step, avg, gpu_scores = full_ms, full_avg, full_scores
         dom = max(full_names, key=lambda k: avg[k])
-        kernel_name = dom.replace("_ms", "")
-        packed = kernel_name == "full16"
-        roof = roofline(kernel_name, avg[dom], cells * OPS_PER_CELL[batch.mode], packed)
-        roof["ops_per_cell"] = OPS_PER_CELL[batch.mode]
-        dtype = "i16x2" if packed else "i32"
+        roof = phase_roofline(full_phases, dom, OPS_PER_CELL[batch.mode])
+        dtype = "i16x2" if dom == "full16_ms" else "i32"
 
     result = {
         "metric": METRIC,
@@ -303,14 +320,14 @@ def main():
     }
     if learned:
         result["value_note"] = "effective GCUPS: sum of m*n over the batch / learned step time"
-        fr = roofline(max(full_names, key=lambda k: full_avg[k]).replace("_ms", ""),
-                      max(full_avg.values()), cells * OPS_PER_CELL[batch.mode], False)
+        fr = {k.replace("_ms", ""): phase_roofline(full_phases, k, OPS_PER_CELL[batch.mode])
+              for k in ("full32_ms", "full16_ms", "long_ms") if full_avg[k] > 0}
         result["full_dp"] = {
             "ms_per_step": round(full_ms, 4),
             "GCUPS": round(cells / (full_ms * 1e-3) / 1e9, 2),
             "pairs_per_s": round(batch.n_pairs / (full_ms * 1e-3), 1),
             "phases_ms": {k: round(v, 4) for k, v in full_avg.items()},
-            "roofline": fr,
+            "roofline_per_kernel": fr,
         }
         result["speedup_vs_full_dp"] = round(full_ms / ms_per_step, 3)
         result["mismatches_vs_full_dp"] = mism_full

@@ -115,6 +115,9 @@ typedef struct {
     int64_t pairs_long;
     int64_t pairs_fallback; /* banded pairs that went to the full DP */
     int64_t cells;      /* sum of m*n over the batch */
+    int64_t cells_full32;   /* sum of m*n of the pairs of each full-DP route */
+    int64_t cells_full16;
+    int64_t cells_long;
 } as_timing;
 
 /*

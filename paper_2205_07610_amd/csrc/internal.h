@@ -63,6 +63,7 @@ struct Counters {
   int32_t band_accepted[8];  // pairs accepted in round r
   unsigned long long band_cells;  // cells computed by the banded kernel
   unsigned long long fallback_cells;  // sum of m*n over the fallback pairs
+  unsigned long long route_cells[4];  // sum of m*n per full-DP route (index = route)
 };
 
 // ---- banded path ----

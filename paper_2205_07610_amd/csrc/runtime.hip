@@ -107,6 +107,7 @@ struct BlockLists {
   int cnt[R];
   int base[R];
   unsigned long long cells;
+  unsigned long long rcells[R];  // m*n per route
 };
 
 __device__ inline unsigned long long valid_cells(int64_t a0, int64_t m, int64_t b0, int64_t n) {
@@ -121,7 +122,10 @@ __global__ void __launch_bounds__(256) classify_kernel(RouteParams c, const int6
   const int64_t chunk = (c.n_pairs + gridDim.x - 1) / gridDim.x;
   const int64_t lo = (int64_t)blockIdx.x * chunk;
   const int64_t hi = lo + chunk < c.n_pairs ? lo + chunk : c.n_pairs;
-  if (threadIdx.x < kFullRoutes) bl.cnt[threadIdx.x] = 0;
+  if (threadIdx.x < kFullRoutes) {
+    bl.cnt[threadIdx.x] = 0;
+    bl.rcells[threadIdx.x] = 0;
+  }
   if (threadIdx.x == 0) bl.cells = 0;
   __syncthreads();
   unsigned long long cells = 0;
@@ -134,6 +138,7 @@ __global__ void __launch_bounds__(256) classify_kernel(RouteParams c, const int6
     const int r = route_full(c, a0, m, b0, n, p, d);
     if (r == kRoute32 && d.n > c.stripe_w) atomicMax(&ctr->max_rows_multi, d.m);
     atomicAdd(&bl.cnt[r], 1);
+    atomicAdd(&bl.rcells[r], (unsigned long long)(m * n));
   }
   atomicAdd(&bl.cells, cells);
   __syncthreads();
@@ -142,7 +147,10 @@ __global__ void __launch_bounds__(256) classify_kernel(RouteParams c, const int6
     bl.base[kRoute16] = bl.cnt[kRoute16] ? atomicAdd(&ctr->n_full16, bl.cnt[kRoute16]) : 0;
     bl.base[kRouteLong] = bl.cnt[kRouteLong] ? atomicAdd(&ctr->n_long, bl.cnt[kRouteLong]) : 0;
     if (bl.cells) atomicAdd(&ctr->cells, bl.cells);
-    for (int r = 0; r < kFullRoutes; ++r) bl.cnt[r] = 0;
+    for (int r = 0; r < kFullRoutes; ++r) {
+      if (bl.rcells[r]) atomicAdd(&ctr->route_cells[r], bl.rcells[r]);
+      bl.cnt[r] = 0;
+    }
   }
   __syncthreads();
   for (int64_t p = lo + threadIdx.x; p < hi; p += blockDim.x) {
@@ -166,7 +174,10 @@ __global__ void __launch_bounds__(256) route_fallback_kernel(RouteParams c, cons
   const int64_t chunk = (total + gridDim.x - 1) / gridDim.x;
   const int64_t lo = (int64_t)blockIdx.x * chunk;
   const int64_t hi = lo + chunk < total ? lo + chunk : total;
-  if (threadIdx.x < kFullRoutes) bl.cnt[threadIdx.x] = 0;
+  if (threadIdx.x < kFullRoutes) {
+    bl.cnt[threadIdx.x] = 0;
+    bl.rcells[threadIdx.x] = 0;
+  }
   if (threadIdx.x == 0) bl.cells = 0;
   __syncthreads();
   unsigned long long cells = 0;
@@ -182,12 +193,15 @@ __global__ void __launch_bounds__(256) route_fallback_kernel(RouteParams c, cons
     const int r = route(i, d);
     if (r == kRoute32 && d.n > c.stripe_w) atomicMax(&ctr->max_rows_multi, d.m);
     atomicAdd(&bl.cnt[r], 1);
+    atomicAdd(&bl.rcells[r], (unsigned long long)((int64_t)d.m * d.n));
     cells += (unsigned long long)((int64_t)d.m * d.n);
   }
   atomicAdd(&bl.cells, cells);
   __syncthreads();
   if (threadIdx.x == 0) {
     if (bl.cells) atomicAdd(&ctr->fallback_cells, bl.cells);
+    for (int r = 0; r < kFullRoutes; ++r)
+      if (bl.rcells[r]) atomicAdd(&ctr->route_cells[r], bl.rcells[r]);
     bl.base[kRoute32] = bl.cnt[kRoute32] ? atomicAdd(&ctr->n_full32, bl.cnt[kRoute32]) : 0;
     bl.base[kRoute16] = bl.cnt[kRoute16] ? atomicAdd(&ctr->n_full16, bl.cnt[kRoute16]) : 0;
     bl.base[kRouteLong] = bl.cnt[kRouteLong] ? atomicAdd(&ctr->n_long, bl.cnt[kRouteLong]) : 0;
@@ -565,6 +579,9 @@ int run_full_lists(Workspace *w, const CallScoring &cs, const uint8_t *seqs_a,
   g_last_timing.pairs_full32 += c.n_full32;
   g_last_timing.pairs_full16 += c.n_full16;
   g_last_timing.pairs_long += c.n_long;
+  g_last_timing.cells_full32 = (int64_t)c2.route_cells[kRoute32];
+  g_last_timing.cells_full16 = (int64_t)c2.route_cells[kRoute16];
+  g_last_timing.cells_long = (int64_t)c2.route_cells[kRouteLong];
   if (timing && c.n_full16 > 0) g_last_timing.full16_ms += elapsed(w->ev[2], w->ev[3]);
   if (timing && c.n_full32 > 0) g_last_timing.full32_ms += elapsed(w->ev[4], w->ev[5]);
   if (timing && c.n_long > 0) g_last_timing.long_ms += elapsed(w->ev[8], w->ev[9]);
