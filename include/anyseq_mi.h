@@ -273,6 +273,53 @@ int as_align_batch_learned(const uint8_t *seqs_a, const int64_t *offs_a, const u
                            int32_t *scores_out, as_band_stats *stats, void *stream);
 
 /*
+ * Full-DP kernel variants per length bin (batching runtime; not in the
+ * paper).  Bin b holds the pairs whose longer sequence has at most 64 << b
+ * residues (b = 0..AS_LEN_BINS-1, the last bin everything longer).  Within
+ * each kernel's work list the pairs are ordered by bin, longest first.  A
+ * bin's variant is one of
+ *   AS_VARIANT_AUTO       automatic: packed 16-bit when the shorter side has
+ *                         at most 256 residues and the range is proven (or
+ *                         local), the wavefront for at least 2048 rows and
+ *                         more than 1024 columns, else 32-bit with K = 16;
+ *   AS_VARIANT_PACKED16   packed 16-bit kernel (two pairs per lane group);
+ *   AS_VARIANT_K8/K16/K32 32-bit stripe kernel with 8/16/32 columns per lane;
+ *   AS_VARIANT_WAVEFRONT  multi-wave wavefront (1024-column stripes).
+ * A pair the bin's variant cannot serve (packed: range or width; wavefront:
+ * at most 1024 columns) takes the automatic rule.  Every variant computes
+ * the same exact scores; the table only changes speed.  Tables are kept per
+ * mode for the process.
+ */
+#define AS_LEN_BINS 12
+#define AS_VARIANT_AUTO (-1)
+#define AS_VARIANT_PACKED16 0
+#define AS_VARIANT_K8 1
+#define AS_VARIANT_K16 2
+#define AS_VARIANT_K32 3
+#define AS_VARIANT_WAVEFRONT 4
+#define AS_VARIANTS 5
+
+/* Set the table of a mode (HOST int8 [AS_LEN_BINS]; NULL: all automatic). */
+int as_set_variants(int32_t mode, const int8_t *table);
+/* Copy the table of a mode into table_out (HOST int8 [AS_LEN_BINS]). */
+int as_get_variants(int32_t mode, int8_t *table_out);
+
+/*
+ * Autotuner: for every length bin present in the batch, time each variant
+ * on a sample of the bin's pairs (every stride-th pair: at most sample_pairs
+ * pairs and about 1e11 cells; best of two runs, HIP events around the DP
+ * kernels) and keep the fastest in the mode's table.  Bins without pairs
+ * keep their entry.  The sample's scores go to library scratch memory.
+ *   gcups_out : optional HOST float [AS_LEN_BINS * AS_VARIANTS]: measured
+ *               GCUPS per (bin, variant), 0 where not measured
+ *   table_out : optional HOST int8 [AS_LEN_BINS]: the resulting table
+ * Same arguments and errors as as_align_batch otherwise.
+ */
+int as_autotune(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t *seqs_b,
+                const int64_t *offs_b, int64_t n_pairs, const as_scoring *scoring, int32_t mode,
+                int32_t sample_pairs, float *gcups_out, int8_t *table_out, void *stream);
+
+/*
  * Saturation threshold of the packed 16-bit local path: a pair whose 16-bit
  * maximum reaches `limit` is treated as saturated and recomputed with 32-bit
  * cells.  The default, 32767, is the int16 saturation value itself; a lower

@@ -105,6 +105,12 @@ def lib() -> ctypes.CDLL:
     L.as_align_batch_learned.restype = ctypes.c_int
     L.as_align_batch_learned.argtypes = [p, p, p, p, i64, ctypes.POINTER(Scoring), i32, p, i32, p,
                                          ctypes.POINTER(BandStats), p]
+    L.as_set_variants.restype = ctypes.c_int
+    L.as_set_variants.argtypes = [i32, p]
+    L.as_get_variants.restype = ctypes.c_int
+    L.as_get_variants.argtypes = [i32, p]
+    L.as_autotune.restype = ctypes.c_int
+    L.as_autotune.argtypes = [p, p, p, p, i64, ctypes.POINTER(Scoring), i32, i32, p, p, p]
     L.as_set_i16_limit.restype = ctypes.c_int
     L.as_set_i16_limit.argtypes = [ctypes.c_int32]
     L.as_enable_timing.restype = ctypes.c_int
@@ -355,6 +361,44 @@ def align_batch_learned(seqs_a, offs_a, seqs_b, offs_b, subst, alpha: int, beta:
     del keep
     _check(rc)
     return scores_out[:n_pairs], st.as_dict()
+
+
+LEN_BINS = 12
+VARIANTS = {"auto": -1, "packed16": 0, "k8": 1, "k16": 2, "k32": 3, "wavefront": 4}
+
+
+def set_variants(mode: int, table=None):
+    """Full-DP variant per length bin for a mode (None: all automatic)."""
+    if table is None:
+        _check(lib().as_set_variants(int(mode), None))
+        return
+    t = np.ascontiguousarray(np.asarray(table, dtype=np.int8))
+    if t.shape != (LEN_BINS,):
+        raise ValueError(f"table must have {LEN_BINS} entries")
+    _check(lib().as_set_variants(int(mode), t.ctypes.data_as(ctypes.c_void_p)))
+
+
+def get_variants(mode: int) -> np.ndarray:
+    t = np.zeros(LEN_BINS, dtype=np.int8)
+    _check(lib().as_get_variants(int(mode), t.ctypes.data_as(ctypes.c_void_p)))
+    return t
+
+
+def autotune(seqs_a, offs_a, seqs_b, offs_b, subst, alpha: int, beta: int, mode: int,
+             sample_pairs: int = 8192, stream=None):
+    """Run the autotuner; returns (table int8 [12], gcups float [12, 5])."""
+    import torch
+    n_pairs = offs_a.numel() - 1
+    dev = offs_a.device
+    sc, keep = make_scoring(subst, alpha, beta)
+    g = np.zeros(LEN_BINS * 5, dtype=np.float32)
+    t = np.zeros(LEN_BINS, dtype=np.int8)
+    rc = lib().as_autotune(*_seq_ptrs(seqs_a, offs_a, seqs_b, offs_b), n_pairs, ctypes.byref(sc),
+                           int(mode), int(sample_pairs), g.ctypes.data_as(ctypes.c_void_p),
+                           t.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(_stream(dev, stream)))
+    del keep
+    _check(rc)
+    return t, g.reshape(LEN_BINS, 5)
 
 
 def enable_timing(on: bool = True) -> bool:

@@ -27,6 +27,13 @@
 //    equals max(..., E, F, 0) because E' = max(E, 0).  Seven operations per
 //    cell plus the running maximum.
 //
+// Variants: K = 8, 16 or 32 columns per lane (stripes of 128, 256 or 512
+// columns).  One persistent launch drains a work list ordered by length bin;
+// the list is laid out in quads (one per wave, one item per group) that never
+// mix variants, and each quad carries its K in the descriptor flags, so a
+// wave takes the matching code path for all four of its groups.  The kernel
+// is instantiated for the set of variants the list holds.
+//
 // Padding: global pads the last stripe on the right (result cell H(m,n) is
 // picked out at the end).  Semi-global and local pad the first stripe on the
 // left with columns whose sigma is 0: such columns keep H = 0 in every row,
@@ -38,8 +45,6 @@
 namespace asmi {
 namespace {
 
-constexpr int kK = 16;                 // columns per lane
-constexpr int kW = kGroup * kK;        // columns per stripe
 
 __device__ __forceinline__ int dpp_shr1(int old, int src) {
   // row_shr:1 -- lane t reads lane t-1 of its 16-lane row; lane 0 keeps `old`.
@@ -65,32 +70,17 @@ __device__ __forceinline__ int wave_max_groups(int v) {
   return v;
 }
 
+// One quad of items (one per group) with K columns per lane.
 template <int MODE, int K>
-__global__ void __launch_bounds__(kWave) full_dp_i32_kernel(FullDpArgs a) {
+__device__ __forceinline__ void align_quad(const FullDpArgs &a, int8_t *prof, int2 *slot, PairDesc d,
+                                           bool has, int t) {
   constexpr int W = kGroup * K;
-  extern __shared__ __align__(16) int8_t lds[];
-  const int lane = threadIdx.x;
-  const int g = lane >> 4;
-  const int t = lane & 15;
   const int asz = a.asz;
-  int8_t *prof = lds + g * asz * W;
   const int alpha = a.alpha, beta = a.beta;
-  const int n_items = *a.n_items;
-  int2 *slot = a.bnd + ((int64_t)blockIdx.x * kGroupsPerWave + g) * 2 * a.bnd_rows;
-
   // Profile bias: the value added to the stored diagonal (see header).
   const int bias = (MODE == kLocal) ? alpha : alpha + beta;
   const int amb = alpha - beta;
-
-  for (;;) {
-    int base = 0;
-    if (lane == 0) base = atomicAdd(a.next, kGroupsPerWave);
-    base = __shfl(base, 0);
-    if (base >= n_items) break;
-    const int item = base + g;
-    const bool has = item < n_items;
-    PairDesc d{0, 0, 0, 0, -1, 0};
-    if (has) d = a.items[item];
+  {
     const int m = has ? d.m : 0;
     const int n = has ? d.n : 0;
     const int S = has ? (n + W - 1) / W : 0;
@@ -183,17 +173,27 @@ __global__ void __launch_bounds__(kWave) full_dp_i32_kernel(FullDpArgs a) {
           const int fl = dpp_shr1(fsrc, fout);
           if ((unsigned)(row - 1) < (unsigned)m_s) {
             const int8_t *pp = prof + qc * W + t * K;
-            int4 pw[K / 16];
+            int pw[K / 4];
+            if constexpr (K % 16 == 0) {
 #pragma unroll
-            for (int v = 0; v < K / 16; ++v) pw[v] = *(const int4 *)(pp + 16 * v);
+              for (int v = 0; v < K / 16; ++v) {
+                const int4 q = *(const int4 *)(pp + 16 * v);
+                pw[4 * v] = q.x;
+                pw[4 * v + 1] = q.y;
+                pw[4 * v + 2] = q.z;
+                pw[4 * v + 3] = q.w;
+              }
+            } else {
+              static_assert(K == 8, "K is 8, 16 or 32");
+              const int2 q = *(const int2 *)pp;
+              pw[0] = q.x;
+              pw[1] = q.y;
+            }
             int dg = hl_prev;
             int f = fl;
 #pragma unroll
             for (int x = 0; x < K; ++x) {
-              const int word = (x & 15) >> 2;
-              const int w32 = word == 0 ? pw[x >> 4].x : word == 1 ? pw[x >> 4].y
-                            : word == 2 ? pw[x >> 4].z : pw[x >> 4].w;
-              const int sc = (int)(int8_t)(w32 >> (8 * (x & 3)));
+              const int sc = (int)(int8_t)(pw[x >> 2] >> (8 * (x & 3)));
               if (MODE == kLocal) {
                 const int e = imax3(Ee[x] - beta, Ha[x], 0);
                 const int h = imax3(dg + sc, e, f);
@@ -259,37 +259,101 @@ __global__ void __launch_bounds__(kWave) full_dp_i32_kernel(FullDpArgs a) {
   }
 }
 
+// Persistent kernel over a quad-aligned list.  KMASK is the set of variants
+// the list may hold (bit 0: K = 8, bit 1: K = 16, bit 2: K = 32); a
+// single-variant instantiation has no dispatch and the register footprint
+// of that variant alone, the mixed one sizes registers and LDS for the
+// widest.
+template <int MODE, int KMASK>
+__global__ void __launch_bounds__(kWave) full_dp_i32_kernel(FullDpArgs a) {
+  constexpr int KMAX = (KMASK & 4) ? 32 : ((KMASK & 2) ? 16 : 8);
+  extern __shared__ __align__(16) int8_t lds[];
+  const int lane = threadIdx.x;
+  const int g = lane >> 4;
+  const int t = lane & 15;
+  int8_t *prof = lds + g * a.asz * (kGroup * KMAX);
+  const int n_items = *a.n_items;
+  int2 *slot = a.bnd + ((int64_t)blockIdx.x * kGroupsPerWave + g) * 2 * a.bnd_rows;
+  for (;;) {
+    int base = 0;
+    if (lane == 0) base = atomicAdd(a.next, kGroupsPerWave);
+    base = __shfl(base, 0);
+    if (base >= n_items) break;
+    const int item = base + g;
+    PairDesc d{0, 0, 0, 0, -1, 0};
+    if (item < n_items) d = a.items[item];
+    const bool has = item < n_items && d.pair >= 0;  // padding slots carry pair -1
+    if constexpr (KMASK == 1) {
+      align_quad<MODE, 8>(a, prof, slot, d, has, t);
+    } else if constexpr (KMASK == 2) {
+      align_quad<MODE, 16>(a, prof, slot, d, has, t);
+    } else if constexpr (KMASK == 4) {
+      align_quad<MODE, 32>(a, prof, slot, d, has, t);
+    } else {
+      // the quad's variant (uniform: quads never mix variants)
+      const int kv = __shfl(variant_of(d.flags), 0);
+      if (kv == kVarI32K8) align_quad<MODE, 8>(a, prof, slot, d, has, t);
+      else if (kv == kVarI32K32) align_quad<MODE, 32>(a, prof, slot, d, has, t);
+      else align_quad<MODE, 16>(a, prof, slot, d, has, t);
+    }
+  }
+}
+
+// The instantiation covering a set of variants: one of them alone, or all.
+int kmask_instance(int kmask) { return (kmask == 1 || kmask == 2 || kmask == 4) ? kmask : 7; }
+
 template <int MODE>
-hipError_t launch_mode(const FullDpArgs &args, int grid, hipStream_t stream) {
-  const size_t lds = full_dp_i32_lds_bytes(args.asz);
-  hipLaunchKernelGGL((full_dp_i32_kernel<MODE, kK>), dim3(grid), dim3(kWave), lds, stream, args);
+hipError_t launch_mode(const FullDpArgs &args, int kmask, int grid, hipStream_t stream) {
+  const size_t lds = full_dp_i32_lds_bytes(args.asz, kmask);
+  switch (kmask_instance(kmask)) {
+    case 1: hipLaunchKernelGGL((full_dp_i32_kernel<MODE, 1>), dim3(grid), dim3(kWave), lds, stream, args); break;
+    case 2: hipLaunchKernelGGL((full_dp_i32_kernel<MODE, 2>), dim3(grid), dim3(kWave), lds, stream, args); break;
+    case 4: hipLaunchKernelGGL((full_dp_i32_kernel<MODE, 4>), dim3(grid), dim3(kWave), lds, stream, args); break;
+    default: hipLaunchKernelGGL((full_dp_i32_kernel<MODE, 7>), dim3(grid), dim3(kWave), lds, stream, args); break;
+  }
   return hipGetLastError();
+}
+
+template <int MODE, int KMASK>
+int occupancy(size_t lds) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, full_dp_i32_kernel<MODE, KMASK>, kWave, lds) !=
+          hipSuccess || nb < 1)
+    nb = 1;
+  return nb;
+}
+
+template <int MODE>
+int occupancy_mode(int kmask, size_t lds) {
+  switch (kmask_instance(kmask)) {
+    case 1: return occupancy<MODE, 1>(lds);
+    case 2: return occupancy<MODE, 2>(lds);
+    case 4: return occupancy<MODE, 4>(lds);
+    default: return occupancy<MODE, 7>(lds);
+  }
 }
 
 }  // namespace
 
-size_t full_dp_i32_lds_bytes(int asz) { return (size_t)kGroupsPerWave * asz * kW; }
-int full_dp_i32_stripe_width() { return kW; }
+size_t full_dp_i32_lds_bytes(int asz, int kmask) {
+  const int inst = kmask_instance(kmask);
+  const int kmax = (inst & 4) ? 32 : ((inst & 2) ? 16 : 8);
+  return (size_t)kGroupsPerWave * asz * kGroup * kmax;
+}
+int full_dp_i32_stripe_width(int k) { return kGroup * k; }
 
-int full_dp_i32_blocks_per_cu(int mode, int asz) {
-  int nb = 0;
-  const size_t lds = full_dp_i32_lds_bytes(asz);
-  hipError_t e;
-  if (mode == kGlobal)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, full_dp_i32_kernel<kGlobal, kK>, kWave, lds);
-  else if (mode == kSemiGlobal)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, full_dp_i32_kernel<kSemiGlobal, kK>, kWave, lds);
-  else
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, full_dp_i32_kernel<kLocal, kK>, kWave, lds);
-  if (e != hipSuccess || nb < 1) nb = 1;
-  return nb;
+int full_dp_i32_blocks_per_cu(int mode, int asz, int kmask) {
+  const size_t lds = full_dp_i32_lds_bytes(asz, kmask);
+  if (mode == kGlobal) return occupancy_mode<kGlobal>(kmask, lds);
+  if (mode == kSemiGlobal) return occupancy_mode<kSemiGlobal>(kmask, lds);
+  return occupancy_mode<kLocal>(kmask, lds);
 }
 
-hipError_t launch_full_dp_i32(int mode, const FullDpArgs &args, int grid, hipStream_t stream) {
+hipError_t launch_full_dp_i32(int mode, const FullDpArgs &args, int kmask, int grid, hipStream_t stream) {
   switch (mode) {
-    case kGlobal: return launch_mode<kGlobal>(args, grid, stream);
-    case kSemiGlobal: return launch_mode<kSemiGlobal>(args, grid, stream);
-    default: return launch_mode<kLocal>(args, grid, stream);
+    case kGlobal: return launch_mode<kGlobal>(args, kmask, grid, stream);
+    case kSemiGlobal: return launch_mode<kSemiGlobal>(args, kmask, grid, stream);
+    default: return launch_mode<kLocal>(args, kmask, grid, stream);
   }
 }
 

@@ -35,11 +35,37 @@ struct PairDesc {
 };
 constexpr int32_t kTransposed = 1;
 
+// Full-DP variants (chosen per length bin, by default or by the autotuner):
+// the packed 16-bit kernel, the 32-bit stripe kernel with K = 8, 16 or 32
+// columns per lane, and the multi-wave wavefront.  Bits 8..15 of
+// PairDesc::flags carry the variant of a 32-bit list item.
+enum Variant : int32_t {
+  kVarI16 = 0,
+  kVarI32K8 = 1,
+  kVarI32K16 = 2,
+  kVarI32K32 = 3,
+  kVarLong = 4,
+  kNumVariants = 5
+};
+__host__ __device__ inline int variant_of(int32_t flags) { return (flags >> 8) & 0xFF; }
+__host__ __device__ inline int32_t with_variant(int32_t flags, int v) { return (flags & ~0xFF00) | (v << 8); }
+__host__ __device__ inline int variant_k(int v) { return v == kVarI32K8 ? 8 : (v == kVarI32K32 ? 32 : 16); }
+
+// Length bins: bin b holds pairs whose longer sequence has at most 64 << b
+// residues (the last bin everything longer).
+constexpr int kLenBins = 12;
+__host__ __device__ inline int length_bin(int64_t longer) {
+  int b = 0;
+  while (b < kLenBins - 1 && longer > ((int64_t)64 << b)) ++b;
+  return b;
+}
+
 // Status word bits, OR-ed by kernels; read back once per call.
 constexpr int32_t kStatusBadOffsets = 1;
 constexpr int32_t kStatusBadResidue = 2;
 constexpr int32_t kStatusRange = 4;
 constexpr int32_t kStatusStall = 8;   // a wavefront wait exceeded its spin limit
+constexpr int32_t kStatusPlan = 32;   // a planned replay met a batch its buffers cannot hold
 
 // Work-list counters written by the classify kernel.
 struct Counters {
@@ -63,7 +89,14 @@ struct Counters {
   int32_t band_accepted[8];  // pairs accepted in round r
   unsigned long long band_cells;  // cells computed by the banded kernel
   unsigned long long fallback_cells;  // sum of m*n over the fallback pairs
-  unsigned long long route_cells[4];  // sum of m*n per full-DP route (index = route)
+  unsigned long long route_cells[4];  // sum of m*n per full-DP list (16-bit, 32-bit, wavefront)
+  // length-binned lists: counts, offsets and scatter cursors per (list, bin)
+  int32_t bin_count[3][kLenBins];
+  int32_t bin_base[3][kLenBins];
+  int32_t bin_cursor[3][kLenBins];
+  int32_t bin_var32[kLenBins];   // 32-bit variant of each bin
+  int32_t kmask32;               // K variants present in the 32-bit list
+  unsigned long long bin_cells[kLenBins];  // sum of m*n of the routed pairs per bin
 };
 
 // ---- banded path ----
@@ -179,6 +212,7 @@ int band_call(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t *seqs_
               int32_t max_rounds, int32_t raw, int32_t exact, int32_t *scores_out, int32_t *lo_out,
               int32_t *hi_out, int32_t *accept_out, as_band_stats *stats, void *stream_ptr);
 bool timing_enabled();
+void release_learned_workspace();
 void record_learned_timing(float features_ms, float mlp_ms);
 hipError_t launch_mlp_train_step(const float *features, const int32_t *labels, const int32_t *order,
                                  int32_t batch, float tau, float *params, float *m1, float *m2,
@@ -249,12 +283,16 @@ int full_dp_i16_blocks_per_cu(int mode);
 int full_dp_i16_stripe_width();
 
 // Launch the persistent 32-bit full-DP kernel for `mode` on `grid` blocks
-// of one wave each.  Returns hipSuccess or the launch error.
-hipError_t launch_full_dp_i32(int mode, const FullDpArgs &args, int grid, hipStream_t stream);
-// Resident one-wave blocks per CU for the kernel (occupancy query).
-int full_dp_i32_blocks_per_cu(int mode, int asz);
+// of one wave each; kmask is the set of K variants the list holds (bit 0:
+// K = 8, bit 1: 16, bit 2: 32).  Returns hipSuccess or the launch error.
+hipError_t launch_full_dp_i32(int mode, const FullDpArgs &args, int kmask, int grid, hipStream_t stream);
+// Resident one-wave blocks per CU for that instantiation (occupancy query).
+int full_dp_i32_blocks_per_cu(int mode, int asz, int kmask);
 // Columns per stripe (16 lanes x K).
-int full_dp_i32_stripe_width();
-size_t full_dp_i32_lds_bytes(int asz);
+int full_dp_i32_stripe_width(int k);
+size_t full_dp_i32_lds_bytes(int asz, int kmask);
+__host__ __device__ inline int kmask_of_variant(int v) {
+  return v == kVarI32K8 ? 1 : (v == kVarI32K32 ? 4 : 2);
+}
 
 }  // namespace asmi

@@ -287,6 +287,25 @@ bool bad_train_args(int64_t n, int32_t n_steps, int32_t batch, int32_t t0, float
 }
 
 }  // namespace
+
+void release_learned_workspace() {
+  std::lock_guard<std::mutex> guard(g_llock);
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  for (LearnedWs &w : g_lws) {
+    if (w.device < 0) continue;
+    (void)hipSetDevice(w.device);
+    void *bufs[] = {w.features, w.w, w.full, w.band, w.accept, w.state, w.labels, w.partials, w.adam, w.dstat};
+    for (void *b : bufs)
+      if (b) (void)hipFree(b);
+    if (w.hstat) (void)hipHostFree(w.hstat);
+    for (auto &e : w.ev)
+      if (e) (void)hipEventDestroy(e);
+    w = LearnedWs();
+  }
+  (void)hipSetDevice(cur);
+}
+
 }  // namespace asmi
 
 using namespace asmi;

@@ -32,40 +32,63 @@ constexpr int32_t kStatusArg = 16;                    // band wider than the wid
 struct RouteParams {
   int64_t n_pairs;
   int32_t mode, alpha, beta, smax_abs, smax_pos;
-  int32_t stripe_w, allow16, stripe_w16;
+  int32_t allow16;        // the scoring fits the packed kernel's byte profile
   int32_t long_w;         // stripe width of the wavefront kernel
-  int32_t long_min_rows;  // pairs with at least this many rows and more than
-                          // one wavefront stripe of columns go to the wavefront
+  int32_t long_min_rows;  // automatic routing: rows needed for the wavefront
+  int32_t only_bin;       // -1, or the one length bin to route (autotuning)
+  int8_t var_of_bin[kLenBins];        // variant per length bin, -1 = automatic
+  int32_t sample_stride[kLenBins];    // route every stride-th pair of a bin (1: all)
 };
 
-enum Route { kRouteNone = 0, kRoute32 = 1, kRoute16 = 2, kRouteLong = 3 };
-constexpr int kFullRoutes = 4;
+// Work lists of the full DP, by kernel.
+enum List { kList16 = 0, kList32 = 1, kListLong = 2, kLists = 3 };
 
-// Orientation and full-DP route of a non-empty pair (A at a0, length m; B at
-// b0, length n).
-__device__ int route_full(const RouteParams &c, int64_t a0, int64_t m, int64_t b0, int64_t n,
-                          int64_t p, PairDesc &d) {
-  // A stripe pass costs (rows + 15) steps over 16*K columns; take the cheaper
-  // of A-as-rows and B-as-rows.
-  const int64_t sa = (n + c.stripe_w - 1) / c.stripe_w, sb = (m + c.stripe_w - 1) / c.stripe_w;
-  const int64_t cost_a = sa * (m + kGroup - 1), cost_b = sb * (n + kGroup - 1);
-  const bool tr = cost_b < cost_a;
+// Orientation minimising the stripe passes of a 32-bit kernel with stripes
+// of W columns: a pass costs (rows + 15) steps.
+__device__ inline bool orient_rows_b(int64_t m, int64_t n, int W) {
+  const int64_t sa = (n + W - 1) / W, sb = (m + W - 1) / W;
+  return sb * (n + kGroup - 1) < sa * (m + kGroup - 1);
+}
+
+__device__ inline void fill_desc(PairDesc &d, bool tr, int64_t a0, int64_t m, int64_t b0, int64_t n,
+                                 int64_t p, int var) {
   d.row_off = tr ? b0 : a0;
   d.col_off = tr ? a0 : b0;
   d.m = (int32_t)(tr ? n : m);
   d.n = (int32_t)(tr ? m : n);
   d.pair = (int32_t)p;
-  d.flags = tr ? kTransposed : 0;
-  if (c.allow16 && d.n <= c.stripe_w16) {
-    if (c.mode == kLocal) return kRoute16;  // saturation is detected at run time
-    // shifted-frame cells stay below sigma_max*min(m,n) + beta*(m+n), plus
-    // the profile byte and the padding offset beta*W16
-    const int64_t ub = (int64_t)c.smax_pos * (m < n ? m : n) + (int64_t)c.beta * (m + n) +
-                       (int64_t)c.beta * c.stripe_w16 + c.alpha + 2 * c.beta + 256;
-    if (ub < 32000) return kRoute16;
+  d.flags = with_variant(tr ? kTransposed : 0, var);
+}
+
+// List, length bin and descriptor of a non-empty pair (A at a0, length m;
+// B at b0, length n), or -1 when the pair is not routed (autotuning runs
+// route one bin, or a sample of it).  A bin's variant applies to the pairs
+// it can serve; the others take the automatic rule: packed 16-bit when the
+// shorter side fits one packed stripe and the range is proven (or local:
+// saturation is detected at run time), the wavefront for pairs with many
+// rows and more than one wavefront stripe, else 32-bit stripes of 256.
+__device__ int route_pair(const RouteParams &c, int64_t a0, int64_t m, int64_t b0, int64_t n, int64_t p,
+                          PairDesc &d, int &bin) {
+  bin = length_bin(m > n ? m : n);
+  if (c.only_bin >= 0 && bin != c.only_bin) return -1;
+  if (c.sample_stride[bin] > 1 && p % c.sample_stride[bin] != 0) return -1;
+  const int v = c.var_of_bin[bin];
+  if (v == kVarI32K8 || v == kVarI32K16 || v == kVarI32K32) {
+    fill_desc(d, orient_rows_b(m, n, kGroup * variant_k(v)), a0, m, b0, n, p, v);
+    return kList32;
   }
-  if (d.n > c.long_w && d.m >= c.long_min_rows) return kRouteLong;
-  return kRoute32;
+  const bool tr = orient_rows_b(m, n, kGroup * 16);
+  fill_desc(d, tr, a0, m, b0, n, p, kVarI32K16);
+  if ((v < 0 || v == kVarI16) && c.allow16 && d.n <= kGroup * 16) {
+    if (c.mode == kLocal) return kList16;
+    // shifted-frame cells stay below sigma_max*min(m,n) + beta*(m+n), plus
+    // the profile byte and the padding offset beta*256
+    const int64_t ub = (int64_t)c.smax_pos * (m < n ? m : n) + (int64_t)c.beta * (m + n) +
+                       (int64_t)c.beta * (kGroup * 16) + c.alpha + 2 * c.beta + 256;
+    if (ub < 32000) return kList16;
+  }
+  if (d.n > c.long_w && (v == kVarLong || (v < 0 && d.m >= c.long_min_rows))) return kListLong;
+  return kList32;
 }
 
 // Validation shared by the classify kernels.  Returns false for pairs that
@@ -99,6 +122,25 @@ __device__ bool check_pair(const RouteParams &c, const int64_t *offs_a, const in
   return true;
 }
 
+// A pair of the source: from the offsets (validated, empty pairs scored) or
+// from a list of descriptors (the banded path's fallback, already valid).
+__device__ bool source_pair(const RouteParams &c, const int64_t *offs_a, const int64_t *offs_b,
+                            const PairDesc *src, int64_t i, Counters *ctr, int32_t *scores, bool first,
+                            int64_t &a0, int64_t &m, int64_t &b0, int64_t &n, int64_t &p) {
+  if (!src) {
+    p = i;
+    return check_pair(c, offs_a, offs_b, i, ctr, scores, first, a0, m, b0, n);
+  }
+  const PairDesc f = src[i];
+  const bool tr = (f.flags & kTransposed) != 0;
+  a0 = tr ? f.col_off : f.row_off;
+  b0 = tr ? f.row_off : f.col_off;
+  m = tr ? f.n : f.m;
+  n = tr ? f.m : f.n;
+  p = f.pair;
+  return true;
+}
+
 // Block-level list reservation: pass 1 counts the routes of the block's
 // pairs in LDS, one global atomic per route reserves the block's slices, pass
 // 2 recomputes the routes and scatters through LDS cursors.
@@ -114,106 +156,137 @@ __device__ inline unsigned long long valid_cells(int64_t a0, int64_t m, int64_t 
   return (a0 >= 0 && b0 >= 0 && m > 0 && n > 0) ? (unsigned long long)(m * n) : 0ull;
 }
 
-__global__ void __launch_bounds__(256) classify_kernel(RouteParams c, const int64_t *offs_a,
-                                                       const int64_t *offs_b, PairDesc *items32,
-                                                       PairDesc *items16, LongItem *items_long,
-                                                       Counters *ctr, int32_t *scores) {
-  __shared__ BlockLists<kFullRoutes> bl;
-  const int64_t chunk = (c.n_pairs + gridDim.x - 1) / gridDim.x;
-  const int64_t lo = (int64_t)blockIdx.x * chunk;
-  const int64_t hi = lo + chunk < c.n_pairs ? lo + chunk : c.n_pairs;
-  if (threadIdx.x < kFullRoutes) {
-    bl.cnt[threadIdx.x] = 0;
-    bl.rcells[threadIdx.x] = 0;
-  }
-  if (threadIdx.x == 0) bl.cells = 0;
-  __syncthreads();
-  unsigned long long cells = 0;
-  for (int64_t p = lo + threadIdx.x; p < hi; p += blockDim.x) {
-    int64_t a0, m, b0, n;
-    const bool dp = check_pair(c, offs_a, offs_b, p, ctr, scores, true, a0, m, b0, n);
-    cells += valid_cells(a0, m, b0, n);
-    if (!dp) continue;
-    PairDesc d;
-    const int r = route_full(c, a0, m, b0, n, p, d);
-    if (r == kRoute32 && d.n > c.stripe_w) atomicMax(&ctr->max_rows_multi, d.m);
-    atomicAdd(&bl.cnt[r], 1);
-    atomicAdd(&bl.rcells[r], (unsigned long long)(m * n));
-  }
-  atomicAdd(&bl.cells, cells);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    bl.base[kRoute32] = bl.cnt[kRoute32] ? atomicAdd(&ctr->n_full32, bl.cnt[kRoute32]) : 0;
-    bl.base[kRoute16] = bl.cnt[kRoute16] ? atomicAdd(&ctr->n_full16, bl.cnt[kRoute16]) : 0;
-    bl.base[kRouteLong] = bl.cnt[kRouteLong] ? atomicAdd(&ctr->n_long, bl.cnt[kRouteLong]) : 0;
-    if (bl.cells) atomicAdd(&ctr->cells, bl.cells);
-    for (int r = 0; r < kFullRoutes; ++r) {
-      if (bl.rcells[r]) atomicAdd(&ctr->route_cells[r], bl.rcells[r]);
-      bl.cnt[r] = 0;
-    }
-  }
-  __syncthreads();
-  for (int64_t p = lo + threadIdx.x; p < hi; p += blockDim.x) {
-    int64_t a0, m, b0, n;
-    if (!check_pair(c, offs_a, offs_b, p, ctr, scores, false, a0, m, b0, n)) continue;
-    PairDesc d;
-    const int r = route_full(c, a0, m, b0, n, p, d);
-    const int slot = bl.base[r] + atomicAdd(&bl.cnt[r], 1);
-    if (r == kRoute32) items32[slot] = d;
-    else if (r == kRoute16) items16[slot] = d;
-    else items_long[slot].d = d;
-  }
+__device__ inline int64_t source_count(const RouteParams &c, const PairDesc *src, const Counters *ctr) {
+  return src ? (int64_t)ctr->n_fallback : c.n_pairs;
 }
 
-// Full-DP routing of the banded path's fallback pairs.
-__global__ void __launch_bounds__(256) route_fallback_kernel(RouteParams c, const PairDesc *fallback,
-                                                             PairDesc *items32, PairDesc *items16,
-                                                             LongItem *items_long, Counters *ctr) {
-  __shared__ BlockLists<kFullRoutes> bl;
-  const int64_t total = ctr->n_fallback;
+// Classification, step 1 of 3: per (list, length bin) counts, cells, the
+// 32-bit variant of every bin and the longest multi-stripe row count.
+__global__ void __launch_bounds__(256) route_count_kernel(RouteParams c, const int64_t *offs_a,
+                                                          const int64_t *offs_b, const PairDesc *src,
+                                                          Counters *ctr, int32_t *scores) {
+  constexpr int R = kLists * kLenBins;
+  __shared__ int cnt[R];
+  __shared__ unsigned long long rcells[kLists];
+  __shared__ unsigned long long bcells[kLenBins];
+  __shared__ unsigned long long cells_sh;
+  const int64_t total = source_count(c, src, ctr);
   const int64_t chunk = (total + gridDim.x - 1) / gridDim.x;
   const int64_t lo = (int64_t)blockIdx.x * chunk;
   const int64_t hi = lo + chunk < total ? lo + chunk : total;
-  if (threadIdx.x < kFullRoutes) {
-    bl.cnt[threadIdx.x] = 0;
-    bl.rcells[threadIdx.x] = 0;
-  }
-  if (threadIdx.x == 0) bl.cells = 0;
+  for (int r = threadIdx.x; r < R; r += blockDim.x) cnt[r] = 0;
+  if (threadIdx.x < kLists) rcells[threadIdx.x] = 0;
+  if (threadIdx.x < kLenBins) bcells[threadIdx.x] = 0;
+  if (threadIdx.x == 0) cells_sh = 0;
   __syncthreads();
   unsigned long long cells = 0;
-  auto route = [&](int64_t i, PairDesc &d) {
-    const PairDesc f = fallback[i];
-    const bool tr = (f.flags & kTransposed) != 0;
-    const int64_t a0 = tr ? f.col_off : f.row_off, b0 = tr ? f.row_off : f.col_off;
-    const int64_t m = tr ? f.n : f.m, n = tr ? f.m : f.n;
-    return route_full(c, a0, m, b0, n, f.pair, d);
-  };
   for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    int64_t a0, m, b0, n, p;
+    const bool dp = source_pair(c, offs_a, offs_b, src, i, ctr, scores, true, a0, m, b0, n, p);
+    cells += src ? (unsigned long long)(m * n) : valid_cells(a0, m, b0, n);
+    if (!dp) continue;
     PairDesc d;
-    const int r = route(i, d);
-    if (r == kRoute32 && d.n > c.stripe_w) atomicMax(&ctr->max_rows_multi, d.m);
-    atomicAdd(&bl.cnt[r], 1);
-    atomicAdd(&bl.rcells[r], (unsigned long long)((int64_t)d.m * d.n));
-    cells += (unsigned long long)((int64_t)d.m * d.n);
+    int bin;
+    const int l = route_pair(c, a0, m, b0, n, p, d, bin);
+    if (l < 0) continue;
+    atomicAdd(&cnt[l * kLenBins + bin], 1);
+    atomicAdd(&rcells[l], (unsigned long long)(m * n));
+    atomicAdd(&bcells[bin], (unsigned long long)(m * n));
+    if (l == kList32) {
+      ctr->bin_var32[bin] = variant_of(d.flags);  // the same for every pair of the bin
+      if (d.n > kGroup * variant_k(variant_of(d.flags))) atomicMax(&ctr->max_rows_multi, d.m);
+    }
   }
-  atomicAdd(&bl.cells, cells);
+  atomicAdd(&cells_sh, cells);
   __syncthreads();
+  for (int r = threadIdx.x; r < R; r += blockDim.x)
+    if (cnt[r]) atomicAdd(&ctr->bin_count[r / kLenBins][r % kLenBins], cnt[r]);
+  if (threadIdx.x < kLists && rcells[threadIdx.x])
+    atomicAdd(&ctr->route_cells[threadIdx.x], rcells[threadIdx.x]);
+  if (threadIdx.x < kLenBins && bcells[threadIdx.x])
+    atomicAdd(&ctr->bin_cells[threadIdx.x], bcells[threadIdx.x]);
   if (threadIdx.x == 0) {
-    if (bl.cells) atomicAdd(&ctr->fallback_cells, bl.cells);
-    for (int r = 0; r < kFullRoutes; ++r)
-      if (bl.rcells[r]) atomicAdd(&ctr->route_cells[r], bl.rcells[r]);
-    bl.base[kRoute32] = bl.cnt[kRoute32] ? atomicAdd(&ctr->n_full32, bl.cnt[kRoute32]) : 0;
-    bl.base[kRoute16] = bl.cnt[kRoute16] ? atomicAdd(&ctr->n_full16, bl.cnt[kRoute16]) : 0;
-    bl.base[kRouteLong] = bl.cnt[kRouteLong] ? atomicAdd(&ctr->n_long, bl.cnt[kRouteLong]) : 0;
-    for (int r = 0; r < kFullRoutes; ++r) bl.cnt[r] = 0;
+    if (cells_sh) atomicAdd(src ? &ctr->fallback_cells : &ctr->cells, cells_sh);
+  }
+}
+
+// Step 2 of 3 (one thread): list offsets of every bin, longest bins first;
+// 32-bit bins are padded to whole quads (a wave never mixes variants) with
+// items of pair -1.  Capacities (0 = unchecked) guard a planned replay: a
+// batch that would overflow the plan's boundary buffer is refused.
+__global__ void route_scan_kernel(Counters *ctr, PairDesc *items32, int64_t bnd_rows_cap) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int kmask = 0;
+  for (int l = 0; l < kLists; ++l) {
+    int base = 0;
+    for (int b = kLenBins - 1; b >= 0; --b) {
+      ctr->bin_base[l][b] = base;
+      int cnt = ctr->bin_count[l][b];
+      if (l == kList32 && cnt > 0) {
+        const int padded = (cnt + kGroupsPerWave - 1) / kGroupsPerWave * kGroupsPerWave;
+        const int v = ctr->bin_var32[b];
+        for (int k = cnt; k < padded; ++k) {
+          PairDesc d{0, 0, 0, 0, -1, with_variant(0, v)};
+          items32[base + k] = d;
+        }
+        kmask |= kmask_of_variant(v);
+        cnt = padded;
+      }
+      base += cnt;
+    }
+    if (l == kList16) ctr->n_full16 = base;
+    else if (l == kList32) ctr->n_full32 = base;
+    else ctr->n_long = base;
+  }
+  ctr->kmask32 = kmask;
+  if (bnd_rows_cap > 0 && ctr->n_full32 > 0 && (int64_t)ctr->max_rows_multi + 1 > bnd_rows_cap) {
+    atomicOr(&ctr->status, kStatusPlan);
+    ctr->n_full32 = ctr->n_full16 = ctr->n_long = 0;
+  }
+}
+
+// Step 3 of 3: scatter into the lists, each block reserving its slice of
+// every (list, bin) with one atomic.
+__global__ void __launch_bounds__(256) route_scatter_kernel(RouteParams c, const int64_t *offs_a,
+                                                            const int64_t *offs_b, const PairDesc *src,
+                                                            PairDesc *items16, PairDesc *items32,
+                                                            LongItem *items_long, Counters *ctr) {
+  constexpr int R = kLists * kLenBins;
+  __shared__ int cnt[R];
+  __shared__ int base[R];
+  if (ctr->status & kStatusPlan) return;
+  const int64_t total = source_count(c, src, ctr);
+  const int64_t chunk = (total + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = (int64_t)blockIdx.x * chunk;
+  const int64_t hi = lo + chunk < total ? lo + chunk : total;
+  for (int r = threadIdx.x; r < R; r += blockDim.x) cnt[r] = 0;
+  __syncthreads();
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    int64_t a0, m, b0, n, p;
+    if (!source_pair(c, offs_a, offs_b, src, i, ctr, nullptr, false, a0, m, b0, n, p)) continue;
+    PairDesc d;
+    int bin;
+    const int l = route_pair(c, a0, m, b0, n, p, d, bin);
+    if (l >= 0) atomicAdd(&cnt[l * kLenBins + bin], 1);
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < R; r += blockDim.x) {
+    const int l = r / kLenBins, b = r % kLenBins;
+    base[r] = cnt[r] ? ctr->bin_base[l][b] + atomicAdd(&ctr->bin_cursor[l][b], cnt[r]) : 0;
+    cnt[r] = 0;
   }
   __syncthreads();
   for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    int64_t a0, m, b0, n, p;
+    if (!source_pair(c, offs_a, offs_b, src, i, ctr, nullptr, false, a0, m, b0, n, p)) continue;
     PairDesc d;
-    const int r = route(i, d);
-    const int slot = bl.base[r] + atomicAdd(&bl.cnt[r], 1);
-    if (r == kRoute32) items32[slot] = d;
-    else if (r == kRoute16) items16[slot] = d;
+    int bin;
+    const int l = route_pair(c, a0, m, b0, n, p, d, bin);
+    if (l < 0) continue;
+    const int r = l * kLenBins + bin;
+    const int slot = base[r] + atomicAdd(&cnt[r], 1);
+    if (l == kList32) items32[slot] = d;
+    else if (l == kList16) items16[slot] = d;
     else items_long[slot].d = d;
   }
 }
@@ -363,10 +436,16 @@ struct Workspace {
   int8_t *subst = nullptr;       // 32*32 bytes
   int2 *bnd = nullptr;
   int64_t bnd_cap = 0;           // int2 elements
+  int32_t *tune_scores = nullptr;  // scores written by autotuning runs
+  int64_t tune_scores_cap = 0;
   hipEvent_t ev[16] = {};
 };
 
 bool g_timing = false;
+// Full-DP variant per (mode, length bin); -1 = automatic routing.
+int8_t g_variants[3][kLenBins] = {{-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1},
+                                  {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1},
+                                  {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1}};
 int32_t g_i16_limit = 32767;
 as_timing g_last_timing;
 
@@ -414,7 +493,7 @@ int status_to_code(int32_t st) {
   if (st & kStatusBadOffsets) return AS_ERR_OFFSETS;
   if (st & kStatusBadResidue) return AS_ERR_RESIDUE;
   if (st & kStatusRange) return AS_ERR_RANGE;
-  if (st & kStatusArg) return AS_ERR_ARG;
+  if (st & (kStatusArg | kStatusPlan)) return AS_ERR_ARG;
   return AS_OK;
 }
 
@@ -463,6 +542,12 @@ int check_scoring(const as_scoring *scoring, int32_t mode, CallScoring *cs) {
   return AS_OK;
 }
 
+int classify_blocks(int64_t n) {
+  int64_t blocks = (n + 1023) / 1024;
+  if (blocks > 1024) blocks = 1024;
+  return blocks < 1 ? 1 : (int)blocks;
+}
+
 RouteParams route_params(const CallScoring &cs, int64_t n_pairs) {
   RouteParams rp;
   rp.n_pairs = n_pairs;
@@ -471,17 +556,39 @@ RouteParams route_params(const CallScoring &cs, int64_t n_pairs) {
   rp.beta = cs.beta;
   rp.smax_abs = cs.smax_abs;
   rp.smax_pos = cs.smax > 0 ? cs.smax : 0;
-  rp.stripe_w = full_dp_i32_stripe_width();
   rp.allow16 = cs.allow16;
-  rp.stripe_w16 = full_dp_i16_stripe_width();
   rp.long_w = long_dp_i32_stripe_width();
   rp.long_min_rows = 2048;
+  rp.only_bin = -1;
+  for (int b = 0; b < kLenBins; ++b) {
+    rp.var_of_bin[b] = g_variants[cs.mode][b];
+    rp.sample_stride[b] = 1;
+  }
   return rp;
+}
+
+// Classification (count, scan, scatter) of the pairs given by the offsets
+// (src == nullptr) or of a descriptor list holding n_src pairs.
+int launch_classify(Workspace *w, const RouteParams &rp, const int64_t *offs_a, const int64_t *offs_b,
+                    const PairDesc *src, int64_t n_src, int32_t *scores, hipStream_t stream,
+                    int64_t bnd_rows_cap = 0) {
+  const int blocks = classify_blocks(n_src);
+  hipLaunchKernelGGL(route_count_kernel, dim3(blocks), dim3(256), 0, stream, rp, offs_a, offs_b, src, w->ctr,
+                     scores);
+  AS_HIP(hipGetLastError());
+  hipLaunchKernelGGL(route_scan_kernel, dim3(1), dim3(64), 0, stream, w->ctr, w->items, bnd_rows_cap);
+  AS_HIP(hipGetLastError());
+  hipLaunchKernelGGL(route_scatter_kernel, dim3(blocks), dim3(256), 0, stream, rp, offs_a, offs_b, src,
+                     w->items16, w->items, w->items_long, w->ctr);
+  AS_HIP(hipGetLastError());
+  return AS_OK;
 }
 
 int lists_capacity(Workspace *w, int64_t n_pairs) {
   int rc;
-  if ((rc = grow((void **)&w->items, &w->items_cap, n_pairs, sizeof(PairDesc)))) return rc;
+  // the 32-bit list pads each length bin to whole quads
+  if ((rc = grow((void **)&w->items, &w->items_cap, n_pairs + kGroupsPerWave * kLenBins, sizeof(PairDesc))))
+    return rc;
   if ((rc = grow((void **)&w->items16, &w->items16_cap, n_pairs, sizeof(PairDesc)))) return rc;
   if ((rc = grow((void **)&w->rerun, &w->rerun_cap, n_pairs, sizeof(PairDesc)))) return rc;
   if ((rc = grow((void **)&w->items_long, &w->items_long_cap, n_pairs, sizeof(LongItem)))) return rc;
@@ -533,7 +640,7 @@ int run_full_lists(Workspace *w, const CallScoring &cs, const uint8_t *seqs_a,
   args.beta = cs.beta;
   args.scores = scores_out;
   if (c.n_full32 > 0) {
-    const int bpc = full_dp_i32_blocks_per_cu(mode, asz);
+    const int bpc = full_dp_i32_blocks_per_cu(mode, asz, c.kmask32);
     int64_t grid = (int64_t)bpc * w->num_cu;
     const int64_t need_waves = ((int64_t)c.n_full32 + kGroupsPerWave - 1) / kGroupsPerWave;
     if (grid > need_waves) grid = need_waves;
@@ -546,7 +653,7 @@ int run_full_lists(Workspace *w, const CallScoring &cs, const uint8_t *seqs_a,
     args.bnd = w->bnd;
     args.bnd_rows = bnd_rows;
     if (timing) AS_HIP(hipEventRecord(w->ev[4], stream));
-    AS_HIP(launch_full_dp_i32(mode, args, (int)grid, stream));
+    AS_HIP(launch_full_dp_i32(mode, args, c.kmask32, (int)grid, stream));
     if (timing) AS_HIP(hipEventRecord(w->ev[5], stream));
   }
   if (c.n_long > 0) {
@@ -579,9 +686,9 @@ int run_full_lists(Workspace *w, const CallScoring &cs, const uint8_t *seqs_a,
   g_last_timing.pairs_full32 += c.n_full32;
   g_last_timing.pairs_full16 += c.n_full16;
   g_last_timing.pairs_long += c.n_long;
-  g_last_timing.cells_full32 = (int64_t)c2.route_cells[kRoute32];
-  g_last_timing.cells_full16 = (int64_t)c2.route_cells[kRoute16];
-  g_last_timing.cells_long = (int64_t)c2.route_cells[kRouteLong];
+  g_last_timing.cells_full32 = (int64_t)c2.route_cells[kList32];
+  g_last_timing.cells_full16 = (int64_t)c2.route_cells[kList16];
+  g_last_timing.cells_long = (int64_t)c2.route_cells[kListLong];
   if (timing && c.n_full16 > 0) g_last_timing.full16_ms += elapsed(w->ev[2], w->ev[3]);
   if (timing && c.n_full32 > 0) g_last_timing.full32_ms += elapsed(w->ev[4], w->ev[5]);
   if (timing && c.n_long > 0) g_last_timing.long_ms += elapsed(w->ev[8], w->ev[9]);
@@ -590,7 +697,7 @@ int run_full_lists(Workspace *w, const CallScoring &cs, const uint8_t *seqs_a,
   // 32-bit re-run of the 16-bit pairs whose maximum saturated
   g_last_timing.pairs_rerun32 += c2.n_rerun32;
   if (c2.n_rerun32 > 0) {
-    const int bpc = full_dp_i32_blocks_per_cu(mode, asz);
+    const int bpc = full_dp_i32_blocks_per_cu(mode, asz, kmask_of_variant(kVarI32K16));
     int64_t grid = (int64_t)bpc * w->num_cu;
     const int64_t need_waves = ((int64_t)c2.n_rerun32 + kGroupsPerWave - 1) / kGroupsPerWave;
     if (grid > need_waves) grid = need_waves;
@@ -602,7 +709,7 @@ int run_full_lists(Workspace *w, const CallScoring &cs, const uint8_t *seqs_a,
     args.bnd = w->bnd;
     args.bnd_rows = 1;
     if (timing) AS_HIP(hipEventRecord(w->ev[6], stream));
-    AS_HIP(launch_full_dp_i32(mode, args, (int)grid, stream));
+    AS_HIP(launch_full_dp_i32(mode, args, kmask_of_variant(kVarI32K16), (int)grid, stream));
     if (timing) AS_HIP(hipEventRecord(w->ev[7], stream));
     Counters c3;
     if ((rc = read_counters(w, stream, &c3))) return rc;
@@ -612,11 +719,6 @@ int run_full_lists(Workspace *w, const CallScoring &cs, const uint8_t *seqs_a,
   return AS_OK;
 }
 
-int classify_blocks(int64_t n) {
-  int64_t blocks = (n + 1023) / 1024;
-  if (blocks > 1024) blocks = 1024;
-  return blocks < 1 ? 1 : (int)blocks;
-}
 
 // Score words of the banded kernel: byte c of word r is sigma(r, c) + alpha +
 // beta with rows from A (table 0) or from B (table 1).
@@ -675,9 +777,7 @@ extern "C" int as_align_batch(const uint8_t *seqs_a, const int64_t *offs_a, cons
   memset(&g_last_timing, 0, sizeof(g_last_timing));
   if (timing) AS_HIP(hipEventRecord(w->ev[0], stream));
   const RouteParams rp = route_params(cs, n_pairs);
-  hipLaunchKernelGGL(classify_kernel, dim3(classify_blocks(n_pairs)), dim3(256), 0, stream, rp, offs_a,
-                     offs_b, w->items, w->items16, w->items_long, w->ctr, scores_out);
-  AS_HIP(hipGetLastError());
+  if ((rc = launch_classify(w, rp, offs_a, offs_b, nullptr, n_pairs, scores_out, stream))) return rc;
   if (timing) AS_HIP(hipEventRecord(w->ev[1], stream));
   Counters c;
   if ((rc = read_counters(w, stream, &c))) return rc;
@@ -790,9 +890,7 @@ int asmi::band_call(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t 
   if (raw || c.n_fallback == 0) return AS_OK;
 
   // full DP for the fallback pairs
-  hipLaunchKernelGGL(route_fallback_kernel, dim3(classify_blocks(c.n_fallback)), dim3(256), 0, stream,
-                     rp, w->fallback, w->items, w->items16, w->items_long, w->ctr);
-  AS_HIP(hipGetLastError());
+  if ((rc = launch_classify(w, rp, offs_a, offs_b, w->fallback, c.n_fallback, scores_out, stream))) return rc;
   if ((rc = read_counters(w, stream, &c))) return rc;
   if ((rc = status_to_code(c.status))) return rc;
   if (stats) stats->fallback_cells = (int64_t)c.fallback_cells;
@@ -831,6 +929,105 @@ void asmi::record_learned_timing(float features_ms, float mlp_ms) {
   g_last_timing.mlp_ms = mlp_ms;
 }
 
+extern "C" int as_set_variants(int32_t mode, const int8_t *table) {
+  if (mode < 0 || mode > 2) return AS_ERR_ARG;
+  if (table)
+    for (int b = 0; b < kLenBins; ++b)
+      if (table[b] < -1 || table[b] >= kNumVariants) return AS_ERR_ARG;
+  std::lock_guard<std::mutex> guard(g_lock);
+  for (int b = 0; b < kLenBins; ++b) g_variants[mode][b] = table ? table[b] : (int8_t)-1;
+  return AS_OK;
+}
+
+extern "C" int as_get_variants(int32_t mode, int8_t *table_out) {
+  if (!table_out) return AS_ERR_NULL;
+  if (mode < 0 || mode > 2) return AS_ERR_ARG;
+  std::lock_guard<std::mutex> guard(g_lock);
+  for (int b = 0; b < kLenBins; ++b) table_out[b] = g_variants[mode][b];
+  return AS_OK;
+}
+
+extern "C" int as_autotune(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t *seqs_b,
+                           const int64_t *offs_b, int64_t n_pairs, const as_scoring *scoring, int32_t mode,
+                           int32_t sample_pairs, float *gcups_out, int8_t *table_out, void *stream_ptr) {
+  if (!scoring || !offs_a || !offs_b || !seqs_a || !seqs_b || !scoring->subst) return AS_ERR_NULL;
+  if (n_pairs < 0 || n_pairs >= ((int64_t)1 << 31) - 1 || sample_pairs < 1) return AS_ERR_ARG;
+  CallScoring cs;
+  int rc = check_scoring(scoring, mode, &cs);
+  if (rc) return rc;
+  if (gcups_out)
+    for (int i = 0; i < kLenBins * kNumVariants; ++i) gcups_out[i] = 0.f;
+  std::lock_guard<std::mutex> guard(g_lock);
+  Workspace *w = nullptr;
+  if ((rc = get_workspace(&w))) return rc;
+  hipStream_t stream = (hipStream_t)stream_ptr;
+  if (n_pairs > 0) {
+    if ((rc = lists_capacity(w, n_pairs))) return rc;
+    if ((rc = grow((void **)&w->tune_scores, &w->tune_scores_cap, n_pairs, sizeof(int32_t)))) return rc;
+    AS_HIP(hipMemcpyAsync(w->subst, scoring->subst, (size_t)cs.asz * cs.asz, hipMemcpyHostToDevice, stream));
+    // pairs and cells per length bin under the automatic rule
+    RouteParams rp = route_params(cs, n_pairs);
+    for (int b = 0; b < kLenBins; ++b) rp.var_of_bin[b] = -1;
+    AS_HIP(hipMemsetAsync(w->ctr, 0, sizeof(Counters), stream));
+    if ((rc = launch_classify(w, rp, offs_a, offs_b, nullptr, n_pairs, w->tune_scores, stream))) return rc;
+    Counters c0;
+    if ((rc = read_counters(w, stream, &c0))) return rc;
+    if ((rc = status_to_code(c0.status))) return rc;
+    const bool timing_was = g_timing;
+    g_timing = true;
+    // A sample of a bin: every stride-th pair, at most sample_pairs pairs
+    // and about 1e11 cells (tens of milliseconds per variant).
+    const double cell_cap = 1e11;
+    for (int b = 0; b < kLenBins; ++b) {
+      int64_t cnt = 0;
+      for (int l = 0; l < 3; ++l) cnt += c0.bin_count[l][b];
+      if (cnt == 0) continue;
+      int64_t stride = cnt / sample_pairs;
+      const int64_t by_cells = (int64_t)((double)c0.bin_cells[b] / cell_cap);
+      if (by_cells > stride) stride = by_cells;
+      if (stride < 1) stride = 1;
+      float best_g = -1.f;
+      int best_v = -1;
+      for (int v = 0; v < kNumVariants; ++v) {
+        if (v == kVarI16 && !cs.allow16) continue;
+        if (v == kVarLong && ((int64_t)64 << b) <= long_dp_i32_stripe_width()) continue;
+        RouteParams t = rp;
+        t.only_bin = b;
+        t.var_of_bin[b] = (int8_t)v;
+        t.sample_stride[b] = (int32_t)(stride > (1 << 30) ? (1 << 30) : stride);
+        float ms_best = -1.f;
+        double cells = 0;
+        for (int rep = 0; rep < 2; ++rep) {
+          AS_HIP(hipMemsetAsync(w->ctr, 0, sizeof(Counters), stream));
+          if ((rc = launch_classify(w, t, offs_a, offs_b, nullptr, n_pairs, w->tune_scores, stream))) break;
+          Counters c;
+          if ((rc = read_counters(w, stream, &c))) break;
+          memset(&g_last_timing, 0, sizeof(g_last_timing));
+          if ((rc = run_full_lists(w, cs, seqs_a, seqs_b, w->tune_scores, stream, true, c))) break;
+          const float ms = g_last_timing.full16_ms + g_last_timing.full32_ms + g_last_timing.long_ms +
+                           g_last_timing.rerun32_ms;
+          cells = (double)(c.route_cells[0] + c.route_cells[1] + c.route_cells[2]);
+          if (ms_best < 0.f || ms < ms_best) ms_best = ms;
+        }
+        if (rc) break;
+        const float g = ms_best > 0.f ? (float)(cells / (ms_best * 1e-3) / 1e9) : 0.f;
+        if (gcups_out) gcups_out[b * kNumVariants + v] = g;
+        if (g > best_g) {
+          best_g = g;
+          best_v = v;
+        }
+      }
+      if (rc) break;
+      g_variants[mode][b] = (int8_t)best_v;
+    }
+    g_timing = timing_was;
+    if (rc) return rc;
+  }
+  if (table_out)
+    for (int b = 0; b < kLenBins; ++b) table_out[b] = g_variants[mode][b];
+  return AS_OK;
+}
+
 extern "C" const char *as_strerror(int code) {
   switch (code) {
     case AS_OK: return "success";
@@ -846,6 +1043,7 @@ extern "C" const char *as_strerror(int code) {
 }
 
 extern "C" int as_release_workspace(void) {
+  release_learned_workspace();  // takes its own lock, never while holding this one
   std::lock_guard<std::mutex> guard(g_lock);
   for (Workspace &w : g_ws) {
     if (w.device < 0) continue;
@@ -853,7 +1051,7 @@ extern "C" int as_release_workspace(void) {
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(w.device);
     void *bufs[] = {w.items, w.items16, w.rerun, w.items_long, w.bnd_long, w.flags, w.band_lists,
-                    w.fallback, w.qwords, w.ctr, w.subst, w.bnd};
+                    w.fallback, w.qwords, w.ctr, w.subst, w.bnd, w.tune_scores};
     for (void *b : bufs)
       if (b) (void)hipFree(b);
     if (w.host_ctr) (void)hipHostFree(w.host_ctr);

@@ -1,0 +1,118 @@
+"""GPU parity of the batching runtime: every full-DP variant forced on every
+length bin gives the oracle's scores (three modes, DNA and protein, lengths
+spanning many bins, ragged quads), and the autotuner's table keeps them."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2205_07610_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+DNA = synth.dna_subst()
+
+
+def _say(msg):
+    print(f"[batching] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2205_07610_amd import binding
+    binding.lib()
+    yield binding
+    for mode in (0, 1, 2):
+        binding.set_variants(mode, None)
+
+
+def _mixed_batch(seed, asz, n_pairs=700):
+    """Log-uniform lengths from 1 to ~6000 (bins 0..7), related and unrelated
+    pairs, a few empty ones."""
+    rng = np.random.default_rng(seed)
+    la = np.exp(rng.uniform(0, np.log(6000), n_pairs)).astype(np.int64)
+    la[::97] = 0
+    sa, oa = synth.random_csr(rng, la, asz)
+    div = rng.uniform(0, 0.2, n_pairs)
+    sb, ob = synth.mutate(rng, sa, oa, div / 2, div / 4, div / 4, asz)
+    # a third of the B sequences are unrelated, with their own lengths
+    pairs = []
+    lb_un = np.exp(rng.uniform(0, np.log(6000), n_pairs)).astype(np.int64)
+    for p in range(n_pairs):
+        a = sa[oa[p]:oa[p + 1]]
+        if p % 3 == 0:
+            b = rng.integers(0, asz, lb_un[p]).astype(np.uint8)
+        else:
+            b = sb[ob[p]:ob[p + 1]]
+        pairs.append((a, b))
+    return pairs
+
+
+def _oracle(oracle_mod, b):
+    return oracle_mod.align_batch(b.seqs_a, b.offs_a, b.seqs_b, b.offs_b, b.subst, b.alpha, b.beta,
+                                  b.mode)
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_forced_variants_dna(gpu, oracle_mod, mode):
+    b = synth.from_pairs("mixed dna", _mixed_batch(900 + mode, 4), DNA, 5, 2, mode)
+    want = _oracle(oracle_mod, b)
+    dev = gpu.to_device(b)
+    for name, v in gpu.VARIANTS.items():
+        gpu.set_variants(mode, [v] * gpu.LEN_BINS)
+        got = gpu.align_batch(*dev, b.subst, b.alpha, b.beta, mode).cpu().numpy()
+        bad = np.nonzero(got != want)[0]
+        _say(f"mode {mode} variant {name}: {b.n_pairs} pairs, {len(bad)} mismatches")
+        assert len(bad) == 0, (name, bad[:5])
+    # a mixed table: every variant somewhere
+    gpu.set_variants(mode, [1, 2, 3, 0, 4, 1, 3, 4, 2, -1, 3, 4])
+    got = gpu.align_batch(*dev, b.subst, b.alpha, b.beta, mode).cpu().numpy()
+    np.testing.assert_array_equal(got, want)
+    gpu.set_variants(mode, None)
+
+
+def test_forced_variants_protein(gpu, oracle_mod):
+    rng = np.random.default_rng(910)
+    sub = synth.protein_subst(rng)
+    b = synth.from_pairs("mixed protein", _mixed_batch(911, 20, n_pairs=300), sub, 11, 1, 2)
+    want = _oracle(oracle_mod, b)
+    dev = gpu.to_device(b)
+    for name, v in gpu.VARIANTS.items():
+        gpu.set_variants(2, [v] * gpu.LEN_BINS)
+        got = gpu.align_batch(*dev, b.subst, b.alpha, b.beta, 2).cpu().numpy()
+        assert np.array_equal(got, want), name
+    gpu.set_variants(2, None)
+
+
+def test_variant_table_errors(gpu):
+    with pytest.raises(gpu.AlignError) as e:
+        gpu.set_variants(0, [7] + [-1] * 11)
+    assert e.value.code == -7
+    with pytest.raises(gpu.AlignError):
+        gpu.set_variants(3, None)
+    gpu.set_variants(1, [2] * 12)
+    assert list(gpu.get_variants(1)) == [2] * 12
+    gpu.set_variants(1, None)
+    assert list(gpu.get_variants(1)) == [-1] * 12
+
+
+def test_autotune_then_exact(gpu, oracle_mod):
+    b = synth.config2(n_pairs=3000, seed=920)
+    dev = gpu.to_device(b)
+    table, g = gpu.autotune(*dev, b.subst, b.alpha, b.beta, b.mode, sample_pairs=512)
+    lens = np.maximum(b.lens_a, b.lens_b)
+    present = sorted({min(11, max(0, int(np.ceil(np.log2(max(x, 1) / 64))))) for x in lens if x > 0})
+    _say(f"autotune table {table.tolist()}")
+    for bb in present:
+        _say(f"  bin {bb} (<= {64 << bb}): GCUPS {np.round(g[bb], 1).tolist()} -> {table[bb]}")
+        assert 0 <= table[bb] < 5
+        assert g[bb].max() > 0
+    got = gpu.align_batch(*dev, b.subst, b.alpha, b.beta, b.mode).cpu().numpy()
+    idx = np.random.default_rng(921).choice(b.n_pairs, 400, replace=False)
+    sub = b.subset(np.sort(idx))
+    np.testing.assert_array_equal(got[np.sort(idx)], _oracle(oracle_mod, sub))
+    gpu.set_variants(b.mode, None)
