@@ -13,8 +13,13 @@ learned-band score is compared with the full-DP score (0 mismatches
 required).  value = effective GCUPS of the learned step (sum of m*n over the
 batch / step time); the full DP's figures are reported beside it.
 
-Other workloads (--workload c0, c1, c2, c3, c3long) time as_align_batch.
-Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+--workload c2 (10^5 semi-global pairs, log-normal lengths): the autotuner
+first picks a kernel variant per length bin (untimed), the batch is captured
+as a plan (one HIP graph of the whole pipeline), and a step is one graph
+replay; eager as_align_batch times with the tuned and the automatic tables
+are reported beside it.  Other workloads (--workload c0, c1, c3, c3long)
+time as_align_batch.  Prints one JSON line.  --gpus N with N > 1 exits: this
+build runs on one GPU.
 """
 from __future__ import annotations
 
@@ -87,15 +92,20 @@ def source_sha(path: str) -> str:
         return hashlib.sha1(f.read()).hexdigest()[:12]
 
 
+WORKLOAD_NAME = {"name": None}
+
+
 def traffic_for(kernel: str):
     """HBM bytes per launch from the committed rocprofv3 PMC summary, if it
-    was taken on the current kernel source; otherwise None."""
+    was taken on the current kernel source and on this workload; else None."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
     if rec.get("source_sha") != source_sha(KERNEL_SOURCES[kernel]):
+        return None
+    if rec.get("workload_name") != WORKLOAD_NAME["name"]:
         return None
     return rec.get("bytes_per_launch")
 
@@ -237,6 +247,7 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     binding.lib()
+    WORKLOAD_NAME["name"] = args.workload
     if args.copy_reference:
         src = torch.ones(1 << 30, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
@@ -261,11 +272,35 @@ def main():
         binding.align_batch(sa, oa, sb, ob, *args_sc, scores_out=out)
 
     full_names = ["full32_ms", "full16_ms", "rerun32_ms", "long_ms", "classify_ms"]
+    graph_info = None
+    if args.workload == "c2":
+        log("autotuning the variant table")
+        binding.set_variants(batch.mode, None)
+        auto_ms, _ = timed(full_step, args.steps, args.warmup, binding, torch)
+        t0 = time.perf_counter()
+        table, gtab = binding.autotune(sa, oa, sb, ob, *args_sc)
+        tune_s = time.perf_counter() - t0
+        log(f"table {table.tolist()} ({tune_s:.1f} s); automatic-table eager step {auto_ms:.3f} ms")
+        plan = binding.Plan(sa, oa, sb, ob, *args_sc, scores_out=out)
+        plan_ms, _ = timed(plan.run, args.steps, args.warmup, binding, torch)
+        plan_scores = out.cpu().numpy()
+        log(f"graph replay: {plan_ms:.3f} ms/step")
+        bins = sorted(set(int(x) for x in np.nonzero(gtab.max(axis=1) > 0)[0]))
+        graph_info = {"table": table.tolist(), "autotune_s": round(tune_s, 2),
+                      "gcups_per_bin_variant": {str(b): [round(float(v), 1) for v in gtab[b]]
+                                                for b in bins},
+                      "variant_names": ["packed16", "k8", "k16", "k32", "wavefront"],
+                      "eager_automatic_table_ms": round(auto_ms, 4)}
     log(f"full DP: warmup {args.warmup}, {args.steps} steps")
     full_ms, full_phases = timed(full_step, args.steps, args.warmup, binding, torch)
     full_avg = mean_phases(full_phases, full_names)
     log(f"full DP: {full_ms:.3f} ms/step")
     full_scores = out.cpu().numpy()
+    if graph_info is not None:
+        graph_info["eager_tuned_table_ms"] = round(full_ms, 4)
+        graph_info["graph_vs_eager_mismatches"] = int(np.count_nonzero(plan_scores != full_scores))
+        plan.close()
+        binding.set_variants(batch.mode, None)
 
     if learned:
         out_l = torch.empty(batch.n_pairs, dtype=torch.int32, device="cuda")
@@ -294,6 +329,8 @@ def main():
         dtype = "i32"
     else:
         ms_per_step, avg, gpu_scores = full_ms, full_avg, full_scores
+        if graph_info is not None:
+            ms_per_step, gpu_scores = plan_ms, plan_scores
         dom = max(full_names, key=lambda k: avg[k])
         roof = phase_roofline(full_phases, dom, OPS_PER_CELL[batch.mode])
         dtype = "i16x2" if dom == "full16_ms" else "i32"
@@ -314,10 +351,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "name": args.workload, "n_pairs": batch.n_pairs,
                    "cells": cells, "mode": MODE_NAMES[batch.mode],
-                   "method": "learned band (certified, exact)" if learned else "full DP"},
+                   "method": ("learned band (certified, exact)" if learned else
+                              "full DP, autotuned variants, graph replay" if graph_info else "full DP")},
         "phases_ms": {k: round(v, 4) for k, v in avg.items()},
         "roofline": roof,
     }
+    if graph_info is not None:
+        result["graph"] = graph_info
+        result["value_note"] = ("whole step = one graph replay; phases and roofline from the eager "
+                                "run with the same (tuned) table")
     if learned:
         result["value_note"] = "effective GCUPS: sum of m*n over the batch / learned step time"
         fr = {k.replace("_ms", ""): phase_roofline(full_phases, k, OPS_PER_CELL[batch.mode])

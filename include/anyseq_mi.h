@@ -320,6 +320,25 @@ int as_autotune(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t *seq
                 int32_t sample_pairs, float *gcups_out, int8_t *table_out, void *stream);
 
 /*
+ * Plans: one batch made replayable as a HIP graph (batching runtime).  A
+ * plan binds the batch's device pointers, scoring, mode and scores_out, and
+ * the mode's variant table at creation; it owns a private workspace sized by
+ * a planning run, and every replay (as_plan_run) runs the whole pipeline --
+ * classification, all DP kernels on persistent grids, the 32-bit re-run --
+ * as one graph launch on `stream`, then waits for it and returns the status.
+ * The caller may change the batch's contents between replays (same
+ * pointers and pair count); a replay whose routing needs more boundary
+ * memory than the plan holds returns AS_ERR_ARG without touching memory
+ * beyond its buffers.  Calls on one plan must not overlap.
+ */
+typedef struct as_plan as_plan;
+int as_plan_create(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t *seqs_b,
+                   const int64_t *offs_b, int64_t n_pairs, const as_scoring *scoring, int32_t mode,
+                   int32_t *scores_out, as_plan **plan_out, void *stream);
+int as_plan_run(as_plan *plan, void *stream);
+int as_plan_destroy(as_plan *plan);
+
+/*
  * Saturation threshold of the packed 16-bit local path: a pair whose 16-bit
  * maximum reaches `limit` is treated as saturated and recomputed with 32-bit
  * cells.  The default, 32767, is the int16 saturation value itself; a lower

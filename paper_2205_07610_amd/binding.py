@@ -105,6 +105,13 @@ def lib() -> ctypes.CDLL:
     L.as_align_batch_learned.restype = ctypes.c_int
     L.as_align_batch_learned.argtypes = [p, p, p, p, i64, ctypes.POINTER(Scoring), i32, p, i32, p,
                                          ctypes.POINTER(BandStats), p]
+    L.as_plan_create.restype = ctypes.c_int
+    L.as_plan_create.argtypes = [p, p, p, p, i64, ctypes.POINTER(Scoring), i32, p,
+                                 ctypes.POINTER(ctypes.c_void_p), p]
+    L.as_plan_run.restype = ctypes.c_int
+    L.as_plan_run.argtypes = [p, p]
+    L.as_plan_destroy.restype = ctypes.c_int
+    L.as_plan_destroy.argtypes = [p]
     L.as_set_variants.restype = ctypes.c_int
     L.as_set_variants.argtypes = [i32, p]
     L.as_get_variants.restype = ctypes.c_int
@@ -361,6 +368,46 @@ def align_batch_learned(seqs_a, offs_a, seqs_b, offs_b, subst, alpha: int, beta:
     del keep
     _check(rc)
     return scores_out[:n_pairs], st.as_dict()
+
+
+class Plan:
+    """A batch captured as a replayable HIP graph (as_plan_*).  Keeps the
+    device tensors it was made from alive; run() replays and raises on error."""
+
+    def __init__(self, seqs_a, offs_a, seqs_b, offs_b, subst, alpha: int, beta: int, mode: int,
+                 scores_out=None, stream=None):
+        import torch
+        n_pairs = offs_a.numel() - 1
+        dev = offs_a.device
+        self.scores = scores_out if scores_out is not None else \
+            torch.empty(max(n_pairs, 1), dtype=torch.int32, device=dev)
+        self._keep = (seqs_a, offs_a, seqs_b, offs_b)
+        self._dev = dev
+        sc, keep = make_scoring(subst, alpha, beta)
+        h = ctypes.c_void_p()
+        rc = lib().as_plan_create(*_seq_ptrs(seqs_a, offs_a, seqs_b, offs_b), n_pairs,
+                                  ctypes.byref(sc), int(mode),
+                                  _dev_ptr(self.scores, torch.int32, "scores_out"), ctypes.byref(h),
+                                  ctypes.c_void_p(_stream(dev, stream)))
+        del keep
+        _check(rc)
+        self._h = h
+        self.n_pairs = n_pairs
+
+    def run(self, stream=None):
+        _check(lib().as_plan_run(self._h, ctypes.c_void_p(_stream(self._dev, stream))))
+        return self.scores[:self.n_pairs]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().as_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 LEN_BINS = 12

@@ -369,7 +369,8 @@ __global__ void __launch_bounds__(256) band_classify_kernel(RouteParams c, const
 // offset of every long pair), and the score seed that the stripes' atomic
 // maxima start from (0 = the empty alignment / boundary cells).
 __global__ void __launch_bounds__(256) long_prep_kernel(LongItem *items, Counters *ctr, int32_t long_w,
-                                                        int32_t mode, int32_t *scores) {
+                                                        int32_t mode, int32_t *scores, int64_t bnd_cap,
+                                                        int64_t tasks_cap) {
   __shared__ int sst[256];
   __shared__ long long sbe[256];
   const int n = ctr->n_long;
@@ -408,7 +409,18 @@ __global__ void __launch_bounds__(256) long_prep_kernel(LongItem *items, Counter
   if (threadIdx.x == 0) {
     ctr->n_long_tasks = task;
     ctr->long_bnd_total = bnd;
+    // a planned replay whose wavefront buffers are too small does no long work
+    if ((bnd_cap > 0 && bnd > bnd_cap) || (tasks_cap > 0 && task > tasks_cap)) {
+      atomicOr(&ctr->status, kStatusPlan);
+      ctr->n_long = 0;
+      ctr->n_long_tasks = 0;
+    }
   }
+}
+
+__global__ void __launch_bounds__(256) fill_kernel(int32_t *p, int64_t n, int32_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
 }
 
 struct Workspace {
@@ -457,21 +469,38 @@ std::vector<Workspace> g_ws;
     if ((call) != hipSuccess) return AS_ERR_HIP; \
   } while (0)
 
+int init_workspace(Workspace &w, int dev) {
+  hipDeviceProp_t prop;
+  AS_HIP(hipGetDeviceProperties(&prop, dev));
+  w.num_cu = prop.multiProcessorCount;
+  AS_HIP(hipMalloc(&w.ctr, sizeof(Counters)));
+  AS_HIP(hipHostMalloc(&w.host_ctr, sizeof(Counters), hipHostMallocDefault));
+  AS_HIP(hipMalloc(&w.subst, 32 * 32));
+  AS_HIP(hipMalloc(&w.qwords, 2 * 32 * sizeof(uint32_t)));
+  for (auto &e : w.ev) AS_HIP(hipEventCreate(&e));
+  w.device = dev;
+  return AS_OK;
+}
+
+void free_workspace(Workspace &w) {
+  void *bufs[] = {w.items, w.items16, w.rerun, w.items_long, w.bnd_long, w.flags, w.band_lists,
+                  w.fallback, w.qwords, w.ctr, w.subst, w.bnd, w.tune_scores};
+  for (void *b : bufs)
+    if (b) (void)hipFree(b);
+  if (w.host_ctr) (void)hipHostFree(w.host_ctr);
+  for (auto &e : w.ev)
+    if (e) (void)hipEventDestroy(e);
+  w = Workspace();
+}
+
 int get_workspace(Workspace **out) {
   int dev = 0;
   AS_HIP(hipGetDevice(&dev));
   if ((int)g_ws.size() <= dev) g_ws.resize(dev + 1);
   Workspace &w = g_ws[dev];
   if (w.device < 0) {
-    hipDeviceProp_t prop;
-    AS_HIP(hipGetDeviceProperties(&prop, dev));
-    w.num_cu = prop.multiProcessorCount;
-    AS_HIP(hipMalloc(&w.ctr, sizeof(Counters)));
-    AS_HIP(hipHostMalloc(&w.host_ctr, sizeof(Counters), hipHostMallocDefault));
-    AS_HIP(hipMalloc(&w.subst, 32 * 32));
-    AS_HIP(hipMalloc(&w.qwords, 2 * 32 * sizeof(uint32_t)));
-    for (auto &e : w.ev) AS_HIP(hipEventCreate(&e));
-    w.device = dev;
+    int rc = init_workspace(w, dev);
+    if (rc) return rc;
   }
   *out = &w;
   return AS_OK;
@@ -605,7 +634,7 @@ int run_full_lists(Workspace *w, const CallScoring &cs, const uint8_t *seqs_a,
   int rc;
   if (c.n_long > 0) {
     hipLaunchKernelGGL(long_prep_kernel, dim3(1), dim3(256), 0, stream, w->items_long, w->ctr,
-                       long_dp_i32_stripe_width(), mode, scores_out);
+                       long_dp_i32_stripe_width(), mode, scores_out, (int64_t)0, (int64_t)0);
     AS_HIP(hipGetLastError());
     if ((rc = read_counters(w, stream, &c))) return rc;
   }
@@ -929,6 +958,204 @@ void asmi::record_learned_timing(float features_ms, float mlp_ms) {
   g_last_timing.mlp_ms = mlp_ms;
 }
 
+// ---------------------------------------------------------------- plans
+//
+// A plan is one batch (its pointers, scoring and mode fixed) made
+// replayable: it owns a private workspace sized by one planning run, and a
+// HIP graph of the whole device-driven pipeline -- counters cleared by a
+// fill kernel, classification, wavefront preparation and progress
+// counters, the packed, 32-bit and wavefront kernels on fixed persistent
+// grids (each reads its list length from device memory), the 32-bit re-run,
+// and a copy of the counters to pinned host memory.  Nothing in it depends on
+// the host between launches.  A replay whose inputs changed so much that the
+// plan's boundary buffers cannot hold them is refused on the device
+// (AS_ERR_ARG), never overrun.
+
+struct PlanImpl {
+  Workspace ws;
+  CallScoring cs;
+  RouteParams rp;
+  const uint8_t *seqs_a, *seqs_b;
+  const int64_t *offs_a, *offs_b;
+  int64_t n_pairs;
+  int32_t *scores;
+  int kmask;
+  int64_t bnd_rows, bnd_long_cap, flags_cap;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+// Enqueue the whole pipeline with fixed grids and no host synchronisation.
+int enqueue_plan(PlanImpl &P, hipStream_t stream) {
+  Workspace *w = &P.ws;
+  const CallScoring &cs = P.cs;
+  const int mode = cs.mode;
+  const int n_words = (int)(sizeof(Counters) / sizeof(int32_t));
+  hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(256), 0, stream, (int32_t *)w->ctr, (int64_t)n_words, 0);
+  AS_HIP(hipGetLastError());
+  int rc = launch_classify(w, P.rp, P.offs_a, P.offs_b, nullptr, P.n_pairs, P.scores, stream, P.bnd_rows);
+  if (rc) return rc;
+  hipLaunchKernelGGL(long_prep_kernel, dim3(1), dim3(256), 0, stream, w->items_long, w->ctr,
+                     long_dp_i32_stripe_width(), mode, P.scores, P.bnd_long_cap, P.flags_cap);
+  AS_HIP(hipGetLastError());
+  hipLaunchKernelGGL(fill_kernel, dim3(64), dim3(256), 0, stream, w->flags, P.flags_cap, 0);
+  AS_HIP(hipGetLastError());
+  if (cs.allow16) {
+    FullDp16Args a16;
+    a16.seqs_a = P.seqs_a;
+    a16.seqs_b = P.seqs_b;
+    a16.items = w->items16;
+    a16.ctr = w->ctr;
+    a16.rerun = w->rerun;
+    a16.subst = w->subst;
+    a16.asz = cs.asz;
+    a16.alpha = cs.alpha;
+    a16.beta = cs.beta;
+    a16.sat_limit = g_i16_limit;
+    a16.scores = P.scores;
+    AS_HIP(launch_full_dp_i16(mode, a16, full_dp_i16_blocks_per_cu(mode) * w->num_cu, stream));
+  }
+  FullDpArgs args;
+  args.seqs_a = P.seqs_a;
+  args.seqs_b = P.seqs_b;
+  args.ctr = w->ctr;
+  args.subst = w->subst;
+  args.asz = cs.asz;
+  args.alpha = cs.alpha;
+  args.beta = cs.beta;
+  args.scores = P.scores;
+  args.items = w->items;
+  args.n_items = &w->ctr->n_full32;
+  args.next = &w->ctr->next_full32;
+  args.bnd = w->bnd;
+  args.bnd_rows = P.bnd_rows;
+  const int grid32 = full_dp_i32_blocks_per_cu(mode, cs.asz, P.kmask) * w->num_cu;
+  AS_HIP(launch_full_dp_i32(mode, args, P.kmask, grid32, stream));
+  LongDpArgs la;
+  la.seqs_a = P.seqs_a;
+  la.seqs_b = P.seqs_b;
+  la.items = w->items_long;
+  la.ctr = w->ctr;
+  la.subst = w->subst;
+  la.asz = cs.asz;
+  la.alpha = cs.alpha;
+  la.beta = cs.beta;
+  la.scores = P.scores;
+  la.bnd = w->bnd_long;
+  la.flags = w->flags;
+  AS_HIP(launch_long_dp_i32(mode, la, long_dp_i32_blocks_per_cu(mode, cs.asz) * w->num_cu, stream));
+  if (cs.allow16) {
+    args.items = w->rerun;
+    args.n_items = &w->ctr->n_rerun32;
+    args.next = &w->ctr->next_rerun32;
+    args.bnd_rows = 1;
+    const int grid_r = full_dp_i32_blocks_per_cu(mode, cs.asz, kmask_of_variant(kVarI32K16)) * w->num_cu;
+    AS_HIP(launch_full_dp_i32(mode, args, kmask_of_variant(kVarI32K16), grid_r, stream));
+  }
+  AS_HIP(hipMemcpyAsync(w->host_ctr, w->ctr, sizeof(Counters), hipMemcpyDeviceToHost, stream));
+  return AS_OK;
+}
+
+void destroy_plan(PlanImpl *P) {
+  if (!P) return;
+  if (P->exec) (void)hipGraphExecDestroy(P->exec);
+  if (P->graph) (void)hipGraphDestroy(P->graph);
+  if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
+  free_workspace(P->ws);
+  delete P;
+}
+
+extern "C" int as_plan_create(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t *seqs_b,
+                              const int64_t *offs_b, int64_t n_pairs, const as_scoring *scoring, int32_t mode,
+                              int32_t *scores_out, as_plan **plan_out, void *stream_ptr) {
+  if (!scoring || !offs_a || !offs_b || !seqs_a || !seqs_b || !scores_out || !scoring->subst || !plan_out)
+    return AS_ERR_NULL;
+  *plan_out = nullptr;
+  if (n_pairs < 1 || n_pairs >= ((int64_t)1 << 31) - 1) return AS_ERR_ARG;
+  CallScoring cs;
+  int rc = check_scoring(scoring, mode, &cs);
+  if (rc) return rc;
+  hipStream_t stream = (hipStream_t)stream_ptr;
+  int dev = 0;
+  AS_HIP(hipGetDevice(&dev));
+  PlanImpl *P = new PlanImpl();
+  auto fail = [&](int code) {
+    destroy_plan(P);
+    return code;
+  };
+  if ((rc = init_workspace(P->ws, dev))) return fail(rc);
+  Workspace *w = &P->ws;
+  P->cs = cs;
+  {
+    std::lock_guard<std::mutex> guard(g_lock);
+    P->rp = route_params(cs, n_pairs);
+  }
+  P->seqs_a = seqs_a;
+  P->seqs_b = seqs_b;
+  P->offs_a = offs_a;
+  P->offs_b = offs_b;
+  P->n_pairs = n_pairs;
+  P->scores = scores_out;
+  if ((rc = lists_capacity(w, n_pairs))) return fail(rc);
+  if (hipMemcpyAsync(w->subst, scoring->subst, (size_t)cs.asz * cs.asz, hipMemcpyHostToDevice, stream) !=
+      hipSuccess)
+    return fail(AS_ERR_HIP);
+  // planning run: classification and wavefront preparation, to size the buffers
+  if (hipMemsetAsync(w->ctr, 0, sizeof(Counters), stream) != hipSuccess) return fail(AS_ERR_HIP);
+  if ((rc = launch_classify(w, P->rp, offs_a, offs_b, nullptr, n_pairs, scores_out, stream))) return fail(rc);
+  hipLaunchKernelGGL(long_prep_kernel, dim3(1), dim3(256), 0, stream, w->items_long, w->ctr,
+                     long_dp_i32_stripe_width(), mode, scores_out, (int64_t)0, (int64_t)0);
+  if (hipGetLastError() != hipSuccess) return fail(AS_ERR_HIP);
+  Counters c;
+  if ((rc = read_counters(w, stream, &c))) return fail(rc);
+  if ((rc = status_to_code(c.status))) return fail(rc);
+  // the 32-bit kernel covers every K the table can route (contents may change between replays)
+  int kmask = kmask_of_variant(kVarI32K16);
+  for (int b = 0; b < kLenBins; ++b) {
+    const int v = P->rp.var_of_bin[b];
+    if (v == kVarI32K8 || v == kVarI32K16 || v == kVarI32K32) kmask |= kmask_of_variant(v);
+  }
+  P->kmask = kmask;
+  P->bnd_rows = (int64_t)(c.max_rows_multi > 0 ? c.max_rows_multi : 0) + 1;
+  const int grid32 = full_dp_i32_blocks_per_cu(mode, cs.asz, kmask) * w->num_cu;
+  const int grid_r = full_dp_i32_blocks_per_cu(mode, cs.asz, kmask_of_variant(kVarI32K16)) * w->num_cu;
+  const int64_t slots = (int64_t)(grid32 > grid_r ? grid32 : grid_r) * kGroupsPerWave;
+  if ((rc = grow((void **)&w->bnd, &w->bnd_cap, slots * 2 * P->bnd_rows, sizeof(int2)))) return fail(rc);
+  P->bnd_long_cap = c.long_bnd_total > 0 ? c.long_bnd_total : 1;
+  P->flags_cap = c.n_long_tasks > 0 ? c.n_long_tasks : 1;
+  if ((rc = grow((void **)&w->bnd_long, &w->bnd_long_cap, P->bnd_long_cap, sizeof(int2)))) return fail(rc);
+  if ((rc = grow((void **)&w->flags, &w->flags_cap, P->flags_cap, sizeof(int32_t)))) return fail(rc);
+  // capture on a private stream of default priority
+  if (hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking) != hipSuccess) return fail(AS_ERR_HIP);
+  if (hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+    return fail(AS_ERR_HIP);
+  rc = enqueue_plan(*P, P->cap_stream);
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(P->cap_stream, &g);
+  P->graph = g;
+  if (rc) return fail(rc);
+  if (ec != hipSuccess || !g) return fail(AS_ERR_HIP);
+  if (hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0) != hipSuccess) return fail(AS_ERR_HIP);
+  *plan_out = reinterpret_cast<as_plan *>(P);
+  return AS_OK;
+}
+
+extern "C" int as_plan_run(as_plan *plan, void *stream_ptr) {
+  if (!plan) return AS_ERR_NULL;
+  PlanImpl *P = reinterpret_cast<PlanImpl *>(plan);
+  hipStream_t stream = (hipStream_t)stream_ptr;
+  AS_HIP(hipGraphLaunch(P->exec, stream));
+  AS_HIP(hipStreamSynchronize(stream));
+  const Counters *c = P->ws.host_ctr;
+  return status_to_code(c->status);
+}
+
+extern "C" int as_plan_destroy(as_plan *plan) {
+  destroy_plan(reinterpret_cast<PlanImpl *>(plan));
+  return AS_OK;
+}
+
 extern "C" int as_set_variants(int32_t mode, const int8_t *table) {
   if (mode < 0 || mode > 2) return AS_ERR_ARG;
   if (table)
@@ -1050,15 +1277,8 @@ extern "C" int as_release_workspace(void) {
     int cur = 0;
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(w.device);
-    void *bufs[] = {w.items, w.items16, w.rerun, w.items_long, w.bnd_long, w.flags, w.band_lists,
-                    w.fallback, w.qwords, w.ctr, w.subst, w.bnd, w.tune_scores};
-    for (void *b : bufs)
-      if (b) (void)hipFree(b);
-    if (w.host_ctr) (void)hipHostFree(w.host_ctr);
-    for (auto &e : w.ev)
-      if (e) (void)hipEventDestroy(e);
+    free_workspace(w);
     (void)hipSetDevice(cur);
-    w = Workspace();
   }
   return AS_OK;
 }

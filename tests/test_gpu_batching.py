@@ -116,3 +116,56 @@ def test_autotune_then_exact(gpu, oracle_mod):
     sub = b.subset(np.sort(idx))
     np.testing.assert_array_equal(got[np.sort(idx)], _oracle(oracle_mod, sub))
     gpu.set_variants(b.mode, None)
+
+
+def test_plan_replays_match_oracle(gpu, oracle_mod):
+    """A captured plan replayed several times, with eager library work and
+    synchronisations between the replays; every replay equals the oracle.
+    Then the B residues change in place (same lengths) and the replay equals
+    the eager full DP of the new contents."""
+    import torch
+    for mode in (0, 1, 2):
+        b = synth.from_pairs("plan", _mixed_batch(930 + mode, 4, n_pairs=500), DNA, 5, 2, mode)
+        want = _oracle(oracle_mod, b)
+        sa, oa, sb, ob = gpu.to_device(b)
+        plan = gpu.Plan(sa, oa, sb, ob, DNA, 5, 2, mode)
+        other = synth.config0(n_pairs=300, seed=931)
+        dother = gpu.to_device(other)
+        for rep in range(3):
+            got = plan.run().cpu().numpy()
+            assert np.array_equal(got, want), (mode, rep)
+            gpu.align_batch(*dother, other.subst, other.alpha, other.beta, other.mode)
+            torch.cuda.synchronize()
+        sb.copy_((sb + 1) % 4)
+        eager = gpu.align_batch(sa, oa, sb, ob, DNA, 5, 2, mode).cpu().numpy()
+        for rep in range(2):
+            assert np.array_equal(plan.run().cpu().numpy(), eager), (mode, "changed", rep)
+        _say(f"plan mode {mode}: 5 replays exact")
+        plan.close()
+
+
+def test_plan_refuses_batch_beyond_its_buffers(gpu):
+    """Offsets changed after planning so that a pair needs more multi-stripe
+    boundary rows than the plan holds: the replay is refused (AS_ERR_ARG);
+    restoring them makes it run again."""
+    import torch
+    rng = np.random.default_rng(940)
+    a = rng.integers(0, 4, 1200).astype(np.uint8)
+    bseq = rng.integers(0, 4, 1200).astype(np.uint8)
+    sa = torch.from_numpy(a).cuda()
+    sb = torch.from_numpy(bseq).cuda()
+    oa = torch.tensor([0, 300, 400], dtype=torch.int64, device="cuda")
+    ob = torch.tensor([0, 600, 700], dtype=torch.int64, device="cuda")
+    plan = gpu.Plan(sa, oa, sb, ob, DNA, 5, 2, 1)
+    first = plan.run().cpu().numpy().copy()
+    oa[2] = 1200
+    ob[2] = 1200
+    torch.cuda.synchronize()
+    with pytest.raises(gpu.AlignError) as e:
+        plan.run()
+    assert e.value.code == -7
+    oa[2] = 400
+    ob[2] = 700
+    torch.cuda.synchronize()
+    assert np.array_equal(plan.run().cpu().numpy(), first)
+    plan.close()
