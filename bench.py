@@ -214,10 +214,29 @@ def train_band_model(binding, torch, synth):
                              TRAIN["steps"], TRAIN["batch"], lr=TRAIN["lr"], tau=TRAIN["tau"])
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
+    # diagnostics on the training set: DP cells of the learned path against
+    # the cells of each pair's own label (its smallest accepted band), both
+    # in the kernel's band widths
+    import numpy as np
+    labels = binding.band_labels(*dev, train.subst, train.alpha, train.beta, train.mode).cpu().numpy()
+    _, st = binding.align_batch_learned(*dev, train.subst, train.alpha, train.beta, train.mode, params)
+    la, lb = train.lens_a.astype(np.int64), train.lens_b.astype(np.int64)
+    rows, dn = np.minimum(la, lb), np.abs(la - lb)
+    widths = np.array([64, 128, 192, 256, 384, 512, 768, 1024])
+    need = dn + 2 * labels + 1
+    cls = np.searchsorted(widths, need)
+    fits = (labels < binding.BAND_WIDE) & (cls < len(widths))
+    fits &= 2 * widths[np.minimum(cls, len(widths) - 1)] < np.maximum(la, lb)
+    ideal = np.where(fits, rows * widths[np.minimum(cls, len(widths) - 1)], la * lb).sum()
     del dev
     return params, {"pairs": train.n_pairs, "steps": TRAIN["steps"], "batch": TRAIN["batch"],
                     "lr": TRAIN["lr"], "tau": TRAIN["tau"], "gen_s": round(t_gen, 2),
-                    "labels_and_training_s": round(t_train, 2)}
+                    "labels_and_training_s": round(t_train, 2),
+                    "train_set_dp_cells_frac": {
+                        "learned": round(st["dp_cells"] / train.cells(), 4),
+                        "own_label_bands": round(float(ideal) / train.cells(), 4),
+                        "label_median": float(np.median(labels)),
+                        "labels_wide": int(np.count_nonzero(labels >= binding.BAND_WIDE))}}
 
 
 def main():

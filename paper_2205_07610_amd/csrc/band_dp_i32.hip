@@ -42,23 +42,37 @@
 namespace asmi {
 namespace {
 
-__device__ __forceinline__ int dpp_shr1(int old, int src) {
-  return __builtin_amdgcn_update_dpp(old, src, 0x111, 0xF, 0xF, false);
+// One-lane shifts inside a group of G lanes: a DPP row (G = 16) or the
+// whole wave (G = 64); the first / last lane of the group keeps `old`.
+template <int G>
+__device__ __forceinline__ int shr1(int old, int src) {
+  return __builtin_amdgcn_update_dpp(old, src, G == 16 ? 0x111 : 0x138, 0xF, 0xF, false);
 }
-__device__ __forceinline__ int dpp_shl1(int old, int src) {
-  return __builtin_amdgcn_update_dpp(old, src, 0x101, 0xF, 0xF, false);
+template <int G>
+__device__ __forceinline__ int shl1(int old, int src) {
+  return __builtin_amdgcn_update_dpp(old, src, G == 16 ? 0x101 : 0x130, 0xF, 0xF, false);
 }
 __device__ __forceinline__ int imax3(int a, int b, int c) { return max(max(a, b), c); }
+// Maximum over the lanes of a group.
+template <int G>
 __device__ __forceinline__ int group_max(int v) {
+  if (G == 64) {
+    v = max(v, __shfl_xor(v, 32));
+    v = max(v, __shfl_xor(v, 16));
+  }
   v = max(v, __shfl_xor(v, 8, 16));
   v = max(v, __shfl_xor(v, 4, 16));
   v = max(v, __shfl_xor(v, 2, 16));
   v = max(v, __shfl_xor(v, 1, 16));
   return v;
 }
+// Maximum over the groups of a wave of a value uniform inside each group.
+template <int G>
 __device__ __forceinline__ int wave_max_groups(int v) {
-  v = max(v, __shfl_xor(v, 16));
-  v = max(v, __shfl_xor(v, 32));
+  if (G == 16) {
+    v = max(v, __shfl_xor(v, 16));
+    v = max(v, __shfl_xor(v, 32));
+  }
   return v;
 }
 
@@ -71,13 +85,14 @@ __device__ __forceinline__ uint32_t col_code(const uint8_t *cols, int n, int j, 
   return (uint32_t)c;
 }
 
-template <int MODE, int K, bool EXACT>
+template <int MODE, int K, bool EXACT, int G>
 __global__ void __launch_bounds__(kWave) band_dp_i32_kernel(BandArgs a, int kc) {
-  constexpr int W = kGroup * K;
+  constexpr int W = G * K;
+  constexpr int GPW = kWave / G;  // groups (pairs) per wave
   constexpr int NV = K / 4;  // selector words per lane
   const int lane = threadIdx.x;
-  const int g = lane >> 4;
-  const int t = lane & 15;
+  const int g = lane / G;
+  const int t = lane % G;
   const int alpha = a.alpha, beta = a.beta, amb = alpha - beta;
   const int asz = a.asz;
   const int cur = a.round & 1;
@@ -89,7 +104,7 @@ __global__ void __launch_bounds__(kWave) band_dp_i32_kernel(BandArgs a, int kc) 
 
   for (;;) {
     int base = 0;
-    if (lane == 0) base = atomicAdd(&a.ctr->next_band[kc], kGroupsPerWave);
+    if (lane == 0) base = atomicAdd(&a.ctr->next_band[kc], GPW);
     base = __shfl(base, 0);
     if (base >= n_list) break;
     const int item = base + g;
@@ -143,8 +158,8 @@ __global__ void __launch_bounds__(kWave) band_dp_i32_kernel(BandArgs a, int kc) 
     int res = kNegInf32;   // this lane's candidate for the banded score
     const int kn = n - m - lo;  // register index of column n at row m
 
-    const int its = m > 0 ? m + kGroup - 1 : 0;
-    const int its_max = wave_max_groups(its);
+    const int its = m > 0 ? m + G - 1 : 0;
+    const int its_max = wave_max_groups<G>(its);
     // feeds, 16 steps per refill: row score words travel down from lane 0
     // (row_shr), new column codes enter at lane 15 (element u in lane 15-u)
     auto qword = [&](int idx) -> uint32_t {
@@ -154,22 +169,24 @@ __global__ void __launch_bounds__(kWave) band_dp_i32_kernel(BandArgs a, int kc) 
       return a.qwords[(tr ? 32 : 0) + r];
     };
     uint32_t qfeed = qword(t);
-    uint32_t cfeed = col_code(cols, n, (15 - t) - 14 + lo + W - 1, asz, bad);
+    // new column codes enter at the group's last lane: element u of a chunk
+    // sits in lane G-1-u (the last 16 lanes)
+    uint32_t cfeed = col_code(cols, n, (G - 1 - t) - (G - 2) + lo + W - 1, asz, bad);
     for (int it0 = 0; it0 < its_max; it0 += kGroup) {
       const uint32_t qnext = qword(it0 + kGroup + t);
-      const uint32_t cnext = col_code(cols, n, it0 + kGroup + (15 - t) - 14 + lo + W - 1, asz, bad);
+      const uint32_t cnext = col_code(cols, n, it0 + kGroup + (G - 1 - t) - (G - 2) + lo + W - 1, asz, bad);
 #pragma unroll
       for (int u = 0; u < kGroup; ++u) {
         const int row = it0 + u + 1 - t;
         // advance this lane's column window to `row`
-        const uint32_t right = (uint32_t)dpp_shl1((int)(cfeed << 8), (int)win[0]);  // byte 1 = new code
+        const uint32_t right = (uint32_t)shl1<G>((int)(cfeed << 8), (int)win[0]);  // byte 1 = new code
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
           const uint32_t nxt = (v + 1 < NV) ? win[v + 1] : (right >> 8);
           win[v] = __builtin_amdgcn_alignbyte(nxt, win[v], 1);
         }
-        qrow = (uint32_t)dpp_shr1((int)qfeed, (int)qrow);
-        const int fl = dpp_shr1(kNegInf32, fout);
+        qrow = (uint32_t)shr1<G>((int)qfeed, (int)qrow);
+        const int fl = shr1<G>(kNegInf32, fout);
         // phase A: diagonal sums and E from the previous row's registers
         int tt[K], ee[K];
 #pragma unroll
@@ -194,8 +211,8 @@ __global__ void __launch_bounds__(kWave) band_dp_i32_kernel(BandArgs a, int kc) 
           Ee[0] = kNegInf32;
           D[0] = kNegInf32;
         }
-        const int eR = dpp_shl1(kNegInf32, max(Ee[0], Ha[0]));
-        const int dR = (MODE == kSemiGlobal) ? dpp_shl1(kNegInf32, D[0]) : 0;
+        const int eR = shl1<G>(kNegInf32, max(Ee[0], Ha[0]));
+        const int dR = (MODE == kSemiGlobal) ? shl1<G>(kNegInf32, D[0]) : 0;
 #pragma unroll
         for (int x = 1; x < K; ++x) {
           const int e = (x + 1 < K) ? ee[x] : eR;
@@ -241,15 +258,15 @@ __global__ void __launch_bounds__(kWave) band_dp_i32_kernel(BandArgs a, int kc) 
           }
         }
         rowoff += beta;
-        qfeed = (uint32_t)dpp_shl1((int)qfeed, (int)qfeed);
-        cfeed = (uint32_t)dpp_shr1((int)cfeed, (int)cfeed);
+        qfeed = (uint32_t)shl1<G>((int)qfeed, (int)qfeed);
+        cfeed = (uint32_t)shr1<G>((int)cfeed, (int)cfeed);
       }
       qfeed = qnext;
       cfeed = cnext;
     }
 
     // ---- banded score ----
-    int score = group_max(res);
+    int score = group_max<G>(res);
     // H(0, n) = 0 counts when that boundary cell lies in the band (H(m, 0) is
     // the last row's column 0, already among the registers when in the band)
     const int blo = EXACT ? L : lo, bhi = EXACT ? U : hi;  // the band scored
@@ -290,22 +307,31 @@ __global__ void __launch_bounds__(kWave) band_dp_i32_kernel(BandArgs a, int kc) 
   }
 }
 
+// Lane-width classes: 64, 128, 192, 256 and 384 diagonals on 16-lane groups
+// (K = 4, 8, 12, 16, 24; four pairs per wave), 512, 768 and 1024 on whole
+// waves (K = 8, 12, 16; one pair per wave), which keeps the registers a lane
+// holds low enough for several waves per SIMD.
+static_assert(kBandClasses == 8, "class table");
+static_assert(sizeof(((Counters *)0)->next_band) == kBandClasses * sizeof(int32_t), "counters");
 template <int MODE, bool EXACT>
 hipError_t launch_mode(const BandArgs &args, int kc, int grid, hipStream_t stream) {
   switch (kc) {
-    case 0: hipLaunchKernelGGL((band_dp_i32_kernel<MODE, 4, EXACT>), dim3(grid), dim3(kWave), 0, stream, args, kc); break;
-    case 1: hipLaunchKernelGGL((band_dp_i32_kernel<MODE, 8, EXACT>), dim3(grid), dim3(kWave), 0, stream, args, kc); break;
-    case 2: hipLaunchKernelGGL((band_dp_i32_kernel<MODE, 16, EXACT>), dim3(grid), dim3(kWave), 0, stream, args, kc); break;
-    case 3: hipLaunchKernelGGL((band_dp_i32_kernel<MODE, 32, EXACT>), dim3(grid), dim3(kWave), 0, stream, args, kc); break;
-    default: hipLaunchKernelGGL((band_dp_i32_kernel<MODE, 64, EXACT>), dim3(grid), dim3(kWave), 0, stream, args, kc); break;
+    case 0: hipLaunchKernelGGL((band_dp_i32_kernel<MODE, 4, EXACT, 16>), dim3(grid), dim3(kWave), 0, stream, args, kc); break;
+    case 1: hipLaunchKernelGGL((band_dp_i32_kernel<MODE, 8, EXACT, 16>), dim3(grid), dim3(kWave), 0, stream, args, kc); break;
+    case 2: hipLaunchKernelGGL((band_dp_i32_kernel<MODE, 12, EXACT, 16>), dim3(grid), dim3(kWave), 0, stream, args, kc); break;
+    case 3: hipLaunchKernelGGL((band_dp_i32_kernel<MODE, 16, EXACT, 16>), dim3(grid), dim3(kWave), 0, stream, args, kc); break;
+    case 4: hipLaunchKernelGGL((band_dp_i32_kernel<MODE, 24, EXACT, 16>), dim3(grid), dim3(kWave), 0, stream, args, kc); break;
+    case 5: hipLaunchKernelGGL((band_dp_i32_kernel<MODE, 8, EXACT, 64>), dim3(grid), dim3(kWave), 0, stream, args, kc); break;
+    case 6: hipLaunchKernelGGL((band_dp_i32_kernel<MODE, 12, EXACT, 64>), dim3(grid), dim3(kWave), 0, stream, args, kc); break;
+    default: hipLaunchKernelGGL((band_dp_i32_kernel<MODE, 16, EXACT, 64>), dim3(grid), dim3(kWave), 0, stream, args, kc); break;
   }
   return hipGetLastError();
 }
 
-template <int MODE, int K>
+template <int MODE, int K, int G>
 int occupancy() {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, band_dp_i32_kernel<MODE, K, false>, kWave, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, band_dp_i32_kernel<MODE, K, false, G>, kWave, 0) !=
           hipSuccess || nb < 1)
     nb = 1;
   return nb;
@@ -321,22 +347,30 @@ hipError_t launch_band_dp_i32(int mode, int kc, const BandArgs &args, int grid, 
                          : launch_mode<kSemiGlobal, false>(args, kc, grid, stream);
 }
 
+int band_dp_i32_pairs_per_wave(int kc) { return kc >= 5 ? 1 : kGroupsPerWave; }
+
 int band_dp_i32_blocks_per_cu(int mode, int kc) {
   if (mode == kGlobal) {
     switch (kc) {
-      case 0: return occupancy<kGlobal, 4>();
-      case 1: return occupancy<kGlobal, 8>();
-      case 2: return occupancy<kGlobal, 16>();
-      case 3: return occupancy<kGlobal, 32>();
-      default: return occupancy<kGlobal, 64>();
+      case 0: return occupancy<kGlobal, 4, 16>();
+      case 1: return occupancy<kGlobal, 8, 16>();
+      case 2: return occupancy<kGlobal, 12, 16>();
+      case 3: return occupancy<kGlobal, 16, 16>();
+      case 4: return occupancy<kGlobal, 24, 16>();
+      case 5: return occupancy<kGlobal, 8, 64>();
+      case 6: return occupancy<kGlobal, 12, 64>();
+      default: return occupancy<kGlobal, 16, 64>();
     }
   }
   switch (kc) {
-    case 0: return occupancy<kSemiGlobal, 4>();
-    case 1: return occupancy<kSemiGlobal, 8>();
-    case 2: return occupancy<kSemiGlobal, 16>();
-    case 3: return occupancy<kSemiGlobal, 32>();
-    default: return occupancy<kSemiGlobal, 64>();
+    case 0: return occupancy<kSemiGlobal, 4, 16>();
+    case 1: return occupancy<kSemiGlobal, 8, 16>();
+    case 2: return occupancy<kSemiGlobal, 12, 16>();
+    case 3: return occupancy<kSemiGlobal, 16, 16>();
+    case 4: return occupancy<kSemiGlobal, 24, 16>();
+    case 5: return occupancy<kSemiGlobal, 8, 64>();
+    case 6: return occupancy<kSemiGlobal, 12, 64>();
+    default: return occupancy<kSemiGlobal, 16, 64>();
   }
 }
 

@@ -84,8 +84,8 @@ struct Counters {
   int32_t n_fallback;    // banded pairs sent to the full DP
   long long long_bnd_total;  // int2 entries of all wavefront boundary columns
   // banded path: lists per round parity and lane-width class
-  int32_t n_band[2][5];
-  int32_t next_band[5];
+  int32_t n_band[2][8];
+  int32_t next_band[8];
   int32_t band_accepted[8];  // pairs accepted in round r
   unsigned long long band_cells;  // cells computed by the banded kernel
   unsigned long long fallback_cells;  // sum of m*n over the fallback pairs
@@ -100,16 +100,20 @@ struct Counters {
 };
 
 // ---- banded path ----
-constexpr int kBandClasses = 5;     // lane widths K = 4, 8, 16, 32, 64 (W = 64 .. 1024)
+// Band widths (diagonals) of the banded kernel's classes: 16-lane groups
+// with K = 4, 8, 12, 16, 24 columns per lane, then whole waves with K = 8,
+// 12, 16.  Consecutive widths differ by at most 1.5x.
+constexpr int kBandClasses = 8;
 constexpr int kMaxBandRounds = 8;
+__host__ __device__ inline int band_class_width(int kc) {
+  return kc == 0 ? 64 : kc == 1 ? 128 : kc == 2 ? 192 : kc == 3 ? 256
+       : kc == 4 ? 384 : kc == 5 ? 512 : kc == 6 ? 768 : 1024;
+}
 
-// Band width (diagonals) of lane-width class kc: 16 lanes x K = 4 << kc.
-__host__ __device__ inline int band_class_width(int kc) { return kGroup * (4 << kc); }
-
-// Smallest class whose band width 16*K holds B diagonals, or -1.
+// Smallest class whose width holds B diagonals, or -1.
 __host__ __device__ inline int band_class_for(int B) {
   for (int kc = 0; kc < kBandClasses; ++kc)
-    if (kGroup * (4 << kc) >= B) return kc;
+    if (band_class_width(kc) >= B) return kc;
   return -1;
 }
 
@@ -188,6 +192,7 @@ struct BandArgs {
 
 hipError_t launch_band_dp_i32(int mode, int kc, const BandArgs &args, int grid, hipStream_t stream);
 int band_dp_i32_blocks_per_cu(int mode, int kc);
+int band_dp_i32_pairs_per_wave(int kc);
 
 // ---- learned band ----
 constexpr int kMlpInputs = 32;

@@ -894,7 +894,8 @@ int asmi::band_call(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t 
       const int cnt = c.n_band[cur][kc];
       if (!cnt) continue;
       int64_t grid = (int64_t)band_dp_i32_blocks_per_cu(mode, kc) * w->num_cu;
-      const int64_t need = ((int64_t)cnt + kGroupsPerWave - 1) / kGroupsPerWave;
+      const int ppw = band_dp_i32_pairs_per_wave(kc);
+      const int64_t need = ((int64_t)cnt + ppw - 1) / ppw;
       if (grid > need) grid = need;
       AS_HIP(launch_band_dp_i32(mode, kc, ba, (int)grid, stream));
     }
