@@ -50,7 +50,7 @@ KERNEL_SOURCES = {
     "band": "paper_2205_07610_amd/csrc/band_dp_i32.hip",
 }
 # band network training of the learned workload (library kernels, untimed)
-TRAIN = {"pairs": 200_000, "seed": 2004, "steps": 4000, "batch": 1024, "lr": 2e-3, "tau": 0.85,
+TRAIN = {"pairs": 200_000, "seed": 2004, "steps": 4000, "batch": 1024, "lr": 2e-3, "tau": 0.7,
          "init_seed": 2005, "order_seed": 2006, "b3": 5.0}
 MODE_NAMES = {0: "global", 1: "semi-global", 2: "local"}
 
@@ -248,6 +248,9 @@ def main():
     ap.add_argument("--workload", default="c4", help="c4 (default), c0, c1, c2, c3, c3long")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tau", type=float, default=TRAIN["tau"], help="pinball quantile of the band network")
+    ap.add_argument("--train-steps", type=int, default=TRAIN["steps"])
+    ap.add_argument("--lr", type=float, default=TRAIN["lr"])
     ap.add_argument("--copy-reference", action="store_true",
                     help="first copy 1 GiB device-to-device three times (untimed): the known-size "
                          "reference that scales HBM byte counters in a profiler run")
@@ -267,6 +270,7 @@ def main():
         sys.exit(1)
     binding.lib()
     WORKLOAD_NAME["name"] = args.workload
+    TRAIN.update(tau=args.tau, steps=args.train_steps, lr=args.lr)
     if args.copy_reference:
         src = torch.ones(1 << 30, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)

@@ -261,3 +261,23 @@ def test_learned_band_exact_and_beats_fixed_width(gpu, oracle_mod):
          f"fixed w0={best}: {st_f['dp_cells'] / test.cells():.4f} "
          f"(accepted {st_f['accepted']}, fallback {st_f['fallback']})")
     assert st_l["dp_cells"] < st_f["dp_cells"]
+
+
+def test_features_many_pairs_per_workgroup(gpu):
+    """200,000 short pairs: every workgroup processes several hundred pairs,
+    so the table's per-pair generations wrap (and the table is cleared)
+    several times; every feature still equals the oracle's."""
+    from oracle import features as F
+    rng = np.random.default_rng(870)
+    n = 200_000
+    la = rng.integers(0, 48, n)
+    sa, oa = synth.random_csr(rng, la, 4)
+    div = rng.uniform(0, 0.3, n)
+    sb, ob = synth.mutate(rng, sa, oa, div / 2, div / 4, div / 4, 4)
+    b = synth.Batch("many short", sa, oa, sb, ob, DNA, 5, 2, 0)
+    got = gpu.pair_features(*gpu.to_device(b)).cpu().numpy()
+    idx = np.arange(0, n, 7)
+    want = np.stack([F.pair_features(*b.pair(int(p))) for p in idx])
+    np.testing.assert_array_equal(got[idx, :30], want[:, :30])
+    np.testing.assert_array_equal(got[idx, 31], want[:, 31])
+    _say(f"features of {n} short pairs: {len(idx)} checked, hits in {np.count_nonzero(want[:, 31])}")
