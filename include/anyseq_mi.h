@@ -339,6 +339,17 @@ int as_plan_run(as_plan *plan, void *stream);
 int as_plan_destroy(as_plan *plan);
 
 /*
+ * Packed 16-bit banded kernel (global mode): a pair whose band cells are
+ * proven to fit int16 (sigma_max*min(m,n) + beta*(m + n + W) + margins below
+ * 32000, W the band width in diagonals) is banded two pairs per lane group
+ * with 16-bit cells, in widths of 64, 128, 256, 512 or 1024 diagonals; the
+ * others use the 32-bit banded kernel.  On by default; on = 0 sends every
+ * pair to the 32-bit kernel (scores are the same either way).  Returns the
+ * previous setting.
+ */
+int as_set_band_packing(int32_t on);
+
+/*
  * Saturation threshold of the packed 16-bit local path: a pair whose 16-bit
  * maximum reaches `limit` is treated as saturated and recomputed with 32-bit
  * cells.  The default, 32767, is the int16 saturation value itself; a lower

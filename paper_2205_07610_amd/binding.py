@@ -112,6 +112,8 @@ def lib() -> ctypes.CDLL:
     L.as_plan_run.argtypes = [p, p]
     L.as_plan_destroy.restype = ctypes.c_int
     L.as_plan_destroy.argtypes = [p]
+    L.as_set_band_packing.restype = ctypes.c_int
+    L.as_set_band_packing.argtypes = [i32]
     L.as_set_variants.restype = ctypes.c_int
     L.as_set_variants.argtypes = [i32, p]
     L.as_get_variants.restype = ctypes.c_int
@@ -189,6 +191,11 @@ def align_batch(seqs_a, offs_a, seqs_b, offs_b, subst, alpha: int, beta: int, mo
     del keep
     _check(rc)
     return scores_out
+
+
+def set_band_packing(on: bool) -> bool:
+    """Packed 16-bit banded kernel for eligible global pairs (default on)."""
+    return bool(lib().as_set_band_packing(1 if on else 0))
 
 
 def set_i16_limit(limit: int) -> int:

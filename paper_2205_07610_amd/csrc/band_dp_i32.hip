@@ -291,19 +291,7 @@ __global__ void __launch_bounds__(kWave) band_dp_i32_kernel(BandArgs a, int kc) 
       atomicAdd(&a.ctr->band_accepted[a.round < kMaxBandRounds ? a.round : kMaxBandRounds - 1], 1);
       continue;
     }
-    const int w2 = bi.w > 0 ? 2 * bi.w : 1;
-    const int B2 = abs(n - m) + 2 * w2 + 1;
-    const int kc2 = band_class_for(B2);
-    if (a.round + 1 >= a.max_rounds || kc2 < 0 || 2 * band_class_width(kc2) >= n) {
-      a.fallback[atomicAdd(&a.ctr->n_fallback, 1)] = d;
-      continue;
-    }
-    BandItem nb;
-    nb.d = d;
-    nb.w = w2;
-    nb.pad_ = 0;
-    const int slot = atomicAdd(&a.ctr->n_band[cur ^ 1][kc2], 1);
-    a.lists[((int64_t)((cur ^ 1) * kBandClasses + kc2)) * a.list_cap + slot] = nb;
+    band_requeue(a, d, bi.w, MODE);
   }
 }
 

@@ -86,6 +86,8 @@ struct Counters {
   // banded path: lists per round parity and lane-width class
   int32_t n_band[2][8];
   int32_t next_band[8];
+  int32_t n_band16[2][5];   // packed 16-bit banded lists per round parity and class
+  int32_t next_band16[5];
   int32_t band_accepted[8];  // pairs accepted in round r
   unsigned long long band_cells;  // cells computed by the banded kernel
   unsigned long long fallback_cells;  // sum of m*n over the fallback pairs
@@ -177,7 +179,10 @@ struct BandArgs {
   const uint8_t *seqs_a;
   const uint8_t *seqs_b;
   BandItem *lists;          // [2 parities][kBandClasses][list_cap]
+  BandItem *lists16;        // [2 parities][kBand16Classes][list_cap] (packed 16-bit kernel)
   int64_t list_cap;
+  int32_t pack16;           // 1: range-proven global pairs may use the packed kernel
+  int32_t smax_pos;         // max(sigma_max, 0)
   Counters *ctr;
   const uint32_t *qwords;   // [2][32]: byte c of word r = sigma(r, c) + alpha + beta (row/col order)
   int32_t asz, alpha, beta, sigma_max;
@@ -193,6 +198,69 @@ struct BandArgs {
 hipError_t launch_band_dp_i32(int mode, int kc, const BandArgs &args, int grid, hipStream_t stream);
 int band_dp_i32_blocks_per_cu(int mode, int kc);
 int band_dp_i32_pairs_per_wave(int kc);
+hipError_t launch_band_dp_i16(int pc, const BandArgs &args, int grid, hipStream_t stream);
+int band_dp_i16_blocks_per_cu(int pc);
+int band_dp_i16_pairs_per_wave(int pc);
+
+// Packed 16-bit banded classes (global mode): 64 << pc diagonals.
+constexpr int kBand16Classes = 5;
+__host__ __device__ inline int band16_class_width(int pc) { return 64 << pc; }
+__host__ __device__ inline int band16_class_for(int B) {
+  for (int pc = 0; pc < kBand16Classes; ++pc)
+    if ((64 << pc) >= B) return pc;
+  return -1;
+}
+// Every shifted cell of a W-diagonal band of an m x n global pair stays
+// below sigma_max*min(m,n) + beta*(m + n + W) (columns run up to n + W),
+// plus the score byte and margins: inside int16 when this is below 32000.
+__host__ __device__ inline bool band16_range_ok(int m, int n, int W, int smax_pos, int alpha, int beta) {
+  const int64_t ub = (int64_t)smax_pos * (m < n ? m : n) + (int64_t)beta * ((int64_t)m + n + W) + alpha +
+                     2 * beta + 256;
+  return ub < 32000;
+}
+// Where a band request of half-width w for an m-row (shorter), n-column pair
+// goes: a packed class (*packed = true), a 32-bit class, or -1 for the full
+// DP (no class holds it, or the band would cover half the matrix).
+__host__ __device__ inline int band_route(int m, int n, int w, bool pack16, int smax_pos, int alpha, int beta,
+                                          bool *packed) {
+  const int B = n - m + 2 * w + 1;
+  if (pack16) {
+    const int pc = band16_class_for(B);
+    if (pc >= 0 && 2 * band16_class_width(pc) < n &&
+        band16_range_ok(m, n, band16_class_width(pc), smax_pos, alpha, beta)) {
+      *packed = true;
+      return pc;
+    }
+  }
+  *packed = false;
+  const int kc = band_class_for(B);
+  if (kc < 0 || 2 * band_class_width(kc) >= n) return -1;
+  return kc;
+}
+// A rejected band: queue the pair for the next round with the half-width
+// doubled, or for the full DP when no band can hold it or the rounds are
+// spent.
+__device__ inline void band_requeue(const BandArgs &a, const PairDesc &d, int w, int mode) {
+  const int w2 = w > 0 ? 2 * w : 1;
+  bool packed = false;
+  const int c = band_route(d.m, d.n, w2, a.pack16 && mode == kGlobal, a.smax_pos, a.alpha, a.beta, &packed);
+  if (a.round + 1 >= a.max_rounds || c < 0) {
+    a.fallback[atomicAdd(&a.ctr->n_fallback, 1)] = d;
+    return;
+  }
+  BandItem nb;
+  nb.d = d;
+  nb.w = w2;
+  nb.pad_ = 0;
+  const int nxt = (a.round & 1) ^ 1;
+  if (packed) {
+    const int slot = atomicAdd(&a.ctr->n_band16[nxt][c], 1);
+    a.lists16[((int64_t)(nxt * kBand16Classes + c)) * a.list_cap + slot] = nb;
+  } else {
+    const int slot = atomicAdd(&a.ctr->n_band[nxt][c], 1);
+    a.lists[((int64_t)(nxt * kBandClasses + c)) * a.list_cap + slot] = nb;
+  }
+}
 
 // ---- learned band ----
 constexpr int kMlpInputs = 32;

@@ -299,9 +299,12 @@ __global__ void __launch_bounds__(256) route_scatter_kernel(RouteParams c, const
 __global__ void __launch_bounds__(256) band_classify_kernel(RouteParams c, const int64_t *offs_a,
                                                             const int64_t *offs_b, const int32_t *w0,
                                                             int32_t raw, int32_t exact, BandItem *lists,
+                                                            BandItem *lists16, int32_t pack16,
                                                             int64_t list_cap, PairDesc *fallback,
                                                             Counters *ctr, int32_t *scores) {
-  constexpr int R = kBandClasses + 1;  // classes, then the fallback list
+  // routes: 32-bit classes, packed classes, then the fallback list
+  constexpr int R = kBandClasses + kBand16Classes + 1;
+  constexpr int kFall = kBandClasses + kBand16Classes;
   __shared__ BlockLists<R> bl;
   const int64_t chunk = (c.n_pairs + gridDim.x - 1) / gridDim.x;
   const int64_t lo = (int64_t)blockIdx.x * chunk;
@@ -327,17 +330,18 @@ __global__ void __launch_bounds__(256) band_classify_kernel(RouteParams c, const
     w = w < 0 ? 0 : (w > (1 << 20) ? (1 << 20) : w);
     bi.w = w;
     bi.pad_ = 0;
-    const int B = bi.d.n - bi.d.m + 2 * w + 1;
-    const int kc = band_class_for(B);
     if (raw) {
+      const int kc = band_class_for(bi.d.n - bi.d.m + 2 * w + 1);
       if (kc < 0) {
         if (first) atomicOr(&ctr->status, kStatusArg);
         return -1;
       }
       return kc;
     }
-    if (kc < 0 || 2 * band_class_width(kc) >= bi.d.n) return kBandClasses;
-    return kc;
+    bool packed = false;
+    const int rc = band_route(bi.d.m, bi.d.n, w, pack16 != 0, c.smax_pos, c.alpha, c.beta, &packed);
+    if (rc < 0) return kFall;
+    return packed ? kBandClasses + rc : rc;
   };
   for (int64_t p = lo + threadIdx.x; p < hi; p += blockDim.x) {
     BandItem bi;
@@ -349,8 +353,10 @@ __global__ void __launch_bounds__(256) band_classify_kernel(RouteParams c, const
   if (threadIdx.x == 0) {
     for (int kc = 0; kc < kBandClasses; ++kc)
       bl.base[kc] = bl.cnt[kc] ? atomicAdd(&ctr->n_band[0][kc], bl.cnt[kc]) : 0;
-    bl.base[kBandClasses] =
-        bl.cnt[kBandClasses] ? atomicAdd(&ctr->n_fallback, bl.cnt[kBandClasses]) : 0;
+    for (int pc = 0; pc < kBand16Classes; ++pc)
+      bl.base[kBandClasses + pc] =
+          bl.cnt[kBandClasses + pc] ? atomicAdd(&ctr->n_band16[0][pc], bl.cnt[kBandClasses + pc]) : 0;
+    bl.base[kFall] = bl.cnt[kFall] ? atomicAdd(&ctr->n_fallback, bl.cnt[kFall]) : 0;
     if (bl.cells) atomicAdd(&ctr->cells, bl.cells);
     for (int r = 0; r < R; ++r) bl.cnt[r] = 0;
   }
@@ -360,7 +366,8 @@ __global__ void __launch_bounds__(256) band_classify_kernel(RouteParams c, const
     const int r = classify(p, false, bi);
     if (r < 0) continue;
     const int slot = bl.base[r] + atomicAdd(&bl.cnt[r], 1);
-    if (r == kBandClasses) fallback[slot] = bi.d;
+    if (r == kFall) fallback[slot] = bi.d;
+    else if (r >= kBandClasses) lists16[(int64_t)(r - kBandClasses) * list_cap + slot] = bi;
     else lists[(int64_t)r * list_cap + slot] = bi;
   }
 }
@@ -440,6 +447,8 @@ struct Workspace {
   int64_t flags_cap = 0;
   BandItem *band_lists = nullptr;  // [2][kBandClasses][cap]
   int64_t band_cap = 0;
+  BandItem *band16_lists = nullptr;  // [2][kBand16Classes][cap]
+  int64_t band16_cap = 0;
   PairDesc *fallback = nullptr;
   int64_t fallback_cap = 0;
   uint32_t *qwords = nullptr;      // [2][32]
@@ -454,6 +463,7 @@ struct Workspace {
 };
 
 bool g_timing = false;
+bool g_band16 = true;  // packed 16-bit banded kernel for eligible global pairs
 // Full-DP variant per (mode, length bin); -1 = automatic routing.
 int8_t g_variants[3][kLenBins] = {{-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1},
                                   {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1},
@@ -484,7 +494,7 @@ int init_workspace(Workspace &w, int dev) {
 
 void free_workspace(Workspace &w) {
   void *bufs[] = {w.items, w.items16, w.rerun, w.items_long, w.bnd_long, w.flags, w.band_lists,
-                  w.fallback, w.qwords, w.ctr, w.subst, w.bnd, w.tune_scores};
+                  w.band16_lists, w.fallback, w.qwords, w.ctr, w.subst, w.bnd, w.tune_scores};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   if (w.host_ctr) (void)hipHostFree(w.host_ctr);
@@ -842,6 +852,11 @@ int asmi::band_call(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t 
   if ((rc = grow((void **)&w->band_lists, &w->band_cap, 2 * kBandClasses * n_pairs, sizeof(BandItem))))
     return rc;
   const int64_t list_cap = w->band_cap / (2 * kBandClasses);
+  // the packed kernel serves range-proven global pairs outside the raw modes
+  const int pack16 = (!raw && mode == kGlobal && g_band16) ? 1 : 0;
+  if (pack16 && (rc = grow((void **)&w->band16_lists, &w->band16_cap, 2 * kBand16Classes * list_cap,
+                           sizeof(BandItem))))
+    return rc;
   if ((rc = grow((void **)&w->fallback, &w->fallback_cap, n_pairs, sizeof(PairDesc)))) return rc;
   uint32_t host_words[64];
   AS_HIP(hipMemcpyAsync(w->subst, scoring->subst, (size_t)cs.asz * cs.asz, hipMemcpyHostToDevice, stream));
@@ -852,8 +867,8 @@ int asmi::band_call(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t 
   if (timing) AS_HIP(hipEventRecord(w->ev[0], stream));
   const RouteParams rp = route_params(cs, n_pairs);
   hipLaunchKernelGGL(band_classify_kernel, dim3(classify_blocks(n_pairs)), dim3(256), 0, stream, rp,
-                     offs_a, offs_b, band_w, raw, exact, w->band_lists, list_cap, w->fallback, w->ctr,
-                     scores_out);
+                     offs_a, offs_b, band_w, raw, exact, w->band_lists, pack16 ? w->band16_lists : nullptr,
+                     pack16, list_cap, w->fallback, w->ctr, scores_out);
   AS_HIP(hipGetLastError());
   if (timing) AS_HIP(hipEventRecord(w->ev[1], stream));
   Counters c;
@@ -866,6 +881,9 @@ int asmi::band_call(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t 
   ba.seqs_a = seqs_a;
   ba.seqs_b = seqs_b;
   ba.lists = w->band_lists;
+  ba.lists16 = pack16 ? w->band16_lists : nullptr;
+  ba.pack16 = pack16;
+  ba.smax_pos = cs.smax > 0 ? cs.smax : 0;
   ba.list_cap = list_cap;
   ba.ctr = w->ctr;
   ba.qwords = w->qwords;
@@ -887,9 +905,19 @@ int asmi::band_call(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t 
     const int cur = r & 1;
     int any = 0;
     for (int kc = 0; kc < kBandClasses; ++kc) any += c.n_band[cur][kc];
+    for (int pc = 0; pc < kBand16Classes; ++pc) any += c.n_band16[cur][pc];
     if (!any) break;
     ba.round = r;
     if (timing) AS_HIP(hipEventRecord(w->ev[10], stream));
+    for (int pc = 0; pc < kBand16Classes; ++pc) {
+      const int cnt = c.n_band16[cur][pc];
+      if (!cnt) continue;
+      int64_t grid = (int64_t)band_dp_i16_blocks_per_cu(pc) * w->num_cu;
+      const int ppw = band_dp_i16_pairs_per_wave(pc);
+      const int64_t need = ((int64_t)cnt + ppw - 1) / ppw;
+      if (grid > need) grid = need;
+      AS_HIP(launch_band_dp_i16(pc, ba, (int)grid, stream));
+    }
     for (int kc = 0; kc < kBandClasses; ++kc) {
       const int cnt = c.n_band[cur][kc];
       if (!cnt) continue;
@@ -903,6 +931,8 @@ int asmi::band_call(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t 
     // this round's lists are consumed: clear their counters and work pointers
     AS_HIP(hipMemsetAsync(&w->ctr->n_band[cur][0], 0, sizeof(int32_t) * kBandClasses, stream));
     AS_HIP(hipMemsetAsync(&w->ctr->next_band[0], 0, sizeof(int32_t) * kBandClasses, stream));
+    AS_HIP(hipMemsetAsync(&w->ctr->n_band16[cur][0], 0, sizeof(int32_t) * kBand16Classes, stream));
+    AS_HIP(hipMemsetAsync(&w->ctr->next_band16[0], 0, sizeof(int32_t) * kBand16Classes, stream));
     if ((rc = read_counters(w, stream, &c))) return rc;
     if (timing) band_ms += elapsed(w->ev[10], w->ev[11]);
     if ((rc = status_to_code(c.status))) return rc;
@@ -1282,6 +1312,13 @@ extern "C" int as_release_workspace(void) {
     (void)hipSetDevice(cur);
   }
   return AS_OK;
+}
+
+extern "C" int as_set_band_packing(int32_t on) {
+  std::lock_guard<std::mutex> guard(g_lock);
+  const int prev = g_band16 ? 1 : 0;
+  g_band16 = on != 0;
+  return prev;
 }
 
 extern "C" int as_set_i16_limit(int32_t limit) {

@@ -119,3 +119,30 @@ def test_band_api_errors(gpu):
     with pytest.raises(AlignError) as e:                 # 20-letter alphabet
         gpu.align_batch_band(*_dev(pb), prot, 11, 1, 0, _w(torch, np.zeros(4)))
     assert e.value.code == -4
+
+
+def test_packed_band_matches_32bit_and_oracle(gpu, oracle_mod):
+    """Global certified banding with the packed 16-bit kernel on (default)
+    and off: both equal the oracle's full DP for every pair.  Lengths run
+    past the packed range limit (pairs of ~4900 and ~6000 residues go to the
+    32-bit kernel, or switch kernels between rounds), initial half-widths
+    range from 0 to wide, so pairs are accepted, doubled and sent to the
+    full DP."""
+    import torch
+    rng = np.random.default_rng(760)
+    b = synth.config4_like(900, 761, min_len=150, max_len=2500, max_div=0.15)
+    big = synth.config4_like(12, 762, min_len=4800, max_len=6200, max_div=0.06)
+    pairs = [b.pair(p) for p in range(b.n_pairs)] + [big.pair(p) for p in range(big.n_pairs)]
+    bb = synth.from_pairs("packed band", pairs, DNA, 5, 2, 0)
+    want = oracle_mod.align_batch(bb.seqs_a, bb.offs_a, bb.seqs_b, bb.offs_b, DNA, 5, 2, 0)
+    dev = gpu.to_device(bb)
+    for w0, rounds in ((0, 6), (20, 6), (120, 6), (3, 2)):
+        w = _w(torch, rng.integers(max(0, w0 - 3), w0 + 4, bb.n_pairs))
+        res = {}
+        for on in (True, False):
+            gpu.set_band_packing(on)
+            sc, st = gpu.align_batch_band(*dev, DNA, 5, 2, 0, w, max_rounds=rounds)
+            res[on] = sc.cpu().numpy()
+            _say(f"packed={on} w0~{w0} rounds={rounds}: {st}")
+            assert np.array_equal(res[on], want), (on, w0, np.nonzero(res[on] != want)[0][:5])
+    gpu.set_band_packing(True)
