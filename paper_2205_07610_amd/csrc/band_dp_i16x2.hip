@@ -24,6 +24,8 @@
 //  * Range: a pair is queued here only when an a priori bound keeps every
 //    shifted cell (band columns up to n + W) inside int16; the others take
 //    the 32-bit banded kernel.
+#include <type_traits>
+
 #include "internal.h"
 
 namespace asmi {
@@ -143,6 +145,14 @@ __global__ void __launch_bounds__(kWave) band_dp_i16_kernel(BandArgs a, int pc) 
       return j < 0 ? kNeg : (j == 0 ? beta - alpha : 2 * beta - 2 * alpha);
     };
     auto init_h = [&](int x) -> s2 { return pk(init1(lo0, x), init1(lo1, x)); };
+    // the same, recomputed where it is used: an empty asm makes the offsets
+    // opaque, so the compiler does not keep K row-0 values live in registers
+    // across the fill chunks
+    auto init_h_here = [&](int x) -> s2 {
+      int l0 = lo0, l1 = lo1;
+      __asm__ volatile("" : "+v"(l0), "+v"(l1));
+      return pk(init1(l0, x), init1(l1, x));
+    };
     s2 Ha[K], Ee[K];
     uint32_t P[K];  // selector words; register x's is P[(x + u) % K] at step u
 #pragma unroll
@@ -164,7 +174,12 @@ __global__ void __launch_bounds__(kWave) band_dp_i16_kernel(BandArgs a, int pc) 
       return make_sel(code(has0, cols0, n0, jo + lo0), code(has1, cols1, n1, jo + lo1));
     };
     uint32_t cfeed = cfeed_at(0);
-    for (int it0 = 0; it0 < its_max; it0 += kGroup) {
+    // One chunk of 16 steps.  FILL: the pipeline is still filling (some
+    // lane's row is <= 0 and is reset to row 0 afterwards); only the first
+    // G / 16 chunks need it, so the main loop carries no reset logic and no
+    // row-0 values stay live in registers.
+    auto chunk = [&](int it0, auto fill_tag) {
+      constexpr bool FILL = decltype(fill_tag)::value;
       const uint32_t qnext0 = qword(rows0, m0, tr0, it0 + kGroup + t);
       const uint32_t qnext1 = qword(rows1, m1, tr1, it0 + kGroup + t);
       const uint32_t cnext = cfeed_at(it0 + kGroup);
@@ -179,39 +194,39 @@ __global__ void __launch_bounds__(kWave) band_dp_i16_kernel(BandArgs a, int pc) 
         qrow0 = (uint32_t)shr1<G>((int)qfeed0, (int)qrow0);
         qrow1 = (uint32_t)shr1<G>((int)qfeed1, (int)qrow1);
         const s2 fl = as_s2(shr1<G>(negi, fout));
-        s2 tt[K], ee[K];
-#pragma unroll
-        for (int x = 0; x < K; ++x) {
-          const s2 sc = as_s2((int)__builtin_amdgcn_perm(qrow1, qrow0, P[(x + u + 1) % K]));
-          tt[x] = add_sat(Ha[x], sc);
-          if (x + 1 < K) ee[x] = vmax(Ee[x + 1], Ha[x + 1]);
-        }
+        // In the sheared layout a cell's diagonal predecessor is its own
+        // register one row earlier and "up" is the next register, so the
+        // update runs in place in ascending order (register x+1 is still the
+        // previous row's when register x reads it).  Register 0 goes first and
+        // its (E, H') moves to lane t-1 before the others.
         s2 f = fl;
         {
-          const s2 hv = vmax(vmax(tt[0], K > 1 ? ee[0] : neg2), f);
+          const s2 sc = as_s2((int)__builtin_amdgcn_perm(qrow1, qrow0, P[(u + 1) % K]));
+          const s2 e = K > 1 ? vmax(Ee[1], Ha[1]) : neg2;
+          const s2 hv = vmax(vmax(add_sat(Ha[0], sc), e), f);
           Ha[0] = sub_sat(hv, amb2);
-          Ee[0] = K > 1 ? ee[0] : neg2;
+          Ee[0] = e;
           f = vmax(f, Ha[0]);
         }
-        const bool filling = __builtin_amdgcn_ballot_w64(row <= 0) != 0;
-        if (filling && row <= 0) {
-          Ha[0] = init_h(0);
+        if (FILL && row <= 0) {
+          Ha[0] = init_h_here(0);
           Ee[0] = neg2;
         }
         const s2 eR = as_s2(shl1<G>(negi, as_i(vmax(Ee[0], Ha[0]))));
 #pragma unroll
         for (int x = 1; x < K; ++x) {
-          const s2 e = (x + 1 < K) ? ee[x] : eR;
-          const s2 hv = vmax(vmax(tt[x], e), f);
+          const s2 sc = as_s2((int)__builtin_amdgcn_perm(qrow1, qrow0, P[(x + u + 1) % K]));
+          const s2 e = (x + 1 < K) ? vmax(Ee[x + 1], Ha[x + 1]) : eR;
+          const s2 hv = vmax(vmax(add_sat(Ha[x], sc), e), f);
           Ha[x] = sub_sat(hv, amb2);
           Ee[x] = e;
           f = vmax(f, Ha[x]);
         }
         fout = as_i(f);
-        if (filling && row <= 0) {
+        if (FILL && row <= 0) {
 #pragma unroll
           for (int x = 1; x < K; ++x) {
-            Ha[x] = init_h(x);
+            Ha[x] = init_h_here(x);
             Ee[x] = neg2;
           }
           fout = negi;
@@ -236,7 +251,10 @@ __global__ void __launch_bounds__(kWave) band_dp_i16_kernel(BandArgs a, int pc) 
       qfeed0 = qnext0;
       qfeed1 = qnext1;
       cfeed = cnext;
-    }
+    };
+    int it0 = 0;
+    for (; it0 < its_max && it0 < G; it0 += kGroup) chunk(it0, std::true_type{});
+    for (; it0 < its_max; it0 += kGroup) chunk(it0, std::false_type{});
 
     const int score0 = group_max<G>(res0), score1 = group_max<G>(res1);
     if (bad) atomicOr(&a.ctr->status, kStatusBadResidue);
