@@ -47,7 +47,9 @@ KERNEL_SOURCES = {
     "full16": "paper_2205_07610_amd/csrc/full_dp_i16x2.hip",
     "rerun32": "paper_2205_07610_amd/csrc/full_dp_i32.hip",
     "long": "paper_2205_07610_amd/csrc/long_dp_i32.hip",
-    "band": "paper_2205_07610_amd/csrc/band_dp_i32.hip",
+    "band32": "paper_2205_07610_amd/csrc/band_dp_i32.hip",
+    "band16": "paper_2205_07610_amd/csrc/band_dp_i16x2.hip",
+    "features": "paper_2205_07610_amd/csrc/features.hip",
 }
 # band network training of the learned workload (library kernels, untimed)
 TRAIN = {"pairs": 200_000, "seed": 2004, "steps": 4000, "batch": 1024, "lr": 2e-3, "tau": 0.7,
@@ -96,8 +98,10 @@ WORKLOAD_NAME = {"name": None}
 
 
 def traffic_for(kernel: str):
-    """HBM bytes per launch from the committed rocprofv3 PMC summary, if it
-    was taken on the current kernel source and on this workload; else None."""
+    """HBM bytes of the kernel's roofline unit (one launch, or all launches of
+    one step for the banded and feature kernels) from the committed rocprofv3
+    PMC summary, if it was taken on the current kernel source and on this
+    workload; else None."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_traffic.json")
     if not os.path.exists(path):
         return None
@@ -107,7 +111,7 @@ def traffic_for(kernel: str):
         return None
     if rec.get("workload_name") != WORKLOAD_NAME["name"]:
         return None
-    return rec.get("bytes_per_launch")
+    return rec.get("bytes_per_unit")
 
 
 def cpu_baseline(batch, seconds: float, gpu_scores):
@@ -341,15 +345,28 @@ def main():
         gpu_scores = out_l.cpu().numpy()
         mism_full = int(np.count_nonzero(gpu_scores != full_scores))
         log(f"learned band: {ms_per_step:.3f} ms/step, mismatches vs full DP {mism_full}")
-        dom = max(["band_ms", "full32_ms", "long_ms"], key=lambda k: avg[k])
-        if dom == "band_ms":
-            roof = roofline("band", avg[dom], stats["band_cells"] * OPS_PER_CELL[batch.mode], False)
-            roof["cells"] = stats["band_cells"]
-            roof["ops_per_cell"] = OPS_PER_CELL[batch.mode]
-            roof["cells_note"] = "cells the banded kernel computed (m x band width, every round)"
+        # the banded phase splits into the packed 16-bit and the 32-bit kernel,
+        # each with its own cells, time and peak
+        opc = OPS_PER_CELL[batch.mode]
+        avg["band16_ms"] = sum(p["band16_ms"] for p in phases) / len(phases)
+        avg["band32_ms"] = avg["band_ms"] - avg["band16_ms"]
+        band_roof = {}
+        for name, cells_k, packed in (("band16", stats["band16_cells"], True),
+                                      ("band32", stats["band_cells"] - stats["band16_cells"], False)):
+            if avg[name + "_ms"] > 0 and cells_k > 0:
+                r = roofline(name, avg[name + "_ms"], cells_k * opc, packed)
+                r["cells"] = cells_k
+                r["ops_per_cell"] = opc
+                r["cells_note"] = "cells the kernel computed (m x band width, every round)"
+                r["unit_of_work"] = "all launches of one learned step (every class and round)"
+                band_roof[name] = r
+        cands = [k for k in ("band16_ms", "band32_ms") if k[:-3] in band_roof] + ["full32_ms", "long_ms"]
+        dom = max(cands, key=lambda k: avg[k])
+        if dom in ("band16_ms", "band32_ms"):
+            roof = band_roof[dom[:-3]]
         else:
-            roof = phase_roofline(phases, dom, OPS_PER_CELL[batch.mode])
-        dtype = "i32"
+            roof = phase_roofline(phases, dom, opc)
+        dtype = "i16x2" if dom == "band16_ms" else "i32"
     else:
         ms_per_step, avg, gpu_scores = full_ms, full_avg, full_scores
         if graph_info is not None:
@@ -397,7 +414,8 @@ def main():
         result["speedup_vs_full_dp"] = round(full_ms / ms_per_step, 3)
         result["mismatches_vs_full_dp"] = mism_full
         result["band_stats"] = {k: stats[k] for k in ("rounds", "accepted", "fallback", "band_cells",
-                                                      "fallback_cells", "dp_cells")}
+                                                      "band16_cells", "fallback_cells", "dp_cells")}
+        result["roofline_band_kernels"] = band_roof
         result["band_stats"]["dp_cells_frac"] = round(stats["dp_cells"] / cells, 4)
         result["training"] = train_info
     if not args.no_cpu_baseline:

@@ -109,6 +109,8 @@ typedef struct {
     float band_ms;      /* banded rounds (as_align_batch_band) */
     float features_ms;  /* k-mer features (as_align_batch_learned) */
     float mlp_ms;       /* band network inference (as_align_batch_learned) */
+    float band16_ms;    /* part of band_ms spent in the packed 16-bit banded kernel */
+    float reserved_ms;
     int64_t pairs_full32;
     int64_t pairs_full16;
     int64_t pairs_rerun32;
@@ -145,6 +147,7 @@ typedef struct {
     int64_t band_cells;    /* DP cells computed by the banded kernel */
     int64_t cells;         /* sum of m*n over the batch */
     int64_t fallback_cells; /* sum of m*n over the pairs aligned with the full DP */
+    int64_t band16_cells;  /* part of band_cells computed with packed 16-bit cells */
 } as_band_stats;
 
 int as_align_batch_band(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t *seqs_b,

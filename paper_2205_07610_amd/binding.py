@@ -37,6 +37,7 @@ class Timing(ctypes.Structure):
                 ("full16_ms", ctypes.c_float), ("rerun32_ms", ctypes.c_float),
                 ("long_ms", ctypes.c_float), ("band_ms", ctypes.c_float),
                 ("features_ms", ctypes.c_float), ("mlp_ms", ctypes.c_float),
+                ("band16_ms", ctypes.c_float), ("reserved_ms", ctypes.c_float),
                 ("pairs_full32", ctypes.c_int64), ("pairs_full16", ctypes.c_int64),
                 ("pairs_rerun32", ctypes.c_int64), ("pairs_long", ctypes.c_int64),
                 ("pairs_fallback", ctypes.c_int64), ("cells", ctypes.c_int64),
@@ -51,12 +52,12 @@ class BandStats(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("accepted", ctypes.c_int64 * 8), ("fallback", ctypes.c_int64),
                 ("band_cells", ctypes.c_int64), ("cells", ctypes.c_int64),
-                ("fallback_cells", ctypes.c_int64)]
+                ("fallback_cells", ctypes.c_int64), ("band16_cells", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {"rounds": self.rounds, "accepted": list(self.accepted)[:max(self.rounds, 1)],
                 "fallback": self.fallback, "band_cells": self.band_cells, "cells": self.cells,
-                "fallback_cells": self.fallback_cells,
+                "fallback_cells": self.fallback_cells, "band16_cells": self.band16_cells,
                 "dp_cells": self.band_cells + self.fallback_cells}
 
 

@@ -96,7 +96,7 @@ __global__ void __launch_bounds__(kWave) band_dp_i16_kernel(BandArgs a, int pc) 
   const int asz = a.asz;
   const int cur = a.round & 1;
   const int n_list = a.ctr->n_band16[cur][pc];
-  const BandItem *list = a.lists16 + ((int64_t)(cur * kBand16Classes + pc)) * a.list_cap;
+  const BandItem *list = a.sorted + a.sorted_base[kBandClasses + pc];
   const s2 amb2 = pk(amb, amb);
   const s2 neg2 = pk(kNeg, kNeg);
   const int negi = as_i(neg2);
@@ -275,6 +275,7 @@ __global__ void __launch_bounds__(kWave) band_dp_i16_kernel(BandArgs a, int pc) 
     int64_t ub = 0;
     const bool leave = band_leave_bound(m, n, lo, hi, a.sigma_max, alpha, beta, kGlobal, &ub);
     atomicAdd(&a.ctr->band_cells, (unsigned long long)((long long)m * W));
+    atomicAdd(&a.ctr->band16_cells, (unsigned long long)((long long)m * W));
     if (!leave || (int64_t)score >= ub) {
       a.scores[d.pair] = score;
       atomicAdd(&a.ctr->band_accepted[a.round < kMaxBandRounds ? a.round : kMaxBandRounds - 1], 1);

@@ -97,7 +97,7 @@ __global__ void __launch_bounds__(kWave) band_dp_i32_kernel(BandArgs a, int kc) 
   const int asz = a.asz;
   const int cur = a.round & 1;
   const int n_list = a.ctr->n_band[cur][kc];
-  const BandItem *list = a.lists + ((int64_t)(cur * kBandClasses + kc)) * a.list_cap;
+  const BandItem *list = a.sorted + a.sorted_base[kc];
   // score words: byte c of qword[r] = sigma(r, c) + alpha + beta (shifted frame)
   // padding byte (selector 4..7): alpha - beta (global) / alpha + beta (semi)
   const uint32_t padword = (uint32_t)((MODE == kGlobal ? alpha - beta : alpha + beta) & 0xFF) * 0x01010101u;

@@ -89,7 +89,8 @@ struct Counters {
   int32_t n_band16[2][5];   // packed 16-bit banded lists per round parity and class
   int32_t next_band16[5];
   int32_t band_accepted[8];  // pairs accepted in round r
-  unsigned long long band_cells;  // cells computed by the banded kernel
+  unsigned long long band_cells;  // cells computed by the banded kernels (both widths)
+  unsigned long long band16_cells;  // of these, cells computed by the packed 16-bit kernel
   unsigned long long fallback_cells;  // sum of m*n over the fallback pairs
   unsigned long long route_cells[4];  // sum of m*n per full-DP list (16-bit, 32-bit, wavefront)
   // length-binned lists: counts, offsets and scatter cursors per (list, bin)
@@ -175,10 +176,22 @@ struct BandItem {
   int32_t pad_;
 };
 
+// Packed 16-bit banded classes (global mode): 64 << pc diagonals.
+constexpr int kBand16Classes = 5;
+// Before each round every band list is sorted by row count, longest first,
+// into one buffer (list l at sorted_base[l]): the pairs of one wave, and the
+// two halves of a packed group, then run about the same number of wavefront
+// steps.  Keys are 32-row buckets, the last one open.
+constexpr int kBandLists = kBandClasses + kBand16Classes;  // 32-bit classes, then packed
+constexpr int kSortBuckets = 512;
+__host__ __device__ inline int sort_bucket(int m) { return (m >> 5) < kSortBuckets - 1 ? (m >> 5) : kSortBuckets - 1; }
+
 struct BandArgs {
+  const BandItem *sorted;   // this round's lists, sorted (the kernels read these)
+  int64_t sorted_base[kBandLists];
   const uint8_t *seqs_a;
   const uint8_t *seqs_b;
-  BandItem *lists;          // [2 parities][kBandClasses][list_cap]
+  BandItem *lists;          // [2 parities][kBandClasses][list_cap] (requeued pairs go here)
   BandItem *lists16;        // [2 parities][kBand16Classes][list_cap] (packed 16-bit kernel)
   int64_t list_cap;
   int32_t pack16;           // 1: range-proven global pairs may use the packed kernel
@@ -202,8 +215,6 @@ hipError_t launch_band_dp_i16(int pc, const BandArgs &args, int grid, hipStream_
 int band_dp_i16_blocks_per_cu(int pc);
 int band_dp_i16_pairs_per_wave(int pc);
 
-// Packed 16-bit banded classes (global mode): 64 << pc diagonals.
-constexpr int kBand16Classes = 5;
 __host__ __device__ inline int band16_class_width(int pc) { return 64 << pc; }
 __host__ __device__ inline int band16_class_for(int B) {
   for (int pc = 0; pc < kBand16Classes; ++pc)

@@ -372,6 +372,93 @@ __global__ void __launch_bounds__(256) band_classify_kernel(RouteParams c, const
   }
 }
 
+// ---- sorting the band lists by row count (before each round) ----
+// The lists of one round, as one virtual sequence: list l holds n[l] items
+// at src[l] and goes to out[base[l] .. base[l] + n[l]).
+struct SortLists {
+  const BandItem *src[kBandLists];
+  int32_t n[kBandLists];
+  int64_t base[kBandLists];
+  int64_t total;
+};
+
+__device__ inline int sort_list_of(const SortLists &s, int64_t g) {
+  int l = 0;
+  while (l < kBandLists - 1 && g >= s.base[l] + s.n[l]) ++l;
+  return l;
+}
+
+// Histogram of (list, bucket) over the round's items: per block in LDS, then
+// one global atomic per non-zero bin.
+__global__ void __launch_bounds__(256) band_sort_count_kernel(SortLists s, int32_t *hist) {
+  __shared__ int32_t h[kBandLists * kSortBuckets];
+  for (int i = threadIdx.x; i < kBandLists * kSortBuckets; i += blockDim.x) h[i] = 0;
+  __syncthreads();
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < s.total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int l = sort_list_of(s, g);
+    const int m = s.src[l][g - s.base[l]].d.m;
+    atomicAdd(&h[l * kSortBuckets + sort_bucket(m)], 1);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kBandLists * kSortBuckets; i += blockDim.x)
+    if (h[i]) atomicAdd(&hist[i], h[i]);
+}
+
+// One wave per list turns its histogram into the first slot of each bucket,
+// largest bucket first (lane j owns 8 consecutive buckets of that order).
+__global__ void __launch_bounds__(1024) band_sort_scan_kernel(SortLists s, int32_t *hist) {
+  const int l = threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  if (l >= kBandLists) return;
+  constexpr int kPer = kSortBuckets / kWave;
+  int32_t *h = hist + l * kSortBuckets;
+  int v[kPer];
+  int sum = 0;
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    v[q] = h[kSortBuckets - 1 - (lane * kPer + q)];
+    sum += v[q];
+  }
+  int incl = sum;  // inclusive prefix of the lanes' sums
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int y = __shfl_up(incl, d);
+    if (lane >= d) incl += y;
+  }
+  int run = (int)s.base[l] + incl - sum;
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    h[kSortBuckets - 1 - (lane * kPer + q)] = run;
+    run += v[q];
+  }
+}
+
+// Each block takes a contiguous slice of the round's items, reserves its
+// part of every (list, bucket) with one global atomic, and places the items.
+__global__ void __launch_bounds__(256) band_sort_scatter_kernel(SortLists s, int32_t *cursor,
+                                                                BandItem *out) {
+  __shared__ int32_t h[kBandLists * kSortBuckets];
+  const int64_t chunk = (s.total + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = (int64_t)blockIdx.x * chunk;
+  const int64_t hi = lo + chunk < s.total ? lo + chunk : s.total;
+  for (int i = threadIdx.x; i < kBandLists * kSortBuckets; i += blockDim.x) h[i] = 0;
+  __syncthreads();
+  for (int64_t g = lo + threadIdx.x; g < hi; g += blockDim.x) {
+    const int l = sort_list_of(s, g);
+    atomicAdd(&h[l * kSortBuckets + sort_bucket(s.src[l][g - s.base[l]].d.m)], 1);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kBandLists * kSortBuckets; i += blockDim.x)
+    if (h[i]) h[i] = atomicAdd(&cursor[i], h[i]);
+  __syncthreads();
+  for (int64_t g = lo + threadIdx.x; g < hi; g += blockDim.x) {
+    const int l = sort_list_of(s, g);
+    const BandItem bi = s.src[l][g - s.base[l]];
+    out[atomicAdd(&h[l * kSortBuckets + sort_bucket(bi.d.m)], 1)] = bi;
+  }
+}
+
 // One block: prefix sums over the wavefront list (first ticket and boundary
 // offset of every long pair), and the score seed that the stripes' atomic
 // maxima start from (0 = the empty alignment / boundary cells).
@@ -449,6 +536,9 @@ struct Workspace {
   int64_t band_cap = 0;
   BandItem *band16_lists = nullptr;  // [2][kBand16Classes][cap]
   int64_t band16_cap = 0;
+  BandItem *band_sorted = nullptr;   // one round's lists, sorted by rows
+  int64_t band_sorted_cap = 0;
+  int32_t *sort_hist = nullptr;      // [kBandLists][kSortBuckets]
   PairDesc *fallback = nullptr;
   int64_t fallback_cap = 0;
   uint32_t *qwords = nullptr;      // [2][32]
@@ -487,6 +577,7 @@ int init_workspace(Workspace &w, int dev) {
   AS_HIP(hipHostMalloc(&w.host_ctr, sizeof(Counters), hipHostMallocDefault));
   AS_HIP(hipMalloc(&w.subst, 32 * 32));
   AS_HIP(hipMalloc(&w.qwords, 2 * 32 * sizeof(uint32_t)));
+  AS_HIP(hipMalloc(&w.sort_hist, kBandLists * kSortBuckets * sizeof(int32_t)));
   for (auto &e : w.ev) AS_HIP(hipEventCreate(&e));
   w.device = dev;
   return AS_OK;
@@ -494,7 +585,8 @@ int init_workspace(Workspace &w, int dev) {
 
 void free_workspace(Workspace &w) {
   void *bufs[] = {w.items, w.items16, w.rerun, w.items_long, w.bnd_long, w.flags, w.band_lists,
-                  w.band16_lists, w.fallback, w.qwords, w.ctr, w.subst, w.bnd, w.tune_scores};
+                  w.band16_lists, w.band_sorted, w.sort_hist, w.fallback, w.qwords, w.ctr, w.subst, w.bnd,
+                  w.tune_scores};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   if (w.host_ctr) (void)hipHostFree(w.host_ctr);
@@ -858,6 +950,7 @@ int asmi::band_call(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t 
                            sizeof(BandItem))))
     return rc;
   if ((rc = grow((void **)&w->fallback, &w->fallback_cap, n_pairs, sizeof(PairDesc)))) return rc;
+  if ((rc = grow((void **)&w->band_sorted, &w->band_sorted_cap, n_pairs, sizeof(BandItem)))) return rc;
   uint32_t host_words[64];
   AS_HIP(hipMemcpyAsync(w->subst, scoring->subst, (size_t)cs.asz * cs.asz, hipMemcpyHostToDevice, stream));
   if ((rc = upload_qwords(w, scoring, cs, stream, host_words))) return rc;
@@ -899,15 +992,38 @@ int asmi::band_call(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t 
   ba.hi_out = hi_out;
   ba.accept_out = accept_out;
   ba.fallback = w->fallback;
+  ba.sorted = w->band_sorted;
   int rounds = 0;
-  float band_ms = 0.f;
+  float band_ms = 0.f, band16_ms = 0.f, sort_ms = 0.f;
   for (int r = 0; r < ba.max_rounds; ++r) {
     const int cur = r & 1;
-    int any = 0;
-    for (int kc = 0; kc < kBandClasses; ++kc) any += c.n_band[cur][kc];
-    for (int pc = 0; pc < kBand16Classes; ++pc) any += c.n_band16[cur][pc];
-    if (!any) break;
+    // this round's lists, sorted by rows into one buffer
+    SortLists sl;
+    int64_t total = 0;
+    for (int l = 0; l < kBandLists; ++l) {
+      const bool p16 = l >= kBandClasses;
+      const int k = p16 ? l - kBandClasses : l;
+      sl.n[l] = p16 ? c.n_band16[cur][k] : c.n_band[cur][k];
+      sl.src[l] = p16 ? (pack16 ? w->band16_lists + (int64_t)(cur * kBand16Classes + k) * list_cap : nullptr)
+                      : w->band_lists + (int64_t)(cur * kBandClasses + k) * list_cap;
+      sl.base[l] = total;
+      ba.sorted_base[l] = total;
+      total += sl.n[l];
+    }
+    sl.total = total;
+    if (!total) break;
+    // (every pair is in at most one list per round, so total <= n_pairs)
+    if ((rc = grow((void **)&w->band_sorted, &w->band_sorted_cap, total, sizeof(BandItem)))) return rc;
+    ba.sorted = w->band_sorted;
     ba.round = r;
+    if (timing) AS_HIP(hipEventRecord(w->ev[13], stream));
+    AS_HIP(hipMemsetAsync(w->sort_hist, 0, kBandLists * kSortBuckets * sizeof(int32_t), stream));
+    const int sort_blocks = (int)((total + 4095) / 4096);
+    hipLaunchKernelGGL(band_sort_count_kernel, dim3(sort_blocks), dim3(256), 0, stream, sl, w->sort_hist);
+    hipLaunchKernelGGL(band_sort_scan_kernel, dim3(1), dim3(kBandLists * kWave), 0, stream, sl, w->sort_hist);
+    hipLaunchKernelGGL(band_sort_scatter_kernel, dim3(sort_blocks), dim3(256), 0, stream, sl, w->sort_hist,
+                       w->band_sorted);
+    AS_HIP(hipGetLastError());
     if (timing) AS_HIP(hipEventRecord(w->ev[10], stream));
     for (int pc = 0; pc < kBand16Classes; ++pc) {
       const int cnt = c.n_band16[cur][pc];
@@ -918,6 +1034,7 @@ int asmi::band_call(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t 
       if (grid > need) grid = need;
       AS_HIP(launch_band_dp_i16(pc, ba, (int)grid, stream));
     }
+    if (timing) AS_HIP(hipEventRecord(w->ev[12], stream));
     for (int kc = 0; kc < kBandClasses; ++kc) {
       const int cnt = c.n_band[cur][kc];
       if (!cnt) continue;
@@ -935,16 +1052,21 @@ int asmi::band_call(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t 
     AS_HIP(hipMemsetAsync(&w->ctr->next_band16[0], 0, sizeof(int32_t) * kBand16Classes, stream));
     if ((rc = read_counters(w, stream, &c))) return rc;
     if (timing) band_ms += elapsed(w->ev[10], w->ev[11]);
+    if (timing) band16_ms += elapsed(w->ev[10], w->ev[12]);
+    if (timing) sort_ms += elapsed(w->ev[13], w->ev[10]);
     if ((rc = status_to_code(c.status))) return rc;
     rounds = r + 1;
   }
   g_last_timing.band_ms = band_ms;
+  g_last_timing.band16_ms = band16_ms;
+  g_last_timing.classify_ms += sort_ms;
   g_last_timing.pairs_fallback = c.n_fallback;
   if (stats) {
     stats->rounds = rounds;
     for (int r = 0; r < kMaxBandRounds; ++r) stats->accepted[r] = c.band_accepted[r];
     stats->fallback = c.n_fallback;
     stats->band_cells = (int64_t)c.band_cells;
+    stats->band16_cells = (int64_t)c.band16_cells;
     stats->cells = (int64_t)c.cells;
   }
   if (raw || c.n_fallback == 0) return AS_OK;

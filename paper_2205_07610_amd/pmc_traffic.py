@@ -1,0 +1,106 @@
+"""HBM traffic per kernel from two rocprofv3 PMC runs of bench.py.
+
+Usage (from the repository root, after the FETCH_SIZE and WRITE_SIZE runs of
+`bench.py --copy-reference`, whose CSV output went to <fetch_dir> and
+<write_dir>):
+
+    python -m paper_2205_07610_amd.pmc_traffic <fetch_dir> <write_dir> <workload_name> \
+        "<workload description>" [--write]
+
+Both counters read in KiB per dispatch.  Each is scaled by what it reads for
+the 1 GiB device copy that `--copy-reference` launches (rocclr's copyBuffer
+with a grid of 131072 threads): the factor that makes the copy read, and
+write, exactly 1 GiB.  With --write, one JSON record per kernel group goes to
+profiles/<group>_traffic.json, keyed by the kernel source's SHA-1 and the
+workload name so that bench.py reports it only for the same source and
+workload.  The unit the bytes cover is the one bench.py's roofline uses for
+that kernel: for the banded and feature kernels all launches of one step,
+for the full-DP kernels the full-DP step's one launch.
+"""
+import csv
+import hashlib
+import json
+import os
+import re
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+COPY_GRID = "131072"
+
+# group -> (kernel-name predicate, source file, which launches form one unit)
+GROUPS = {
+    "band32": (lambda k: k.startswith("band_dp_i32_kernel") and k.endswith("false>"),
+               "paper_2205_07610_amd/csrc/band_dp_i32.hip", "all"),
+    "band16": (lambda k: k.startswith("band_dp_i16_kernel"),
+               "paper_2205_07610_amd/csrc/band_dp_i16x2.hip", "all"),
+    "features": (lambda k: k.startswith("features_kernel"),
+                 "paper_2205_07610_amd/csrc/features.hip", "all"),
+    "long": (lambda k: k.startswith("long_dp_i32_kernel"),
+             "paper_2205_07610_amd/csrc/long_dp_i32.hip", "largest"),
+    "full32": (lambda k: k.startswith("full_dp_i32_kernel"),
+               "paper_2205_07610_amd/csrc/full_dp_i32.hip", "largest"),
+    "full16": (lambda k: k.startswith("full_dp_i16_kernel"),
+               "paper_2205_07610_amd/csrc/full_dp_i16x2.hip", "largest"),
+}
+
+
+def short(name: str) -> str:
+    name = name.replace("void ", "").replace("asmi::(anonymous namespace)::", "")
+    return re.sub(r"\(.*$", "", name)
+
+
+def load(d: str):
+    with open(os.path.join(d, "run_counter_collection.csv")) as f:
+        return list(csv.DictReader(f))
+
+
+def copy_scale(rows) -> float:
+    copies = [float(r["Counter_Value"]) for r in rows
+              if r["Kernel_Name"] == "__amd_rocclr_copyBuffer" and r["Grid_Size"] == COPY_GRID][:3]
+    if not copies:
+        raise SystemExit("no 1 GiB reference copy in the counter run (bench.py --copy-reference)")
+    return (1 << 30) / (sum(copies) / len(copies) * 1024)
+
+
+def sha(path: str) -> str:
+    with open(os.path.join(ROOT, path), "rb") as f:
+        return hashlib.sha1(f.read()).hexdigest()[:12]
+
+
+def summarise(fetch_dir, write_dir, workload_name, workload_desc):
+    F, W = load(fetch_dir), load(write_dir)
+    sf, sw = copy_scale(F), copy_scale(W)
+    out = {}
+    for g, (pred, src, unit) in GROUPS.items():
+        fr = [float(r["Counter_Value"]) for r in F if pred(short(r["Kernel_Name"]))]
+        wr = [float(r["Counter_Value"]) for r in W if pred(short(r["Kernel_Name"]))]
+        if not fr or len(fr) != len(wr):
+            continue
+        note = "unit: all launches of the one timed step (every class and round)"
+        if unit == "largest":   # the full-DP step's launch is the largest of the run
+            i = max(range(len(fr)), key=lambda k: fr[k])
+            fr, wr = [fr[i]], [wr[i]]
+            note = "unit: the full-DP step's launch (largest of the run)"
+        n = len(fr)
+        fb = sum(fr) * 1024 * sf
+        wb = sum(wr) * 1024 * sw
+        out[g] = {"kernel": g, "source": src, "source_sha": sha(src), "launches": n, "note": note,
+                  "fetch_bytes": fb, "write_bytes": wb, "bytes_per_unit": fb + wb,
+                  "fetch_scale": round(sf, 4), "write_scale": round(sw, 4),
+                  "workload": workload_desc, "workload_name": workload_name}
+    return out
+
+
+def main(argv):
+    if len(argv) < 4:
+        raise SystemExit(__doc__)
+    recs = summarise(argv[0], argv[1], argv[2], argv[3])
+    for g, rec in recs.items():
+        print(g, json.dumps(rec))
+        if "--write" in argv:
+            with open(os.path.join(ROOT, "profiles", f"{g}_traffic.json"), "w") as f:
+                json.dump(rec, f, indent=1)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])

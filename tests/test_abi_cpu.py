@@ -72,3 +72,30 @@ def test_python_binding_rejects_host_tensors():
     with pytest.raises(TypeError):
         binding.align_batch(t, o, t, o, np.eye(4, dtype=np.int8), 5, 2, 0,
                             scores_out=torch.zeros(1, dtype=torch.int32), stream=0)
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The binding's ctypes structs have the C header's field offsets and
+    sizes (a host C program built with gcc against include/anyseq_mi.h)."""
+    import os
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    structs = {"as_scoring": binding.Scoring, "as_timing": binding.Timing,
+               "as_band_stats": binding.BandStats}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "anyseq_mi.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for field, _ in py._fields_:
+            lines.append(f'printf("{cname} {field} %zu\\n", offsetof({cname}, {field}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(root, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for field, _ in py._fields_:
+            assert got[(cname, field)] == getattr(py, field).offset, (cname, field)
