@@ -13,7 +13,8 @@
 //    row, register x takes the selector of register x+1 and the last one
 //    takes lane t+1's register 1 (that lane runs one row behind) or the
 //    column feed -- a rotation of the register names, free in the 16-step
-//    unrolled loop because K divides 16.
+//    unrolled chunks; when K does not divide 16 the chunks come in
+//    K / gcd(K, 16) compile-time phases of the rotation.
 //  * Columns left of column 0: in global mode no alignment path visits them,
 //    so they hold -infinity (int16 saturation), and column 0 itself is then
 //    produced exactly by the recurrence: E carries the corner value down,
@@ -84,10 +85,22 @@ __device__ __forceinline__ uint32_t make_sel(uint32_t c0, uint32_t c1) {
   return c0 | 0x0C00u | (s1 << 16) | 0x0C000000u;
 }
 
+constexpr int gcd16(int k) { return k % 16 == 0 ? 16 : k % 8 == 0 ? 8 : k % 4 == 0 ? 4 : k % 2 == 0 ? 2 : 1; }
+
+// Waves per SIMD the register allocation aims for: four for the narrowest
+// class, three for the others (what the compiler would pick for the wider
+// ones is two; the few values it then spills are reloaded once per pair,
+// outside the DP loops).
 template <int K, int G>
-__global__ void __launch_bounds__(kWave) band_dp_i16_kernel(BandArgs a, int pc) {
-  static_assert(kGroup % K == 0, "the selector rotation needs K to divide 16");
+constexpr int kWavesPerEu = (K == 4 && G == kGroup) ? 4 : 3;
+
+template <int K, int G>
+__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(kWavesPerEu<K, G>)))
+band_dp_i16_kernel(BandArgs a, int pc) {
   constexpr int W = G * K;
+  // 16-step chunks come in NR phases of the selector rotation (K / gcd(K, 16))
+  constexpr int NR = K / gcd16(K);
+  static_assert(NR >= 1 && NR <= 3, "rotation phases");
   constexpr int GPW = kWave / G;
   const int lane = threadIdx.x;
   const int g = lane / G;
@@ -105,7 +118,7 @@ __global__ void __launch_bounds__(kWave) band_dp_i16_kernel(BandArgs a, int pc) 
   for (;;) {
     int base = 0;
     if (lane == 0) base = atomicAdd(&a.ctr->next_band16[pc], 2 * GPW);
-    base = __shfl(base, 0);
+    base = __builtin_amdgcn_readfirstlane(base);
     if (base >= n_list) break;
     // the two pairs of this group: 0 in the low halves, 1 in the high halves
     const int item0 = base + 2 * g, item1 = item0 + 1;
@@ -145,14 +158,6 @@ __global__ void __launch_bounds__(kWave) band_dp_i16_kernel(BandArgs a, int pc) 
       return j < 0 ? kNeg : (j == 0 ? beta - alpha : 2 * beta - 2 * alpha);
     };
     auto init_h = [&](int x) -> s2 { return pk(init1(lo0, x), init1(lo1, x)); };
-    // the same, recomputed where it is used: an empty asm makes the offsets
-    // opaque, so the compiler does not keep K row-0 values live in registers
-    // across the fill chunks
-    auto init_h_here = [&](int x) -> s2 {
-      int l0 = lo0, l1 = lo1;
-      __asm__ volatile("" : "+v"(l0), "+v"(l1));
-      return pk(init1(l0, x), init1(l1, x));
-    };
     s2 Ha[K], Ee[K];
     uint32_t P[K];  // selector words; register x's is P[(x + u) % K] at step u
 #pragma unroll
@@ -175,11 +180,11 @@ __global__ void __launch_bounds__(kWave) band_dp_i16_kernel(BandArgs a, int pc) 
     };
     uint32_t cfeed = cfeed_at(0);
     // One chunk of 16 steps.  FILL: the pipeline is still filling (some
-    // lane's row is <= 0 and is reset to row 0 afterwards); only the first
-    // G / 16 chunks need it, so the main loop carries no reset logic and no
-    // row-0 values stay live in registers.
-    auto chunk = [&](int it0, auto fill_tag) {
+    // lane's row is <= 0); only the first G / 16 chunks need the test, so the
+    // main loop carries none.  R0: the rotation phase (16 c mod K for chunk c).
+    auto chunk = [&](int it0, auto fill_tag, auto r0_tag) __attribute__((always_inline)) {
       constexpr bool FILL = decltype(fill_tag)::value;
+      constexpr int R0 = decltype(r0_tag)::value;
       const uint32_t qnext0 = qword(rows0, m0, tr0, it0 + kGroup + t);
       const uint32_t qnext1 = qword(rows1, m1, tr1, it0 + kGroup + t);
       const uint32_t cnext = cfeed_at(it0 + kGroup);
@@ -190,7 +195,7 @@ __global__ void __launch_bounds__(kWave) band_dp_i16_kernel(BandArgs a, int pc) 
         // last register takes lane t+1's register 1 of the previous step --
         // lane t+1 runs one row behind, so that is this row's next column --
         // or, in the group's last lane, the column feed
-        P[u % K] = (uint32_t)shl1<G>((int)cfeed, (int)P[(u + 1) % K]);
+        P[(u + R0) % K] = (uint32_t)shl1<G>((int)cfeed, (int)P[(u + R0 + 1) % K]);
         qrow0 = (uint32_t)shr1<G>((int)qfeed0, (int)qrow0);
         qrow1 = (uint32_t)shr1<G>((int)qfeed1, (int)qrow1);
         const s2 fl = as_s2(shr1<G>(negi, fout));
@@ -199,38 +204,33 @@ __global__ void __launch_bounds__(kWave) band_dp_i16_kernel(BandArgs a, int pc) 
         // update runs in place in ascending order (register x+1 is still the
         // previous row's when register x reads it).  Register 0 goes first and
         // its (E, H') moves to lane t-1 before the others.
+        // While the pipeline fills, a lane whose row is still <= 0 skips the
+        // update (a branch on the execution mask), so its registers keep the
+        // row-0 values set before the loop and its outputs to the neighbour
+        // lanes are row 0's.
+        const bool live = !FILL || row > 0;
         s2 f = fl;
-        {
-          const s2 sc = as_s2((int)__builtin_amdgcn_perm(qrow1, qrow0, P[(u + 1) % K]));
+        if (live) {
+          const s2 sc = as_s2((int)__builtin_amdgcn_perm(qrow1, qrow0, P[(u + R0 + 1) % K]));
           const s2 e = K > 1 ? vmax(Ee[1], Ha[1]) : neg2;
           const s2 hv = vmax(vmax(add_sat(Ha[0], sc), e), f);
           Ha[0] = sub_sat(hv, amb2);
           Ee[0] = e;
           f = vmax(f, Ha[0]);
         }
-        if (FILL && row <= 0) {
-          Ha[0] = init_h_here(0);
-          Ee[0] = neg2;
-        }
         const s2 eR = as_s2(shl1<G>(negi, as_i(vmax(Ee[0], Ha[0]))));
-#pragma unroll
-        for (int x = 1; x < K; ++x) {
-          const s2 sc = as_s2((int)__builtin_amdgcn_perm(qrow1, qrow0, P[(x + u + 1) % K]));
-          const s2 e = (x + 1 < K) ? vmax(Ee[x + 1], Ha[x + 1]) : eR;
-          const s2 hv = vmax(vmax(add_sat(Ha[x], sc), e), f);
-          Ha[x] = sub_sat(hv, amb2);
-          Ee[x] = e;
-          f = vmax(f, Ha[x]);
-        }
-        fout = as_i(f);
-        if (FILL && row <= 0) {
+        if (live) {
 #pragma unroll
           for (int x = 1; x < K; ++x) {
-            Ha[x] = init_h_here(x);
-            Ee[x] = neg2;
+            const s2 sc = as_s2((int)__builtin_amdgcn_perm(qrow1, qrow0, P[(x + u + R0 + 1) % K]));
+            const s2 e = (x + 1 < K) ? vmax(Ee[x + 1], Ha[x + 1]) : eR;
+            const s2 hv = vmax(vmax(add_sat(Ha[x], sc), e), f);
+            Ha[x] = sub_sat(hv, amb2);
+            Ee[x] = e;
+            f = vmax(f, Ha[x]);
           }
-          fout = negi;
         }
+        fout = live ? as_i(f) : negi;
         // a pair's last row: H(m, n) sits in register kn of lane kn / K
         if (__builtin_amdgcn_ballot_w64(row == m0 || row == m1) != 0) {
           if (row == m0 && kn0 / K == t) {
@@ -252,9 +252,15 @@ __global__ void __launch_bounds__(kWave) band_dp_i16_kernel(BandArgs a, int pc) 
       qfeed1 = qnext1;
       cfeed = cnext;
     };
-    int it0 = 0;
-    for (; it0 < its_max && it0 < G; it0 += kGroup) chunk(it0, std::true_type{});
-    for (; it0 < its_max; it0 += kGroup) chunk(it0, std::false_type{});
+    auto phase = [&](int it0, int c, auto fill_tag) __attribute__((always_inline)) {
+      const int ph = NR == 1 ? 0 : c % NR;
+      if (ph == 0) chunk(it0, fill_tag, std::integral_constant<int, 0>{});
+      else if (NR > 1 && ph == 1) chunk(it0, fill_tag, std::integral_constant<int, kGroup % K>{});
+      else if (NR > 2) chunk(it0, fill_tag, std::integral_constant<int, (2 * kGroup) % K>{});
+    };
+    int it0 = 0, c = 0;
+    for (; it0 < its_max && it0 < G; it0 += kGroup, ++c) phase(it0, c, std::true_type{});
+    for (; it0 < its_max; it0 += kGroup, ++c) phase(it0, c, std::false_type{});
 
     const int score0 = group_max<G>(res0), score1 = group_max<G>(res1);
     if (bad) atomicOr(&a.ctr->status, kStatusBadResidue);
@@ -281,7 +287,7 @@ __global__ void __launch_bounds__(kWave) band_dp_i16_kernel(BandArgs a, int pc) 
       atomicAdd(&a.ctr->band_accepted[a.round < kMaxBandRounds ? a.round : kMaxBandRounds - 1], 1);
       continue;
     }
-    band_requeue(a, d, w, kGlobal);
+    band_requeue(a, d, w, kGlobal, W);
   }
 }
 
@@ -296,29 +302,33 @@ int occupancy() {
 
 }  // namespace
 
-// Packed classes: 64, 128, 256 diagonals on 16-lane groups (K = 4, 8, 16;
-// eight pairs per wave), 512 and 1024 on whole waves (K = 8, 16; two pairs).
+// Packed classes (widths 1.5x or 1.33x apart): 64, 96, 128, 192, 256
+// diagonals on 16-lane groups (K = 4, 6, 8, 12, 16; eight pairs per wave),
+// 384, 512, 768, 1024 on whole waves (K = 6, 8, 12, 16; two pairs).
+#define AS_BAND16_CLASSES(X) \
+  X(0, 4, 16) X(1, 6, 16) X(2, 8, 16) X(3, 12, 16) X(4, 16, 16) X(5, 6, 64) X(6, 8, 64) X(7, 12, 64) X(8, 16, 64)
+
 hipError_t launch_band_dp_i16(int pc, const BandArgs &args, int grid, hipStream_t stream) {
   switch (pc) {
-    case 0: hipLaunchKernelGGL((band_dp_i16_kernel<4, 16>), dim3(grid), dim3(kWave), 0, stream, args, pc); break;
-    case 1: hipLaunchKernelGGL((band_dp_i16_kernel<8, 16>), dim3(grid), dim3(kWave), 0, stream, args, pc); break;
-    case 2: hipLaunchKernelGGL((band_dp_i16_kernel<16, 16>), dim3(grid), dim3(kWave), 0, stream, args, pc); break;
-    case 3: hipLaunchKernelGGL((band_dp_i16_kernel<8, 64>), dim3(grid), dim3(kWave), 0, stream, args, pc); break;
-    default: hipLaunchKernelGGL((band_dp_i16_kernel<16, 64>), dim3(grid), dim3(kWave), 0, stream, args, pc); break;
+#define AS_LAUNCH(PC, K, G) \
+  case PC: hipLaunchKernelGGL((band_dp_i16_kernel<K, G>), dim3(grid), dim3(kWave), 0, stream, args, pc); break;
+    AS_BAND16_CLASSES(AS_LAUNCH)
+#undef AS_LAUNCH
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 int band_dp_i16_blocks_per_cu(int pc) {
   switch (pc) {
-    case 0: return occupancy<4, 16>();
-    case 1: return occupancy<8, 16>();
-    case 2: return occupancy<16, 16>();
-    case 3: return occupancy<8, 64>();
-    default: return occupancy<16, 64>();
+#define AS_OCC(PC, K, G) \
+  case PC: return occupancy<K, G>();
+    AS_BAND16_CLASSES(AS_OCC)
+#undef AS_OCC
+    default: return 1;
   }
 }
 
-int band_dp_i16_pairs_per_wave(int pc) { return pc >= 3 ? 2 : 2 * kGroupsPerWave; }
+int band_dp_i16_pairs_per_wave(int pc) { return band16_class_lanes(pc) == kWave ? 2 : 2 * kGroupsPerWave; }
 
 }  // namespace asmi

@@ -291,7 +291,7 @@ __global__ void __launch_bounds__(kWave) band_dp_i32_kernel(BandArgs a, int kc) 
       atomicAdd(&a.ctr->band_accepted[a.round < kMaxBandRounds ? a.round : kMaxBandRounds - 1], 1);
       continue;
     }
-    band_requeue(a, d, bi.w, MODE);
+    band_requeue(a, d, bi.w, MODE, W);
   }
 }
 

@@ -67,6 +67,12 @@ constexpr int32_t kStatusRange = 4;
 constexpr int32_t kStatusStall = 8;   // a wavefront wait exceeded its spin limit
 constexpr int32_t kStatusPlan = 32;   // a planned replay met a batch its buffers cannot hold
 
+// Banded classes: 32-bit (band_class_width) and packed 16-bit
+// (band16_class_width); banded rounds.
+constexpr int kBandClasses = 8;
+constexpr int kBand16Classes = 9;
+constexpr int kMaxBandRounds = 8;
+
 // Work-list counters written by the classify kernel.
 struct Counters {
   int32_t n_full32;      // items queued for the 32-bit full DP
@@ -84,10 +90,10 @@ struct Counters {
   int32_t n_fallback;    // banded pairs sent to the full DP
   long long long_bnd_total;  // int2 entries of all wavefront boundary columns
   // banded path: lists per round parity and lane-width class
-  int32_t n_band[2][8];
-  int32_t next_band[8];
-  int32_t n_band16[2][5];   // packed 16-bit banded lists per round parity and class
-  int32_t next_band16[5];
+  int32_t n_band[2][kBandClasses];
+  int32_t next_band[kBandClasses];
+  int32_t n_band16[2][kBand16Classes];   // packed 16-bit banded lists per round parity and class
+  int32_t next_band16[kBand16Classes];
   int32_t band_accepted[8];  // pairs accepted in round r
   unsigned long long band_cells;  // cells computed by the banded kernels (both widths)
   unsigned long long band16_cells;  // of these, cells computed by the packed 16-bit kernel
@@ -106,8 +112,6 @@ struct Counters {
 // Band widths (diagonals) of the banded kernel's classes: 16-lane groups
 // with K = 4, 8, 12, 16, 24 columns per lane, then whole waves with K = 8,
 // 12, 16.  Consecutive widths differ by at most 1.5x.
-constexpr int kBandClasses = 8;
-constexpr int kMaxBandRounds = 8;
 __host__ __device__ inline int band_class_width(int kc) {
   return kc == 0 ? 64 : kc == 1 ? 128 : kc == 2 ? 192 : kc == 3 ? 256
        : kc == 4 ? 384 : kc == 5 ? 512 : kc == 6 ? 768 : 1024;
@@ -177,7 +181,6 @@ struct BandItem {
 };
 
 // Packed 16-bit banded classes (global mode): 64 << pc diagonals.
-constexpr int kBand16Classes = 5;
 // Before each round every band list is sorted by row count, longest first,
 // into one buffer (list l at sorted_base[l]): the pairs of one wave, and the
 // two halves of a packed group, then run about the same number of wavefront
@@ -215,10 +218,16 @@ hipError_t launch_band_dp_i16(int pc, const BandArgs &args, int grid, hipStream_
 int band_dp_i16_blocks_per_cu(int pc);
 int band_dp_i16_pairs_per_wave(int pc);
 
-__host__ __device__ inline int band16_class_width(int pc) { return 64 << pc; }
+// Widths of the packed classes (lane-group size x registers per lane):
+// 16 x {4, 6, 8, 12, 16}, then 64 x {6, 8, 12, 16}.
+__host__ __device__ inline int band16_class_width(int pc) {
+  return pc == 0 ? 64 : pc == 1 ? 96 : pc == 2 ? 128 : pc == 3 ? 192 : pc == 4 ? 256
+       : pc == 5 ? 384 : pc == 6 ? 512 : pc == 7 ? 768 : 1024;
+}
+__host__ __device__ inline int band16_class_lanes(int pc) { return pc < 5 ? kGroup : kWave; }
 __host__ __device__ inline int band16_class_for(int B) {
   for (int pc = 0; pc < kBand16Classes; ++pc)
-    if ((64 << pc) >= B) return pc;
+    if (band16_class_width(pc) >= B) return pc;
   return -1;
 }
 // Every shifted cell of a W-diagonal band of an m x n global pair stays
@@ -248,13 +257,34 @@ __host__ __device__ inline int band_route(int m, int n, int w, bool pack16, int 
   if (kc < 0 || 2 * band_class_width(kc) >= n) return -1;
   return kc;
 }
-// A rejected band: queue the pair for the next round with the half-width
-// doubled, or for the full DP when no band can hold it or the rounds are
+// Widest band (diagonals) any class may hold for an m-row, n-column pair
+// (m <= n): the widest class with 2 W < n; 0 if none.
+__host__ __device__ inline int band_widest(int n) {
+  int best = 0;
+  for (int kc = 0; kc < kBandClasses; ++kc)
+    if (2 * band_class_width(kc) < n && band_class_width(kc) > best) best = band_class_width(kc);
+  for (int pc = 0; pc < kBand16Classes; ++pc)
+    if (2 * band16_class_width(pc) < n && band16_class_width(pc) > best) best = band16_class_width(pc);
+  return best;
+}
+// A rejected band (this round computed W_cur diagonals): queue the pair for
+// the next round with the half-width doubled.  When the doubled band fits no
+// class but a class wider than W_cur exists, the pair gets the widest band
+// instead; the full DP takes it when no wider band is left or the rounds are
 // spent.
-__device__ inline void band_requeue(const BandArgs &a, const PairDesc &d, int w, int mode) {
-  const int w2 = w > 0 ? 2 * w : 1;
+__device__ inline void band_requeue(const BandArgs &a, const PairDesc &d, int w, int mode, int W_cur) {
+  int w2 = w > 0 ? 2 * w : 1;
   bool packed = false;
-  const int c = band_route(d.m, d.n, w2, a.pack16 && mode == kGlobal, a.smax_pos, a.alpha, a.beta, &packed);
+  const bool p16 = a.pack16 && mode == kGlobal;
+  int c = band_route(d.m, d.n, w2, p16, a.smax_pos, a.alpha, a.beta, &packed);
+  if (c < 0) {
+    const int Wmax = band_widest(d.n);
+    const int wcap = (Wmax - (d.n - d.m) - 1) / 2;
+    if (Wmax > W_cur && wcap > w) {
+      w2 = wcap;
+      c = band_route(d.m, d.n, w2, p16, a.smax_pos, a.alpha, a.beta, &packed);
+    }
+  }
   if (a.round + 1 >= a.max_rounds || c < 0) {
     a.fallback[atomicAdd(&a.ctr->n_fallback, 1)] = d;
     return;

@@ -407,30 +407,31 @@ __global__ void __launch_bounds__(256) band_sort_count_kernel(SortLists s, int32
 
 // One wave per list turns its histogram into the first slot of each bucket,
 // largest bucket first (lane j owns 8 consecutive buckets of that order).
-__global__ void __launch_bounds__(1024) band_sort_scan_kernel(SortLists s, int32_t *hist) {
-  const int l = threadIdx.x / kWave;
+constexpr int kSortScanThreads = 1024;
+__global__ void __launch_bounds__(kSortScanThreads) band_sort_scan_kernel(SortLists s, int32_t *hist) {
   const int lane = threadIdx.x % kWave;
-  if (l >= kBandLists) return;
   constexpr int kPer = kSortBuckets / kWave;
-  int32_t *h = hist + l * kSortBuckets;
-  int v[kPer];
-  int sum = 0;
+  for (int l = threadIdx.x / kWave; l < kBandLists; l += kSortScanThreads / kWave) {
+    int32_t *h = hist + l * kSortBuckets;
+    int v[kPer];
+    int sum = 0;
 #pragma unroll
-  for (int q = 0; q < kPer; ++q) {
-    v[q] = h[kSortBuckets - 1 - (lane * kPer + q)];
-    sum += v[q];
-  }
-  int incl = sum;  // inclusive prefix of the lanes' sums
+    for (int q = 0; q < kPer; ++q) {
+      v[q] = h[kSortBuckets - 1 - (lane * kPer + q)];
+      sum += v[q];
+    }
+    int incl = sum;  // inclusive prefix of the lanes' sums
 #pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const int y = __shfl_up(incl, d);
-    if (lane >= d) incl += y;
-  }
-  int run = (int)s.base[l] + incl - sum;
+    for (int d = 1; d < kWave; d <<= 1) {
+      const int y = __shfl_up(incl, d);
+      if (lane >= d) incl += y;
+    }
+    int run = (int)s.base[l] + incl - sum;
 #pragma unroll
-  for (int q = 0; q < kPer; ++q) {
-    h[kSortBuckets - 1 - (lane * kPer + q)] = run;
-    run += v[q];
+    for (int q = 0; q < kPer; ++q) {
+      h[kSortBuckets - 1 - (lane * kPer + q)] = run;
+      run += v[q];
+    }
   }
 }
 
@@ -1020,7 +1021,7 @@ int asmi::band_call(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t 
     AS_HIP(hipMemsetAsync(w->sort_hist, 0, kBandLists * kSortBuckets * sizeof(int32_t), stream));
     const int sort_blocks = (int)((total + 4095) / 4096);
     hipLaunchKernelGGL(band_sort_count_kernel, dim3(sort_blocks), dim3(256), 0, stream, sl, w->sort_hist);
-    hipLaunchKernelGGL(band_sort_scan_kernel, dim3(1), dim3(kBandLists * kWave), 0, stream, sl, w->sort_hist);
+    hipLaunchKernelGGL(band_sort_scan_kernel, dim3(1), dim3(kSortScanThreads), 0, stream, sl, w->sort_hist);
     hipLaunchKernelGGL(band_sort_scatter_kernel, dim3(sort_blocks), dim3(256), 0, stream, sl, w->sort_hist,
                        w->band_sorted);
     AS_HIP(hipGetLastError());

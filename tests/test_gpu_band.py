@@ -127,7 +127,9 @@ def test_packed_band_matches_32bit_and_oracle(gpu, oracle_mod):
     past the packed range limit (pairs of ~4900 and ~6000 residues go to the
     32-bit kernel, or switch kernels between rounds), initial half-widths
     range from 0 to wide, so pairs are accepted, doubled and sent to the
-    full DP."""
+    full DP; one case spreads the initial widths over every class.  The
+    packed classes of 96, 192, 384 and 768 diagonals (K = 6 or 12 registers
+    per lane) run their selector rotation in three phases."""
     import torch
     rng = np.random.default_rng(760)
     b = synth.config4_like(900, 761, min_len=150, max_len=2500, max_div=0.15)
@@ -136,8 +138,12 @@ def test_packed_band_matches_32bit_and_oracle(gpu, oracle_mod):
     bb = synth.from_pairs("packed band", pairs, DNA, 5, 2, 0)
     want = oracle_mod.align_batch(bb.seqs_a, bb.offs_a, bb.seqs_b, bb.offs_b, DNA, 5, 2, 0)
     dev = gpu.to_device(bb)
-    for w0, rounds in ((0, 6), (20, 6), (120, 6), (3, 2)):
-        w = _w(torch, rng.integers(max(0, w0 - 3), w0 + 4, bb.n_pairs))
+    # the last case spreads the first round over every lane-width class
+    for w0, rounds in ((0, 6), (20, 6), (120, 6), (3, 2), (None, 3)):
+        if w0 is None:
+            w = _w(torch, rng.integers(0, 520, bb.n_pairs))
+        else:
+            w = _w(torch, rng.integers(max(0, w0 - 3), w0 + 4, bb.n_pairs))
         res = {}
         for on in (True, False):
             gpu.set_band_packing(on)
