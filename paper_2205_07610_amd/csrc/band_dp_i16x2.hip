@@ -11,17 +11,29 @@
 //    selector [code_lo, 0, code_hi + 4, 0] picks each half's byte and
 //    zero-extends it.  Each register keeps its selector word; going down a
 //    row, register x takes the selector of register x+1 and the last one
-//    takes lane t+1's register 1 (that lane runs one row behind) or the
-//    column feed -- a rotation of the register names, free in the 16-step
-//    unrolled chunks; when K does not divide 16 the chunks come in
-//    K / gcd(K, 16) compile-time phases of the rotation.
-//  * Columns left of column 0: in global mode no alignment path visits them,
-//    so they hold -infinity (int16 saturation), and column 0 itself is then
-//    produced exactly by the recurrence: E carries the corner value down,
-//    which in the shifted frame is the constant boundary H'(i,0) = 2(beta -
-//    alpha).  All packed arithmetic saturates, so -infinity stays put and
-//    never wraps.  Columns right of n use selector 0 (score 0) and never
-//    influence column n or any cell left of it.
+//    takes lane t+1's register 1 (that lane runs one row behind) or, in the
+//    group's last lane, the selector of the column entering the band -- a
+//    rotation of the register names, free in the 16-step unrolled chunks;
+//    when K does not divide 16 the chunks come in K / gcd(K, 16)
+//    compile-time phases of the rotation.
+//  * Feeds through LDS: at the start of each 16-step chunk, lanes 0..15 of a
+//    group write the score words of the chunk's 16 new rows into a ring of
+//    128 rows (rows 0..15 mirrored past its end, so a lane's 16 reads of a
+//    chunk are contiguous and take the step from the instruction's offset)
+//    and the selectors of the 16 entering columns; the residues were loaded
+//    one chunk ahead.  A step then costs the cell updates, two LDS reads and
+//    three DPP moves.
+//  * Values are stored with a bias of 32768 as unsigned 16-bit numbers, so 0
+//    is -infinity: DPP moves that shift in from outside the group write 0
+//    themselves, and all packed arithmetic saturates, so -infinity stays put
+//    and never wraps.  Columns left of column 0 hold -infinity (in global
+//    mode no alignment path visits them) and column 0 itself is produced
+//    exactly by the recurrence: E carries the corner value down, which in
+//    the shifted frame is the constant boundary H'(i,0) = 2(beta - alpha).
+//    Columns right of n use selector 0 (score 0) and never influence column
+//    n or any cell left of it.
+//  * Results: a chunk in which some lane reaches a pair's last row runs a
+//    variant with the per-step test for H(m, n); the others carry none.
 //  * Range: a pair is queued here only when an a priori bound keeps every
 //    shifted cell (band columns up to n + W) inside int16; the others take
 //    the 32-bit banded kernel.
@@ -32,25 +44,32 @@
 namespace asmi {
 namespace {
 
-typedef short s2 __attribute__((ext_vector_type(2)));
+typedef unsigned short u2 __attribute__((ext_vector_type(2)));
 
-constexpr short kNeg = -32768;
+constexpr int kBias = 32768;  // stored = shifted-frame value + kBias; 0 is -infinity
+constexpr int kRing = 128;    // rows held in a group's row-word ring
 
-__device__ __forceinline__ int as_i(s2 v) { return __builtin_bit_cast(int, v); }
-__device__ __forceinline__ s2 as_s2(int v) { return __builtin_bit_cast(s2, v); }
-__device__ __forceinline__ s2 pk(int lo, int hi) {
-  s2 r;
-  r.x = (short)lo;
-  r.y = (short)hi;
+__device__ __forceinline__ int as_i(u2 v) { return __builtin_bit_cast(int, v); }
+__device__ __forceinline__ u2 as_u2(int v) { return __builtin_bit_cast(u2, v); }
+__device__ __forceinline__ u2 pk(int lo, int hi) {
+  u2 r;
+  r.x = (unsigned short)lo;
+  r.y = (unsigned short)hi;
   return r;
 }
-__device__ __forceinline__ s2 vmax(s2 a, s2 b) { return __builtin_elementwise_max(a, b); }
-__device__ __forceinline__ s2 add_sat(s2 a, s2 b) { return __builtin_elementwise_add_sat(a, b); }
-__device__ __forceinline__ s2 sub_sat(s2 a, s2 b) { return __builtin_elementwise_sub_sat(a, b); }
+__device__ __forceinline__ u2 vmax(u2 a, u2 b) { return __builtin_elementwise_max(a, b); }
+__device__ __forceinline__ u2 add_sat(u2 a, u2 b) { return __builtin_elementwise_add_sat(a, b); }
+__device__ __forceinline__ u2 sub_sat(u2 a, u2 b) { return __builtin_elementwise_sub_sat(a, b); }
 
+// Group-local shifts by one lane: shr1z/shl1z write 0 where the source lane
+// is outside the group; shl1 keeps `old` there.
 template <int G>
-__device__ __forceinline__ int shr1(int old, int src) {
-  return __builtin_amdgcn_update_dpp(old, src, G == 16 ? 0x111 : 0x138, 0xF, 0xF, false);
+__device__ __forceinline__ int shr1z(int src) {
+  return __builtin_amdgcn_update_dpp(0, src, G == 16 ? 0x111 : 0x138, 0xF, 0xF, true);
+}
+template <int G>
+__device__ __forceinline__ int shl1z(int src) {
+  return __builtin_amdgcn_update_dpp(0, src, G == 16 ? 0x101 : 0x130, 0xF, 0xF, true);
 }
 template <int G>
 __device__ __forceinline__ int shl1(int old, int src) {
@@ -101,19 +120,23 @@ band_dp_i16_kernel(BandArgs a, int pc) {
   // 16-step chunks come in NR phases of the selector rotation (K / gcd(K, 16))
   constexpr int NR = K / gcd16(K);
   static_assert(NR >= 1 && NR <= 3, "rotation phases");
+  static_assert(kRing >= G + 2 * kGroup, "the ring holds every row a chunk reads and the next chunk's");
   constexpr int GPW = kWave / G;
+  __shared__ uint2 rq[GPW][kRing + kGroup];  // row words (low pair, high pair) by row mod kRing
+  __shared__ uint32_t sq[GPW][kGroup];       // selectors entering at the last lane, by step of the chunk
+  __shared__ uint32_t qt[8];                 // score word by (orientation, letter)
   const int lane = threadIdx.x;
   const int g = lane / G;
   const int t = lane % G;
   const int alpha = a.alpha, beta = a.beta, amb = alpha - beta;
-  const int asz = a.asz;
+  const uint32_t asz = (uint32_t)a.asz;  // at most 4 on this path
   const int cur = a.round & 1;
   const int n_list = a.ctr->n_band16[cur][pc];
   const BandItem *list = a.sorted + a.sorted_base[kBandClasses + pc];
-  const s2 amb2 = pk(amb, amb);
-  const s2 neg2 = pk(kNeg, kNeg);
-  const int negi = as_i(neg2);
+  const u2 amb2 = pk(amb, amb);
   const int kb = t * K;
+  if (lane < 8) qt[lane] = a.qwords[(lane >> 2) * 32 + (lane & 3)];
+  __builtin_amdgcn_wave_barrier();
 
   for (;;) {
     int base = 0;
@@ -139,66 +162,97 @@ band_dp_i16_kernel(BandArgs a, int pc) {
     };
     const int lo0 = band_lo(m0, n0, b0.w), lo1 = band_lo(m1, n1, b1.w);
     const int kn0 = n0 - m0 - lo0, kn1 = n1 - m1 - lo1;  // register of column n at row m
+    // the step at which this lane holds H(m, n) of each half (-1: never)
+    const int e0 = (has0 && t == kn0 / K) ? m0 - 1 + t : -1;
+    const int e1 = (has1 && t == kn1 / K) ? m1 - 1 + t : -1;
     int bad = 0;
-    auto code = [&](bool has, const uint8_t *cols, int n, int j) -> uint32_t {
+    // loads are clamped into the sequence so that they can be issued early;
+    // what they mean is decided where they are used
+    auto col_byte = [&](const uint8_t *cols, int n, int j) -> uint32_t {
+      return cols[min(max(j - 1, 0), max(n - 1, 0))];
+    };
+    auto col_code = [&](bool has, int n, int j, uint32_t c) -> uint32_t {
       if (!has || j < 1 || j > n) return 12u;
-      uint32_t c = cols[j - 1];
-      if (c >= (uint32_t)asz) { bad = 1; c = 0; }
+      if (c >= asz) { bad = 1; c = 0; }
       return c;
     };
-    auto qword = [&](const uint8_t *rows, int m, bool tr, int idx) -> uint32_t {
+    auto row_byte = [&](const uint8_t *rows, int m, int idx) -> uint32_t {
+      return rows[min(max(idx, 0), max(m - 1, 0))];
+    };
+    auto row_word = [&](int m, bool tr, int idx, uint32_t r) -> uint32_t {
       if (idx < 0 || idx >= m) return 0u;
-      int r = rows[idx];
       if (r >= asz) { bad = 1; r = 0; }
-      return a.qwords[(tr ? 32 : 0) + r];
+      return qt[(tr ? 4 : 0) + r];
     };
     // row 0: column 0 is the corner, columns left of it are outside the matrix
     auto init1 = [&](int lo, int x) -> int {
       const int j = lo + kb + x;
-      return j < 0 ? kNeg : (j == 0 ? beta - alpha : 2 * beta - 2 * alpha);
+      return j < 0 ? 0 : kBias + (j == 0 ? beta - alpha : 2 * beta - 2 * alpha);
     };
-    auto init_h = [&](int x) -> s2 { return pk(init1(lo0, x), init1(lo1, x)); };
-    s2 Ha[K], Ee[K];
+    u2 Ha[K], Ee[K];
     uint32_t P[K];  // selector words; register x's is P[(x + u) % K] at step u
 #pragma unroll
     for (int x = 0; x < K; ++x) {
-      Ha[x] = init_h(x);
-      Ee[x] = neg2;
-      P[x] = make_sel(code(has0, cols0, n0, -t + lo0 + kb + x), code(has1, cols1, n1, -t + lo1 + kb + x));
+      Ha[x] = pk(init1(lo0, x), init1(lo1, x));
+      Ee[x] = pk(0, 0);
+      const int j0 = -t + lo0 + kb + x, j1 = -t + lo1 + kb + x;
+      P[x] = make_sel(col_code(has0, n0, j0, col_byte(cols0, n0, j0)),
+                      col_code(has1, n1, j1, col_byte(cols1, n1, j1)));
     }
-    int fout = negi;
-    uint32_t qrow0 = 0, qrow1 = 0;
+    int fout = 0;
     int res0 = kNegInf32, res1 = kNegInf32;
     const int mmax = max(m0, m1);
     const int its = mmax > 0 ? mmax + G - 1 : 0;
     const int its_max = wave_max_groups<G>(its);
-    uint32_t qfeed0 = qword(rows0, m0, tr0, t), qfeed1 = qword(rows1, m1, tr1, t);
-    // new selectors enter at the group's last lane (element u in lane G-1-u)
-    auto cfeed_at = [&](int it0) -> uint32_t {
-      const int jo = it0 + (G - 1 - t) - (G - 2) + W - 1;
-      return make_sel(code(has0, cols0, n0, jo + lo0), code(has1, cols1, n1, jo + lo1));
+    // column entering the band at the group's last lane at step it
+    constexpr int kEnter = W - G + 1;
+    // residues of the chunk starting at it0 (lanes t < 16): row it0 + 1 + t
+    // and the column entering at step it0 + t, loaded one chunk ahead
+    uint32_t rb0 = 0, rb1 = 0, cb0 = 0, cb1 = 0;
+    auto prefetch = [&](int it0) {
+      if (t < kGroup) {
+        rb0 = row_byte(rows0, m0, it0 + t);
+        rb1 = row_byte(rows1, m1, it0 + t);
+        cb0 = col_byte(cols0, n0, it0 + t + lo0 + kEnter);
+        cb1 = col_byte(cols1, n1, it0 + t + lo1 + kEnter);
+      }
     };
-    uint32_t cfeed = cfeed_at(0);
+    auto feed = [&](int it0) {
+      if (t < kGroup) {
+        const int r = it0 + 1 + t;
+        uint2 v;
+        v.x = row_word(m0, tr0, r - 1, rb0);
+        v.y = row_word(m1, tr1, r - 1, rb1);
+        const int slot = r & (kRing - 1);
+        rq[g][slot] = v;
+        if (slot < kGroup) rq[g][slot + kRing] = v;
+        const int j0 = it0 + t + lo0 + kEnter, j1 = it0 + t + lo1 + kEnter;
+        sq[g][t] = make_sel(col_code(has0, n0, j0, cb0), col_code(has1, n1, j1, cb1));
+      }
+      __builtin_amdgcn_wave_barrier();
+    };
+    prefetch(0);
     // One chunk of 16 steps.  FILL: the pipeline is still filling (some
-    // lane's row is <= 0); only the first G / 16 chunks need the test, so the
-    // main loop carries none.  R0: the rotation phase (16 c mod K for chunk c).
-    auto chunk = [&](int it0, auto fill_tag, auto r0_tag) __attribute__((always_inline)) {
+    // lane's row is <= 0); only the first G / 16 chunks need the test.
+    // EXT: some lane reaches a pair's last row in this chunk.  R0: the
+    // rotation phase (16 c mod K for chunk c).
+    auto chunk = [&](int it0, auto fill_tag, auto ext_tag, auto r0_tag) __attribute__((always_inline)) {
       constexpr bool FILL = decltype(fill_tag)::value;
+      constexpr bool EXT = decltype(ext_tag)::value;
       constexpr int R0 = decltype(r0_tag)::value;
-      const uint32_t qnext0 = qword(rows0, m0, tr0, it0 + kGroup + t);
-      const uint32_t qnext1 = qword(rows1, m1, tr1, it0 + kGroup + t);
-      const uint32_t cnext = cfeed_at(it0 + kGroup);
+      feed(it0);
+      prefetch(it0 + kGroup);
+      const uint2 *rrow = &rq[g][(it0 + 1 - t) & (kRing - 1)];
 #pragma unroll
       for (int u = 0; u < kGroup; ++u) {
         const int row = it0 + u + 1 - t;
         // this row's selectors: the register names rotate by one, and the
         // last register takes lane t+1's register 1 of the previous step --
         // lane t+1 runs one row behind, so that is this row's next column --
-        // or, in the group's last lane, the column feed
-        P[(u + R0) % K] = (uint32_t)shl1<G>((int)cfeed, (int)P[(u + R0 + 1) % K]);
-        qrow0 = (uint32_t)shr1<G>((int)qfeed0, (int)qrow0);
-        qrow1 = (uint32_t)shr1<G>((int)qfeed1, (int)qrow1);
-        const s2 fl = as_s2(shr1<G>(negi, fout));
+        // or, in the group's last lane, the entering column's
+        P[(u + R0) % K] = (uint32_t)shl1<G>((int)sq[g][u], (int)P[(u + R0 + 1) % K]);
+        const uint2 q = rrow[u];
+        const u2 fl = as_u2(shr1z<G>(fout));
         // In the sheared layout a cell's diagonal predecessor is its own
         // register one row earlier and "up" is the next register, so the
         // update runs in place in ascending order (register x+1 is still the
@@ -209,58 +263,59 @@ band_dp_i16_kernel(BandArgs a, int pc) {
         // row-0 values set before the loop and its outputs to the neighbour
         // lanes are row 0's.
         const bool live = !FILL || row > 0;
-        s2 f = fl;
+        u2 f = fl;
         if (live) {
-          const s2 sc = as_s2((int)__builtin_amdgcn_perm(qrow1, qrow0, P[(u + R0 + 1) % K]));
-          const s2 e = K > 1 ? vmax(Ee[1], Ha[1]) : neg2;
-          const s2 hv = vmax(vmax(add_sat(Ha[0], sc), e), f);
+          const u2 sc = as_u2((int)__builtin_amdgcn_perm(q.y, q.x, P[(u + R0 + 1) % K]));
+          const u2 e = K > 1 ? vmax(Ee[1], Ha[1]) : pk(0, 0);
+          const u2 hv = vmax(vmax(add_sat(Ha[0], sc), e), f);
           Ha[0] = sub_sat(hv, amb2);
           Ee[0] = e;
           f = vmax(f, Ha[0]);
         }
-        const s2 eR = as_s2(shl1<G>(negi, as_i(vmax(Ee[0], Ha[0]))));
+        const u2 eR = as_u2(shl1z<G>(as_i(vmax(Ee[0], Ha[0]))));
         if (live) {
 #pragma unroll
           for (int x = 1; x < K; ++x) {
-            const s2 sc = as_s2((int)__builtin_amdgcn_perm(qrow1, qrow0, P[(x + u + R0 + 1) % K]));
-            const s2 e = (x + 1 < K) ? vmax(Ee[x + 1], Ha[x + 1]) : eR;
-            const s2 hv = vmax(vmax(add_sat(Ha[x], sc), e), f);
+            const u2 sc = as_u2((int)__builtin_amdgcn_perm(q.y, q.x, P[(x + u + R0 + 1) % K]));
+            const u2 e = (x + 1 < K) ? vmax(Ee[x + 1], Ha[x + 1]) : eR;
+            const u2 hv = vmax(vmax(add_sat(Ha[x], sc), e), f);
             Ha[x] = sub_sat(hv, amb2);
             Ee[x] = e;
             f = vmax(f, Ha[x]);
           }
         }
-        fout = live ? as_i(f) : negi;
-        // a pair's last row: H(m, n) sits in register kn of lane kn / K
-        if (__builtin_amdgcn_ballot_w64(row == m0 || row == m1) != 0) {
-          if (row == m0 && kn0 / K == t) {
+        fout = live ? as_i(f) : 0;
+        if (EXT) {  // a pair's last row: H(m, n) sits in register kn of lane kn / K
+          if (it0 + u == e0) {
 #pragma unroll
             for (int x = 0; x < K; ++x)
-              if (x == kn0 % K) res0 = (int)Ha[x].x + amb - beta * (m0 + n0);
+              if (x == kn0 % K) res0 = (int)Ha[x].x - kBias + amb - beta * (m0 + n0);
           }
-          if (row == m1 && kn1 / K == t) {
+          if (it0 + u == e1) {
 #pragma unroll
             for (int x = 0; x < K; ++x)
-              if (x == kn1 % K) res1 = (int)Ha[x].y + amb - beta * (m1 + n1);
+              if (x == kn1 % K) res1 = (int)Ha[x].y - kBias + amb - beta * (m1 + n1);
           }
         }
-        qfeed0 = (uint32_t)shl1<G>((int)qfeed0, (int)qfeed0);
-        qfeed1 = (uint32_t)shl1<G>((int)qfeed1, (int)qfeed1);
-        cfeed = (uint32_t)shr1<G>((int)cfeed, (int)cfeed);
       }
-      qfeed0 = qnext0;
-      qfeed1 = qnext1;
-      cfeed = cnext;
+      __builtin_amdgcn_wave_barrier();  // this chunk's LDS reads stay before the next feed
     };
-    auto phase = [&](int it0, int c, auto fill_tag) __attribute__((always_inline)) {
+    auto ends_in = [&](int it0) -> bool {
+      return __builtin_amdgcn_ballot_w64((e0 >= it0 && e0 < it0 + kGroup) ||
+                                         (e1 >= it0 && e1 < it0 + kGroup)) != 0;
+    };
+    auto phase = [&](int it0, int c, auto fill_tag, auto ext_tag) __attribute__((always_inline)) {
       const int ph = NR == 1 ? 0 : c % NR;
-      if (ph == 0) chunk(it0, fill_tag, std::integral_constant<int, 0>{});
-      else if (NR > 1 && ph == 1) chunk(it0, fill_tag, std::integral_constant<int, kGroup % K>{});
-      else if (NR > 2) chunk(it0, fill_tag, std::integral_constant<int, (2 * kGroup) % K>{});
+      if (ph == 0) chunk(it0, fill_tag, ext_tag, std::integral_constant<int, 0>{});
+      else if (NR > 1 && ph == 1) chunk(it0, fill_tag, ext_tag, std::integral_constant<int, kGroup % K>{});
+      else if (NR > 2) chunk(it0, fill_tag, ext_tag, std::integral_constant<int, (2 * kGroup) % K>{});
     };
     int it0 = 0, c = 0;
-    for (; it0 < its_max && it0 < G; it0 += kGroup, ++c) phase(it0, c, std::true_type{});
-    for (; it0 < its_max; it0 += kGroup, ++c) phase(it0, c, std::false_type{});
+    for (; it0 < its_max && it0 < G; it0 += kGroup, ++c) phase(it0, c, std::true_type{}, std::true_type{});
+    for (; it0 < its_max; it0 += kGroup, ++c) {
+      if (ends_in(it0)) phase(it0, c, std::false_type{}, std::true_type{});
+      else phase(it0, c, std::false_type{}, std::false_type{});
+    }
 
     const int score0 = group_max<G>(res0), score1 = group_max<G>(res1);
     if (bad) atomicOr(&a.ctr->status, kStatusBadResidue);

@@ -199,6 +199,7 @@ struct BandArgs {
   int64_t list_cap;
   int32_t pack16;           // 1: range-proven global pairs may use the packed kernel
   int32_t smax_pos;         // max(sigma_max, 0)
+  int32_t drop16;           // max(0, -(sigma_min + 2 beta)) (packed range proof)
   Counters *ctr;
   const uint32_t *qwords;   // [2][32]: byte c of word r = sigma(r, c) + alpha + beta (row/col order)
   int32_t asz, alpha, beta, sigma_max;
@@ -232,22 +233,28 @@ __host__ __device__ inline int band16_class_for(int B) {
 }
 // Every shifted cell of a W-diagonal band of an m x n global pair stays
 // below sigma_max*min(m,n) + beta*(m + n + W) (columns run up to n + W),
-// plus the score byte and margins: inside int16 when this is below 32000.
-__host__ __device__ inline bool band16_range_ok(int m, int n, int W, int smax_pos, int alpha, int beta) {
-  const int64_t ub = (int64_t)smax_pos * (m < n ? m : n) + (int64_t)beta * ((int64_t)m + n + W) + alpha +
-                     2 * beta + 256;
-  return ub < 32000;
+// plus the score byte and margins; and above -(drop*min(m,n) + 3(alpha -
+// beta)), drop = max(0, -(sigma_min + 2 beta)): the band holds the path
+// that runs down diagonal 0 and then takes one gap run to the cell, and in
+// the shifted frame a diagonal step adds sigma + 2 beta and a gap run costs
+// alpha - beta.  Inside int16 when both stay within 32000.
+__host__ __device__ inline bool band16_range_ok(int m, int n, int W, int smax_pos, int drop, int alpha,
+                                                int beta) {
+  const int64_t mn = m < n ? m : n;
+  const int64_t ub = (int64_t)smax_pos * mn + (int64_t)beta * ((int64_t)m + n + W) + alpha + 2 * beta + 256;
+  const int64_t lb = (int64_t)drop * mn + 3LL * (alpha - beta) + 256;
+  return ub < 32000 && lb < 32000;
 }
 // Where a band request of half-width w for an m-row (shorter), n-column pair
 // goes: a packed class (*packed = true), a 32-bit class, or -1 for the full
 // DP (no class holds it, or the band would cover half the matrix).
-__host__ __device__ inline int band_route(int m, int n, int w, bool pack16, int smax_pos, int alpha, int beta,
-                                          bool *packed) {
+__host__ __device__ inline int band_route(int m, int n, int w, bool pack16, int smax_pos, int drop, int alpha,
+                                          int beta,                                          bool *packed) {
   const int B = n - m + 2 * w + 1;
   if (pack16) {
     const int pc = band16_class_for(B);
     if (pc >= 0 && 2 * band16_class_width(pc) < n &&
-        band16_range_ok(m, n, band16_class_width(pc), smax_pos, alpha, beta)) {
+        band16_range_ok(m, n, band16_class_width(pc), smax_pos, drop, alpha, beta)) {
       *packed = true;
       return pc;
     }
@@ -276,13 +283,13 @@ __device__ inline void band_requeue(const BandArgs &a, const PairDesc &d, int w,
   int w2 = w > 0 ? 2 * w : 1;
   bool packed = false;
   const bool p16 = a.pack16 && mode == kGlobal;
-  int c = band_route(d.m, d.n, w2, p16, a.smax_pos, a.alpha, a.beta, &packed);
+  int c = band_route(d.m, d.n, w2, p16, a.smax_pos, a.drop16, a.alpha, a.beta, &packed);
   if (c < 0) {
     const int Wmax = band_widest(d.n);
     const int wcap = (Wmax - (d.n - d.m) - 1) / 2;
     if (Wmax > W_cur && wcap > w) {
       w2 = wcap;
-      c = band_route(d.m, d.n, w2, p16, a.smax_pos, a.alpha, a.beta, &packed);
+      c = band_route(d.m, d.n, w2, p16, a.smax_pos, a.drop16, a.alpha, a.beta, &packed);
     }
   }
   if (a.round + 1 >= a.max_rounds || c < 0) {

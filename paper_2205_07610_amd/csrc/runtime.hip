@@ -32,6 +32,7 @@ constexpr int32_t kStatusArg = 16;                    // band wider than the wid
 struct RouteParams {
   int64_t n_pairs;
   int32_t mode, alpha, beta, smax_abs, smax_pos;
+  int32_t drop16;         // max(0, -(sigma_min + 2 beta)): the banded int16 range proof
   int32_t allow16;        // the scoring fits the packed kernel's byte profile
   int32_t long_w;         // stripe width of the wavefront kernel
   int32_t long_min_rows;  // automatic routing: rows needed for the wavefront
@@ -339,7 +340,7 @@ __global__ void __launch_bounds__(256) band_classify_kernel(RouteParams c, const
       return kc;
     }
     bool packed = false;
-    const int rc = band_route(bi.d.m, bi.d.n, w, pack16 != 0, c.smax_pos, c.alpha, c.beta, &packed);
+    const int rc = band_route(bi.d.m, bi.d.n, w, pack16 != 0, c.smax_pos, c.drop16, c.alpha, c.beta, &packed);
     if (rc < 0) return kFall;
     return packed ? kBandClasses + rc : rc;
   };
@@ -688,6 +689,7 @@ RouteParams route_params(const CallScoring &cs, int64_t n_pairs) {
   rp.beta = cs.beta;
   rp.smax_abs = cs.smax_abs;
   rp.smax_pos = cs.smax > 0 ? cs.smax : 0;
+  rp.drop16 = cs.smin + 2 * cs.beta < 0 ? -(cs.smin + 2 * cs.beta) : 0;
   rp.allow16 = cs.allow16;
   rp.long_w = long_dp_i32_stripe_width();
   rp.long_min_rows = 2048;
@@ -978,6 +980,7 @@ int asmi::band_call(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t 
   ba.lists16 = pack16 ? w->band16_lists : nullptr;
   ba.pack16 = pack16;
   ba.smax_pos = cs.smax > 0 ? cs.smax : 0;
+  ba.drop16 = cs.smin + 2 * cs.beta < 0 ? -(cs.smin + 2 * cs.beta) : 0;
   ba.list_cap = list_cap;
   ba.ctr = w->ctr;
   ba.qwords = w->qwords;

@@ -152,3 +152,36 @@ def test_packed_band_matches_32bit_and_oracle(gpu, oracle_mod):
             _say(f"packed={on} w0~{w0} rounds={rounds}: {st}")
             assert np.array_equal(res[on], want), (on, w0, np.nonzero(res[on] != want)[0][:5])
     gpu.set_band_packing(True)
+
+
+def test_packed_band_lower_range_harsh_scoring(gpu, oracle_mod):
+    """A scheme whose diagonal steps lose score in the shifted frame (sigma
+    + 2 beta < 0): banded cells of long pairs fall far below zero, so the
+    packed kernel's range proof must also bound them from below and send
+    the longest pairs to the 32-bit kernel.  Every score equals the
+    oracle's, with the packed kernel on and off."""
+    import torch
+    rng = np.random.default_rng(780)
+    sub = np.full((4, 4), -12, dtype=np.int8)
+    np.fill_diagonal(sub, 3)
+    alpha, beta = 12, 0
+    lens = [300, 900, 1500, 2300, 2900, 3600]
+    pairs = []
+    for L in lens:
+        for rel in (True, False):
+            a = rng.integers(0, 4, L).astype(np.uint8)
+            if rel:
+                sb, _ = synth.mutate(rng, a, np.array([0, L]), [0.08], [0.02], [0.02], 4)
+            else:
+                sb = rng.integers(0, 4, L + int(rng.integers(-40, 40))).astype(np.uint8)
+            pairs.append((a, sb))
+    bb = synth.from_pairs("harsh", pairs, sub, alpha, beta, 0)
+    want = oracle_mod.align_batch(bb.seqs_a, bb.offs_a, bb.seqs_b, bb.offs_b, sub, alpha, beta, 0)
+    dev = gpu.to_device(bb)
+    w = _w(torch, np.full(bb.n_pairs, 60))
+    for on in (True, False):
+        gpu.set_band_packing(on)
+        sc, st = gpu.align_batch_band(*dev, sub, alpha, beta, 0, w, max_rounds=4)
+        _say(f"harsh scoring packed={on}: {st}")
+        assert np.array_equal(sc.cpu().numpy(), want), (on, np.nonzero(sc.cpu().numpy() != want)[0])
+    gpu.set_band_packing(True)

@@ -36,7 +36,8 @@ def _t(x, dtype=None):
 
 def _feature_cases(rng):
     """Hand-shaped pairs (empty, short, identical, duplicated k-mers, a B
-    beyond the position cap) plus related and unrelated random pairs."""
+    beyond the position cap, sequences longer than one staging tile) plus
+    related and unrelated random pairs."""
     pairs = [([], []), ([0, 1, 2], [0, 1, 2]), ([1] * 50, []), ([2] * 7, [2] * 7)]
     a = rng.integers(0, 4, 300).tolist()
     pairs += [(a, a), (a, a + a), (a, a[40:]), (a[:100], rng.integers(0, 4, 20).tolist() + a)]
@@ -47,6 +48,13 @@ def _feature_cases(rng):
     far2[65_534:65_541] = [0, 1] * 3 + [0]
     far2[65_535:65_542] = [2] * 7
     pairs.append(([2] * 7, far2))
+    # sequences longer than the kernel's 8192-position staging tile: k-mers
+    # straddle tile edges in A and in B
+    long_a = rng.integers(0, 4, 17_000)
+    sl, ol = synth.mutate(rng, long_a.astype(np.uint8), np.array([0, len(long_a)]), [0.03], [0.01],
+                          [0.01], 4)
+    pairs.append((long_a.tolist(), sl.tolist()))
+    pairs.append((long_a[:9000].tolist(), long_a[8150:8400].tolist()))
     sa, oa, sb, ob = synth.random_small(rng, 400, 600, related=0.8)
     for p in range(400):
         pairs.append((sa[oa[p]:oa[p + 1]].tolist(), sb[ob[p]:ob[p + 1]].tolist()))
