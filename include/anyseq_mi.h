@@ -131,12 +131,14 @@ typedef struct {
  * on the requested one).  The banded score is accepted when it is at least
  * an upper bound on every alignment path that leaves the computed band
  * (closed form from the path structure of Eq. (1),(4),(5)); then it is the
- * optimal score.  Otherwise w doubles, for at most max_rounds rounds (1..8);
- * when the doubled band would fit no lane width (at most 1024 diagonals and
- * less than half the longer sequence) but a wider one than the last round's
- * exists, the pair takes the widest such band instead.  A pair with no wider
- * band left, or out of rounds, is aligned with the full DP.  Every returned
- * score is exact.
+ * optimal score.  Otherwise w doubles, for at most max_rounds rounds (1..8).
+ * A band is used only when some lane width holds it: at most 1024
+ * diagonals, and less than half the longer sequence (32-bit cells) or at
+ * most three quarters of it (packed 16-bit cells, global mode).  A request
+ * that no width holds -- the initial one, or a doubled one when a wider band
+ * than the last round's exists -- takes the widest band the pair allows
+ * instead.  A pair with no band left, or out of rounds, is aligned with the
+ * full DP.  Every returned score is exact.
  *   band_w0    : device, int32 [n_pairs], initial half-widths (< 0 read as 0)
  *   stats      : HOST, optional (NULL), filled on return
  * Local mode returns AS_ERR_ARG; alphabets above four letters, or scores

@@ -245,15 +245,22 @@ __host__ __device__ inline bool band16_range_ok(int m, int n, int W, int smax_po
   const int64_t lb = (int64_t)drop * mn + 3LL * (alpha - beta) + 256;
   return ub < 32000 && lb < 32000;
 }
+// Whether a band of W diagonals is worth computing for an n-column pair
+// instead of the full DP: a packed band at most 3/4 of the row (it costs
+// about 0.6 W / n of the 32-bit full DP per attempt), a 32-bit band less
+// than half of it.  Either way lo > -m and hi < n, so the band stays inside
+// the matrix's diagonals.
+__host__ __device__ inline bool band16_worth(int W, int n) { return 4 * W <= 3 * n; }
+__host__ __device__ inline bool band32_worth(int W, int n) { return 2 * W < n; }
 // Where a band request of half-width w for an m-row (shorter), n-column pair
 // goes: a packed class (*packed = true), a 32-bit class, or -1 for the full
-// DP (no class holds it, or the band would cover half the matrix).
+// DP (no class holds it, or it is not worth it).
 __host__ __device__ inline int band_route(int m, int n, int w, bool pack16, int smax_pos, int drop, int alpha,
-                                          int beta,                                          bool *packed) {
+                                          int beta, bool *packed) {
   const int B = n - m + 2 * w + 1;
   if (pack16) {
     const int pc = band16_class_for(B);
-    if (pc >= 0 && 2 * band16_class_width(pc) < n &&
+    if (pc >= 0 && band16_worth(band16_class_width(pc), n) &&
         band16_range_ok(m, n, band16_class_width(pc), smax_pos, drop, alpha, beta)) {
       *packed = true;
       return pc;
@@ -261,18 +268,30 @@ __host__ __device__ inline int band_route(int m, int n, int w, bool pack16, int 
   }
   *packed = false;
   const int kc = band_class_for(B);
-  if (kc < 0 || 2 * band_class_width(kc) >= n) return -1;
+  if (kc < 0 || !band32_worth(band_class_width(kc), n)) return -1;
   return kc;
 }
-// Widest band (diagonals) any class may hold for an m-row, n-column pair
-// (m <= n): the widest class with 2 W < n; 0 if none.
-__host__ __device__ inline int band_widest(int n) {
+// Widest band (diagonals) a class may hold for an m-row, n-column pair
+// (m <= n); 0 if none.
+__host__ __device__ inline int band_widest(int m, int n, bool pack16, int smax_pos, int drop, int alpha,
+                                           int beta) {
   int best = 0;
   for (int kc = 0; kc < kBandClasses; ++kc)
-    if (2 * band_class_width(kc) < n && band_class_width(kc) > best) best = band_class_width(kc);
-  for (int pc = 0; pc < kBand16Classes; ++pc)
-    if (2 * band16_class_width(pc) < n && band16_class_width(pc) > best) best = band16_class_width(pc);
+    if (band32_worth(band_class_width(kc), n) && band_class_width(kc) > best) best = band_class_width(kc);
+  if (pack16)
+    for (int pc = 0; pc < kBand16Classes; ++pc) {
+      const int W = band16_class_width(pc);
+      if (band16_worth(W, n) && W > best && band16_range_ok(m, n, W, smax_pos, drop, alpha, beta)) best = W;
+    }
   return best;
+}
+// Half-width of the widest band for the pair, or -1 when no band is worth it.
+__host__ __device__ inline int band_widest_w(int m, int n, bool pack16, int smax_pos, int drop, int alpha,
+                                             int beta, int *W_out) {
+  const int W = band_widest(m, n, pack16, smax_pos, drop, alpha, beta);
+  *W_out = W;
+  const int w = (W - (n - m) - 1) / 2;
+  return (W > 0 && W >= n - m + 1) ? w : -1;
 }
 // A rejected band (this round computed W_cur diagonals): queue the pair for
 // the next round with the half-width doubled.  When the doubled band fits no
@@ -285,8 +304,8 @@ __device__ inline void band_requeue(const BandArgs &a, const PairDesc &d, int w,
   const bool p16 = a.pack16 && mode == kGlobal;
   int c = band_route(d.m, d.n, w2, p16, a.smax_pos, a.drop16, a.alpha, a.beta, &packed);
   if (c < 0) {
-    const int Wmax = band_widest(d.n);
-    const int wcap = (Wmax - (d.n - d.m) - 1) / 2;
+    int Wmax = 0;
+    const int wcap = band_widest_w(d.m, d.n, p16, a.smax_pos, a.drop16, a.alpha, a.beta, &Wmax);
     if (Wmax > W_cur && wcap > w) {
       w2 = wcap;
       c = band_route(d.m, d.n, w2, p16, a.smax_pos, a.drop16, a.alpha, a.beta, &packed);

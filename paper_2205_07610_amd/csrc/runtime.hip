@@ -340,8 +340,15 @@ __global__ void __launch_bounds__(256) band_classify_kernel(RouteParams c, const
       return kc;
     }
     bool packed = false;
-    const int rc = band_route(bi.d.m, bi.d.n, w, pack16 != 0, c.smax_pos, c.drop16, c.alpha, c.beta, &packed);
-    if (rc < 0) return kFall;
+    int rc = band_route(bi.d.m, bi.d.n, w, pack16 != 0, c.smax_pos, c.drop16, c.alpha, c.beta, &packed);
+    if (rc < 0) {  // no class holds the request: start from the widest band instead
+      int Wmax = 0;
+      const int wcap = band_widest_w(bi.d.m, bi.d.n, pack16 != 0, c.smax_pos, c.drop16, c.alpha, c.beta, &Wmax);
+      if (wcap < 0) return kFall;
+      bi.w = wcap;
+      rc = band_route(bi.d.m, bi.d.n, wcap, pack16 != 0, c.smax_pos, c.drop16, c.alpha, c.beta, &packed);
+      if (rc < 0) return kFall;
+    }
     return packed ? kBandClasses + rc : rc;
   };
   for (int64_t p = lo + threadIdx.x; p < hi; p += blockDim.x) {
