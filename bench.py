@@ -203,6 +203,34 @@ def phase_roofline(phases, name, ops_per_cell):
     return r
 
 
+def own_label_cells(batch, labels, band_wide):
+    """DP cells if every pair were banded at its own label: the smallest
+    lane width holding the label's band, packed widths first where the
+    library would use them (global mode, range proof, at most 3/4 of the
+    row), else 32-bit widths (less than half the row), else the full DP."""
+    import numpy as np
+    la, lb = batch.lens_a.astype(np.int64), batch.lens_b.astype(np.int64)
+    rows, cols, dn = np.minimum(la, lb), np.maximum(la, lb), np.abs(la - lb)
+    need = dn + 2 * labels.astype(np.int64) + 1
+    smax_pos = max(int(batch.subst.max()), 0)
+    drop = max(0, -(int(batch.subst.min()) + 2 * batch.beta))
+    cells = la * lb
+    chosen = np.zeros(len(la), dtype=bool)
+    ok_label = labels < band_wide
+    if batch.mode == 0:
+        for W in (64, 96, 128, 192, 256, 384, 512, 768, 1024):
+            ub = smax_pos * rows + batch.beta * (la + lb + W) + batch.alpha + 2 * batch.beta + 256
+            lo = drop * rows + 3 * (batch.alpha - batch.beta) + 256
+            ok = ok_label & ~chosen & (need <= W) & (4 * W <= 3 * cols) & (ub < 32000) & (lo < 32000)
+            cells = np.where(ok, rows * W, cells)
+            chosen |= ok
+    for W in (64, 128, 192, 256, 384, 512, 768, 1024):
+        ok = ok_label & ~chosen & (need <= W) & (2 * W < cols)
+        cells = np.where(ok, rows * W, cells)
+        chosen |= ok
+    return int(cells.sum())
+
+
 def train_band_model(binding, torch, synth):
     """Labels and training on the training set; returns params and a summary."""
     t0 = time.perf_counter()
@@ -224,14 +252,7 @@ def train_band_model(binding, torch, synth):
     import numpy as np
     labels = binding.band_labels(*dev, train.subst, train.alpha, train.beta, train.mode).cpu().numpy()
     _, st = binding.align_batch_learned(*dev, train.subst, train.alpha, train.beta, train.mode, params)
-    la, lb = train.lens_a.astype(np.int64), train.lens_b.astype(np.int64)
-    rows, dn = np.minimum(la, lb), np.abs(la - lb)
-    widths = np.array([64, 128, 192, 256, 384, 512, 768, 1024])
-    need = dn + 2 * labels + 1
-    cls = np.searchsorted(widths, need)
-    fits = (labels < binding.BAND_WIDE) & (cls < len(widths))
-    fits &= 2 * widths[np.minimum(cls, len(widths) - 1)] < np.maximum(la, lb)
-    ideal = np.where(fits, rows * widths[np.minimum(cls, len(widths) - 1)], la * lb).sum()
+    ideal = own_label_cells(train, labels, binding.BAND_WIDE)
     del dev
     return params, {"pairs": train.n_pairs, "steps": TRAIN["steps"], "batch": TRAIN["batch"],
                     "lr": TRAIN["lr"], "tau": TRAIN["tau"], "gen_s": round(t_gen, 2),

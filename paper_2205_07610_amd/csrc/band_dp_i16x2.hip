@@ -13,15 +13,14 @@
 //    row, register x takes the selector of register x+1 and the last one
 //    takes lane t+1's register 1 (that lane runs one row behind) or, in the
 //    group's last lane, the selector of the column entering the band -- a
-//    rotation of the register names, free in the 16-step unrolled chunks;
-//    when K does not divide 16 the chunks come in K / gcd(K, 16)
-//    compile-time phases of the rotation.
-//  * Feeds through LDS: at the start of each 16-step chunk, lanes 0..15 of a
-//    group write the score words of the chunk's 16 new rows into a ring of
-//    128 rows (rows 0..15 mirrored past its end, so a lane's 16 reads of a
-//    chunk are contiguous and take the step from the instruction's offset)
-//    and the selectors of the 16 entering columns; the residues were loaded
-//    one chunk ahead.  A step then costs the cell updates, two LDS reads and
+//    rotation of the register names, free in the unrolled chunks of CH
+//    steps (32, or 24 / 48 when K is 6 or 12: CH is a multiple of K).
+//  * Feeds through LDS: at the start of each chunk the group's lanes write
+//    the score words of the chunk's CH new rows into a ring of rows (its
+//    first CH slots mirrored past its end, so a lane's CH reads of a chunk
+//    are contiguous and take the step from the instruction's offset) and
+//    the selectors of the CH entering columns; the residues were loaded one
+//    chunk ahead.  A step then costs the cell updates, two LDS reads and
 //    three DPP moves.
 //  * Values are stored with a bias of 32768 as unsigned 16-bit numbers, so 0
 //    is -infinity: DPP moves that shift in from outside the group write 0
@@ -47,7 +46,6 @@ namespace {
 typedef unsigned short u2 __attribute__((ext_vector_type(2)));
 
 constexpr int kBias = 32768;  // stored = shifted-frame value + kBias; 0 is -infinity
-constexpr int kRing = 128;    // rows held in a group's row-word ring
 
 __device__ __forceinline__ int as_i(u2 v) { return __builtin_bit_cast(int, v); }
 __device__ __forceinline__ u2 as_u2(int v) { return __builtin_bit_cast(u2, v); }
@@ -104,7 +102,10 @@ __device__ __forceinline__ uint32_t make_sel(uint32_t c0, uint32_t c1) {
   return c0 | 0x0C00u | (s1 << 16) | 0x0C000000u;
 }
 
-constexpr int gcd16(int k) { return k % 16 == 0 ? 16 : k % 8 == 0 ? 8 : k % 4 == 0 ? 4 : k % 2 == 0 ? 2 : 1; }
+// Steps per unrolled chunk: a multiple of K, so the selector rotation
+// returns to the identity at every chunk boundary (24 rather than 48 for
+// K = 6, 12 on 16-lane groups, whose registers are already scarce).
+constexpr int chunk_steps(int K, int G) { return 32 % K == 0 ? 32 : (G == kGroup ? 24 : 48); }
 
 // Waves per SIMD the register allocation aims for: four for the narrowest
 // class, three for the others (what the compiler would pick for the wider
@@ -117,13 +118,14 @@ template <int K, int G>
 __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(kWavesPerEu<K, G>)))
 band_dp_i16_kernel(BandArgs a, int pc) {
   constexpr int W = G * K;
-  // 16-step chunks come in NR phases of the selector rotation (K / gcd(K, 16))
-  constexpr int NR = K / gcd16(K);
-  static_assert(NR >= 1 && NR <= 3, "rotation phases");
-  static_assert(kRing >= G + 2 * kGroup, "the ring holds every row a chunk reads and the next chunk's");
+  constexpr int CH = chunk_steps(K, G);
+  static_assert(CH % K == 0, "the rotation must close over a chunk");
+  // rows a chunk reads span G + CH - 1; the next chunk's CH are written past them
+  constexpr int kRing = (G + 2 * CH <= 128) ? 128 : 256;
+  constexpr int NF = (CH + G - 1) / G;  // rows (and entering columns) each lane feeds per chunk
   constexpr int GPW = kWave / G;
-  __shared__ uint2 rq[GPW][kRing + kGroup];  // row words (low pair, high pair) by row mod kRing
-  __shared__ uint32_t sq[GPW][kGroup];       // selectors entering at the last lane, by step of the chunk
+  __shared__ uint2 rq[GPW][kRing + CH];  // row words (low pair, high pair) by row mod kRing
+  __shared__ uint32_t sq[GPW][CH];       // selectors entering at the last lane, by step of the chunk
   __shared__ uint32_t qt[8];                 // score word by (orientation, letter)
   const int lane = threadIdx.x;
   const int g = lane / G;
@@ -206,45 +208,53 @@ band_dp_i16_kernel(BandArgs a, int pc) {
     const int its_max = wave_max_groups<G>(its);
     // column entering the band at the group's last lane at step it
     constexpr int kEnter = W - G + 1;
-    // residues of the chunk starting at it0 (lanes t < 16): row it0 + 1 + t
-    // and the column entering at step it0 + t, loaded one chunk ahead
-    uint32_t rb0 = 0, rb1 = 0, cb0 = 0, cb1 = 0;
+    // residues of the chunk starting at it0, loaded one chunk ahead: lane t
+    // feeds steps s = t + G f (f < NF, s < CH), i.e. row it0 + 1 + s and the
+    // column entering at step it0 + s
+    uint32_t rb0[NF], rb1[NF], cb0[NF], cb1[NF];
     auto prefetch = [&](int it0) {
-      if (t < kGroup) {
-        rb0 = row_byte(rows0, m0, it0 + t);
-        rb1 = row_byte(rows1, m1, it0 + t);
-        cb0 = col_byte(cols0, n0, it0 + t + lo0 + kEnter);
-        cb1 = col_byte(cols1, n1, it0 + t + lo1 + kEnter);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        const int s = t + G * f;
+        if (s < CH) {
+          rb0[f] = row_byte(rows0, m0, it0 + s);
+          rb1[f] = row_byte(rows1, m1, it0 + s);
+          cb0[f] = col_byte(cols0, n0, it0 + s + lo0 + kEnter);
+          cb1[f] = col_byte(cols1, n1, it0 + s + lo1 + kEnter);
+        }
       }
     };
     auto feed = [&](int it0) {
-      if (t < kGroup) {
-        const int r = it0 + 1 + t;
-        uint2 v;
-        v.x = row_word(m0, tr0, r - 1, rb0);
-        v.y = row_word(m1, tr1, r - 1, rb1);
-        const int slot = r & (kRing - 1);
-        rq[g][slot] = v;
-        if (slot < kGroup) rq[g][slot + kRing] = v;
-        const int j0 = it0 + t + lo0 + kEnter, j1 = it0 + t + lo1 + kEnter;
-        sq[g][t] = make_sel(col_code(has0, n0, j0, cb0), col_code(has1, n1, j1, cb1));
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        const int s = t + G * f;
+        if (s < CH) {
+          const int r = it0 + 1 + s;
+          uint2 v;
+          v.x = row_word(m0, tr0, r - 1, rb0[f]);
+          v.y = row_word(m1, tr1, r - 1, rb1[f]);
+          const int slot = r & (kRing - 1);
+          rq[g][slot] = v;
+          if (slot < CH) rq[g][slot + kRing] = v;
+          const int j0 = it0 + s + lo0 + kEnter, j1 = it0 + s + lo1 + kEnter;
+          sq[g][s] = make_sel(col_code(has0, n0, j0, cb0[f]), col_code(has1, n1, j1, cb1[f]));
+        }
       }
       __builtin_amdgcn_wave_barrier();
     };
     prefetch(0);
-    // One chunk of 16 steps.  FILL: the pipeline is still filling (some
-    // lane's row is <= 0); only the first G / 16 chunks need the test.
-    // EXT: some lane reaches a pair's last row in this chunk.  R0: the
-    // rotation phase (16 c mod K for chunk c).
-    auto chunk = [&](int it0, auto fill_tag, auto ext_tag, auto r0_tag) __attribute__((always_inline)) {
+    // One chunk of CH steps.  FILL: the pipeline is still filling (some
+    // lane's row is <= 0); only the chunks starting before step G need the
+    // test.  EXT: some lane reaches a pair's last row in this chunk.
+    auto chunk = [&](int it0, auto fill_tag, auto ext_tag) __attribute__((always_inline)) {
       constexpr bool FILL = decltype(fill_tag)::value;
       constexpr bool EXT = decltype(ext_tag)::value;
-      constexpr int R0 = decltype(r0_tag)::value;
+      constexpr int R0 = 0;
       feed(it0);
-      prefetch(it0 + kGroup);
+      prefetch(it0 + CH);
       const uint2 *rrow = &rq[g][(it0 + 1 - t) & (kRing - 1)];
 #pragma unroll
-      for (int u = 0; u < kGroup; ++u) {
+      for (int u = 0; u < CH; ++u) {
         const int row = it0 + u + 1 - t;
         // this row's selectors: the register names rotate by one, and the
         // last register takes lane t+1's register 1 of the previous step --
@@ -301,20 +311,13 @@ band_dp_i16_kernel(BandArgs a, int pc) {
       __builtin_amdgcn_wave_barrier();  // this chunk's LDS reads stay before the next feed
     };
     auto ends_in = [&](int it0) -> bool {
-      return __builtin_amdgcn_ballot_w64((e0 >= it0 && e0 < it0 + kGroup) ||
-                                         (e1 >= it0 && e1 < it0 + kGroup)) != 0;
+      return __builtin_amdgcn_ballot_w64((e0 >= it0 && e0 < it0 + CH) || (e1 >= it0 && e1 < it0 + CH)) != 0;
     };
-    auto phase = [&](int it0, int c, auto fill_tag, auto ext_tag) __attribute__((always_inline)) {
-      const int ph = NR == 1 ? 0 : c % NR;
-      if (ph == 0) chunk(it0, fill_tag, ext_tag, std::integral_constant<int, 0>{});
-      else if (NR > 1 && ph == 1) chunk(it0, fill_tag, ext_tag, std::integral_constant<int, kGroup % K>{});
-      else if (NR > 2) chunk(it0, fill_tag, ext_tag, std::integral_constant<int, (2 * kGroup) % K>{});
-    };
-    int it0 = 0, c = 0;
-    for (; it0 < its_max && it0 < G; it0 += kGroup, ++c) phase(it0, c, std::true_type{}, std::true_type{});
-    for (; it0 < its_max; it0 += kGroup, ++c) {
-      if (ends_in(it0)) phase(it0, c, std::false_type{}, std::true_type{});
-      else phase(it0, c, std::false_type{}, std::false_type{});
+    int it0 = 0;
+    for (; it0 < its_max && it0 < G; it0 += CH) chunk(it0, std::true_type{}, std::true_type{});
+    for (; it0 < its_max; it0 += CH) {
+      if (__builtin_expect(ends_in(it0), 0)) chunk(it0, std::false_type{}, std::true_type{});
+      else chunk(it0, std::false_type{}, std::false_type{});
     }
 
     const int score0 = group_max<G>(res0), score1 = group_max<G>(res1);
