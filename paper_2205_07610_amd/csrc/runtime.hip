@@ -526,6 +526,8 @@ __global__ void __launch_bounds__(256) fill_kernel(int32_t *p, int64_t n, int32_
     p[i] = v;
 }
 
+constexpr int kSideStreams = 3;
+
 struct Workspace {
   int device = -1;
   int num_cu = 0;
@@ -559,6 +561,10 @@ struct Workspace {
   int32_t *tune_scores = nullptr;  // scores written by autotuning runs
   int64_t tune_scores_cap = 0;
   hipEvent_t ev[16] = {};
+  // side streams of the banded rounds (default priority): one round's class
+  // launches run on them concurrently, so a launch's tail overlaps the next
+  hipStream_t side[kSideStreams] = {};
+  hipEvent_t side_ev[kSideStreams + 1] = {};
 };
 
 bool g_timing = false;
@@ -588,6 +594,8 @@ int init_workspace(Workspace &w, int dev) {
   AS_HIP(hipMalloc(&w.qwords, 2 * 32 * sizeof(uint32_t)));
   AS_HIP(hipMalloc(&w.sort_hist, kBandLists * kSortBuckets * sizeof(int32_t)));
   for (auto &e : w.ev) AS_HIP(hipEventCreate(&e));
+  for (auto &st : w.side) AS_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  for (auto &e : w.side_ev) AS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   w.device = dev;
   return AS_OK;
 }
@@ -600,6 +608,10 @@ void free_workspace(Workspace &w) {
     if (b) (void)hipFree(b);
   if (w.host_ctr) (void)hipHostFree(w.host_ctr);
   for (auto &e : w.ev)
+    if (e) (void)hipEventDestroy(e);
+  for (auto &st : w.side)
+    if (st) (void)hipStreamDestroy(st);
+  for (auto &e : w.side_ev)
     if (e) (void)hipEventDestroy(e);
   w = Workspace();
 }
@@ -928,6 +940,53 @@ extern "C" int as_align_batch(const uint8_t *seqs_a, const int64_t *offs_a, cons
   return run_full_lists(w, cs, seqs_a, seqs_b, scores_out, stream, timing, c);
 }
 
+// One round's class launches of one kernel family (packed or 32-bit), largest
+// work (pairs x width) first, spread over the side streams and joined back
+// into `stream`: every launch is persistent and fills the GPU, so running
+// them concurrently lets the next one take over the slots that a finishing
+// launch's last waves leave idle.
+int launch_band_round(Workspace *w, const BandArgs &ba, int mode, const Counters &c, int cur, bool packed,
+                      hipStream_t stream) {
+  struct Launch {
+    int cls;
+    int64_t work, grid;
+  };
+  Launch ls[kBandLists];
+  int nl = 0;
+  const int ncls = packed ? kBand16Classes : kBandClasses;
+  for (int k = 0; k < ncls; ++k) {
+    const int cnt = packed ? c.n_band16[cur][k] : c.n_band[cur][k];
+    if (!cnt) continue;
+    const int width = packed ? band16_class_width(k) : band_class_width(k);
+    int64_t grid = (int64_t)(packed ? band_dp_i16_blocks_per_cu(k) : band_dp_i32_blocks_per_cu(mode, k)) *
+                   w->num_cu;
+    const int ppw = packed ? band_dp_i16_pairs_per_wave(k) : band_dp_i32_pairs_per_wave(k);
+    const int64_t need = ((int64_t)cnt + ppw - 1) / ppw;
+    if (grid > need) grid = need;
+    Launch l{k, (int64_t)cnt * width, grid};
+    int i = nl++;
+    while (i > 0 && ls[i - 1].work < l.work) {
+      ls[i] = ls[i - 1];
+      --i;
+    }
+    ls[i] = l;
+  }
+  if (!nl) return AS_OK;
+  const int ns = nl < kSideStreams ? nl : kSideStreams;
+  AS_HIP(hipEventRecord(w->side_ev[kSideStreams], stream));
+  for (int i = 0; i < ns; ++i) AS_HIP(hipStreamWaitEvent(w->side[i], w->side_ev[kSideStreams], 0));
+  for (int i = 0; i < nl; ++i) {
+    hipStream_t st = w->side[i % ns];
+    if (packed) AS_HIP(launch_band_dp_i16(ls[i].cls, ba, (int)ls[i].grid, st));
+    else AS_HIP(launch_band_dp_i32(mode, ls[i].cls, ba, (int)ls[i].grid, st));
+  }
+  for (int i = 0; i < ns; ++i) {
+    AS_HIP(hipEventRecord(w->side_ev[i], w->side[i]));
+    AS_HIP(hipStreamWaitEvent(stream, w->side_ev[i], 0));
+  }
+  return AS_OK;
+}
+
 // Banded entry points share everything up to the rounds.
 int asmi::band_call(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t *seqs_b,
                     const int64_t *offs_b, int64_t n_pairs, const as_scoring *scoring, int32_t mode,
@@ -1036,25 +1095,9 @@ int asmi::band_call(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t 
                        w->band_sorted);
     AS_HIP(hipGetLastError());
     if (timing) AS_HIP(hipEventRecord(w->ev[10], stream));
-    for (int pc = 0; pc < kBand16Classes; ++pc) {
-      const int cnt = c.n_band16[cur][pc];
-      if (!cnt) continue;
-      int64_t grid = (int64_t)band_dp_i16_blocks_per_cu(pc) * w->num_cu;
-      const int ppw = band_dp_i16_pairs_per_wave(pc);
-      const int64_t need = ((int64_t)cnt + ppw - 1) / ppw;
-      if (grid > need) grid = need;
-      AS_HIP(launch_band_dp_i16(pc, ba, (int)grid, stream));
-    }
+    if ((rc = launch_band_round(w, ba, mode, c, cur, true, stream))) return rc;
     if (timing) AS_HIP(hipEventRecord(w->ev[12], stream));
-    for (int kc = 0; kc < kBandClasses; ++kc) {
-      const int cnt = c.n_band[cur][kc];
-      if (!cnt) continue;
-      int64_t grid = (int64_t)band_dp_i32_blocks_per_cu(mode, kc) * w->num_cu;
-      const int ppw = band_dp_i32_pairs_per_wave(kc);
-      const int64_t need = ((int64_t)cnt + ppw - 1) / ppw;
-      if (grid > need) grid = need;
-      AS_HIP(launch_band_dp_i32(mode, kc, ba, (int)grid, stream));
-    }
+    if ((rc = launch_band_round(w, ba, mode, c, cur, false, stream))) return rc;
     if (timing) AS_HIP(hipEventRecord(w->ev[11], stream));
     // this round's lists are consumed: clear their counters and work pointers
     AS_HIP(hipMemsetAsync(&w->ctr->n_band[cur][0], 0, sizeof(int32_t) * kBandClasses, stream));
