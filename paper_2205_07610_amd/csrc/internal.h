@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #include "anyseq_mi.h"
@@ -73,6 +74,11 @@ constexpr int kBandClasses = 8;
 constexpr int kBand16Classes = 9;
 constexpr int kMaxBandRounds = 8;
 
+// Cost classes of the 32-bit full-DP list inside a length bin: 8 per
+// halving of stripes x (rows + 15) below the bin's largest cost.  The list
+// is ordered by them, so the four pairs of a wave cost about the same.
+constexpr int kCostClasses = 64;
+
 // Work-list counters written by the classify kernel.
 struct Counters {
   int32_t n_full32;      // items queued for the 32-bit full DP
@@ -106,7 +112,14 @@ struct Counters {
   int32_t bin_var32[kLenBins];   // 32-bit variant of each bin
   int32_t kmask32;               // K variants present in the 32-bit list
   unsigned long long bin_cells[kLenBins];  // sum of m*n of the routed pairs per bin
+  // The 32-bit list inside each length bin, by cost class (largest first):
+  // counts, offsets and scatter cursors.  Device-only: the host reads back
+  // the counters up to kCountersHead.
+  int32_t cost_count[kLenBins][kCostClasses];
+  int32_t cost_base[kLenBins][kCostClasses];
+  int32_t cost_cursor[kLenBins][kCostClasses];
 };
+constexpr size_t kCountersHead = offsetof(Counters, cost_count);
 
 // ---- banded path ----
 // Band widths (diagonals) of the banded kernel's classes: 16-lane groups

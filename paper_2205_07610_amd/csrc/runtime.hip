@@ -163,11 +163,23 @@ __device__ inline int64_t source_count(const RouteParams &c, const PairDesc *src
 
 // Classification, step 1 of 3: per (list, length bin) counts, cells, the
 // 32-bit variant of every bin and the longest multi-stripe row count.
+// Cost class of a 32-bit list item inside its length bin (0 = costliest).
+__device__ inline int cost_class(const PairDesc &d, int bin) {
+  const int ws = kGroup * variant_k(variant_of(d.flags));  // stripe width
+  const float longer = (float)(64 << bin);                  // the bin's longest side
+  const float cmax = ceilf(longer / (float)ws) * (longer + 15.f);
+  const float cost = (float)((d.n + ws - 1) / ws) * (float)(d.m + 15);
+  const int c = (int)(8.f * log2f(cmax / cost));
+  return c < 0 ? 0 : (c >= kCostClasses ? kCostClasses - 1 : c);
+}
+
 __global__ void __launch_bounds__(256) route_count_kernel(RouteParams c, const int64_t *offs_a,
                                                           const int64_t *offs_b, const PairDesc *src,
                                                           Counters *ctr, int32_t *scores) {
   constexpr int R = kLists * kLenBins;
+  constexpr int RC = kLenBins * kCostClasses;
   __shared__ int cnt[R];
+  __shared__ int ccnt[RC];
   __shared__ unsigned long long rcells[kLists];
   __shared__ unsigned long long bcells[kLenBins];
   __shared__ unsigned long long cells_sh;
@@ -176,6 +188,7 @@ __global__ void __launch_bounds__(256) route_count_kernel(RouteParams c, const i
   const int64_t lo = (int64_t)blockIdx.x * chunk;
   const int64_t hi = lo + chunk < total ? lo + chunk : total;
   for (int r = threadIdx.x; r < R; r += blockDim.x) cnt[r] = 0;
+  for (int r = threadIdx.x; r < RC; r += blockDim.x) ccnt[r] = 0;
   if (threadIdx.x < kLists) rcells[threadIdx.x] = 0;
   if (threadIdx.x < kLenBins) bcells[threadIdx.x] = 0;
   if (threadIdx.x == 0) cells_sh = 0;
@@ -194,6 +207,7 @@ __global__ void __launch_bounds__(256) route_count_kernel(RouteParams c, const i
     atomicAdd(&rcells[l], (unsigned long long)(m * n));
     atomicAdd(&bcells[bin], (unsigned long long)(m * n));
     if (l == kList32) {
+      atomicAdd(&ccnt[bin * kCostClasses + cost_class(d, bin)], 1);
       ctr->bin_var32[bin] = variant_of(d.flags);  // the same for every pair of the bin
       if (d.n > kGroup * variant_k(variant_of(d.flags))) atomicMax(&ctr->max_rows_multi, d.m);
     }
@@ -202,6 +216,8 @@ __global__ void __launch_bounds__(256) route_count_kernel(RouteParams c, const i
   __syncthreads();
   for (int r = threadIdx.x; r < R; r += blockDim.x)
     if (cnt[r]) atomicAdd(&ctr->bin_count[r / kLenBins][r % kLenBins], cnt[r]);
+  for (int r = threadIdx.x; r < RC; r += blockDim.x)
+    if (ccnt[r]) atomicAdd(&ctr->cost_count[r / kCostClasses][r % kCostClasses], ccnt[r]);
   if (threadIdx.x < kLists && rcells[threadIdx.x])
     atomicAdd(&ctr->route_cells[threadIdx.x], rcells[threadIdx.x]);
   if (threadIdx.x < kLenBins && bcells[threadIdx.x])
@@ -215,30 +231,45 @@ __global__ void __launch_bounds__(256) route_count_kernel(RouteParams c, const i
 // 32-bit bins are padded to whole quads (a wave never mixes variants) with
 // items of pair -1.  Capacities (0 = unchecked) guard a planned replay: a
 // batch that would overflow the plan's boundary buffer is refused.
-__global__ void route_scan_kernel(Counters *ctr, PairDesc *items32, int64_t bnd_rows_cap) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ void __launch_bounds__(kWave) route_scan_kernel(Counters *ctr, PairDesc *items32,
+                                                            int64_t bnd_rows_cap) {
+  static_assert(kCostClasses == kWave, "one lane per cost class");
+  if (blockIdx.x != 0) return;
+  const int lane = threadIdx.x;
   int kmask = 0;
   for (int l = 0; l < kLists; ++l) {
     int base = 0;
     for (int b = kLenBins - 1; b >= 0; --b) {
-      ctr->bin_base[l][b] = base;
+      if (lane == 0) ctr->bin_base[l][b] = base;
       int cnt = ctr->bin_count[l][b];
       if (l == kList32 && cnt > 0) {
+        // cost classes of the bin, costliest first (a prefix sum over the lanes)
+        const int c = ctr->cost_count[b][lane];
+        int incl = c;
+#pragma unroll
+        for (int dd = 1; dd < kWave; dd <<= 1) {
+          const int y = __shfl_up(incl, dd);
+          if (lane >= dd) incl += y;
+        }
+        ctr->cost_base[b][lane] = base + incl - c;
         const int padded = (cnt + kGroupsPerWave - 1) / kGroupsPerWave * kGroupsPerWave;
         const int v = ctr->bin_var32[b];
-        for (int k = cnt; k < padded; ++k) {
+        if (lane < padded - cnt) {
           PairDesc d{0, 0, 0, 0, -1, with_variant(0, v)};
-          items32[base + k] = d;
+          items32[base + cnt + lane] = d;
         }
         kmask |= kmask_of_variant(v);
         cnt = padded;
       }
       base += cnt;
     }
-    if (l == kList16) ctr->n_full16 = base;
-    else if (l == kList32) ctr->n_full32 = base;
-    else ctr->n_long = base;
+    if (lane == 0) {
+      if (l == kList16) ctr->n_full16 = base;
+      else if (l == kList32) ctr->n_full32 = base;
+      else ctr->n_long = base;
+    }
   }
+  if (lane != 0) return;
   ctr->kmask32 = kmask;
   if (bnd_rows_cap > 0 && ctr->n_full32 > 0 && (int64_t)ctr->max_rows_multi + 1 > bnd_rows_cap) {
     atomicOr(&ctr->status, kStatusPlan);
@@ -253,14 +284,18 @@ __global__ void __launch_bounds__(256) route_scatter_kernel(RouteParams c, const
                                                             PairDesc *items16, PairDesc *items32,
                                                             LongItem *items_long, Counters *ctr) {
   constexpr int R = kLists * kLenBins;
+  constexpr int RC = kLenBins * kCostClasses;
   __shared__ int cnt[R];
   __shared__ int base[R];
+  __shared__ int ccnt[RC];
+  __shared__ int cbase[RC];
   if (ctr->status & kStatusPlan) return;
   const int64_t total = source_count(c, src, ctr);
   const int64_t chunk = (total + gridDim.x - 1) / gridDim.x;
   const int64_t lo = (int64_t)blockIdx.x * chunk;
   const int64_t hi = lo + chunk < total ? lo + chunk : total;
   for (int r = threadIdx.x; r < R; r += blockDim.x) cnt[r] = 0;
+  for (int r = threadIdx.x; r < RC; r += blockDim.x) ccnt[r] = 0;
   __syncthreads();
   for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
     int64_t a0, m, b0, n, p;
@@ -268,13 +303,19 @@ __global__ void __launch_bounds__(256) route_scatter_kernel(RouteParams c, const
     PairDesc d;
     int bin;
     const int l = route_pair(c, a0, m, b0, n, p, d, bin);
-    if (l >= 0) atomicAdd(&cnt[l * kLenBins + bin], 1);
+    if (l == kList32) atomicAdd(&ccnt[bin * kCostClasses + cost_class(d, bin)], 1);
+    else if (l >= 0) atomicAdd(&cnt[l * kLenBins + bin], 1);
   }
   __syncthreads();
   for (int r = threadIdx.x; r < R; r += blockDim.x) {
     const int l = r / kLenBins, b = r % kLenBins;
     base[r] = cnt[r] ? ctr->bin_base[l][b] + atomicAdd(&ctr->bin_cursor[l][b], cnt[r]) : 0;
     cnt[r] = 0;
+  }
+  for (int r = threadIdx.x; r < RC; r += blockDim.x) {
+    const int b = r / kCostClasses, k = r % kCostClasses;
+    cbase[r] = ccnt[r] ? ctr->cost_base[b][k] + atomicAdd(&ctr->cost_cursor[b][k], ccnt[r]) : 0;
+    ccnt[r] = 0;
   }
   __syncthreads();
   for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
@@ -284,10 +325,14 @@ __global__ void __launch_bounds__(256) route_scatter_kernel(RouteParams c, const
     int bin;
     const int l = route_pair(c, a0, m, b0, n, p, d, bin);
     if (l < 0) continue;
+    if (l == kList32) {
+      const int r = bin * kCostClasses + cost_class(d, bin);
+      items32[cbase[r] + atomicAdd(&ccnt[r], 1)] = d;
+      continue;
+    }
     const int r = l * kLenBins + bin;
     const int slot = base[r] + atomicAdd(&cnt[r], 1);
-    if (l == kList32) items32[slot] = d;
-    else if (l == kList16) items16[slot] = d;
+    if (l == kList16) items16[slot] = d;
     else items_long[slot].d = d;
   }
 }
@@ -650,7 +695,7 @@ int status_to_code(int32_t st) {
 }
 
 int read_counters(Workspace *w, hipStream_t stream, Counters *c) {
-  AS_HIP(hipMemcpyAsync(w->host_ctr, w->ctr, sizeof(Counters), hipMemcpyDeviceToHost, stream));
+  AS_HIP(hipMemcpyAsync(w->host_ctr, w->ctr, kCountersHead, hipMemcpyDeviceToHost, stream));
   AS_HIP(hipStreamSynchronize(stream));
   *c = *w->host_ctr;
   return AS_OK;
@@ -1260,7 +1305,7 @@ int enqueue_plan(PlanImpl &P, hipStream_t stream) {
     const int grid_r = full_dp_i32_blocks_per_cu(mode, cs.asz, kmask_of_variant(kVarI32K16)) * w->num_cu;
     AS_HIP(launch_full_dp_i32(mode, args, kmask_of_variant(kVarI32K16), grid_r, stream));
   }
-  AS_HIP(hipMemcpyAsync(w->host_ctr, w->ctr, sizeof(Counters), hipMemcpyDeviceToHost, stream));
+  AS_HIP(hipMemcpyAsync(w->host_ctr, w->ctr, kCountersHead, hipMemcpyDeviceToHost, stream));
   return AS_OK;
 }
 
