@@ -74,10 +74,13 @@ constexpr int kBandClasses = 8;
 constexpr int kBand16Classes = 9;
 constexpr int kMaxBandRounds = 8;
 
-// Cost classes of the 32-bit full-DP list inside a length bin: 8 per
-// halving of stripes x (rows + 15) below the bin's largest cost.  The list
-// is ordered by them, so the four pairs of a wave cost about the same.
-constexpr int kCostClasses = 64;
+// Cost classes of the 32-bit full-DP list inside a length bin: 8 classes of
+// stripe count by 16 of row count, most stripes and rows first.  A wave's
+// four pairs run their stripes in lockstep, each as long as the longest
+// pair's, so the list is ordered by both, not by their product.
+constexpr int kStripeClasses = 8;
+constexpr int kRowClasses = 16;
+constexpr int kCostClasses = kStripeClasses * kRowClasses;
 
 // Work-list counters written by the classify kernel.
 struct Counters {

@@ -163,14 +163,19 @@ __device__ inline int64_t source_count(const RouteParams &c, const PairDesc *src
 
 // Classification, step 1 of 3: per (list, length bin) counts, cells, the
 // 32-bit variant of every bin and the longest multi-stripe row count.
-// Cost class of a 32-bit list item inside its length bin (0 = costliest).
+// Cost class of a 32-bit list item inside its length bin (0 = costliest):
+// stripe class (exact up to 8 stripes, else 8 even ranges) by row class (16
+// even ranges of the bin's longest side).
 __device__ inline int cost_class(const PairDesc &d, int bin) {
   const int ws = kGroup * variant_k(variant_of(d.flags));  // stripe width
-  const float longer = (float)(64 << bin);                  // the bin's longest side
-  const float cmax = ceilf(longer / (float)ws) * (longer + 15.f);
-  const float cost = (float)((d.n + ws - 1) / ws) * (float)(d.m + 15);
-  const int c = (int)(8.f * log2f(cmax / cost));
-  return c < 0 ? 0 : (c >= kCostClasses ? kCostClasses - 1 : c);
+  const int64_t longer = (int64_t)64 << bin;                // the bin's longest side
+  const int64_t smax = (longer + ws - 1) / ws;
+  int64_t st = smax - ((int64_t)d.n + ws - 1) / ws;         // 0 = most stripes
+  if (smax > kStripeClasses) st = st * kStripeClasses / smax;
+  st = st < 0 ? 0 : (st >= kStripeClasses ? kStripeClasses - 1 : st);
+  int64_t rc = kRowClasses - 1 - (int64_t)d.m * kRowClasses / (longer + 1);  // 0 = most rows
+  rc = rc < 0 ? 0 : (rc >= kRowClasses ? kRowClasses - 1 : rc);
+  return (int)(st * kRowClasses + rc);
 }
 
 __global__ void __launch_bounds__(256) route_count_kernel(RouteParams c, const int64_t *offs_a,
@@ -233,7 +238,7 @@ __global__ void __launch_bounds__(256) route_count_kernel(RouteParams c, const i
 // batch that would overflow the plan's boundary buffer is refused.
 __global__ void __launch_bounds__(kWave) route_scan_kernel(Counters *ctr, PairDesc *items32,
                                                             int64_t bnd_rows_cap) {
-  static_assert(kCostClasses == kWave, "one lane per cost class");
+  static_assert(kCostClasses == 2 * kWave, "two cost classes per lane");
   if (blockIdx.x != 0) return;
   const int lane = threadIdx.x;
   int kmask = 0;
@@ -243,15 +248,18 @@ __global__ void __launch_bounds__(kWave) route_scan_kernel(Counters *ctr, PairDe
       if (lane == 0) ctr->bin_base[l][b] = base;
       int cnt = ctr->bin_count[l][b];
       if (l == kList32 && cnt > 0) {
-        // cost classes of the bin, costliest first (a prefix sum over the lanes)
-        const int c = ctr->cost_count[b][lane];
-        int incl = c;
+        // cost classes of the bin, costliest first (a prefix sum over the
+        // lanes, lane j holding classes 2j and 2j + 1)
+        const int c0 = ctr->cost_count[b][2 * lane], c1 = ctr->cost_count[b][2 * lane + 1];
+        int incl = c0 + c1;
 #pragma unroll
         for (int dd = 1; dd < kWave; dd <<= 1) {
           const int y = __shfl_up(incl, dd);
           if (lane >= dd) incl += y;
         }
-        ctr->cost_base[b][lane] = base + incl - c;
+        const int first = base + incl - c0 - c1;
+        ctr->cost_base[b][2 * lane] = first;
+        ctr->cost_base[b][2 * lane + 1] = first + c0;
         const int padded = (cnt + kGroupsPerWave - 1) / kGroupsPerWave * kGroupsPerWave;
         const int v = ctr->bin_var32[b];
         if (lane < padded - cnt) {
