@@ -84,18 +84,15 @@ __device__ __forceinline__ uint32_t make_sel(int c0, int c1) {
   return s0 | 0x0C00u | (s1 << 16) | 0x0C000000u;
 }
 
-template <int MODE>
-__device__ __forceinline__ uint32_t profile_word(const FullDp16Args &a, const uint8_t *cols, int n,
-                                                 bool tr, int j, int bias, int pad_val, int &bad) {
-  if (j < 1 || j > n) return (uint32_t)(pad_val & 0xFF) * 0x01010101u;
+// Profile word of column j: byte c = sigma(c, s_j) + bias for the row
+// letters c, from the per-orientation table ptab (one word per column
+// letter); padding columns hold pad_val in every byte.
+__device__ __forceinline__ uint32_t profile_word(const uint32_t *ptab, const uint8_t *cols, int n, bool tr,
+                                                 int j, int asz, uint32_t pad_word, int &bad) {
+  if (j < 1 || j > n) return pad_word;
   int s = cols[j - 1];
-  if (s >= a.asz) { bad = 1; s = 0; }
-  uint32_t w = 0;
-  for (int c = 0; c < a.asz; ++c) {
-    const int sv = tr ? a.subst[s * a.asz + c] : a.subst[c * a.asz + s];
-    w |= (uint32_t)((sv + bias) & 0xFF) << (8 * c);
-  }
-  return w;
+  if (s >= asz) { bad = 1; s = 0; }
+  return ptab[(tr ? 4 : 0) + s];
 }
 
 template <int MODE, int K>
@@ -112,6 +109,20 @@ __global__ void __launch_bounds__(kWave) full_dp_i16_kernel(FullDp16Args a) {
   const s2 beta2 = pk(beta, beta);
   const s2 alpha2 = pk(alpha, alpha);
   const s2 amb2 = pk(amb, amb);
+  const uint32_t pad_word = (uint32_t)(pad_val & 0xFF) * 0x01010101u;
+  // profile words by (orientation, column letter): at most 4 letters here
+  __shared__ uint32_t ptab[8];
+  if (lane < 8) {
+    const int o = lane >> 2, sl = lane & 3;
+    uint32_t w = 0;
+    if (sl < asz)
+      for (int c = 0; c < asz; ++c) {
+        const int sv = o ? a.subst[sl * asz + c] : a.subst[c * asz + sl];
+        w |= (uint32_t)((sv + bias) & 0xFF) << (8 * c);
+      }
+    ptab[lane] = w;
+  }
+  __syncthreads();
 
   for (;;) {
     int base = 0;
@@ -142,8 +153,8 @@ __global__ void __launch_bounds__(kWave) full_dp_i16_kernel(FullDp16Args a) {
 #pragma unroll
     for (int x = 0; x < K; ++x) {
       const int jp = t * K + x + 1;
-      Plo[x] = profile_word<MODE>(a, cols0, n0, tr0, jp - P0, bias, pad_val, bad);
-      Phi[x] = profile_word<MODE>(a, cols1, n1, tr1, jp - P1, bias, pad_val, bad);
+      Plo[x] = profile_word(ptab, cols0, n0, tr0, jp - P0, asz, pad_word, bad);
+      Phi[x] = profile_word(ptab, cols1, n1, tr1, jp - P1, asz, pad_word, bad);
     }
 
     // ---- row-0 state ----
