@@ -189,34 +189,42 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4
           stage_pack(nk + kK - 1, xa, bufA, bad);
           __syncthreads();
         }
-        const int64_t i_first = i0 + threadIdx.x;
-        int64_t eq = i_first * dabs / m, er = i_first * dabs % m;
-        // every lane of a wave runs the same number of iterations (the wave
-        // aggregates its histogram updates); lanes past the tile add nothing
-        const int iters = (nk + kThreads - 1) / kThreads;
-        for (int r = 0; r < iters; ++r) {
-          const int q = threadIdx.x + r * kThreads;
-          int bin = -1;
-          if (q < nk) {
-            const int64_t i = i0 + q;
-            const uint32_t e = tab[kmer_at(bufA, q)];
-            if ((e & kGenMask) == tag && !(e & kDupBit)) {
-              const int64_t j = (int64_t)(e & kPosMask) - 1;
-              const int64_t delta = (j - i) - (n >= m ? eq : -eq);
-              const int64_t ad = delta < 0 ? -delta : delta;
-              int b = 63 - __clzll((unsigned long long)(ad + 1));
-              b = b < 14 ? b : 14;
-              bin = delta >= 0 ? 15 + b : 14 - b;
+        // the lookups of this tile; T = int when every position, shift and
+        // shift step fits 30 bits (always in practice), else int64_t
+        auto lookups = [&](auto zero) {
+          using T = decltype(zero);
+          const T i_first = (T)(i0 + threadIdx.x);
+          T eq = (T)(((int64_t)i_first * dabs) / m), er = (T)(((int64_t)i_first * dabs) % m);
+          const T tsq = (T)sq, tsr = (T)sr, tm = (T)m, ti0 = (T)i0;
+          const bool wide = n >= m;
+          // every lane of a wave runs the same number of iterations (the wave
+          // aggregates its histogram updates); lanes past the tile add nothing
+          const int iters = (nk + kThreads - 1) / kThreads;
+          for (int r = 0; r < iters; ++r) {
+            const int q = threadIdx.x + r * kThreads;
+            int bin = -1;
+            if (q < nk) {
+              const uint32_t e = tab[kmer_at(bufA, q)];
+              if ((e & kGenMask) == tag && !(e & kDupBit)) {
+                const T j = (T)(e & kPosMask) - 1;
+                const T delta = (j - (ti0 + q)) - (wide ? eq : -eq);
+                const T ad = delta < 0 ? -delta : delta;
+                int b = sizeof(T) == 4 ? 31 - __clz((int)(ad + 1)) : 63 - __clzll((long long)(ad + 1));
+                b = b < 14 ? b : 14;
+                bin = delta >= 0 ? 15 + b : 14 - b;
+              }
+            }
+            wave_hist_add(h, bin);
+            eq += tsq;
+            er += tsr;
+            if (er >= tm) {
+              er -= tm;
+              ++eq;
             }
           }
-          wave_hist_add(h, bin);
-          eq += sq;
-          er += sr;
-          if (er >= m) {
-            er -= m;
-            ++eq;
-          }
-        }
+        };
+        if (m < (1 << 30) && n < (1 << 30) && sq < (1 << 30)) lookups(0);
+        else lookups((int64_t)0);
       }
     }
     __syncthreads();  // the histogram is complete
