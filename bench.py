@@ -47,6 +47,7 @@ KERNEL_SOURCES = {
     "full16": "paper_2205_07610_amd/csrc/full_dp_i16x2.hip",
     "rerun32": "paper_2205_07610_amd/csrc/full_dp_i32.hip",
     "long": "paper_2205_07610_amd/csrc/long_dp_i32.hip",
+    "long16": "paper_2205_07610_amd/csrc/long_dp_i16x2.hip",
     "band32": "paper_2205_07610_amd/csrc/band_dp_i32.hip",
     "band16": "paper_2205_07610_amd/csrc/band_dp_i16x2.hip",
     "features": "paper_2205_07610_amd/csrc/features.hip",
@@ -190,14 +191,16 @@ def mean_phases(phases, names):
 
 
 # cells each full-DP phase processed, from the library's per-route counts
-PHASE_CELLS = {"full32_ms": "cells_full32", "full16_ms": "cells_full16", "long_ms": "cells_long"}
+PHASE_CELLS = {"full32_ms": "cells_full32", "full16_ms": "cells_full16", "long_ms": "cells_long",
+               "long16_ms": "cells_long16"}
+PACKED_PHASES = ("full16_ms", "long16_ms")
 
 
 def phase_roofline(phases, name, ops_per_cell):
     """Roofline of one full-DP phase: its own cells x ops per cell / its time."""
     ms = sum(p[name] for p in phases) / len(phases)
     cells = phases[-1][PHASE_CELLS[name]] if name in PHASE_CELLS else 0
-    r = roofline(name.replace("_ms", ""), ms, cells * ops_per_cell, name == "full16_ms")
+    r = roofline(name.replace("_ms", ""), ms, cells * ops_per_cell, name in PACKED_PHASES)
     r["cells"] = cells
     r["ops_per_cell"] = ops_per_cell
     return r
@@ -319,7 +322,7 @@ def main():
     def full_step():
         binding.align_batch(sa, oa, sb, ob, *args_sc, scores_out=out)
 
-    full_names = ["full32_ms", "full16_ms", "rerun32_ms", "long_ms", "classify_ms"]
+    full_names = ["full32_ms", "full16_ms", "rerun32_ms", "long_ms", "long16_ms", "classify_ms"]
     graph_info = None
     if args.workload == "c2":
         log("autotuning the variant table")
@@ -360,7 +363,7 @@ def main():
         log(f"learned band: warmup {args.warmup}, {args.steps} steps")
         ms_per_step, phases = timed(learned_step, args.steps, args.warmup, binding, torch)
         names = ["features_ms", "mlp_ms", "classify_ms", "band_ms", "full32_ms", "full16_ms",
-                 "rerun32_ms", "long_ms"]
+                 "rerun32_ms", "long_ms", "long16_ms"]
         avg = mean_phases(phases, names)
         stats = phases[-1]["stats"]
         gpu_scores = out_l.cpu().numpy()
@@ -381,7 +384,8 @@ def main():
                 r["cells_note"] = "cells the kernel computed (m x band width, every round)"
                 r["unit_of_work"] = "all launches of one learned step (every class and round)"
                 band_roof[name] = r
-        cands = [k for k in ("band16_ms", "band32_ms") if k[:-3] in band_roof] + ["full32_ms", "long_ms"]
+        cands = [k for k in ("band16_ms", "band32_ms") if k[:-3] in band_roof] + ["full32_ms", "long_ms",
+                                                                                   "long16_ms"]
         dom = max(cands, key=lambda k: avg[k])
         if dom in ("band16_ms", "band32_ms"):
             roof = band_roof[dom[:-3]]
@@ -394,7 +398,7 @@ def main():
             ms_per_step, gpu_scores = plan_ms, plan_scores
         dom = max(full_names, key=lambda k: avg[k])
         roof = phase_roofline(full_phases, dom, OPS_PER_CELL[batch.mode])
-        dtype = "i16x2" if dom == "full16_ms" else "i32"
+        dtype = "i16x2" if dom in PACKED_PHASES else "i32"
 
     result = {
         "metric": METRIC,
@@ -424,7 +428,7 @@ def main():
     if learned:
         result["value_note"] = "effective GCUPS: sum of m*n over the batch / learned step time"
         fr = {k.replace("_ms", ""): phase_roofline(full_phases, k, OPS_PER_CELL[batch.mode])
-              for k in ("full32_ms", "full16_ms", "long_ms") if full_avg[k] > 0}
+              for k in ("full32_ms", "full16_ms", "long_ms", "long16_ms") if full_avg[k] > 0}
         result["full_dp"] = {
             "ms_per_step": round(full_ms, 4),
             "GCUPS": round(cells / (full_ms * 1e-3) / 1e9, 2),

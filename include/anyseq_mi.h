@@ -110,7 +110,7 @@ typedef struct {
     float features_ms;  /* k-mer features (as_align_batch_learned) */
     float mlp_ms;       /* band network inference (as_align_batch_learned) */
     float band16_ms;    /* part of band_ms spent in the packed 16-bit banded kernel */
-    float reserved_ms;
+    float long16_ms;    /* packed 16-bit wavefront for long global pairs, two per wave */
     int64_t pairs_full32;
     int64_t pairs_full16;
     int64_t pairs_rerun32;
@@ -120,6 +120,8 @@ typedef struct {
     int64_t cells_full32;   /* sum of m*n of the pairs of each full-DP route */
     int64_t cells_full16;
     int64_t cells_long;
+    int64_t pairs_long16;
+    int64_t cells_long16;
 } as_timing;
 
 /*

@@ -37,12 +37,13 @@ class Timing(ctypes.Structure):
                 ("full16_ms", ctypes.c_float), ("rerun32_ms", ctypes.c_float),
                 ("long_ms", ctypes.c_float), ("band_ms", ctypes.c_float),
                 ("features_ms", ctypes.c_float), ("mlp_ms", ctypes.c_float),
-                ("band16_ms", ctypes.c_float), ("reserved_ms", ctypes.c_float),
+                ("band16_ms", ctypes.c_float), ("long16_ms", ctypes.c_float),
                 ("pairs_full32", ctypes.c_int64), ("pairs_full16", ctypes.c_int64),
                 ("pairs_rerun32", ctypes.c_int64), ("pairs_long", ctypes.c_int64),
                 ("pairs_fallback", ctypes.c_int64), ("cells", ctypes.c_int64),
                 ("cells_full32", ctypes.c_int64), ("cells_full16", ctypes.c_int64),
-                ("cells_long", ctypes.c_int64)]
+                ("cells_long", ctypes.c_int64), ("pairs_long16", ctypes.c_int64),
+                ("cells_long16", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

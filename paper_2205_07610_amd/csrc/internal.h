@@ -74,6 +74,10 @@ constexpr int kBandClasses = 8;
 constexpr int kBand16Classes = 9;
 constexpr int kMaxBandRounds = 8;
 
+// Full-DP work lists: packed 16-bit, 32-bit stripes, 32-bit wavefront,
+// packed 16-bit wavefront (global mode, two pairs per wave).
+constexpr int kListSlots = 4;
+
 // Cost classes of the 32-bit full-DP list inside a length bin: 8 classes of
 // stripe count by 16 of row count, most stripes and rows first.  A wave's
 // four pairs run their stripes in lockstep, each as long as the longest
@@ -97,6 +101,11 @@ struct Counters {
   int32_t n_long_tasks;  // their stripes (one task per stripe)
   int32_t next_long;     // ticket counter of the wavefront kernel
   int32_t n_fallback;    // banded pairs sent to the full DP
+  int32_t n_long16;      // pairs queued for the packed wavefront (consecutive pairs form duos)
+  int32_t n_long16_tasks;  // their stripes (one task per duo stripe)
+  int32_t next_long16;   // ticket counter of the packed wavefront kernel
+  int32_t pad_long16_;
+  long long long16_bnd_total;  // uint2 entries of all packed wavefront boundary columns
   long long long_bnd_total;  // int2 entries of all wavefront boundary columns
   // banded path: lists per round parity and lane-width class
   int32_t n_band[2][kBandClasses];
@@ -109,18 +118,18 @@ struct Counters {
   unsigned long long fallback_cells;  // sum of m*n over the fallback pairs
   unsigned long long route_cells[4];  // sum of m*n per full-DP list (16-bit, 32-bit, wavefront)
   // length-binned lists: counts, offsets and scatter cursors per (list, bin)
-  int32_t bin_count[3][kLenBins];
-  int32_t bin_base[3][kLenBins];
-  int32_t bin_cursor[3][kLenBins];
+  int32_t bin_count[kListSlots][kLenBins];
+  int32_t bin_base[kListSlots][kLenBins];
+  int32_t bin_cursor[kListSlots][kLenBins];
   int32_t bin_var32[kLenBins];   // 32-bit variant of each bin
   int32_t kmask32;               // K variants present in the 32-bit list
   unsigned long long bin_cells[kLenBins];  // sum of m*n of the routed pairs per bin
   // The 32-bit list inside each length bin, by cost class (largest first):
   // counts, offsets and scatter cursors.  Device-only: the host reads back
   // the counters up to kCountersHead.
-  int32_t cost_count[kLenBins][kCostClasses];
-  int32_t cost_base[kLenBins][kCostClasses];
-  int32_t cost_cursor[kLenBins][kCostClasses];
+  int32_t cost_count[2][kLenBins][kCostClasses];   // [0]: 32-bit list, [1]: packed wavefront list
+  int32_t cost_base[2][kLenBins][kCostClasses];
+  int32_t cost_cursor[2][kLenBins][kCostClasses];
 };
 constexpr size_t kCountersHead = offsetof(Counters, cost_count);
 
@@ -398,6 +407,30 @@ struct LongDpArgs {
 };
 
 hipError_t launch_long_dp_i32(int mode, const LongDpArgs &args, int grid, hipStream_t stream);
+
+// Packed 16-bit wavefront (global mode): duos of consecutive list items.
+struct Long16Args {
+  const uint8_t *seqs_a;
+  const uint8_t *seqs_b;
+  const LongItem *items;    // duo d: items 2d, 2d+1; item 2d holds the duo's task0, stripes, bnd_off
+  Counters *ctr;
+  const int8_t *subst;      // sigma, asz x asz row-major (at most 4 letters)
+  int32_t asz, alpha, beta;
+  int32_t *scores;
+  uint2 *bnd;               // boundary columns, (max(m0, m1) + 1) rows per stripe edge
+  int32_t *flags;           // rows published per task, zeroed before launch
+};
+hipError_t launch_long_dp_i16(const Long16Args &args, int grid, hipStream_t stream);
+int long_dp_i16_blocks_per_cu();
+int long_dp_i16_stripe_width();
+constexpr int kLong16Width = 1024;  // columns per packed wavefront stripe (64 lanes x 16)
+// A global pair whose every shifted cell provably fits int16 (columns past n
+// only lower cells, so the full matrix bound holds for the padded stripes).
+__host__ __device__ inline bool long16_range_ok(int64_t m, int64_t n, int smax_pos, int alpha, int beta) {
+  const int64_t ub = (int64_t)smax_pos * (m < n ? m : n) + (int64_t)beta * (m + n) + alpha + 2 * beta + 256;
+  const int64_t lb = 3LL * (alpha - beta) + 256;
+  return ub < 32000 && lb < 32000;
+}
 int long_dp_i32_blocks_per_cu(int mode, int asz);
 int long_dp_i32_stripe_width();
 size_t long_dp_i32_lds_bytes(int asz);

@@ -36,13 +36,16 @@ struct RouteParams {
   int32_t allow16;        // the scoring fits the packed kernel's byte profile
   int32_t long_w;         // stripe width of the wavefront kernel
   int32_t long_min_rows;  // automatic routing: rows needed for the wavefront
+  int32_t long16;         // global range-proven wavefront pairs may take the packed wavefront
   int32_t only_bin;       // -1, or the one length bin to route (autotuning)
   int8_t var_of_bin[kLenBins];        // variant per length bin, -1 = automatic
   int32_t sample_stride[kLenBins];    // route every stride-th pair of a bin (1: all)
 };
 
 // Work lists of the full DP, by kernel.
-enum List { kList16 = 0, kList32 = 1, kListLong = 2, kLists = 3 };
+enum List { kList16 = 0, kList32 = 1, kListLong = 2, kListLong16 = 3, kLists = kListSlots };
+// lists ordered by cost class inside each bin (index into the cost arrays), or -1
+__host__ __device__ inline int cost_list(int l) { return l == kList32 ? 0 : (l == kListLong16 ? 1 : -1); }
 
 // Orientation minimising the stripe passes of a 32-bit kernel with stripes
 // of W columns: a pass costs (rows + 15) steps.
@@ -88,7 +91,11 @@ __device__ int route_pair(const RouteParams &c, int64_t a0, int64_t m, int64_t b
                        (int64_t)c.beta * (kGroup * 16) + c.alpha + 2 * c.beta + 256;
     if (ub < 32000) return kList16;
   }
-  if (d.n > c.long_w && (v == kVarLong || (v < 0 && d.m >= c.long_min_rows))) return kListLong;
+  if (d.n > c.long_w && (v == kVarLong || (v < 0 && d.m >= c.long_min_rows))) {
+    if (c.long16 && c.mode == kGlobal && c.allow16 && long16_range_ok(m, n, c.smax_pos, c.alpha, c.beta))
+      return kListLong16;
+    return kListLong;
+  }
   return kList32;
 }
 
@@ -163,11 +170,11 @@ __device__ inline int64_t source_count(const RouteParams &c, const PairDesc *src
 
 // Classification, step 1 of 3: per (list, length bin) counts, cells, the
 // 32-bit variant of every bin and the longest multi-stripe row count.
-// Cost class of a 32-bit list item inside its length bin (0 = costliest):
-// stripe class (exact up to 8 stripes, else 8 even ranges) by row class (16
-// even ranges of the bin's longest side).
-__device__ inline int cost_class(const PairDesc &d, int bin) {
-  const int ws = kGroup * variant_k(variant_of(d.flags));  // stripe width
+// Cost class of an item of an ordered list inside its length bin (0 =
+// costliest): stripe class (exact up to 8 stripes, else 8 even ranges) by row
+// class (16 even ranges of the bin's longest side).
+__device__ inline int cost_class(const PairDesc &d, int bin, int l) {
+  const int ws = l == kListLong16 ? kLong16Width : kGroup * variant_k(variant_of(d.flags));  // stripe width
   const int64_t longer = (int64_t)64 << bin;                // the bin's longest side
   const int64_t smax = (longer + ws - 1) / ws;
   int64_t st = smax - ((int64_t)d.n + ws - 1) / ws;         // 0 = most stripes
@@ -184,7 +191,7 @@ __global__ void __launch_bounds__(256) route_count_kernel(RouteParams c, const i
   constexpr int R = kLists * kLenBins;
   constexpr int RC = kLenBins * kCostClasses;
   __shared__ int cnt[R];
-  __shared__ int ccnt[RC];
+  __shared__ int ccnt[2 * RC];
   __shared__ unsigned long long rcells[kLists];
   __shared__ unsigned long long bcells[kLenBins];
   __shared__ unsigned long long cells_sh;
@@ -193,7 +200,7 @@ __global__ void __launch_bounds__(256) route_count_kernel(RouteParams c, const i
   const int64_t lo = (int64_t)blockIdx.x * chunk;
   const int64_t hi = lo + chunk < total ? lo + chunk : total;
   for (int r = threadIdx.x; r < R; r += blockDim.x) cnt[r] = 0;
-  for (int r = threadIdx.x; r < RC; r += blockDim.x) ccnt[r] = 0;
+  for (int r = threadIdx.x; r < 2 * RC; r += blockDim.x) ccnt[r] = 0;
   if (threadIdx.x < kLists) rcells[threadIdx.x] = 0;
   if (threadIdx.x < kLenBins) bcells[threadIdx.x] = 0;
   if (threadIdx.x == 0) cells_sh = 0;
@@ -211,8 +218,8 @@ __global__ void __launch_bounds__(256) route_count_kernel(RouteParams c, const i
     atomicAdd(&cnt[l * kLenBins + bin], 1);
     atomicAdd(&rcells[l], (unsigned long long)(m * n));
     atomicAdd(&bcells[bin], (unsigned long long)(m * n));
+    if (cost_list(l) >= 0) atomicAdd(&ccnt[cost_list(l) * RC + bin * kCostClasses + cost_class(d, bin, l)], 1);
     if (l == kList32) {
-      atomicAdd(&ccnt[bin * kCostClasses + cost_class(d, bin)], 1);
       ctr->bin_var32[bin] = variant_of(d.flags);  // the same for every pair of the bin
       if (d.n > kGroup * variant_k(variant_of(d.flags))) atomicMax(&ctr->max_rows_multi, d.m);
     }
@@ -221,8 +228,8 @@ __global__ void __launch_bounds__(256) route_count_kernel(RouteParams c, const i
   __syncthreads();
   for (int r = threadIdx.x; r < R; r += blockDim.x)
     if (cnt[r]) atomicAdd(&ctr->bin_count[r / kLenBins][r % kLenBins], cnt[r]);
-  for (int r = threadIdx.x; r < RC; r += blockDim.x)
-    if (ccnt[r]) atomicAdd(&ctr->cost_count[r / kCostClasses][r % kCostClasses], ccnt[r]);
+  for (int r = threadIdx.x; r < 2 * RC; r += blockDim.x)
+    if (ccnt[r]) atomicAdd(&ctr->cost_count[r / RC][(r % RC) / kCostClasses][r % kCostClasses], ccnt[r]);
   if (threadIdx.x < kLists && rcells[threadIdx.x])
     atomicAdd(&ctr->route_cells[threadIdx.x], rcells[threadIdx.x]);
   if (threadIdx.x < kLenBins && bcells[threadIdx.x])
@@ -247,10 +254,11 @@ __global__ void __launch_bounds__(kWave) route_scan_kernel(Counters *ctr, PairDe
     for (int b = kLenBins - 1; b >= 0; --b) {
       if (lane == 0) ctr->bin_base[l][b] = base;
       int cnt = ctr->bin_count[l][b];
-      if (l == kList32 && cnt > 0) {
+      const int cl = cost_list(l);
+      if (cl >= 0 && cnt > 0) {
         // cost classes of the bin, costliest first (a prefix sum over the
         // lanes, lane j holding classes 2j and 2j + 1)
-        const int c0 = ctr->cost_count[b][2 * lane], c1 = ctr->cost_count[b][2 * lane + 1];
+        const int c0 = ctr->cost_count[cl][b][2 * lane], c1 = ctr->cost_count[cl][b][2 * lane + 1];
         int incl = c0 + c1;
 #pragma unroll
         for (int dd = 1; dd < kWave; dd <<= 1) {
@@ -258,8 +266,10 @@ __global__ void __launch_bounds__(kWave) route_scan_kernel(Counters *ctr, PairDe
           if (lane >= dd) incl += y;
         }
         const int first = base + incl - c0 - c1;
-        ctr->cost_base[b][2 * lane] = first;
-        ctr->cost_base[b][2 * lane + 1] = first + c0;
+        ctr->cost_base[cl][b][2 * lane] = first;
+        ctr->cost_base[cl][b][2 * lane + 1] = first + c0;
+      }
+      if (l == kList32 && cnt > 0) {
         const int padded = (cnt + kGroupsPerWave - 1) / kGroupsPerWave * kGroupsPerWave;
         const int v = ctr->bin_var32[b];
         if (lane < padded - cnt) {
@@ -274,14 +284,15 @@ __global__ void __launch_bounds__(kWave) route_scan_kernel(Counters *ctr, PairDe
     if (lane == 0) {
       if (l == kList16) ctr->n_full16 = base;
       else if (l == kList32) ctr->n_full32 = base;
-      else ctr->n_long = base;
+      else if (l == kListLong) ctr->n_long = base;
+      else ctr->n_long16 = base;
     }
   }
   if (lane != 0) return;
   ctr->kmask32 = kmask;
   if (bnd_rows_cap > 0 && ctr->n_full32 > 0 && (int64_t)ctr->max_rows_multi + 1 > bnd_rows_cap) {
     atomicOr(&ctr->status, kStatusPlan);
-    ctr->n_full32 = ctr->n_full16 = ctr->n_long = 0;
+    ctr->n_full32 = ctr->n_full16 = ctr->n_long = ctr->n_long16 = 0;
   }
 }
 
@@ -290,20 +301,21 @@ __global__ void __launch_bounds__(kWave) route_scan_kernel(Counters *ctr, PairDe
 __global__ void __launch_bounds__(256) route_scatter_kernel(RouteParams c, const int64_t *offs_a,
                                                             const int64_t *offs_b, const PairDesc *src,
                                                             PairDesc *items16, PairDesc *items32,
-                                                            LongItem *items_long, Counters *ctr) {
+                                                            LongItem *items_long, LongItem *items_long16,
+                                                            Counters *ctr) {
   constexpr int R = kLists * kLenBins;
   constexpr int RC = kLenBins * kCostClasses;
   __shared__ int cnt[R];
   __shared__ int base[R];
-  __shared__ int ccnt[RC];
-  __shared__ int cbase[RC];
+  __shared__ int ccnt[2 * RC];
+  __shared__ int cbase[2 * RC];
   if (ctr->status & kStatusPlan) return;
   const int64_t total = source_count(c, src, ctr);
   const int64_t chunk = (total + gridDim.x - 1) / gridDim.x;
   const int64_t lo = (int64_t)blockIdx.x * chunk;
   const int64_t hi = lo + chunk < total ? lo + chunk : total;
   for (int r = threadIdx.x; r < R; r += blockDim.x) cnt[r] = 0;
-  for (int r = threadIdx.x; r < RC; r += blockDim.x) ccnt[r] = 0;
+  for (int r = threadIdx.x; r < 2 * RC; r += blockDim.x) ccnt[r] = 0;
   __syncthreads();
   for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
     int64_t a0, m, b0, n, p;
@@ -311,8 +323,10 @@ __global__ void __launch_bounds__(256) route_scatter_kernel(RouteParams c, const
     PairDesc d;
     int bin;
     const int l = route_pair(c, a0, m, b0, n, p, d, bin);
-    if (l == kList32) atomicAdd(&ccnt[bin * kCostClasses + cost_class(d, bin)], 1);
-    else if (l >= 0) atomicAdd(&cnt[l * kLenBins + bin], 1);
+    if (l < 0) continue;
+    const int cl = cost_list(l);
+    if (cl >= 0) atomicAdd(&ccnt[cl * RC + bin * kCostClasses + cost_class(d, bin, l)], 1);
+    else atomicAdd(&cnt[l * kLenBins + bin], 1);
   }
   __syncthreads();
   for (int r = threadIdx.x; r < R; r += blockDim.x) {
@@ -320,9 +334,9 @@ __global__ void __launch_bounds__(256) route_scatter_kernel(RouteParams c, const
     base[r] = cnt[r] ? ctr->bin_base[l][b] + atomicAdd(&ctr->bin_cursor[l][b], cnt[r]) : 0;
     cnt[r] = 0;
   }
-  for (int r = threadIdx.x; r < RC; r += blockDim.x) {
-    const int b = r / kCostClasses, k = r % kCostClasses;
-    cbase[r] = ccnt[r] ? ctr->cost_base[b][k] + atomicAdd(&ctr->cost_cursor[b][k], ccnt[r]) : 0;
+  for (int r = threadIdx.x; r < 2 * RC; r += blockDim.x) {
+    const int cl = r / RC, b = (r % RC) / kCostClasses, k = r % kCostClasses;
+    cbase[r] = ccnt[r] ? ctr->cost_base[cl][b][k] + atomicAdd(&ctr->cost_cursor[cl][b][k], ccnt[r]) : 0;
     ccnt[r] = 0;
   }
   __syncthreads();
@@ -333,9 +347,12 @@ __global__ void __launch_bounds__(256) route_scatter_kernel(RouteParams c, const
     int bin;
     const int l = route_pair(c, a0, m, b0, n, p, d, bin);
     if (l < 0) continue;
-    if (l == kList32) {
-      const int r = bin * kCostClasses + cost_class(d, bin);
-      items32[cbase[r] + atomicAdd(&ccnt[r], 1)] = d;
+    const int cl = cost_list(l);
+    if (cl >= 0) {
+      const int r = cl * RC + bin * kCostClasses + cost_class(d, bin, l);
+      const int slot = cbase[r] + atomicAdd(&ccnt[r], 1);
+      if (l == kList32) items32[slot] = d;
+      else items_long16[slot].d = d;
       continue;
     }
     const int r = l * kLenBins + bin;
@@ -430,6 +447,56 @@ __global__ void __launch_bounds__(256) band_classify_kernel(RouteParams c, const
     if (r == kFall) fallback[slot] = bi.d;
     else if (r >= kBandClasses) lists16[(int64_t)(r - kBandClasses) * list_cap + slot] = bi;
     else lists[(int64_t)r * list_cap + slot] = bi;
+  }
+}
+
+// One block: the packed wavefront's duos (items 2d, 2d+1): stripes
+// max(S0, S1), first ticket and boundary offset of each duo (prefix sums).
+__global__ void __launch_bounds__(256) long16_prep_kernel(LongItem *items, Counters *ctr) {
+  __shared__ int sst[256];
+  __shared__ long long sbe[256];
+  const int n = ctr->n_long16;
+  const int nd = (n + 1) / 2;
+  int task = 0;
+  long long bnd = 0;
+  for (int b = 0; b < nd; b += 256) {
+    const int i = b + threadIdx.x;
+    int st = 0;
+    long long be = 0;
+    if (i < nd) {
+      const PairDesc d0 = items[2 * i].d;
+      int S = (d0.n + kLong16Width - 1) / kLong16Width, mm = d0.m;
+      if (2 * i + 1 < n) {
+        const PairDesc d1 = items[2 * i + 1].d;
+        S = max(S, (d1.n + kLong16Width - 1) / kLong16Width);
+        mm = max(mm, d1.m);
+      }
+      st = S;
+      be = (long long)(S - 1) * (mm + 1);
+    }
+    sst[threadIdx.x] = st;
+    sbe[threadIdx.x] = be;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+      const int vs = threadIdx.x >= off ? sst[threadIdx.x - off] : 0;
+      const long long vb = threadIdx.x >= off ? sbe[threadIdx.x - off] : 0;
+      __syncthreads();
+      sst[threadIdx.x] += vs;
+      sbe[threadIdx.x] += vb;
+      __syncthreads();
+    }
+    if (i < nd) {
+      items[2 * i].task0 = task + sst[threadIdx.x] - st;
+      items[2 * i].stripes = st;
+      items[2 * i].bnd_off = bnd + sbe[threadIdx.x] - be;
+    }
+    task += sst[255];
+    bnd += sbe[255];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    ctr->n_long16_tasks = task;
+    ctr->long16_bnd_total = bnd;
   }
 }
 
@@ -592,6 +659,12 @@ struct Workspace {
   int64_t rerun_cap = 0;
   LongItem *items_long = nullptr;  // wavefront list
   int64_t items_long_cap = 0;
+  LongItem *items_long16 = nullptr;  // packed wavefront list (duos)
+  int64_t items_long16_cap = 0;
+  uint2 *bnd_long16 = nullptr;       // packed wavefront boundary columns
+  int64_t bnd_long16_cap = 0;
+  int32_t *flags16 = nullptr;        // packed wavefront progress counters
+  int64_t flags16_cap = 0;
   int2 *bnd_long = nullptr;        // wavefront boundary columns
   int64_t bnd_long_cap = 0;
   int32_t *flags = nullptr;        // wavefront progress counters
@@ -654,7 +727,8 @@ int init_workspace(Workspace &w, int dev) {
 }
 
 void free_workspace(Workspace &w) {
-  void *bufs[] = {w.items, w.items16, w.rerun, w.items_long, w.bnd_long, w.flags, w.band_lists,
+  void *bufs[] = {w.items, w.items16, w.rerun, w.items_long, w.bnd_long, w.flags, w.items_long16,
+                  w.bnd_long16, w.flags16, w.band_lists,
                   w.band16_lists, w.band_sorted, w.sort_hist, w.fallback, w.qwords, w.ctr, w.subst, w.bnd,
                   w.tune_scores};
   for (void *b : bufs)
@@ -765,6 +839,7 @@ RouteParams route_params(const CallScoring &cs, int64_t n_pairs) {
   rp.allow16 = cs.allow16;
   rp.long_w = long_dp_i32_stripe_width();
   rp.long_min_rows = 2048;
+  rp.long16 = 1;
   rp.only_bin = -1;
   for (int b = 0; b < kLenBins; ++b) {
     rp.var_of_bin[b] = g_variants[cs.mode][b];
@@ -785,7 +860,7 @@ int launch_classify(Workspace *w, const RouteParams &rp, const int64_t *offs_a, 
   hipLaunchKernelGGL(route_scan_kernel, dim3(1), dim3(64), 0, stream, w->ctr, w->items, bnd_rows_cap);
   AS_HIP(hipGetLastError());
   hipLaunchKernelGGL(route_scatter_kernel, dim3(blocks), dim3(256), 0, stream, rp, offs_a, offs_b, src,
-                     w->items16, w->items, w->items_long, w->ctr);
+                     w->items16, w->items, w->items_long, w->items_long16, w->ctr);
   AS_HIP(hipGetLastError());
   return AS_OK;
 }
@@ -798,6 +873,7 @@ int lists_capacity(Workspace *w, int64_t n_pairs) {
   if ((rc = grow((void **)&w->items16, &w->items16_cap, n_pairs, sizeof(PairDesc)))) return rc;
   if ((rc = grow((void **)&w->rerun, &w->rerun_cap, n_pairs, sizeof(PairDesc)))) return rc;
   if ((rc = grow((void **)&w->items_long, &w->items_long_cap, n_pairs, sizeof(LongItem)))) return rc;
+  if ((rc = grow((void **)&w->items_long16, &w->items_long16_cap, n_pairs, sizeof(LongItem)))) return rc;
   return AS_OK;
 }
 
@@ -809,12 +885,17 @@ int run_full_lists(Workspace *w, const CallScoring &cs, const uint8_t *seqs_a,
                    Counters c) {
   const int mode = cs.mode, asz = cs.asz;
   int rc;
+  if (c.n_long16 > 0) {
+    hipLaunchKernelGGL(long16_prep_kernel, dim3(1), dim3(256), 0, stream, w->items_long16, w->ctr);
+    AS_HIP(hipGetLastError());
+  }
   if (c.n_long > 0) {
     hipLaunchKernelGGL(long_prep_kernel, dim3(1), dim3(256), 0, stream, w->items_long, w->ctr,
                        long_dp_i32_stripe_width(), mode, scores_out, (int64_t)0, (int64_t)0);
     AS_HIP(hipGetLastError());
-    if ((rc = read_counters(w, stream, &c))) return rc;
   }
+  if (c.n_long > 0 || c.n_long16 > 0)
+    if ((rc = read_counters(w, stream, &c))) return rc;
   if (c.n_full16 > 0) {
     const int bpc = full_dp_i16_blocks_per_cu(mode);
     int64_t grid = (int64_t)bpc * w->num_cu;
@@ -887,8 +968,35 @@ int run_full_lists(Workspace *w, const CallScoring &cs, const uint8_t *seqs_a,
     AS_HIP(launch_long_dp_i32(mode, la, (int)grid, stream));
     if (timing) AS_HIP(hipEventRecord(w->ev[9], stream));
   }
+  if (c.n_long16 > 0) {
+    if ((rc = grow((void **)&w->bnd_long16, &w->bnd_long16_cap,
+                   c.long16_bnd_total > 0 ? c.long16_bnd_total : 1, sizeof(uint2))))
+      return rc;
+    if ((rc = grow((void **)&w->flags16, &w->flags16_cap, c.n_long16_tasks, sizeof(int32_t)))) return rc;
+    AS_HIP(hipMemsetAsync(w->flags16, 0, sizeof(int32_t) * (size_t)c.n_long16_tasks, stream));
+    int64_t grid = (int64_t)long_dp_i16_blocks_per_cu() * w->num_cu;
+    if (grid > c.n_long16_tasks) grid = c.n_long16_tasks;
+    Long16Args l16;
+    l16.seqs_a = seqs_a;
+    l16.seqs_b = seqs_b;
+    l16.items = w->items_long16;
+    l16.ctr = w->ctr;
+    l16.subst = w->subst;
+    l16.asz = asz;
+    l16.alpha = cs.alpha;
+    l16.beta = cs.beta;
+    l16.scores = scores_out;
+    l16.bnd = w->bnd_long16;
+    l16.flags = w->flags16;
+    if (timing) AS_HIP(hipEventRecord(w->ev[14], stream));
+    AS_HIP(launch_long_dp_i16(l16, (int)grid, stream));
+    if (timing) AS_HIP(hipEventRecord(w->ev[15], stream));
+  }
   Counters c2;
   if ((rc = read_counters(w, stream, &c2))) return rc;
+  g_last_timing.pairs_long16 += c.n_long16;
+  g_last_timing.cells_long16 = (int64_t)c2.route_cells[kListLong16];
+  if (timing && c.n_long16 > 0) g_last_timing.long16_ms += elapsed(w->ev[14], w->ev[15]);
   g_last_timing.pairs_full32 += c.n_full32;
   g_last_timing.pairs_full16 += c.n_full16;
   g_last_timing.pairs_long += c.n_long;
@@ -1350,6 +1458,7 @@ extern "C" int as_plan_create(const uint8_t *seqs_a, const int64_t *offs_a, cons
   {
     std::lock_guard<std::mutex> guard(g_lock);
     P->rp = route_params(cs, n_pairs);
+    P->rp.long16 = 0;  // plans keep the 32-bit wavefront
   }
   P->seqs_a = seqs_a;
   P->seqs_b = seqs_b;

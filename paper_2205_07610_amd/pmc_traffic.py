@@ -37,6 +37,8 @@ GROUPS = {
                  "paper_2205_07610_amd/csrc/features.hip", "all"),
     "long": (lambda k: k.startswith("long_dp_i32_kernel"),
              "paper_2205_07610_amd/csrc/long_dp_i32.hip", "largest"),
+    "long16": (lambda k: k.startswith("long_dp_i16_kernel"),
+               "paper_2205_07610_amd/csrc/long_dp_i16x2.hip", "largest"),
     "full32": (lambda k: k.startswith("full_dp_i32_kernel"),
                "paper_2205_07610_amd/csrc/full_dp_i32.hip", "largest"),
     "full16": (lambda k: k.startswith("full_dp_i16_kernel"),
@@ -77,9 +79,9 @@ def summarise(fetch_dir, write_dir, workload_name, workload_desc):
 
     # bench.py times the full DP before the learned path, so the timed
     # learned step's launches are the ones after the full-DP step's
-    # wavefront launch (the largest of the run); earlier ones belong to
-    # training and its diagnostics
-    long_rows = rows_of(F, GROUPS["long"][0])
+    # wavefront launch (the largest wavefront launch of the run, 32-bit or
+    # packed); earlier ones belong to training and its diagnostics
+    long_rows = rows_of(F, GROUPS["long"][0]) + rows_of(F, GROUPS["long16"][0])
     after = max(long_rows, key=lambda x: x[1])[0] if long_rows else -1
     out = {}
     for g, (pred, src, unit) in GROUPS.items():

@@ -205,8 +205,54 @@ def test_wavefront_long_pairs(gpu, oracle_mod, mode):
         tm = gpu.last_timing()
     finally:
         gpu.enable_timing(False)
-    # (2048, 1025) is oriented with 1025 rows and stays on the 16-lane path
-    assert tm["pairs_long"] == len(pairs) - 1
+    # (2048, 1025) is oriented with 1025 rows and stays on the 16-lane path;
+    # in global mode the others fit the packed wavefront's range proof
+    if mode == 0:
+        assert tm["pairs_long16"] == len(pairs) - 1 and tm["pairs_long"] == 0
+    else:
+        assert tm["pairs_long"] == len(pairs) - 1 and tm["pairs_long16"] == 0
+
+
+def test_packed_wavefront_duos(gpu, oracle_mod):
+    """Global long pairs on the packed wavefront: an odd number of pairs (the
+    last duo has one half), duos whose halves differ in stripe and row
+    counts, both orientations, related and unrelated pairs, and one pair
+    beyond the int16 range proof that stays on the 32-bit wavefront."""
+    rng = np.random.default_rng(530)
+    pairs = []
+    for k in range(36):
+        m = int(rng.integers(2048, 4600))
+        n = int(rng.integers(1025, 5200))
+        if k % 3 == 0:
+            m, n = n + 1100, m  # rows from B
+        a = rng.integers(0, 4, size=m).astype(np.uint8)
+        if k % 2:
+            s, _ = synth.mutate(rng, a, np.array([0, m]), 0.06, 0.02, 0.02, 4)
+            s = s[:n] if len(s) >= n else np.concatenate([s, rng.integers(0, 4, n - len(s)).astype(np.uint8)])
+        else:
+            s = rng.integers(0, 4, size=n).astype(np.uint8)
+        pairs.append((a, s))
+    big = rng.integers(0, 4, size=8200).astype(np.uint8)
+    sbig, _ = synth.mutate(rng, big, np.array([0, 8200]), 0.03, 0.01, 0.01, 4)
+    pairs.append((big, sbig))
+    b = synth.from_pairs("packed wavefront", pairs, DNA, 5, 2, 0)
+    gpu.enable_timing(True)
+    try:
+        _check(gpu, oracle_mod, b, "packed wavefront duos")
+        tm = gpu.last_timing()
+    finally:
+        gpu.enable_timing(False)
+    _say(f"packed wavefront: {tm['pairs_long16']} pairs in {tm['long16_ms']:.2f} ms, "
+         f"32-bit wavefront {tm['pairs_long']}")
+    # the routing: rows/columns oriented to minimise 256-column stripe passes;
+    # wavefront pairs have at least 2048 rows and more than 1024 columns
+    def wavefront(m, n):
+        sa, sb = (n + 255) // 256, (m + 255) // 256
+        rows, cols = (n, m) if sb * (n + 15) < sa * (m + 15) else (m, n)
+        return rows >= 2048 and cols > 1024
+    expect = sum(wavefront(len(a), len(s)) for a, s in pairs[:-1])
+    assert expect >= 20
+    assert tm["pairs_long16"] == expect and tm["pairs_long"] == 1
 
 
 def test_config3_long_pairs_full_size_sampled(gpu, oracle_mod):
