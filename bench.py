@@ -55,6 +55,8 @@ KERNEL_SOURCES = {
 # band network training of the learned workload (library kernels, untimed)
 TRAIN = {"pairs": 200_000, "seed": 2004, "steps": 4000, "batch": 1024, "lr": 2e-3, "tau": 0.7,
          "init_seed": 2005, "order_seed": 2006, "b3": 5.0}
+# constant initial half-widths tried for the fixed-band comparison
+FIXED_W0 = (16, 32, 48, 64, 96, 128, 192, 256, 384, 512)
 MODE_NAMES = {0: "global", 1: "semi-global", 2: "local"}
 
 
@@ -256,6 +258,20 @@ def train_band_model(binding, torch, synth):
     labels = binding.band_labels(*dev, train.subst, train.alpha, train.beta, train.mode).cpu().numpy()
     _, st = binding.align_batch_learned(*dev, train.subst, train.alpha, train.beta, train.mode, params)
     ideal = own_label_cells(train, labels, binding.BAND_WIDE)
+    # the fixed-band comparison: the constant initial half-width that makes
+    # the certified banded path fastest on the training set
+    fixed = {}
+    for w0 in FIXED_W0:
+        band_w0 = torch.full((train.n_pairs,), w0, dtype=torch.int32, device="cuda")
+        ts = []
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            binding.align_batch_band(*dev, train.subst, train.alpha, train.beta, train.mode, band_w0)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+        fixed[w0] = round(ts[-1] * 1e3, 3)
+    best_w0 = min(fixed, key=fixed.get)
     del dev
     return params, {"pairs": train.n_pairs, "steps": TRAIN["steps"], "batch": TRAIN["batch"],
                     "lr": TRAIN["lr"], "tau": TRAIN["tau"], "gen_s": round(t_gen, 2),
@@ -264,7 +280,8 @@ def train_band_model(binding, torch, synth):
                         "learned": round(st["dp_cells"] / train.cells(), 4),
                         "own_label_bands": round(float(ideal) / train.cells(), 4),
                         "label_median": float(np.median(labels)),
-                        "labels_wide": int(np.count_nonzero(labels >= binding.BAND_WIDE))}}
+                        "labels_wide": int(np.count_nonzero(labels >= binding.BAND_WIDE))},
+                    "fixed_w0_train_ms": fixed, "fixed_w0_best": best_w0}
 
 
 def main():
@@ -392,6 +409,29 @@ def main():
         else:
             roof = phase_roofline(phases, dom, opc)
         dtype = "i16x2" if dom == "band16_ms" else "i32"
+
+        # (iii) the same certified banded path from one constant initial
+        # half-width for every pair, the best constant on the training set
+        w0 = train_info["fixed_w0_best"]
+        band_w0 = torch.full((batch.n_pairs,), w0, dtype=torch.int32, device="cuda")
+        out_f = torch.empty(batch.n_pairs, dtype=torch.int32, device="cuda")
+
+        def fixed_step():
+            return binding.align_batch_band(sa, oa, sb, ob, *args_sc, band_w0, max_rounds=6,
+                                            scores_out=out_f)[1]
+
+        log(f"fixed band w0={w0}: warmup {args.warmup}, {args.steps} steps")
+        fixed_ms, fphases = timed(fixed_step, args.steps, args.warmup, binding, torch)
+        fst = fphases[-1]["stats"]
+        fixed_info = {"w0": w0, "ms_per_step": round(fixed_ms, 4),
+                      "GCUPS": round(cells / (fixed_ms * 1e-3) / 1e9, 2),
+                      "pairs_per_s": round(batch.n_pairs / (fixed_ms * 1e-3), 1),
+                      "mismatches_vs_full_dp": int(np.count_nonzero(out_f.cpu().numpy() != full_scores)),
+                      "dp_cells_frac": round(fst["dp_cells"] / cells, 4),
+                      "accepted": fst["accepted"], "fallback": fst["fallback"],
+                      "learned_speedup": round(fixed_ms / ms_per_step, 3)}
+        log(f"fixed band: {fixed_ms:.3f} ms/step")
+        del out_f, band_w0
     else:
         ms_per_step, avg, gpu_scores = full_ms, full_avg, full_scores
         if graph_info is not None:
@@ -443,6 +483,7 @@ def main():
         result["roofline_band_kernels"] = band_roof
         result["band_stats"]["dp_cells_frac"] = round(stats["dp_cells"] / cells, 4)
         result["training"] = train_info
+        result["fixed_band"] = fixed_info
     if not args.no_cpu_baseline:
         log(f"cpu baseline (~{args.cpu_seconds} s)")
         cb, mism, checked = cpu_baseline(batch, args.cpu_seconds, gpu_scores)

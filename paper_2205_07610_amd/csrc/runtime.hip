@@ -171,14 +171,22 @@ __device__ inline int64_t source_count(const RouteParams &c, const PairDesc *src
 // Classification, step 1 of 3: per (list, length bin) counts, cells, the
 // 32-bit variant of every bin and the longest multi-stripe row count.
 // Cost class of an item of an ordered list inside its length bin (0 =
-// costliest): stripe class (exact up to 8 stripes, else 8 even ranges) by row
-// class (16 even ranges of the bin's longest side).
+// costliest): stripe class (32-bit list: the stripe count, exact up to 8
+// stripes, else 8 even ranges; packed wavefront list: 8 even ranges of the
+// column count) by row class (16 even ranges of the bin's longest side).
 __device__ inline int cost_class(const PairDesc &d, int bin, int l) {
-  const int ws = l == kListLong16 ? kLong16Width : kGroup * variant_k(variant_of(d.flags));  // stripe width
   const int64_t longer = (int64_t)64 << bin;                // the bin's longest side
-  const int64_t smax = (longer + ws - 1) / ws;
-  int64_t st = smax - ((int64_t)d.n + ws - 1) / ws;         // 0 = most stripes
-  if (smax > kStripeClasses) st = st * kStripeClasses / smax;
+  int64_t st;
+  if (l == kListLong16) {
+    // column class: 8 even ranges of the bin's longest side, so the duos of
+    // a class share their stripe count and use at most four stripe widths
+    st = kStripeClasses - 1 - (int64_t)d.n * kStripeClasses / (longer + 1);
+  } else {
+    const int ws = kGroup * variant_k(variant_of(d.flags));  // stripe width
+    const int64_t smax = (longer + ws - 1) / ws;
+    st = smax - ((int64_t)d.n + ws - 1) / ws;               // 0 = most stripes
+    if (smax > kStripeClasses) st = st * kStripeClasses / smax;
+  }
   st = st < 0 ? 0 : (st >= kStripeClasses ? kStripeClasses - 1 : st);
   int64_t rc = kRowClasses - 1 - (int64_t)d.m * kRowClasses / (longer + 1);  // 0 = most rows
   rc = rc < 0 ? 0 : (rc >= kRowClasses ? kRowClasses - 1 : rc);

@@ -41,6 +41,14 @@ def _check(gpu, oracle_mod, batch, label, nthreads=None):
     return got
 
 
+def _oriented(m, n):
+    """(rows, columns) as the routing orients a pair of lengths m (A) and n
+    (B): the orientation with fewer 256-column stripe passes of (rows + 15)
+    steps."""
+    sa, sb = (n + 255) // 256, (m + 255) // 256
+    return (n, m) if sb * (n + 15) < sa * (m + 15) else (m, n)
+
+
 def test_config0_all_pairs(gpu, oracle_mod):
     _check(gpu, oracle_mod, synth.config0(), "c0")
 
@@ -244,15 +252,49 @@ def test_packed_wavefront_duos(gpu, oracle_mod):
         gpu.enable_timing(False)
     _say(f"packed wavefront: {tm['pairs_long16']} pairs in {tm['long16_ms']:.2f} ms, "
          f"32-bit wavefront {tm['pairs_long']}")
-    # the routing: rows/columns oriented to minimise 256-column stripe passes;
     # wavefront pairs have at least 2048 rows and more than 1024 columns
     def wavefront(m, n):
-        sa, sb = (n + 255) // 256, (m + 255) // 256
-        rows, cols = (n, m) if sb * (n + 15) < sa * (m + 15) else (m, n)
+        rows, cols = _oriented(m, n)
         return rows >= 2048 and cols > 1024
     expect = sum(wavefront(len(a), len(s)) for a, s in pairs[:-1])
     assert expect >= 20
     assert tm["pairs_long16"] == expect and tm["pairs_long"] == 1
+
+
+def test_packed_wavefront_stripe_widths(gpu, oracle_mod):
+    """Packed wavefront duos whose stripes narrow to 64 K columns, K = 11..16,
+    over 3 to 6 stripes: column counts just past a multiple of 1024 (the
+    narrowest K for their stripe count), in between, and exact multiples;
+    halves of one duo with different stripe and row counts."""
+    rng = np.random.default_rng(540)
+    lens = [2049, 2112, 2113, 2400, 2600, 2800, 3072, 3073, 3500, 4096, 4097, 4500, 5120, 5121]
+    pairs = []
+    for k, L in enumerate(lens):
+        for rel in (0, 1):
+            m = L + int(rng.integers(0, 24))
+            a = rng.integers(0, 4, size=m).astype(np.uint8)
+            if rel:
+                s, _ = synth.mutate(rng, a, np.array([0, m]), 0.05, 0.02, 0.02, 4)
+                s = s[:L] if len(s) >= L else np.concatenate([s, rng.integers(0, 4, L - len(s)).astype(np.uint8)])
+            else:
+                s = rng.integers(0, 4, size=L).astype(np.uint8)
+            pairs.append((a, s) if k % 2 else (s, a))
+    b = synth.from_pairs("packed wavefront widths", pairs, DNA, 5, 2, 0)
+    gpu.enable_timing(True)
+    try:
+        _check(gpu, oracle_mod, b, "packed wavefront stripe widths")
+        tm = gpu.last_timing()
+    finally:
+        gpu.enable_timing(False)
+    assert tm["pairs_long16"] == len(pairs) and tm["pairs_long"] == 0
+    # registers per lane of each pair alone: the smallest K whose 1024-column
+    # stripe count of 64 K columns covers its columns
+    def k_of(m, n):
+        cols = _oriented(m, n)[1]
+        S = -(-cols // 1024)
+        return max(10, -(-cols // (64 * S)))
+    ks = {k_of(len(a), len(s)) for a, s in pairs}
+    assert ks >= {11, 12, 13, 14, 15, 16}
 
 
 def test_config3_long_pairs_full_size_sampled(gpu, oracle_mod):
