@@ -12,7 +12,10 @@
 // its progress counter bypass the non-coherent caches, the producer waits
 // for its stores to complete (s_waitcnt) before it publishes how many rows
 // are done, every 16 steps, and the consumer spins on the counter before it
-// loads the rows of its next 16-step chunk, one chunk ahead.  No L2
+// loads the rows of its next 16-step chunk, one chunk ahead.  The rows lane
+// 63 finishes during a chunk are staged in LDS and stored at its end by 16
+// lanes as one contiguous 128-byte block, so the device-coherent stores
+// write whole cache lines instead of one partial line per row.  No L2
 // write-back or invalidation is needed, which the agent-scope fences would
 // issue on every hand-off.  Stripes are taken by persistent waves in ticket
 // order (pair-major, stripe-minor), so a wave only ever waits for a stripe
@@ -84,6 +87,7 @@ template <int MODE, int K>
 __global__ void __launch_bounds__(kWave) long_dp_i32_kernel(LongDpArgs a) {
   constexpr int W = kWave * K;
   extern __shared__ __align__(16) int8_t lds[];
+  __shared__ int2 xq[kChunk];  // the exported column of one chunk
   const int t = threadIdx.x;
   const int asz = a.asz;
   int8_t *prof = lds;
@@ -221,7 +225,7 @@ __global__ void __launch_bounds__(kWave) long_dp_i32_kernel(LongDpArgs a) {
           }
           fout = f;
           if (MODE == kSemiGlobal) rm = max(rm, Ha[K - 1] - rowoff);
-          if (export_ && t == kWave - 1) store_bnd(bout + row, Ha[K - 1], fout);
+          if (export_ && t == kWave - 1) xq[u] = make_int2(Ha[K - 1], fout);
         }
         hl_prev = hl;
         if (MODE == kSemiGlobal) { hb += beta; fb = hb; }
@@ -233,8 +237,18 @@ __global__ void __launch_bounds__(kWave) long_dp_i32_kernel(LongDpArgs a) {
       qfeed = qnext;
       hfeed = hnext;
       ffeed = fnext;
-      // lane 63 finished row it0 + 15 - 62; publish every complete row
       if (export_) {
+        // lane u stores the row lane 63 finished at step it0 + u; then every
+        // complete row is published
+        __builtin_amdgcn_wave_barrier();
+        if (t < kChunk) {
+          const int row = it0 + t - (kWave - 2);
+          if (row >= 1 && row <= m) {
+            const int2 v = xq[t];
+            store_bnd(bout + row, v.x, v.y);
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
         const int done = min(it0 + kChunk - (kWave - 1), m);
         if (done > 0) publish_rows(flag_out, done);
       }
