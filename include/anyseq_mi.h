@@ -129,17 +129,18 @@ typedef struct {
  * paper).  For global and semi-global alignment of alphabets of at most four
  * letters.  Pair p is first aligned inside the band of diagonals
  *   min(0, n-m) - w <= j - i <= max(0, n-m) + w,   w = band_w0[p]
- * widened to the kernel's lane width (a band of 64..1024 diagonals, centred
- * on the requested one).  The banded score is accepted when it is at least
- * an upper bound on every alignment path that leaves the computed band
+ * widened to the kernel's lane width (a band of 64..1536 diagonals,
+ * centred on the requested one).  The banded score is accepted when it is at
+ * least an upper bound on every alignment path that leaves the computed band
  * (closed form from the path structure of Eq. (1),(4),(5)); then it is the
- * optimal score.  Otherwise w doubles, for at most max_rounds rounds (1..8).
- * A band is used only when some lane width holds it: at most 1024
- * diagonals, and less than half the longer sequence (32-bit cells) or at
+ * optimal score.  Otherwise, for at most max_rounds rounds (1..8), the next
+ * half-width is (global) the smallest one whose bound the rejected score
+ * would pass, or (semi-global) twice w.  A band is used only when some lane
+ * width holds it: at most 1536 diagonals, and less than half the longer sequence (32-bit cells) or at
  * most three quarters of it (packed 16-bit cells, global mode).  A request
- * that no width holds -- the initial one, or a doubled one when a wider band
- * than the last round's exists -- takes the widest band the pair allows
- * instead.  A pair with no band left, or out of rounds, is aligned with the
+ * that no width holds -- the initial one, or a widened one when a wider band
+ * than the last round's exists and the rejected score does not already rule
+ * it out -- takes the widest band the pair allows instead.  A pair with no band left, or out of rounds, is aligned with the
  * full DP.  Every returned score is exact.
  *   band_w0    : device, int32 [n_pairs], initial half-widths (< 0 read as 0)
  *   stats      : HOST, optional (NULL), filled on return
@@ -352,7 +353,7 @@ int as_plan_destroy(as_plan *plan);
  * Packed 16-bit banded kernel (global mode): a pair whose band cells are
  * proven to fit int16 (sigma_max*min(m,n) + beta*(m + n + W) + margins below
  * 32000, W the band width in diagonals) is banded two pairs per lane group
- * with 16-bit cells, in widths of 64, 128, 256, 512 or 1024 diagonals; the
+ * with 16-bit cells, in widths of 64 to 1536 diagonals; the
  * others use the 32-bit banded kernel.  On by default; on = 0 sends every
  * pair to the 32-bit kernel (scores are the same either way).  Returns the
  * previous setting.

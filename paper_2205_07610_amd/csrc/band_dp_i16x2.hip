@@ -104,15 +104,19 @@ __device__ __forceinline__ uint32_t make_sel(uint32_t c0, uint32_t c1) {
 
 // Steps per unrolled chunk: a multiple of K, so the selector rotation
 // returns to the identity at every chunk boundary (24 rather than 48 for
-// K = 6, 12 on 16-lane groups, whose registers are already scarce).
-constexpr int chunk_steps(int K, int G) { return 32 % K == 0 ? 32 : (G == kGroup ? 24 : 48); }
+// K = 6, 12 on 16-lane groups, whose registers are already scarce; 40 for
+// K = 20).
+constexpr int chunk_steps(int K, int G) {
+  return 32 % K == 0 ? 32 : (G == kGroup ? 24 : (48 % K == 0 ? 48 : 40));
+}
 
 // Waves per SIMD the register allocation aims for: four for the narrowest
-// class, three for the others (what the compiler would pick for the wider
-// ones is two; the few values it then spills are reloaded once per pair,
-// outside the DP loops).
+// class, two for K = 20 and 24 (their state alone fills three waves'
+// registers), three for the others (what the compiler would pick for the
+// wider ones is two; the few values it then spills are reloaded once per
+// pair, outside the DP loops).
 template <int K, int G>
-constexpr int kWavesPerEu = (K == 4 && G == kGroup) ? 4 : 3;
+constexpr int kWavesPerEu = (K == 4 && G == kGroup) ? 4 : (K >= 20 ? 2 : 3);
 
 template <int K, int G>
 __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(kWavesPerEu<K, G>)))
@@ -345,7 +349,7 @@ band_dp_i16_kernel(BandArgs a, int pc) {
       atomicAdd(&a.ctr->band_accepted[a.round < kMaxBandRounds ? a.round : kMaxBandRounds - 1], 1);
       continue;
     }
-    band_requeue(a, d, w, kGlobal, W);
+    band_requeue(a, d, w, kGlobal, W, score);
   }
 }
 
@@ -360,11 +364,13 @@ int occupancy() {
 
 }  // namespace
 
-// Packed classes (widths 1.5x or 1.33x apart): 64, 96, 128, 192, 256
+// Packed classes (widths at most 1.5x apart): 64, 96, 128, 192, 256
 // diagonals on 16-lane groups (K = 4, 6, 8, 12, 16; eight pairs per wave),
-// 384, 512, 768, 1024 on whole waves (K = 6, 8, 12, 16; two pairs).
-#define AS_BAND16_CLASSES(X) \
-  X(0, 4, 16) X(1, 6, 16) X(2, 8, 16) X(3, 12, 16) X(4, 16, 16) X(5, 6, 64) X(6, 8, 64) X(7, 12, 64) X(8, 16, 64)
+// 384, 512, 768, 1024, 1280, 1536 on whole waves (K = 6, 8, 12, 16, 20, 24;
+// two pairs).
+#define AS_BAND16_CLASSES(X)                                                                               \
+  X(0, 4, 16) X(1, 6, 16) X(2, 8, 16) X(3, 12, 16) X(4, 16, 16) X(5, 6, 64) X(6, 8, 64) X(7, 12, 64) X(8, 16, 64) \
+      X(9, 20, 64) X(10, 24, 64)
 
 hipError_t launch_band_dp_i16(int pc, const BandArgs &args, int grid, hipStream_t stream) {
   switch (pc) {

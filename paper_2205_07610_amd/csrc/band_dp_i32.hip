@@ -291,15 +291,15 @@ __global__ void __launch_bounds__(kWave) band_dp_i32_kernel(BandArgs a, int kc) 
       atomicAdd(&a.ctr->band_accepted[a.round < kMaxBandRounds ? a.round : kMaxBandRounds - 1], 1);
       continue;
     }
-    band_requeue(a, d, bi.w, MODE, W);
+    band_requeue(a, d, bi.w, MODE, W, score);
   }
 }
 
 // Lane-width classes: 64, 128, 192, 256 and 384 diagonals on 16-lane groups
-// (K = 4, 8, 12, 16, 24; four pairs per wave), 512, 768 and 1024 on whole
-// waves (K = 8, 12, 16; one pair per wave), which keeps the registers a lane
-// holds low enough for several waves per SIMD.
-static_assert(kBandClasses == 8, "class table");
+// (K = 4, 8, 12, 16, 24; four pairs per wave), 512, 768, 1024, 1280 and 1536
+// on whole waves (K = 8, 12, 16, 20, 24; one pair per wave), which keeps the
+// registers a lane holds low enough for several waves per SIMD.
+static_assert(kBandClasses == 10, "class table");
 static_assert(sizeof(((Counters *)0)->next_band) == kBandClasses * sizeof(int32_t), "counters");
 template <int MODE, bool EXACT>
 hipError_t launch_mode(const BandArgs &args, int kc, int grid, hipStream_t stream) {
@@ -311,7 +311,9 @@ hipError_t launch_mode(const BandArgs &args, int kc, int grid, hipStream_t strea
     case 4: hipLaunchKernelGGL((band_dp_i32_kernel<MODE, 24, EXACT, 16>), dim3(grid), dim3(kWave), 0, stream, args, kc); break;
     case 5: hipLaunchKernelGGL((band_dp_i32_kernel<MODE, 8, EXACT, 64>), dim3(grid), dim3(kWave), 0, stream, args, kc); break;
     case 6: hipLaunchKernelGGL((band_dp_i32_kernel<MODE, 12, EXACT, 64>), dim3(grid), dim3(kWave), 0, stream, args, kc); break;
-    default: hipLaunchKernelGGL((band_dp_i32_kernel<MODE, 16, EXACT, 64>), dim3(grid), dim3(kWave), 0, stream, args, kc); break;
+    case 7: hipLaunchKernelGGL((band_dp_i32_kernel<MODE, 16, EXACT, 64>), dim3(grid), dim3(kWave), 0, stream, args, kc); break;
+    case 8: hipLaunchKernelGGL((band_dp_i32_kernel<MODE, 20, EXACT, 64>), dim3(grid), dim3(kWave), 0, stream, args, kc); break;
+    default: hipLaunchKernelGGL((band_dp_i32_kernel<MODE, 24, EXACT, 64>), dim3(grid), dim3(kWave), 0, stream, args, kc); break;
   }
   return hipGetLastError();
 }
@@ -347,7 +349,9 @@ int band_dp_i32_blocks_per_cu(int mode, int kc) {
       case 4: return occupancy<kGlobal, 24, 16>();
       case 5: return occupancy<kGlobal, 8, 64>();
       case 6: return occupancy<kGlobal, 12, 64>();
-      default: return occupancy<kGlobal, 16, 64>();
+      case 7: return occupancy<kGlobal, 16, 64>();
+      case 8: return occupancy<kGlobal, 20, 64>();
+      default: return occupancy<kGlobal, 24, 64>();
     }
   }
   switch (kc) {
@@ -358,7 +362,9 @@ int band_dp_i32_blocks_per_cu(int mode, int kc) {
     case 4: return occupancy<kSemiGlobal, 24, 16>();
     case 5: return occupancy<kSemiGlobal, 8, 64>();
     case 6: return occupancy<kSemiGlobal, 12, 64>();
-    default: return occupancy<kSemiGlobal, 16, 64>();
+    case 7: return occupancy<kSemiGlobal, 16, 64>();
+    case 8: return occupancy<kSemiGlobal, 20, 64>();
+    default: return occupancy<kSemiGlobal, 24, 64>();
   }
 }
 

@@ -70,8 +70,8 @@ constexpr int32_t kStatusPlan = 32;   // a planned replay met a batch its buffer
 
 // Banded classes: 32-bit (band_class_width) and packed 16-bit
 // (band16_class_width); banded rounds.
-constexpr int kBandClasses = 8;
-constexpr int kBand16Classes = 9;
+constexpr int kBandClasses = 10;
+constexpr int kBand16Classes = 11;
 constexpr int kMaxBandRounds = 8;
 
 // Full-DP work lists: packed 16-bit, 32-bit stripes, 32-bit wavefront,
@@ -136,11 +136,13 @@ constexpr size_t kCountersHead = offsetof(Counters, cost_count);
 // ---- banded path ----
 // Band widths (diagonals) of the banded kernel's classes: 16-lane groups
 // with K = 4, 8, 12, 16, 24 columns per lane, then whole waves with K = 8,
-// 12, 16.  Consecutive widths differ by at most 1.5x.
+// 12, 16, 20, 24.  Consecutive widths differ by at most 1.5x.
 __host__ __device__ inline int band_class_width(int kc) {
   return kc == 0 ? 64 : kc == 1 ? 128 : kc == 2 ? 192 : kc == 3 ? 256
-       : kc == 4 ? 384 : kc == 5 ? 512 : kc == 6 ? 768 : 1024;
+       : kc == 4 ? 384 : kc == 5 ? 512 : kc == 6 ? 768 : kc == 7 ? 1024 : kc == 8 ? 1280 : 1536;
 }
+// Widest band of the exact and raw entry points and of the label search.
+constexpr int kRawBandMax = 1024;
 
 // Smallest class whose width holds B diagonals, or -1.
 __host__ __device__ inline int band_class_for(int B) {
@@ -245,10 +247,10 @@ int band_dp_i16_blocks_per_cu(int pc);
 int band_dp_i16_pairs_per_wave(int pc);
 
 // Widths of the packed classes (lane-group size x registers per lane):
-// 16 x {4, 6, 8, 12, 16}, then 64 x {6, 8, 12, 16}.
+// 16 x {4, 6, 8, 12, 16}, then 64 x {6, 8, 12, 16, 20, 24}.
 __host__ __device__ inline int band16_class_width(int pc) {
   return pc == 0 ? 64 : pc == 1 ? 96 : pc == 2 ? 128 : pc == 3 ? 192 : pc == 4 ? 256
-       : pc == 5 ? 384 : pc == 6 ? 512 : pc == 7 ? 768 : 1024;
+       : pc == 5 ? 384 : pc == 6 ? 512 : pc == 7 ? 768 : pc == 8 ? 1024 : pc == 9 ? 1280 : 1536;
 }
 __host__ __device__ inline int band16_class_lanes(int pc) { return pc < 5 ? kGroup : kWave; }
 __host__ __device__ inline int band16_class_for(int B) {
@@ -318,20 +320,47 @@ __host__ __device__ inline int band_widest_w(int m, int n, bool pack16, int smax
   const int w = (W - (n - m) - 1) / 2;
   return (W > 0 && W >= n - m + 1) ? w : -1;
 }
-// A rejected band (this round computed W_cur diagonals): queue the pair for
-// the next round with the half-width doubled.  When the doubled band fits no
-// class but a class wider than W_cur exists, the pair gets the widest band
-// instead; the full DP takes it when no wider band is left or the rounds are
-// spent.
-__device__ inline void band_requeue(const BandArgs &a, const PairDesc &d, int w, int mode, int W_cur) {
+// Global mode: the smallest half-width w whose band of diagonals
+// [min(0, n-m) - w, max(0, n-m) + w] has a leave bound (band_leave_bound) of
+// at most `score`: sigma_max (min(m, n) - w - 1) - 2 alpha - beta (|n - m| +
+// 2 w) <= score.  A band that contains the rejected one scores at least
+// `score`, so it is accepted from this half-width on; when the rejected band
+// held an optimal path this is exactly the pair's smallest accepted band.
+// -1 when the bound does not shrink with w.
+__host__ __device__ inline int band_w_for_score(int m, int n, int score, int sigma_max, int alpha, int beta) {
+  const int64_t den = (int64_t)sigma_max + 2LL * beta;
+  if (den <= 0) return -1;
+  const int64_t mn = m < n ? m : n, dn = m < n ? n - m : m - n;
+  const int64_t num = (int64_t)sigma_max * (mn - 1) - 2LL * alpha - (int64_t)beta * dn - score;
+  if (num <= 0) return 0;
+  const int64_t w = (num + den - 1) / den;
+  return w < (1 << 30) ? (int)w : (1 << 30);
+}
+
+// A rejected band (this round computed W_cur diagonals, banded score
+// `score`): queue the pair for the next round.  Global mode takes the
+// half-width at which the score would pass the certificate
+// (band_w_for_score), semi-global doubles it.  When that band fits no class
+// but a class wider than W_cur exists, the pair gets the widest band
+// instead, unless (global) the score already shows that the widest band
+// cannot pass with the same score; the full DP takes it when no wider band
+// is left or the rounds are spent.
+__device__ inline void band_requeue(const BandArgs &a, const PairDesc &d, int w, int mode, int W_cur, int score) {
   int w2 = w > 0 ? 2 * w : 1;
+  const int wr = mode == kGlobal ? band_w_for_score(d.m, d.n, score, a.sigma_max, a.alpha, a.beta) : -1;
+  if (wr > w) w2 = wr;
   bool packed = false;
   const bool p16 = a.pack16 && mode == kGlobal;
   int c = band_route(d.m, d.n, w2, p16, a.smax_pos, a.drop16, a.alpha, a.beta, &packed);
+  if (c >= 0 && wr > w && (packed ? band16_class_width(c) : band_class_width(c)) <= W_cur) {
+    // the computed band would not grow (class rounding): double instead
+    w2 = 2 * w2;
+    c = band_route(d.m, d.n, w2, p16, a.smax_pos, a.drop16, a.alpha, a.beta, &packed);
+  }
   if (c < 0) {
     int Wmax = 0;
     const int wcap = band_widest_w(d.m, d.n, p16, a.smax_pos, a.drop16, a.alpha, a.beta, &Wmax);
-    if (Wmax > W_cur && wcap > w) {
+    if (Wmax > W_cur && wcap > w && !(wr > wcap)) {
       w2 = wcap;
       c = band_route(d.m, d.n, w2, p16, a.smax_pos, a.drop16, a.alpha, a.beta, &packed);
     }

@@ -410,7 +410,8 @@ __global__ void __launch_bounds__(256) band_classify_kernel(RouteParams c, const
     bi.w = w;
     bi.pad_ = 0;
     if (raw) {
-      const int kc = band_class_for(bi.d.n - bi.d.m + 2 * w + 1);
+      const int B = bi.d.n - bi.d.m + 2 * w + 1;
+      const int kc = B <= kRawBandMax ? band_class_for(B) : -1;
       if (kc < 0) {
         if (first) atomicOr(&ctr->status, kStatusArg);
         return -1;

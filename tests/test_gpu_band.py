@@ -185,3 +185,40 @@ def test_packed_band_lower_range_harsh_scoring(gpu, oracle_mod):
         _say(f"harsh scoring packed={on}: {st}")
         assert np.array_equal(sc.cpu().numpy(), want), (on, np.nonzero(sc.cpu().numpy() != want)[0])
     gpu.set_band_packing(True)
+
+
+def test_wide_band_classes(gpu, oracle_mod):
+    """Bands of 1280 and 1536 diagonals (whole-wave lane groups with K = 20
+    and 24 registers per lane): pairs of ~3000 residues take the packed
+    kernel, pairs of ~4900 (past the packed range proof) the 32-bit one.
+    Related pairs at 10-14% divergence need more than 1024 diagonals, so the
+    wide classes accept what the full DP would otherwise compute; unrelated
+    pairs are rejected and fall back.  Every score equals the oracle's, with
+    the packed kernel on and off."""
+    import torch
+    rng = np.random.default_rng(790)
+    pairs = []
+    for L in (2900, 3100, 4800, 4950):
+        for div in (0.10, 0.14, None):
+            a = rng.integers(0, 4, L).astype(np.uint8)
+            if div is None:
+                sb = rng.integers(0, 4, L + int(rng.integers(-30, 30))).astype(np.uint8)
+            else:
+                sb, _ = synth.mutate(rng, a, np.array([0, L]), [div / 2], [div / 4], [div / 4], 4)
+            pairs.append((a, sb))
+    bb = synth.from_pairs("wide bands", pairs, DNA, 5, 2, 0)
+    want = oracle_mod.align_batch(bb.seqs_a, bb.offs_a, bb.seqs_b, bb.offs_b, DNA, 5, 2, 0)
+    dev = gpu.to_device(bb)
+    dn = np.abs(bb.lens_a.astype(np.int64) - bb.lens_b.astype(np.int64))
+    for need in (1200, 1500):
+        # half-widths whose request needs about `need` diagonals
+        w = _w(torch, np.maximum(0, (need - 1 - dn) // 2))
+        for on in (True, False):
+            gpu.set_band_packing(on)
+            sc, st = gpu.align_batch_band(*dev, DNA, 5, 2, 0, w, max_rounds=3)
+            _say(f"wide bands need~{need} packed={on}: {st}")
+            assert np.array_equal(sc.cpu().numpy(), want), (need, on, np.nonzero(sc.cpu().numpy() != want)[0])
+            assert st["accepted"][0] >= 4, st
+            if on:
+                assert st["band16_cells"] > 0 and st["band_cells"] > st["band16_cells"], st
+    gpu.set_band_packing(True)
