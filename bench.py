@@ -226,7 +226,7 @@ def own_label_cells(batch, labels, band_wide):
         for W in (64, 96, 128, 192, 256, 384, 512, 768, 1024, 1280, 1536):
             ub = smax_pos * rows + batch.beta * (la + lb + W) + batch.alpha + 2 * batch.beta + 256
             lo = drop * rows + 3 * (batch.alpha - batch.beta) + 256
-            ok = ok_label & ~chosen & (need <= W) & (4 * W <= 3 * cols) & (ub < 32000) & (lo < 32000)
+            ok = ok_label & ~chosen & (need <= W) & (4 * W <= 3 * cols) & (ub + lo < 65000) & (lo < 32000)
             cells = np.where(ok, rows * W, cells)
             chosen |= ok
     for W in (64, 128, 192, 256, 384, 512, 768, 1024, 1280, 1536):

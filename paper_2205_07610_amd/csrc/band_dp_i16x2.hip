@@ -22,8 +22,9 @@
 //    the selectors of the CH entering columns; the residues were loaded one
 //    chunk ahead.  A step then costs the cell updates, two LDS reads and
 //    three DPP moves.
-//  * Values are stored with a bias of 32768 as unsigned 16-bit numbers, so 0
-//    is -infinity: DPP moves that shift in from outside the group write 0
+//  * Values are stored with a bias as unsigned 16-bit numbers, so 0 is
+//    -infinity (the bias is 32768, or lower for a pair whose upper bound
+//    needs the room: band16_bias): DPP moves that shift in from outside the group write 0
 //    themselves, and all packed arithmetic saturates, so -infinity stays put
 //    and never wraps.  Columns left of column 0 hold -infinity (in global
 //    mode no alignment path visits them) and column 0 itself is produced
@@ -45,7 +46,6 @@ namespace {
 
 typedef unsigned short u2 __attribute__((ext_vector_type(2)));
 
-constexpr int kBias = 32768;  // stored = shifted-frame value + kBias; 0 is -infinity
 
 __device__ __forceinline__ int as_i(u2 v) { return __builtin_bit_cast(int, v); }
 __device__ __forceinline__ u2 as_u2(int v) { return __builtin_bit_cast(u2, v); }
@@ -191,15 +191,17 @@ band_dp_i16_kernel(BandArgs a, int pc) {
       return qt[(tr ? 4 : 0) + r];
     };
     // row 0: column 0 is the corner, columns left of it are outside the matrix
-    auto init1 = [&](int lo, int x) -> int {
+    const int bias0 = band16_bias(m0, n0, W, a.smax_pos, alpha, beta);
+    const int bias1 = band16_bias(m1, n1, W, a.smax_pos, alpha, beta);
+    auto init1 = [&](int lo, int bias, int x) -> int {
       const int j = lo + kb + x;
-      return j < 0 ? 0 : kBias + (j == 0 ? beta - alpha : 2 * beta - 2 * alpha);
+      return j < 0 ? 0 : bias + (j == 0 ? beta - alpha : 2 * beta - 2 * alpha);
     };
     u2 Ha[K], Ee[K];
     uint32_t P[K];  // selector words; register x's is P[(x + u) % K] at step u
 #pragma unroll
     for (int x = 0; x < K; ++x) {
-      Ha[x] = pk(init1(lo0, x), init1(lo1, x));
+      Ha[x] = pk(init1(lo0, bias0, x), init1(lo1, bias1, x));
       Ee[x] = pk(0, 0);
       const int j0 = -t + lo0 + kb + x, j1 = -t + lo1 + kb + x;
       P[x] = make_sel(col_code(has0, n0, j0, col_byte(cols0, n0, j0)),
@@ -303,12 +305,12 @@ band_dp_i16_kernel(BandArgs a, int pc) {
           if (it0 + u == e0) {
 #pragma unroll
             for (int x = 0; x < K; ++x)
-              if (x == kn0 % K) res0 = (int)Ha[x].x - kBias + amb - beta * (m0 + n0);
+              if (x == kn0 % K) res0 = (int)Ha[x].x - bias0 + amb - beta * (m0 + n0);
           }
           if (it0 + u == e1) {
 #pragma unroll
             for (int x = 0; x < K; ++x)
-              if (x == kn1 % K) res1 = (int)Ha[x].y - kBias + amb - beta * (m1 + n1);
+              if (x == kn1 % K) res1 = (int)Ha[x].y - bias1 + amb - beta * (m1 + n1);
           }
         }
       }

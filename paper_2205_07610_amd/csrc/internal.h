@@ -264,13 +264,28 @@ __host__ __device__ inline int band16_class_for(int B) {
 // beta)), drop = max(0, -(sigma_min + 2 beta)): the band holds the path
 // that runs down diagonal 0 and then takes one gap run to the cell, and in
 // the shifted frame a diagonal step adds sigma + 2 beta and a gap run costs
-// alpha - beta.  Inside int16 when both stay within 32000.
+// alpha - beta.  The packed kernel stores a cell as its value plus a bias
+// in an unsigned 16-bit number with 0 as -infinity (band16_bias), so the
+// whole range, from the lower bound to the upper one, has to fit 65535.
+__host__ __device__ inline int64_t band16_ub(int m, int n, int W, int smax_pos, int alpha, int beta) {
+  const int64_t mn = m < n ? m : n;
+  return (int64_t)smax_pos * mn + (int64_t)beta * ((int64_t)m + n + W) + alpha + 2 * beta + 256;
+}
+__host__ __device__ inline int64_t band16_lb(int m, int n, int drop, int alpha, int beta) {
+  const int64_t mn = m < n ? m : n;
+  return (int64_t)drop * mn + 3LL * (alpha - beta) + 256;
+}
 __host__ __device__ inline bool band16_range_ok(int m, int n, int W, int smax_pos, int drop, int alpha,
                                                 int beta) {
-  const int64_t mn = m < n ? m : n;
-  const int64_t ub = (int64_t)smax_pos * mn + (int64_t)beta * ((int64_t)m + n + W) + alpha + 2 * beta + 256;
-  const int64_t lb = (int64_t)drop * mn + 3LL * (alpha - beta) + 256;
-  return ub < 32000 && lb < 32000;
+  const int64_t ub = band16_ub(m, n, W, smax_pos, alpha, beta), lb = band16_lb(m, n, drop, alpha, beta);
+  return lb < 32000 && ub + lb < 65000;
+}
+// Bias of a range-proven pair: 32768 when its upper bound leaves room, else
+// as low as the upper bound needs (at least lb + 1 by the range proof), so
+// every cell is stored in [1, 65280].
+__host__ __device__ inline int band16_bias(int m, int n, int W, int smax_pos, int alpha, int beta) {
+  const int64_t room = 65280 - band16_ub(m, n, W, smax_pos, alpha, beta);
+  return room < 32768 ? (int)room : 32768;
 }
 // Whether a band of W diagonals is worth computing for an n-column pair
 // instead of the full DP: a packed band at most 3/4 of the row (it costs

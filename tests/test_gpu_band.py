@@ -123,9 +123,9 @@ def test_band_api_errors(gpu):
 
 def test_packed_band_matches_32bit_and_oracle(gpu, oracle_mod):
     """Global certified banding with the packed 16-bit kernel on (default)
-    and off: both equal the oracle's full DP for every pair.  Lengths run
-    past the packed range limit (pairs of ~4900 and ~6000 residues go to the
-    32-bit kernel, or switch kernels between rounds), initial half-widths
+    and off: both equal the oracle's full DP for every pair.  Pairs of ~4900
+    and ~6000 residues need the packed kernel's lowered bias (their upper
+    bound passes 32768), initial half-widths
     range from 0 to wide, so pairs are accepted, doubled and sent to the
     full DP; one case spreads the initial widths over every class.  The
     packed classes of 96, 192, 384 and 768 diagonals (K = 6 or 12 registers
@@ -190,16 +190,16 @@ def test_packed_band_lower_range_harsh_scoring(gpu, oracle_mod):
 def test_wide_band_classes(gpu, oracle_mod):
     """Bands of 1280 and 1536 diagonals (whole-wave lane groups with K = 20
     and 24 registers per lane): pairs of ~3000 residues take the packed
-    kernel, pairs of ~4900 (past the packed range proof) the 32-bit one.
-    Related pairs at 10-14% divergence need more than 1024 diagonals, so the
-    wide classes accept what the full DP would otherwise compute; unrelated
-    pairs are rejected and fall back.  Every score equals the oracle's, with
-    the packed kernel on and off."""
+    kernel, pairs of ~10500 (past the packed range proof) the 32-bit one.
+    Related pairs at 10-14% (short) or 5-6.5% (long) divergence need more
+    than 1024 diagonals, so the wide classes accept what the full DP would
+    otherwise compute; unrelated pairs are rejected and fall back.  Every
+    score equals the oracle's, with the packed kernel on and off."""
     import torch
     rng = np.random.default_rng(790)
     pairs = []
-    for L in (2900, 3100, 4800, 4950):
-        for div in (0.10, 0.14, None):
+    for L, divs in ((2900, (0.10, 0.14)), (3100, (0.10, 0.14)), (10400, (0.05, 0.065)), (10600, (0.05, 0.065))):
+        for div in divs + (None,):
             a = rng.integers(0, 4, L).astype(np.uint8)
             if div is None:
                 sb = rng.integers(0, 4, L + int(rng.integers(-30, 30))).astype(np.uint8)
