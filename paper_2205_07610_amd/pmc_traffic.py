@@ -77,12 +77,18 @@ def summarise(fetch_dir, write_dir, workload_name, workload_desc):
         return sorted(((int(r["Dispatch_Id"]), float(r["Counter_Value"])) for r in R
                        if pred(short(r["Kernel_Name"]))), key=lambda x: x[0])
 
-    # bench.py times the full DP before the learned path, so the timed
-    # learned step's launches are the ones after the full-DP step's
-    # wavefront launch (the largest wavefront launch of the run, 32-bit or
-    # packed); earlier ones belong to training and its diagnostics
+    # bench.py times the full DP, then the learned path, then the fixed-band
+    # comparison.  The timed learned step starts with the first feature
+    # launch after the full-DP step's wavefront launch (the largest
+    # wavefront launch of the run, 32-bit or packed; earlier launches belong
+    # to training and its diagnostics) and ends before the next call's band
+    # classification (the step itself classifies once).
     long_rows = rows_of(F, GROUPS["long"][0]) + rows_of(F, GROUPS["long16"][0])
     after = max(long_rows, key=lambda x: x[1])[0] if long_rows else -1
+    feats = [d for d, _ in rows_of(F, GROUPS["features"][0]) if d > after]
+    start = feats[0] if feats else after + 1
+    classify = [d for d, _ in rows_of(F, lambda k: k.startswith("band_classify_kernel")) if d > start]
+    end = classify[1] if len(classify) > 1 else float("inf")
     out = {}
     for g, (pred, src, unit) in GROUPS.items():
         fr, wr = rows_of(F, pred), rows_of(W, pred)
@@ -93,8 +99,8 @@ def summarise(fetch_dir, write_dir, workload_name, workload_desc):
             fr, wr = [fr[i]], [wr[i]]
             note = "unit: the full-DP step's launch (largest of the run)"
         else:
-            fr = [x for x in fr if x[0] > after]
-            wr = [x for x in wr if x[0] > after]
+            fr = [x for x in fr if start <= x[0] < end]
+            wr = [x for x in wr if start <= x[0] < end]
             note = "unit: all launches of the one timed learned step (every class and round)"
         if not fr:
             continue
