@@ -71,7 +71,7 @@ constexpr int32_t kStatusPlan = 32;   // a planned replay met a batch its buffer
 // Banded classes: 32-bit (band_class_width) and packed 16-bit
 // (band16_class_width); banded rounds.
 constexpr int kBandClasses = 10;
-constexpr int kBand16Classes = 11;
+constexpr int kBand16Classes = 19;
 constexpr int kMaxBandRounds = 8;
 
 // Full-DP work lists: packed 16-bit, 32-bit stripes, 32-bit wavefront,
@@ -246,13 +246,17 @@ hipError_t launch_band_dp_i16(int pc, const BandArgs &args, int grid, hipStream_
 int band_dp_i16_blocks_per_cu(int pc);
 int band_dp_i16_pairs_per_wave(int pc);
 
-// Widths of the packed classes (lane-group size x registers per lane):
-// 16 x {4, 6, 8, 12, 16}, then 64 x {6, 8, 12, 16, 20, 24}.
-__host__ __device__ inline int band16_class_width(int pc) {
-  return pc == 0 ? 64 : pc == 1 ? 96 : pc == 2 ? 128 : pc == 3 ? 192 : pc == 4 ? 256
-       : pc == 5 ? 384 : pc == 6 ? 512 : pc == 7 ? 768 : pc == 8 ? 1024 : pc == 9 ? 1280 : 1536;
+// Packed classes (lane-group size x registers per lane): 16 x {4, 5, 6, 7,
+// 8, 10, 12, 14, 16}, then 64 x {5, 6, 7, 8, 10, 12, 14, 16, 20, 24}:
+// widths 64..256 and 320..1536 diagonals, adjacent ones 1.14-1.25x apart.
+constexpr int kBand16Narrow = 9;  // classes on 16-lane groups
+__host__ __device__ constexpr int band16_class_k(int pc) {
+  const int k8 = pc < kBand16Narrow ? pc : pc - kBand16Narrow + 1;  // the same K ladder from 4 on
+  return k8 == 0 ? 4 : k8 == 1 ? 5 : k8 == 2 ? 6 : k8 == 3 ? 7 : k8 == 4 ? 8 : k8 == 5 ? 10
+       : k8 == 6 ? 12 : k8 == 7 ? 14 : k8 == 8 ? 16 : k8 == 9 ? 20 : 24;
 }
-__host__ __device__ inline int band16_class_lanes(int pc) { return pc < 5 ? kGroup : kWave; }
+__host__ __device__ constexpr int band16_class_lanes(int pc) { return pc < kBand16Narrow ? kGroup : kWave; }
+__host__ __device__ constexpr int band16_class_width(int pc) { return band16_class_lanes(pc) * band16_class_k(pc); }
 __host__ __device__ inline int band16_class_for(int B) {
   for (int pc = 0; pc < kBand16Classes; ++pc)
     if (band16_class_width(pc) >= B) return pc;
