@@ -223,7 +223,7 @@ def own_label_cells(batch, labels, band_wide):
     chosen = np.zeros(len(la), dtype=bool)
     ok_label = labels < band_wide
     if batch.mode == 0:
-        for W in (64, 80, 96, 112, 128, 160, 192, 224, 256, 320, 384, 448, 512, 640, 768, 896, 1024, 1280, 1536):
+        for W in (80, 96, 112, 128, 160, 192, 224, 256, 320, 384, 448, 512, 640, 768, 896, 1024, 1280, 1536):
             ub = smax_pos * rows + batch.beta * (la + lb + W) + batch.alpha + 2 * batch.beta + 256
             lo = drop * rows + 3 * (batch.alpha - batch.beta) + 256
             ok = ok_label & ~chosen & (need <= W) & (4 * W <= 3 * cols) & (ub + lo < 65000) & (lo < 32000)

@@ -353,7 +353,7 @@ int as_plan_destroy(as_plan *plan);
  * Packed 16-bit banded kernel (global mode): a pair whose band cells are
  * proven to fit int16 (sigma_max*min(m,n) + beta*(m + n + W) + margins below
  * 32000, W the band width in diagonals) is banded two pairs per lane group
- * with 16-bit cells, in widths of 64 to 1536 diagonals; the
+ * with 16-bit cells, in widths of 80 to 1536 diagonals; the
  * others use the 32-bit banded kernel.  On by default; on = 0 sends every
  * pair to the 32-bit kernel (scores are the same either way).  Returns the
  * previous setting.

@@ -112,14 +112,14 @@ constexpr int chunk_steps(int K, int G) {
                      : (K == 7 || K == 14 ? 42 : K == 5 || K == 10 || K == 20 ? 40 : 48);
 }
 
-// Waves per SIMD the register allocation aims for: four for the narrowest
-// class; two for K = 20 and 24 (their state alone fills three waves'
-// registers) and for K = 10..14 on 16-lane groups (K = 12 measured 8% faster
-// than three with spills); three for the others (what the compiler would pick for the
-// wider ones is two; the few values it then spills are reloaded once per
-// pair, outside the DP loops, and two waves measured slower for K = 16).
+// Waves per SIMD the register allocation aims for: two for K = 20 and 24
+// (their state alone fills three waves' registers) and for K = 10..14 on
+// 16-lane groups (K = 12 measured 8% faster than three with spills); three
+// for the others (what the compiler would pick for the wider ones is two;
+// the few values it then spills are reloaded once per pair, outside the DP
+// loops, and two waves measured slower for K = 16).
 template <int K, int G>
-constexpr int kWavesPerEu = (K == 4 && G == kGroup) ? 4 : (K >= 20 || (K >= 10 && K <= 14 && G == kGroup) ? 2 : 3);
+constexpr int kWavesPerEu = (K >= 20 || (K >= 10 && K <= 14 && G == kGroup)) ? 2 : 3;
 
 template <int K, int G>
 __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(kWavesPerEu<K, G>)))
@@ -369,19 +369,19 @@ int occupancy() {
 
 }  // namespace
 
-// Packed classes (band16_class_k): 64..256 diagonals on 16-lane groups
-// (K = 4, 5, 6, 7, 8, 10, 12, 14, 16; eight pairs per wave), 320..1536 on
+// Packed classes (band16_class_k): 80..256 diagonals on 16-lane groups
+// (K = 5, 6, 7, 8, 10, 12, 14, 16; eight pairs per wave), 320..1536 on
 // whole waves (K = 5, 6, 7, 8, 10, 12, 14, 16, 20, 24; two pairs).
 #define AS_BAND16_CLASSES(X)                                                                             \
-  X(0, 4, 16) X(1, 5, 16) X(2, 6, 16) X(3, 7, 16) X(4, 8, 16) X(5, 10, 16) X(6, 12, 16) X(7, 14, 16)       \
-      X(8, 16, 16) X(9, 5, 64) X(10, 6, 64) X(11, 7, 64) X(12, 8, 64) X(13, 10, 64) X(14, 12, 64)         \
-          X(15, 14, 64) X(16, 16, 64) X(17, 20, 64) X(18, 24, 64)
+  X(0, 5, 16) X(1, 6, 16) X(2, 7, 16) X(3, 8, 16) X(4, 10, 16) X(5, 12, 16) X(6, 14, 16) X(7, 16, 16)     \
+      X(8, 5, 64) X(9, 6, 64) X(10, 7, 64) X(11, 8, 64) X(12, 10, 64) X(13, 12, 64) X(14, 14, 64)         \
+          X(15, 16, 64) X(16, 20, 64) X(17, 24, 64)
 
 #define AS_CHECK(PC, K, G) \
   static_assert(band16_class_k(PC) == K && band16_class_lanes(PC) == G, "packed class table");
 AS_BAND16_CLASSES(AS_CHECK)
 #undef AS_CHECK
-static_assert(kBand16Classes == 19, "packed class list");
+static_assert(kBand16Classes == 18, "packed class list");
 
 hipError_t launch_band_dp_i16(int pc, const BandArgs &args, int grid, hipStream_t stream) {
   switch (pc) {

@@ -71,7 +71,7 @@ constexpr int32_t kStatusPlan = 32;   // a planned replay met a batch its buffer
 // Banded classes: 32-bit (band_class_width) and packed 16-bit
 // (band16_class_width); banded rounds.
 constexpr int kBandClasses = 10;
-constexpr int kBand16Classes = 19;
+constexpr int kBand16Classes = 18;
 constexpr int kMaxBandRounds = 8;
 
 // Full-DP work lists: packed 16-bit, 32-bit stripes, 32-bit wavefront,
@@ -246,14 +246,17 @@ hipError_t launch_band_dp_i16(int pc, const BandArgs &args, int grid, hipStream_
 int band_dp_i16_blocks_per_cu(int pc);
 int band_dp_i16_pairs_per_wave(int pc);
 
-// Packed classes (lane-group size x registers per lane): 16 x {4, 5, 6, 7,
-// 8, 10, 12, 14, 16}, then 64 x {5, 6, 7, 8, 10, 12, 14, 16, 20, 24}:
-// widths 64..256 and 320..1536 diagonals, adjacent ones 1.14-1.25x apart.
-constexpr int kBand16Narrow = 9;  // classes on 16-lane groups
+// Packed classes (lane-group size x registers per lane): 16 x {5, 6, 7, 8,
+// 10, 12, 14, 16}, then 64 x {5, 6, 7, 8, 10, 12, 14, 16, 20, 24}: widths
+// 80..256 and 320..1536 diagonals, adjacent ones 1.14-1.25x apart.  No
+// 64-diagonal class: with four registers per lane the step's fixed costs
+// and dependency chain leave it at 0.35-0.41 of the packed peak against
+// 0.60 for 80 diagonals, so the wider band is the faster one.
+constexpr int kBand16Narrow = 8;  // classes on 16-lane groups
 __host__ __device__ constexpr int band16_class_k(int pc) {
-  const int k8 = pc < kBand16Narrow ? pc : pc - kBand16Narrow + 1;  // the same K ladder from 4 on
-  return k8 == 0 ? 4 : k8 == 1 ? 5 : k8 == 2 ? 6 : k8 == 3 ? 7 : k8 == 4 ? 8 : k8 == 5 ? 10
-       : k8 == 6 ? 12 : k8 == 7 ? 14 : k8 == 8 ? 16 : k8 == 9 ? 20 : 24;
+  const int k = pc < kBand16Narrow ? pc : pc - kBand16Narrow;  // the same K ladder on both
+  return k == 0 ? 5 : k == 1 ? 6 : k == 2 ? 7 : k == 3 ? 8 : k == 4 ? 10 : k == 5 ? 12
+       : k == 6 ? 14 : k == 7 ? 16 : k == 8 ? 20 : 24;
 }
 __host__ __device__ constexpr int band16_class_lanes(int pc) { return pc < kBand16Narrow ? kGroup : kWave; }
 __host__ __device__ constexpr int band16_class_width(int pc) { return band16_class_lanes(pc) * band16_class_k(pc); }
