@@ -103,14 +103,17 @@ WORKLOAD_NAME = {"name": None}
 def traffic_for(kernel: str):
     """HBM bytes of the kernel's roofline unit (one launch, or all launches of
     one step for the banded and feature kernels) from the committed rocprofv3
-    PMC summary, if it was taken on the current kernel source and on this
-    workload; else None."""
+    PMC summary, if it was taken on the current kernel and routing sources
+    and on this workload; else None."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
     if rec.get("source_sha") != source_sha(KERNEL_SOURCES[kernel]):
+        return None
+    from paper_2205_07610_amd.pmc_traffic import routing_sha
+    if rec.get("routing_sha") != routing_sha():
         return None
     if rec.get("workload_name") != WORKLOAD_NAME["name"]:
         return None

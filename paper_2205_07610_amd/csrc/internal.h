@@ -475,6 +475,10 @@ hipError_t launch_long_dp_i16(const Long16Args &args, int grid, hipStream_t stre
 int long_dp_i16_blocks_per_cu();
 int long_dp_i16_stripe_width();
 constexpr int kLong16Width = 1024;  // columns per packed wavefront stripe (64 lanes x 16)
+// Rows from which the automatic routing takes the packed wavefront: its
+// 63-step pipeline fill per stripe is then at most 6% of the stripe, and it
+// runs faster than the 32-bit stripe kernel from there on.
+constexpr int kLong16MinRows = 1024;
 // A global pair whose every shifted cell provably fits int16 (columns past n
 // only lower cells, so the full matrix bound holds for the padded stripes).
 __host__ __device__ inline bool long16_range_ok(int64_t m, int64_t n, int smax_pos, int alpha, int beta) {

@@ -70,7 +70,8 @@ __device__ inline void fill_desc(PairDesc &d, bool tr, int64_t a0, int64_t m, in
 // it can serve; the others take the automatic rule: packed 16-bit when the
 // shorter side fits one packed stripe and the range is proven (or local:
 // saturation is detected at run time), the wavefront for pairs with many
-// rows and more than one wavefront stripe, else 32-bit stripes of 256.
+// rows (the packed one from 1024, the 32-bit one from 2048) and more than
+// one wavefront stripe, else 32-bit stripes of 256.
 __device__ int route_pair(const RouteParams &c, int64_t a0, int64_t m, int64_t b0, int64_t n, int64_t p,
                           PairDesc &d, int &bin) {
   bin = length_bin(m > n ? m : n);
@@ -91,10 +92,11 @@ __device__ int route_pair(const RouteParams &c, int64_t a0, int64_t m, int64_t b
                        (int64_t)c.beta * (kGroup * 16) + c.alpha + 2 * c.beta + 256;
     if (ub < 32000) return kList16;
   }
-  if (d.n > c.long_w && (v == kVarLong || (v < 0 && d.m >= c.long_min_rows))) {
-    if (c.long16 && c.mode == kGlobal && c.allow16 && long16_range_ok(m, n, c.smax_pos, c.alpha, c.beta))
+  if (d.n > c.long_w && (v == kVarLong || v < 0)) {
+    if (c.long16 && c.mode == kGlobal && c.allow16 && (v == kVarLong || d.m >= kLong16MinRows) &&
+        long16_range_ok(m, n, c.smax_pos, c.alpha, c.beta))
       return kListLong16;
-    return kListLong;
+    if (v == kVarLong || d.m >= c.long_min_rows) return kListLong;
   }
   return kList32;
 }

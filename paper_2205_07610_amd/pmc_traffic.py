@@ -12,8 +12,8 @@ the 1 GiB device copy that `--copy-reference` launches (rocclr's copyBuffer
 with a grid of 131072 threads): the factor that makes the copy read, and
 write, exactly 1 GiB.  With --write, one JSON record per kernel group goes to
 profiles/<group>_traffic.json, keyed by the kernel source's SHA-1 and the
-workload name so that bench.py reports it only for the same source and
-workload.  The unit the bytes cover is the one bench.py's roofline uses for
+workload name (and the runtime's routing source) so that bench.py reports
+it only for the same sources and workload.  The unit the bytes cover is the one bench.py's roofline uses for
 that kernel: for the banded and feature kernels all launches of one step,
 for the full-DP kernels the full-DP step's one launch.
 """
@@ -69,6 +69,19 @@ def sha(path: str) -> str:
         return hashlib.sha1(f.read()).hexdigest()[:12]
 
 
+# The runtime's routing decides which pairs each kernel gets, so a record also
+# holds the hash of the runtime source and the shared header.
+ROUTING_SOURCES = ("paper_2205_07610_amd/csrc/runtime.hip", "paper_2205_07610_amd/csrc/internal.h")
+
+
+def routing_sha() -> str:
+    h = hashlib.sha1()
+    for path in ROUTING_SOURCES:
+        with open(os.path.join(ROOT, path), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:12]
+
+
 def summarise(fetch_dir, write_dir, workload_name, workload_desc):
     F, W = load(fetch_dir), load(write_dir)
     sf, sw = copy_scale(F), copy_scale(W)
@@ -107,7 +120,8 @@ def summarise(fetch_dir, write_dir, workload_name, workload_desc):
         n = len(fr)
         fb = sum(x[1] for x in fr) * 1024 * sf
         wb = sum(x[1] for x in wr) * 1024 * sw
-        out[g] = {"kernel": g, "source": src, "source_sha": sha(src), "launches": n, "note": note,
+        out[g] = {"kernel": g, "source": src, "source_sha": sha(src), "routing_sha": routing_sha(),
+                  "launches": n, "note": note,
                   "fetch_bytes": fb, "write_bytes": wb, "bytes_per_unit": fb + wb,
                   "fetch_scale": round(sf, 4), "write_scale": round(sw, 4),
                   "workload": workload_desc, "workload_name": workload_name}

@@ -213,10 +213,11 @@ def test_wavefront_long_pairs(gpu, oracle_mod, mode):
         tm = gpu.last_timing()
     finally:
         gpu.enable_timing(False)
-    # (2048, 1025) is oriented with 1025 rows and stays on the 16-lane path;
-    # in global mode the others fit the packed wavefront's range proof
+    # (2048, 1025) is oriented with 1025 rows: the packed wavefront takes it
+    # in global mode (from 1024 rows), the 32-bit wavefront does not (2048);
+    # in global mode every pair fits the packed wavefront's range proof
     if mode == 0:
-        assert tm["pairs_long16"] == len(pairs) - 1 and tm["pairs_long"] == 0
+        assert tm["pairs_long16"] == len(pairs) and tm["pairs_long"] == 0
     else:
         assert tm["pairs_long"] == len(pairs) - 1 and tm["pairs_long16"] == 0
 
@@ -252,10 +253,10 @@ def test_packed_wavefront_duos(gpu, oracle_mod):
         gpu.enable_timing(False)
     _say(f"packed wavefront: {tm['pairs_long16']} pairs in {tm['long16_ms']:.2f} ms, "
          f"32-bit wavefront {tm['pairs_long']}")
-    # wavefront pairs have at least 2048 rows and more than 1024 columns
+    # packed wavefront pairs have at least 1024 rows and more than 1024 columns
     def wavefront(m, n):
         rows, cols = _oriented(m, n)
-        return rows >= 2048 and cols > 1024
+        return rows >= 1024 and cols > 1024
     expect = sum(wavefront(len(a), len(s)) for a, s in pairs[:-1])
     assert expect >= 20
     assert tm["pairs_long16"] == expect and tm["pairs_long"] == 1
