@@ -136,7 +136,7 @@ constexpr size_t kCountersHead = offsetof(Counters, cost_count);
 // ---- banded path ----
 // Band widths (diagonals) of the banded kernel's classes: 16-lane groups
 // with K = 4, 8, 12, 16, 24 columns per lane, then whole waves with K = 8,
-// 12, 16, 20, 24.  Consecutive widths differ by at most 1.5x.
+// 12, 16, 20, 24.  Consecutive widths differ by at most 1.5x from 128 on.
 __host__ __device__ inline int band_class_width(int kc) {
   return kc == 0 ? 64 : kc == 1 ? 128 : kc == 2 ? 192 : kc == 3 ? 256
        : kc == 4 ? 384 : kc == 5 ? 512 : kc == 6 ? 768 : kc == 7 ? 1024 : kc == 8 ? 1280 : 1536;
