@@ -222,3 +222,24 @@ def test_wide_band_classes(gpu, oracle_mod):
             if on:
                 assert st["band16_cells"] > 0 and st["band_cells"] > st["band16_cells"], st
     gpu.set_band_packing(True)
+
+
+def test_global_retry_settles_in_round_two(gpu, oracle_mod):
+    """A rejected global band retries at the half-width its banded score
+    would pass; the retry's band contains the rejected one, so its score is
+    at least as high and it passes: every pair is settled (accepted or sent
+    to the full DP) by the second round, from any initial width.  Scores
+    equal the oracle's, packed kernel on and off."""
+    import torch
+    b = synth.config4_like(1500, 795, min_len=300, max_len=3000, max_div=0.15)
+    want = oracle_mod.align_batch(b.seqs_a, b.offs_a, b.seqs_b, b.offs_b, DNA, 5, 2, 0)
+    dev = gpu.to_device(b)
+    for w0 in (0, 10, 60):
+        w = _w(torch, np.full(b.n_pairs, w0))
+        for on in (True, False):
+            gpu.set_band_packing(on)
+            sc, st = gpu.align_batch_band(*dev, DNA, 5, 2, 0, w, max_rounds=6)
+            _say(f"retry w0={w0} packed={on}: {st}")
+            assert np.array_equal(sc.cpu().numpy(), want), (w0, on, np.nonzero(sc.cpu().numpy() != want)[0][:5])
+            assert sum(st["accepted"][2:]) == 0 and len(st["accepted"]) == 2 and st["accepted"][1] > 0, st
+    gpu.set_band_packing(True)
