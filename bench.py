@@ -304,7 +304,7 @@ def main():
                          "reference that scales HBM byte counters in a profiler run")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported "
               "(pairs are independent; see the sharding note in the design document)",
               file=sys.stderr)
         sys.exit(2)
