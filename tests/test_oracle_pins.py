@@ -348,3 +348,121 @@ def test_diag_band_matches_w_band_and_brute(oracle_mod):
                 assert out == float("-inf")
             else:
                 assert out <= ub
+
+
+# ---- band acceptance bound: its value, pinned by enumeration ------------------
+
+@pytest.mark.parametrize("mode", [GLOBAL, SEMIGLOBAL])
+def test_band_bound_value_equals_best_leaving_path(oracle_mod, mode):
+    """On one-letter pairs every diagonal step scores sigma_max, so the bound
+    is attained: the best band-leaving path found by enumerating every
+    alignment equals UB_out exactly (not merely stays below it).  A dropped
+    gap run (-alpha instead of -2 alpha), a wrong count of gap columns (the
+    -2 in beta*(m+n-2g-2)) or a wrong diagonal length in semi-global mode
+    changes the value and fails here.  sigma ranges over negative values too,
+    where the best leaving path takes no diagonal step at all."""
+    from oracle import band
+    rng = np.random.default_rng(91 + mode)
+    checked = 0
+    for sigma in (-4, -3, -1, 0, 1, 2, 3, 5):
+        sub = np.array([[sigma]], dtype=np.int8)
+        for _ in range(8 if mode == GLOBAL else 5):
+            beta = int(rng.integers(0, 4))
+            alpha = beta + int(rng.integers(0, 5))
+            m = int(rng.integers(0, 7 if mode == GLOBAL else 6))
+            n = int(rng.integers(0, 7 if mode == GLOBAL else 6))
+            q, s = [0] * m, [0] * n
+            for w in range(0, max(m, n) + 1):
+                ub = band.ub_outside(m, n, w, sigma, alpha, beta, mode)
+                out = brute.SCORERS[mode](q, s, sub, alpha, beta, cell_ok=_band_ok(m, n, w),
+                                          escape=True)
+                if ub is None:
+                    assert out == float("-inf"), (m, n, w)
+                    continue
+                assert out == ub, (mode, sigma, alpha, beta, m, n, w, out, ub)
+                checked += 1
+    assert checked > (100 if mode == GLOBAL else 40)
+
+
+def test_band_bound_closed_form_grid():
+    """Global mode, sigma_max + 2 beta >= 0: the bound is the closed form
+    sigma_max (min(m,n) - w - 1) - 2 alpha - beta (|n - m| + 2 w) of the
+    corner-to-corner path with two gap runs (the best path off the band
+    leaves it on either side with w + 1 gap columns and returns), on a grid
+    of shapes, widths and scores; and no bound exists once the band holds
+    every diagonal of the matrix."""
+    from oracle import band
+    for m in (1, 2, 5, 17, 40):
+        for n in (1, 3, 17, 41, 90):
+            for w in range(0, max(m, n) + 2, 3):
+                for smax, alpha, beta in ((2, 5, 2), (1, 1, 1), (3, 11, 1), (5, 0, 0), (1, 7, 3)):
+                    for mode in (GLOBAL, SEMIGLOBAL):
+                        ub = band.ub_outside(m, n, w, smax, alpha, beta, mode)
+                        lo, hi = band.band_limits(m, n, w)
+                        if lo <= -m and hi >= n:
+                            assert ub is None
+                            continue
+                        if mode == GLOBAL:
+                            want = smax * (min(m, n) - w - 1) - 2 * alpha - beta * (abs(n - m) + 2 * w)
+                        else:
+                            # the longest diagonal just outside the band
+                            lens = []
+                            if hi + 1 <= n:
+                                lens.append(min(m, n - hi - 1))
+                            if lo - 1 >= -m:
+                                lens.append(min(m + lo - 1, n))
+                            want = smax * max(lens)
+                        assert ub == want, (m, n, w, smax, alpha, beta, mode, ub, want)
+
+
+def _accepted_by_scan(oracle_mod, a, b, sub, alpha, beta, mode):
+    """Smallest accepted half-width by a plain scan upward from 0."""
+    from oracle import band
+    smax = int(np.asarray(sub).max())
+    w = 0
+    while True:
+        sb = oracle_mod.banded_pair(a, b, sub, alpha, beta, mode, w)
+        if band.accepts(sb, band.ub_outside(len(a), len(b), w, smax, alpha, beta, mode)):
+            return w
+        w += 1
+
+
+@pytest.mark.parametrize("mode", [GLOBAL, SEMIGLOBAL])
+def test_accepted_width_is_minimal(oracle_mod, mode):
+    """The bisection's width is the smallest accepted one: it equals a linear
+    scan from w = 0, and for wa > 0 the band of half-width wa - 1 is
+    rejected.  Random tiny pairs (random scoring) and short related pairs
+    (the benchmark scoring) cover rejected, accepted-at-zero and
+    band-covers-everything cases."""
+    from oracle import band
+    rng = np.random.default_rng(97 + mode)
+    positive = 0
+    cases = []
+    for _ in range(60):
+        sub, alpha, beta = _random_scoring(rng, 3)
+        q = rng.integers(0, 3, size=int(rng.integers(0, 9))).tolist()
+        s = rng.integers(0, 3, size=int(rng.integers(0, 9))).tolist()
+        cases.append((q, s, sub, alpha, beta))
+    for _ in range(40):
+        a = rng.integers(0, 4, size=int(rng.integers(5, 90))).tolist()
+        b = list(a)
+        for _k in range(int(rng.integers(0, 10))):
+            pos = int(rng.integers(0, len(b)))
+            r = rng.random()
+            if r < 0.35 and len(b) > 1:
+                del b[pos]
+            elif r < 0.7:
+                b.insert(pos, int(rng.integers(0, 4)))
+            else:
+                b[pos] = int(rng.integers(0, 4))
+        cases.append((a, b, DNA, 5, 2))
+    for q, s, sub, alpha, beta in cases:
+        wa = band.accepted_width(q, s, sub, alpha, beta, mode)
+        assert wa == _accepted_by_scan(oracle_mod, q, s, sub, alpha, beta, mode), (q, s)
+        if wa > 0:
+            positive += 1
+            smax = int(np.asarray(sub).max())
+            sb = oracle_mod.banded_pair(q, s, sub, alpha, beta, mode, wa - 1)
+            assert not band.accepts(sb, band.ub_outside(len(q), len(s), wa - 1, smax, alpha, beta,
+                                                        mode)), (q, s, wa)
+    assert positive > 20
