@@ -61,6 +61,14 @@ def _load():
     lib.oracle_diag_band_batch.argtypes = [p, p, p, p, i64, p, i32, i64, i64, i32, p, p, i32, p]
     lib.oracle_banded_batch.restype = None
     lib.oracle_banded_batch.argtypes = [p, p, p, p, i64, p, i32, i64, i64, i32, p, i32, p]
+    lib.oracle_alignment_score.restype = i64
+    lib.oracle_alignment_score.argtypes = [p, i64, p, i64, p, i32, i64, i64, i32, p, i64, p]
+    lib.oracle_traceback_pair.restype = i64
+    lib.oracle_traceback_pair.argtypes = [p, i64, p, i64, p, i32, i64, i64, i32, p, p]
+    lib.oracle_traceback_batch.restype = None
+    lib.oracle_traceback_batch.argtypes = [p, p, p, p, i64, p, i32, i64, i64, i32, i32, p, p, p]
+    lib.oracle_alignment_score_batch.restype = None
+    lib.oracle_alignment_score_batch.argtypes = [p, p, p, p, i64, p, i32, i64, i64, i32, i32, p, p, p]
     _lib = lib
     return lib
 
@@ -156,3 +164,70 @@ def diag_band_batch(seqs_a, offs_a, seqs_b, offs_b, subst, alpha: int, beta: int
                                    int(alpha), int(beta), int(mode), _ptr(lo), _ptr(hi),
                                    nthreads or default_threads(), _ptr(out))
     return out
+
+
+# ---- alignments (the "Traceback" paragraph of the paper's section 2.1) ----
+
+INVALID = -(1 << 63)   # oracle_alignment_score's value for an alignment the mode does not admit
+
+
+def alignment_score(q, s, subst, alpha: int, beta: int, mode: int, ops, span) -> int:
+    """Score of one alignment by its definition (sigma over aligned columns,
+    alpha + (k-1) beta per maximal gap run), or INVALID when its columns
+    ('M', 'I' = q_i against a gap, 'D' = s_j against a gap) do not consume
+    exactly span = (a0, a1, b0, b1) or the mode does not admit that span."""
+    q, s = _u8(q), _u8(s)
+    sub, asz = _subst(subst)
+    o = np.frombuffer(ops.encode() if isinstance(ops, str) else bytes(ops), dtype=np.uint8).copy()
+    sp = np.ascontiguousarray(span, dtype=np.int32)
+    return int(_load().oracle_alignment_score(_ptr(q), len(q), _ptr(s), len(s), _ptr(sub), asz,
+                                              int(alpha), int(beta), int(mode),
+                                              _ptr(o) if len(o) else _ptr(np.zeros(1, np.uint8)),
+                                              len(o), _ptr(sp)))
+
+
+def traceback_pair(q, s, subst, alpha: int, beta: int, mode: int):
+    """(score, ops string, span (a0, a1, b0, b1)) of one optimal alignment."""
+    q, s = _u8(q), _u8(s)
+    sub, asz = _subst(subst)
+    ops = np.zeros(len(q) + len(s) + 1, dtype=np.uint8)
+    sp = np.zeros(5, dtype=np.int32)
+    sc = int(_load().oracle_traceback_pair(_ptr(q), len(q), _ptr(s), len(s), _ptr(sub), asz,
+                                           int(alpha), int(beta), int(mode), _ptr(ops), _ptr(sp)))
+    return sc, ops[:sp[0]].tobytes().decode(), tuple(int(x) for x in sp[1:])
+
+
+def alignment_score_batch(seqs_a, offs_a, seqs_b, offs_b, subst, alpha: int, beta: int, mode: int,
+                          ops, span, nthreads: int | None = None) -> np.ndarray:
+    """Score of every pair's alignment (INVALID where it is not one): pair p's
+    columns are ops[(offs_a[p] - offs_a[0]) + (offs_b[p] - offs_b[0]):][:span[p][0]],
+    span[p] = (n_ops, a0, a1, b0, b1)."""
+    sa, sb = _u8(seqs_a), _u8(seqs_b)
+    oa = np.ascontiguousarray(offs_a, dtype=np.int64)
+    ob = np.ascontiguousarray(offs_b, dtype=np.int64)
+    n = len(oa) - 1
+    o = np.ascontiguousarray(ops, dtype=np.uint8)
+    sp = np.ascontiguousarray(span, dtype=np.int32).reshape(n, 5)
+    sub, asz = _subst(subst)
+    out = np.zeros(n, dtype=np.int64)
+    _load().oracle_alignment_score_batch(_ptr(sa), _ptr(oa), _ptr(sb), _ptr(ob), n, _ptr(sub), asz,
+                                         int(alpha), int(beta), int(mode),
+                                         nthreads or default_threads(), _ptr(o), _ptr(sp), _ptr(out))
+    return out
+
+
+def traceback_batch(seqs_a, offs_a, seqs_b, offs_b, subst, alpha: int, beta: int, mode: int,
+                    nthreads: int | None = None):
+    """(scores, ops, span) of every pair, in the layout of alignment_score_batch."""
+    sa, sb = _u8(seqs_a), _u8(seqs_b)
+    oa = np.ascontiguousarray(offs_a, dtype=np.int64)
+    ob = np.ascontiguousarray(offs_b, dtype=np.int64)
+    n = len(oa) - 1
+    sub, asz = _subst(subst)
+    ops = np.zeros(max(1, int(oa[-1] - oa[0] + ob[-1] - ob[0])), dtype=np.uint8)
+    sp = np.zeros((n, 5), dtype=np.int32)
+    out = np.zeros(n, dtype=np.int64)
+    _load().oracle_traceback_batch(_ptr(sa), _ptr(oa), _ptr(sb), _ptr(ob), n, _ptr(sub), asz,
+                                   int(alpha), int(beta), int(mode), nthreads or default_threads(),
+                                   _ptr(ops), _ptr(sp), _ptr(out))
+    return out, ops, sp

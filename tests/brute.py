@@ -84,3 +84,32 @@ def semiglobal_score(q, s, subst, alpha, beta, cell_ok=None, escape=False):
 
 
 SCORERS = {0: global_score, 1: semiglobal_score, 2: local_score}
+
+
+def all_alignments(q, s, subst, alpha, beta):
+    """Every global alignment of q against s as (columns, score): columns is
+    a string over 'M' (q_i with s_j), 'I' (q_i against a gap), 'D' (s_j
+    against a gap); the score is computed by the definition above, column
+    by column."""
+    m, n = len(q), len(s)
+    out = []
+
+    def rec(i, j, last, score, cols):
+        if i == m and j == n:
+            out.append(("".join(cols), score))
+            return
+        if i < m and j < n:
+            cols.append("M")
+            rec(i + 1, j + 1, "M", score + int(subst[q[i]][s[j]]), cols)
+            cols.pop()
+        if i < m:
+            cols.append("I")
+            rec(i + 1, j, "I", score - (beta if last == "I" else alpha), cols)
+            cols.pop()
+        if j < n:
+            cols.append("D")
+            rec(i, j + 1, "D", score - (beta if last == "D" else alpha), cols)
+            cols.pop()
+
+    rec(0, 0, None, 0, [])
+    return out
