@@ -51,9 +51,16 @@ typedef enum {
 typedef struct {
     int32_t alphabet_size; /* 2..32 */
     const int8_t *subst;   /* HOST pointer, alphabet_size^2 entries, row-major */
-    int32_t gap_open;      /* alpha: cost of a gap's first residue, 0..10000 */
+    int32_t gap_open;      /* alpha: cost of a gap's first residue */
     int32_t gap_extend;    /* beta: cost of each further residue, 0 <= beta <= alpha */
 } as_scoring;
+/*
+ * Limits of a scoring scheme (AS_ERR_SCORING otherwise): with bias =
+ * alpha + beta (global, semi-global) or alpha (local), bias <= 127 and every
+ * sigma + bias lies in -128..127 (the 32-bit kernels keep sigma + bias as one
+ * signed byte per letter and column).  The banded and learned entry points
+ * also need at most four letters and sigma + alpha + beta in 0..255.
+ */
 
 /* Return codes. */
 #define AS_OK 0
@@ -166,9 +173,13 @@ int as_align_batch_band(const uint8_t *seqs_a, const int64_t *offs_a, const uint
 /*
  * Raw banded scores: the optimal score of pair p restricted to the band the
  * kernel computes for half-width band_w[p] (see above), with no acceptance
- * test.  lo_out/hi_out (device int32 [n_pairs], both or neither) receive the
+ * test.  The kernel is the one the certified rounds would use: in global
+ * mode the packed 16-bit kernel (widths 80..1536) when packing is on
+ * (as_set_band_packing) and the pair's range proof holds for the class that
+ * fits the request, else the 32-bit kernel (widths 64..1536).
+ * lo_out/hi_out (device int32 [n_pairs], both or neither) receive the
  * diagonal limits actually computed, in A-rows/B-columns orientation
- * (j - i, j over B).  A band wider than 1024 diagonals returns AS_ERR_ARG.
+ * (j - i, j over B).  A request wider than 1536 diagonals returns AS_ERR_ARG.
  */
 int as_band_scores(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t *seqs_b,
                    const int64_t *offs_b, int64_t n_pairs, const as_scoring *scoring, int32_t mode,
@@ -351,12 +362,16 @@ int as_plan_destroy(as_plan *plan);
 
 /*
  * Packed 16-bit banded kernel (global mode): a pair whose band cells are
- * proven to fit int16 (sigma_max*min(m,n) + beta*(m + n + W) + margins below
- * 32000, W the band width in diagonals) is banded two pairs per lane group
- * with 16-bit cells, in widths of 80 to 1536 diagonals; the
- * others use the 32-bit banded kernel.  On by default; on = 0 sends every
- * pair to the 32-bit kernel (scores are the same either way).  Returns the
- * previous setting.
+ * proven to fit an unsigned 16-bit number with a per-pair bias is banded two
+ * pairs per lane group with 16-bit cells, in widths of 80 to 1536 diagonals;
+ * the others use the 32-bit banded kernel.  The proof, for an m x n pair and
+ * a band of W diagonals, with UB = max(sigma_max, 0)*min(m,n) +
+ * beta*(m + n + W) + alpha + 2*beta + 256 and LB = max(0, -(sigma_min +
+ * 2*beta))*min(m,n) + 3*(alpha - beta) + 256: LB < 32000 and UB + LB < 65000.
+ * On by default (certified rounds and as_band_scores; as_band_certify and
+ * the labels always use 32-bit cells); on = 0 sends every pair to the
+ * 32-bit kernel (scores are the same either way).  Returns the previous
+ * setting.
  */
 int as_set_band_packing(int32_t on);
 

@@ -37,6 +37,8 @@
 //  * Range: a pair is queued here only when an a priori bound keeps every
 //    shifted cell (band columns up to n + W) inside int16; the others take
 //    the 32-bit banded kernel.
+//  * Raw mode writes each pair's banded score and the band's limits and
+//    queues nothing.
 #include <type_traits>
 
 #include "internal.h"
@@ -347,6 +349,16 @@ band_dp_i16_kernel(BandArgs a, int pc) {
     const int m = d.m, n = d.n, lo = t == 0 ? lo0 : lo1, hi = lo + W - 1;
     int64_t ub = 0;
     const bool leave = band_leave_bound(m, n, lo, hi, a.sigma_max, alpha, beta, kGlobal, &ub);
+    if (a.raw) {  // the band's score and limits (A/B orientation), no rounds
+      const bool tr = (d.flags & kTransposed) != 0;
+      a.scores[d.pair] = score;
+      if (a.lo_out) {
+        a.lo_out[d.pair] = tr ? -hi : lo;
+        a.hi_out[d.pair] = tr ? -lo : hi;
+      }
+      if (a.accept_out) a.accept_out[d.pair] = (!leave || (int64_t)score >= ub) ? 1 : 0;
+      continue;
+    }
     atomicAdd(&a.ctr->band_cells, (unsigned long long)((long long)m * W));
     atomicAdd(&a.ctr->band16_cells, (unsigned long long)((long long)m * W));
     if (!leave || (int64_t)score >= ub) {

@@ -141,8 +141,10 @@ __host__ __device__ inline int band_class_width(int kc) {
   return kc == 0 ? 64 : kc == 1 ? 128 : kc == 2 ? 192 : kc == 3 ? 256
        : kc == 4 ? 384 : kc == 5 ? 512 : kc == 6 ? 768 : kc == 7 ? 1024 : kc == 8 ? 1280 : 1536;
 }
-// Widest band of the exact and raw entry points and of the label search.
-constexpr int kRawBandMax = 1024;
+// Widest band of the raw entry point (every class), and of the exact entry
+// point and the label search.
+constexpr int kRawBandMax = 1536;
+constexpr int kExactBandMax = 1024;
 
 // Smallest class whose width holds B diagonals, or -1.
 __host__ __device__ inline int band_class_for(int B) {

@@ -131,8 +131,8 @@ __global__ void __launch_bounds__(256) label_init_kernel(const int64_t *offs_a, 
   // orientation of the banded kernel: rows = the shorter sequence
   const int m = (int)(m0 < n0 ? m0 : n0), n = (int)(m0 < n0 ? n0 : m0);
   const int dn = n - m;
-  const int cap = (kRawBandMax - 1 - dn) / 2;
-  if (dn > kRawBandMax - 1) {
+  const int cap = (kExactBandMax - 1 - dn) / 2;
+  if (dn > kExactBandMax - 1) {
     labels[p] = kWideLabel;
     return;
   }

@@ -375,8 +375,8 @@ __global__ void __launch_bounds__(256) route_scatter_kernel(RouteParams c, const
 // Banded path entry: orientation (rows = the shorter sequence), initial
 // half-width, lane-width class; pairs whose first band is already wider than
 // the widest class, or than half the matrix, go straight to the fallback list.
-// raw = 1 queues every pair (too wide a band is an error); with exact = 1 a
-// negative half-width leaves the pair out.
+// raw = 1 queues every pair in the class that holds its request (too wide a
+// band is an error); with exact = 1 a negative half-width leaves the pair out.
 __global__ void __launch_bounds__(256) band_classify_kernel(RouteParams c, const int64_t *offs_a,
                                                             const int64_t *offs_b, const int32_t *w0,
                                                             int32_t raw, int32_t exact, BandItem *lists,
@@ -413,12 +413,19 @@ __global__ void __launch_bounds__(256) band_classify_kernel(RouteParams c, const
     bi.pad_ = 0;
     if (raw) {
       const int B = bi.d.n - bi.d.m + 2 * w + 1;
-      const int kc = B <= kRawBandMax ? band_class_for(B) : -1;
-      if (kc < 0) {
+      if (B > (exact ? kExactBandMax : kRawBandMax)) {
         if (first) atomicOr(&ctr->status, kStatusArg);
         return -1;
       }
-      return kc;
+      // raw scores come from the kernel the rounds would use: the packed one
+      // when the range proof holds for the class that fits the request
+      if (pack16) {
+        const int pc = band16_class_for(B);
+        if (pc >= 0 && band16_range_ok(bi.d.m, bi.d.n, band16_class_width(pc), c.smax_pos, c.drop16, c.alpha,
+                                       c.beta))
+          return kBandClasses + pc;
+      }
+      return band_class_for(B);
     }
     bool packed = false;
     int rc = band_route(bi.d.m, bi.d.n, w, pack16 != 0, c.smax_pos, c.drop16, c.alpha, c.beta, &packed);
@@ -1185,8 +1192,9 @@ int asmi::band_call(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t 
   if ((rc = grow((void **)&w->band_lists, &w->band_cap, 2 * kBandClasses * n_pairs, sizeof(BandItem))))
     return rc;
   const int64_t list_cap = w->band_cap / (2 * kBandClasses);
-  // the packed kernel serves range-proven global pairs outside the raw modes
-  const int pack16 = (!raw && mode == kGlobal && g_band16) ? 1 : 0;
+  // the packed kernel serves range-proven global pairs, except in the exact
+  // mode (it has no per-diagonal mask)
+  const int pack16 = (!exact && mode == kGlobal && g_band16) ? 1 : 0;
   if (pack16 && (rc = grow((void **)&w->band16_lists, &w->band16_cap, 2 * kBand16Classes * list_cap,
                            sizeof(BandItem))))
     return rc;

@@ -111,8 +111,11 @@ def test_band_api_errors(gpu):
     with pytest.raises(AlignError) as e:                 # local mode has no band path
         gpu.align_batch_band(*_dev(b), b.subst, 5, 2, 2, _w(torch, np.zeros(10)))
     assert e.value.code == -7
-    with pytest.raises(AlignError) as e:                 # band wider than 1024 diagonals
-        gpu.band_scores(*_dev(b), b.subst, 5, 2, 0, _w(torch, np.full(10, 600)))
+    with pytest.raises(AlignError) as e:                 # band wider than 1536 diagonals
+        gpu.band_scores(*_dev(b), b.subst, 5, 2, 0, _w(torch, np.full(10, 800)))
+    assert e.value.code == -7
+    with pytest.raises(AlignError) as e:                 # exact band wider than 1024 diagonals
+        gpu.band_certify(*_dev(b), b.subst, 5, 2, 0, _w(torch, np.full(10, 600)))
     assert e.value.code == -7
     prot = synth.protein_subst(np.random.default_rng(1))
     pb = synth.config3(n_pairs=4, n_long=0)
@@ -243,3 +246,101 @@ def test_global_retry_settles_in_round_two(gpu, oracle_mod):
             assert np.array_equal(sc.cpu().numpy(), want), (w0, on, np.nonzero(sc.cpu().numpy() != want)[0][:5])
             assert sum(st["accepted"][2:]) == 0 and len(st["accepted"]) == 2 and st["accepted"][1] > 0, st
     gpu.set_band_packing(True)
+
+
+# Lane-width classes of the two banded kernels (diagonals).
+PACKED_WIDTHS = (80, 96, 112, 128, 160, 192, 224, 256, 320, 384, 448, 512, 640, 768, 896, 1024,
+                 1280, 1536)
+WIDTHS32 = (64, 128, 192, 256, 384, 512, 768, 1024, 1280, 1536)
+
+
+def test_raw_packed_band_every_class(gpu, oracle_mod):
+    """Raw banded scores of the packed 16-bit kernel against the oracle's DP
+    restricted to the diagonals it reports, in every one of its 18 classes:
+    per class, pairs of 300-2600 residues with unequal row counts (so the
+    two halves of a lane group end on different steps) and requests that
+    just fit the class; the 96/192/384/768 and 1280 classes run their
+    selector rotation in phases (K = 6, 12, 20).  Pairs of 4.8-6.2 kb in
+    the widest classes carry the lowered bias (their upper bound passes
+    32768).  With packing off the same requests take the 32-bit kernel;
+    both equal the oracle."""
+    import torch
+    rng = np.random.default_rng(7300)
+    pairs, target = [], []
+    for W in PACKED_WIDTHS:
+        base = synth.config4_like(36, int(rng.integers(1 << 30)), min_len=max(300, (4 * W) // 3 + 40),
+                                  max_len=max(900, (4 * W) // 3 + 1400), max_div=0.12)
+        for p in range(base.n_pairs):
+            pairs.append(base.pair(p))
+            target.append(W)
+    big = synth.config4_like(10, 7301, min_len=4800, max_len=6200, max_div=0.08)
+    for p in range(big.n_pairs):
+        pairs.append(big.pair(p))
+        target.append(1280 if p % 2 else 1536)
+    bb = synth.from_pairs("raw packed", pairs, DNA, 5, 2, 0)
+    target = np.asarray(target)
+    dn = np.abs(bb.lens_a.astype(np.int64) - bb.lens_b.astype(np.int64))
+    keep = dn + 1 <= target
+    bb = bb.subset(np.nonzero(keep)[0])
+    target, dn = target[keep], dn[keep]
+    w = np.maximum(0, (target - 1 - dn) // 2)          # B = dn + 2w + 1 just fits the class
+    dev = gpu.to_device(bb)
+    L = np.minimum(0, bb.lens_b - bb.lens_a) - w
+    U = np.maximum(0, bb.lens_b - bb.lens_a) + w
+    for on in (True, False):
+        gpu.set_band_packing(on)
+        got, lo, hi = gpu.band_scores(*dev, DNA, 5, 2, 0, _w(torch, w))
+        got, lo, hi = got.cpu().numpy(), lo.cpu().numpy(), hi.cpu().numpy()
+        widths = hi - lo + 1
+        _say(f"raw packed={on}: {bb.n_pairs} pairs, widths {sorted(set(widths.tolist()))}")
+        assert np.all(lo <= L) and np.all(hi >= U)
+        if on:
+            assert np.array_equal(widths, target), np.nonzero(widths != target)[0][:5]
+        else:
+            assert set(widths.tolist()) <= set(WIDTHS32)
+        want = oracle_mod.diag_band_batch(bb.seqs_a, bb.offs_a, bb.seqs_b, bb.offs_b, DNA, 5, 2, 0, lo, hi)
+        bad = np.nonzero(got.astype(np.int64) != want)[0]
+        assert len(bad) == 0, (f"packed={on}: {len(bad)} mismatches, first pair {bad[0]}: gpu {got[bad[0]]} "
+                               f"oracle {want[bad[0]]} m={bb.lens_a[bad[0]]} n={bb.lens_b[bad[0]]} "
+                               f"lo={lo[bad[0]]} hi={hi[bad[0]]}")
+    gpu.set_band_packing(True)
+
+
+def _widest_packed(m, n):
+    """Widest packed class a global pair may take in the rounds (at most
+    three quarters of the longer sequence; DNA pairs of these lengths pass
+    the range proof)."""
+    ok = [W for W in PACKED_WIDTHS if 4 * W <= 3 * max(m, n)]
+    return max(ok) if ok else 0
+
+
+def test_no_fallback_when_first_band_holds_the_path(gpu, oracle_mod):
+    """Pairs whose first computed band already holds an optimal path (the
+    oracle's score of that band equals the full DP's) and whose
+    certificate width fits a class: a rejected band retries at the width
+    its score passes, so every such pair is accepted by the second round
+    and none falls back to the full DP."""
+    import torch
+    b = synth.config4_like(1200, 7310, min_len=1200, max_len=3200, max_div=0.08)
+    full = oracle_mod.align_batch(b.seqs_a, b.offs_a, b.seqs_b, b.offs_b, DNA, 5, 2, 0)
+    m = b.lens_a.astype(np.int64)
+    n = b.lens_b.astype(np.int64)
+    mn, dn = np.minimum(m, n), np.abs(n - m)
+    # smallest half-width whose leave bound the full score passes (global)
+    num = 2 * (mn - 1) - 2 * 5 - 2 * dn - full
+    wcert = np.where(num <= 0, 0, (num + 5) // 6)
+    widest = np.array([_widest_packed(int(a), int(c)) for a, c in zip(m, n)])
+    gpu.set_band_packing(True)
+    dev = gpu.to_device(b)
+    for w0 in (0, 10):
+        w = np.full(b.n_pairs, w0)
+        _, lo, hi = gpu.band_scores(*dev, DNA, 5, 2, 0, _w(torch, w))
+        first = oracle_mod.diag_band_batch(b.seqs_a, b.offs_a, b.seqs_b, b.offs_b, DNA, 5, 2, 0,
+                                           lo.cpu().numpy(), hi.cpu().numpy())
+        sel = np.nonzero((first == full) & (dn + 2 * wcert + 1 <= widest))[0]
+        assert len(sel) > b.n_pairs // 2
+        sub = b.subset(sel)
+        sc, st = gpu.align_batch_band(*gpu.to_device(sub), DNA, 5, 2, 0, _w(torch, w[sel]), max_rounds=6)
+        _say(f"first band holds the path, w0={w0}: {len(sel)} pairs, {st}")
+        assert np.array_equal(sc.cpu().numpy(), full[sel])
+        assert st["fallback"] == 0 and sum(st["accepted"][2:]) == 0, st
