@@ -157,13 +157,19 @@ def test_predict_matches_oracle(gpu):
     w, y = gpu.band_predict(_t(flat), _t(x), with_y=True)
     w, y = w.cpu().numpy(), y.cpu().numpy()
     yo, _ = mlp.forward(_oracle_params(flat), x)
-    # one bfloat16 rounding of a hidden activation can flip with the
-    # summation order (float32 on the GPU, float64 here): a 2^-8 relative
-    # change of one of 64 terms, so |dy| stays well below 1e-2 * (1 + |y|)
+    # Summation order alone (float32 on the GPU, float64 here) moves y by
+    # about 1e-7 relative.  Rarely it also flips one bfloat16 rounding of a
+    # hidden activation (a 2^-8 relative change of one of 64 terms), which
+    # moves y by less than 1e-2 * (1 + |y|).  So: every sample within the
+    # summation-order tolerance except at most 1% of them, and those within
+    # the flip bound (a CPU emulation with shuffled float32 sums flips none
+    # of these 1000 samples).
     err = np.abs(y - yo)
-    _say(f"predict: max |dy| {err.max():.3g}, median {np.median(err):.3g}")
+    tight = err <= 1e-5 * (1 + np.abs(yo))
+    _say(f"predict: max |dy| {err.max():.3g}, median {np.median(err):.3g}, "
+         f"{int((~tight).sum())} samples beyond 1e-5")
+    assert int((~tight).sum()) <= len(yo) // 100
     assert np.all(err <= 1e-2 * (1 + np.abs(yo)))
-    assert np.median(err) < 1e-5
     wo = mlp.predict_width(yo)
     # the width is ceil(2^y - 1): equal unless 2^y - 1 sits within the y error of an integer
     t = np.exp2(yo) - 1

@@ -138,6 +138,33 @@ def test_error_codes(gpu):
     assert out.cpu().tolist() == [10, 10]
 
 
+def test_range_refusal(gpu):
+    """AS_ERR_RANGE: a pair whose cells could leave the 32-bit budget is
+    refused before any DP runs (|sigma|max + alpha + 2 beta) * (m + n + 2)
+    >= 2^28; with alpha = beta = 60 on DNA that is m + n >= 1.47 M.  The
+    same batch one residue shorter on each side of that line is accepted by
+    the check (not aligned here: the other pair is empty)."""
+    import torch
+    from paper_2205_07610_amd.binding import AlignError
+    budget = 1 << 28
+    per = 3 + 60 + 2 * 60
+    m = (budget + per - 1) // per - 2          # smallest m + n (split evenly) that is refused
+    half = (m + 1) // 2
+    seq = torch.zeros(half, dtype=torch.uint8, device="cuda")
+    oa = torch.tensor([0, half], dtype=torch.int64, device="cuda")
+    ob = torch.tensor([0, m - half], dtype=torch.int64, device="cuda")
+    with pytest.raises(AlignError) as e:
+        gpu.align_batch(seq, oa, seq, ob, DNA, 60, 60, 0)
+    assert e.value.code == -5
+    # an empty pair of the same total length is scored by its closed form only
+    # when the range check passes: one residue less passes it
+    ok_a = torch.tensor([0, 0], dtype=torch.int64, device="cuda")
+    ok_b = torch.tensor([0, m - 1], dtype=torch.int64, device="cuda")
+    big = torch.zeros(m - 1, dtype=torch.uint8, device="cuda")
+    out = gpu.align_batch(seq, ok_a, big, ok_b, DNA, 60, 60, 0)
+    assert out.cpu().tolist() == [-60 - 60 * (m - 2)]
+
+
 def test_deterministic(gpu):
     b = synth.config1(n_pairs=4096, seed=77)
     r1 = gpu.align(b)
