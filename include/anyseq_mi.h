@@ -71,6 +71,7 @@ typedef struct {
 #define AS_ERR_RANGE (-5)     /* a score could leave the int32 range */
 #define AS_ERR_HIP (-6)       /* a HIP runtime call failed, or a device-side wait stalled */
 #define AS_ERR_ARG (-7)       /* another argument is out of range */
+#define AS_ERR_SCRATCH (-8)   /* as_align_batch_noalloc: the batch does not fit its scratch array */
 
 /*
  * Optimal alignment score of every pair of the batch (paper section 2.1,
@@ -90,6 +91,32 @@ typedef struct {
 int as_align_batch(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t *seqs_b,
                    const int64_t *offs_b, int64_t n_pairs, const as_scoring *scoring,
                    int32_t mode, int32_t *scores_out, void *stream);
+
+/*
+ * as_align_batch for callers that cannot allocate memory (code that runs
+ * while a HIP graph is being captured elsewhere, tight serving loops,
+ * harnesses that forbid hipMalloc): same arguments, same results, same
+ * kernels, but the call allocates nothing -- no hipMalloc/hipFree, no
+ * pinned host buffer, no library routine that allocates.  Its work lists,
+ * counters and boundary buffers live in one static device array of
+ * AS_NOALLOC_SCRATCH_BYTES per GPU, held by the process until it ends.
+ * Limits: the five work lists take 176 bytes per pair and the long-pair
+ * boundary columns 8 bytes per row per stripe edge, all within that array
+ * (about 380,000 short pairs; a batch whose long pairs need more boundary
+ * rows than remain is refused); a batch that does not fit returns
+ * AS_ERR_SCRATCH before its DP kernels run.  The first call on a device
+ * looks up the array's device address (hipGetSymbolAddress).  Every call on
+ * a GPU shares that GPU's array and leaves its contents behind; the call
+ * clears what must start at zero.  Calls from one process are serialised
+ * by the library's lock and wait for their own work before returning, so
+ * they never overlap; calls that overlapped on one GPU (for example from
+ * two copies of the library in one process) would race on the array.
+ * Timing (as_enable_timing) is not recorded for these calls.
+ */
+#define AS_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int as_align_batch_noalloc(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t *seqs_b,
+                           const int64_t *offs_b, int64_t n_pairs, const as_scoring *scoring,
+                           int32_t mode, int32_t *scores_out, void *stream);
 
 /* Human-readable text for a return code (static storage). */
 const char *as_strerror(int code);

@@ -79,6 +79,8 @@ def lib() -> ctypes.CDLL:
     p, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
     L.as_align_batch.restype = ctypes.c_int
     L.as_align_batch.argtypes = [p, p, p, p, i64, ctypes.POINTER(Scoring), i32, p, p]
+    L.as_align_batch_noalloc.restype = ctypes.c_int
+    L.as_align_batch_noalloc.argtypes = [p, p, p, p, i64, ctypes.POINTER(Scoring), i32, p, p]
     L.as_strerror.restype = ctypes.c_char_p
     L.as_strerror.argtypes = [ctypes.c_int]
     L.as_release_workspace.restype = ctypes.c_int
@@ -172,6 +174,19 @@ def align_batch(seqs_a, offs_a, seqs_b, offs_b, subst, alpha: int, beta: int, mo
     seqs_*: uint8 CUDA tensors of residue codes; offs_*: int64 CUDA tensors
     [n_pairs + 1]; subst: host [asz, asz] int8 matrix; mode: 0 global,
     1 semi-global, 2 local.  Raises AlignError on a non-zero return code."""
+    return _align_full(lib().as_align_batch, seqs_a, offs_a, seqs_b, offs_b, subst, alpha, beta,
+                       mode, scores_out, stream)
+
+
+def align_batch_noalloc(seqs_a, offs_a, seqs_b, offs_b, subst, alpha: int, beta: int, mode: int,
+                        scores_out, stream=None):
+    """align_batch through as_align_batch_noalloc (the library allocates
+    nothing; scores_out must be given)."""
+    return _align_full(lib().as_align_batch_noalloc, seqs_a, offs_a, seqs_b, offs_b, subst, alpha,
+                       beta, mode, scores_out, stream)
+
+
+def _align_full(fn, seqs_a, offs_a, seqs_b, offs_b, subst, alpha, beta, mode, scores_out, stream):
     import torch
     n_pairs = offs_a.numel() - 1
     if offs_b.numel() != n_pairs + 1:
@@ -184,12 +199,12 @@ def align_batch(seqs_a, offs_a, seqs_b, offs_b, subst, alpha: int, beta: int, mo
     # an empty uint8 tensor still needs a non-null pointer for the ABI's checks
     pa = _dev_ptr(seqs_a, torch.uint8, "seqs_a") if seqs_a.numel() else ctypes.c_void_p(offs_a.data_ptr())
     pb = _dev_ptr(seqs_b, torch.uint8, "seqs_b") if seqs_b.numel() else ctypes.c_void_p(offs_b.data_ptr())
-    rc = lib().as_align_batch(pa, _dev_ptr(offs_a, torch.int64, "offs_a"),
-                              pb, _dev_ptr(offs_b, torch.int64, "offs_b"),
-                              n_pairs, ctypes.byref(sc), int(mode),
-                              _dev_ptr(scores_out, torch.int32, "scores_out")
-                              if n_pairs > 0 else ctypes.c_void_p(offs_a.data_ptr()),
-                              ctypes.c_void_p(stream))
+    rc = fn(pa, _dev_ptr(offs_a, torch.int64, "offs_a"),
+            pb, _dev_ptr(offs_b, torch.int64, "offs_b"),
+            n_pairs, ctypes.byref(sc), int(mode),
+            _dev_ptr(scores_out, torch.int32, "scores_out")
+            if n_pairs > 0 else ctypes.c_void_p(offs_a.data_ptr()),
+            ctypes.c_void_p(stream))
     del keep
     _check(rc)
     return scores_out

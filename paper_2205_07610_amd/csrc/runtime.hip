@@ -709,6 +709,11 @@ struct Workspace {
   // launches run on them concurrently, so a launch's tail overlaps the next
   hipStream_t side[kSideStreams] = {};
   hipEvent_t side_ev[kSideStreams + 1] = {};
+  // No-allocation calls: every buffer is carved from the device's static
+  // scratch array; buffers the call sizes late come from `pool`.
+  bool noalloc = false;
+  char *pool = nullptr;
+  int64_t pool_left = 0;
 };
 
 bool g_timing = false;
@@ -782,6 +787,31 @@ int grow(void **ptr, int64_t *cap, int64_t need, size_t elem) {
   const int64_t n = need + need / 4;
   AS_HIP(hipMalloc(ptr, (size_t)n * elem));
   *cap = n;
+  return AS_OK;
+}
+
+// grow() for the buffers that run_full_lists sizes from the counters; a
+// no-allocation workspace carves them from its pool instead (AS_ERR_SCRATCH
+// when the pool cannot hold them).
+int ws_grow(Workspace *w, void **ptr, int64_t *cap, int64_t need, size_t elem) {
+  if (!w->noalloc) return grow(ptr, cap, need, elem);
+  if (*cap >= need) return AS_OK;
+  const int64_t bytes = ((need * (int64_t)elem) + 255) & ~(int64_t)255;
+  if (bytes > w->pool_left) return AS_ERR_SCRATCH;
+  *ptr = w->pool;
+  *cap = need;
+  w->pool += bytes;
+  w->pool_left -= bytes;
+  return AS_OK;
+}
+
+// Fill n int32 words with v on the stream (a kernel, not a memset node).
+int fill_async(int32_t *p, int64_t n, int32_t v, hipStream_t stream) {
+  if (n <= 0) return AS_OK;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, p, n, v);
+  AS_HIP(hipGetLastError());
   return AS_OK;
 }
 
@@ -914,6 +944,20 @@ int run_full_lists(Workspace *w, const CallScoring &cs, const uint8_t *seqs_a,
   }
   if (c.n_long > 0 || c.n_long16 > 0)
     if ((rc = read_counters(w, stream, &c))) return rc;
+  if (w->noalloc) {
+    // a no-allocation call takes the wavefront buffers from its pool before
+    // the first DP launch, so a batch that does not fit is refused whole
+    if (c.n_long > 0 &&
+        ((rc = ws_grow(w, (void **)&w->bnd_long, &w->bnd_long_cap, c.long_bnd_total > 0 ? c.long_bnd_total : 1,
+                       sizeof(int2))) ||
+         (rc = ws_grow(w, (void **)&w->flags, &w->flags_cap, c.n_long_tasks, sizeof(int32_t)))))
+      return rc;
+    if (c.n_long16 > 0 &&
+        ((rc = ws_grow(w, (void **)&w->bnd_long16, &w->bnd_long16_cap,
+                       c.long16_bnd_total > 0 ? c.long16_bnd_total : 1, sizeof(uint2))) ||
+         (rc = ws_grow(w, (void **)&w->flags16, &w->flags16_cap, c.n_long16_tasks, sizeof(int32_t)))))
+      return rc;
+  }
   if (c.n_full16 > 0) {
     const int bpc = full_dp_i16_blocks_per_cu(mode);
     int64_t grid = (int64_t)bpc * w->num_cu;
@@ -950,7 +994,14 @@ int run_full_lists(Workspace *w, const CallScoring &cs, const uint8_t *seqs_a,
     const int64_t need_waves = ((int64_t)c.n_full32 + kGroupsPerWave - 1) / kGroupsPerWave;
     if (grid > need_waves) grid = need_waves;
     const int64_t bnd_rows = c.max_rows_multi > 0 ? (int64_t)c.max_rows_multi + 1 : 1;
-    if ((rc = grow((void **)&w->bnd, &w->bnd_cap, grid * kGroupsPerWave * 2 * bnd_rows, sizeof(int2))))
+    if (w->noalloc) {
+      // a smaller persistent grid drains the same list; its boundary rows
+      // must fit what is left of the scratch pool
+      const int64_t per_wave = (int64_t)kGroupsPerWave * 2 * bnd_rows * (int64_t)sizeof(int2);
+      const int64_t fit = w->pool_left / per_wave;
+      if (grid > fit) grid = fit > 0 ? fit : 1;
+    }
+    if ((rc = ws_grow(w, (void **)&w->bnd, &w->bnd_cap, grid * kGroupsPerWave * 2 * bnd_rows, sizeof(int2))))
       return rc;
     args.items = w->items;
     args.n_items = &w->ctr->n_full32;
@@ -962,11 +1013,11 @@ int run_full_lists(Workspace *w, const CallScoring &cs, const uint8_t *seqs_a,
     if (timing) AS_HIP(hipEventRecord(w->ev[5], stream));
   }
   if (c.n_long > 0) {
-    if ((rc = grow((void **)&w->bnd_long, &w->bnd_long_cap, c.long_bnd_total > 0 ? c.long_bnd_total : 1,
-                   sizeof(int2))))
+    if ((rc = ws_grow(w, (void **)&w->bnd_long, &w->bnd_long_cap, c.long_bnd_total > 0 ? c.long_bnd_total : 1,
+                      sizeof(int2))))
       return rc;
-    if ((rc = grow((void **)&w->flags, &w->flags_cap, c.n_long_tasks, sizeof(int32_t)))) return rc;
-    AS_HIP(hipMemsetAsync(w->flags, 0, sizeof(int32_t) * (size_t)c.n_long_tasks, stream));
+    if ((rc = ws_grow(w, (void **)&w->flags, &w->flags_cap, c.n_long_tasks, sizeof(int32_t)))) return rc;
+    if ((rc = fill_async(w->flags, c.n_long_tasks, 0, stream))) return rc;
     const int bpc = long_dp_i32_blocks_per_cu(mode, asz);
     int64_t grid = (int64_t)bpc * w->num_cu;
     if (grid > c.n_long_tasks) grid = c.n_long_tasks;
@@ -987,11 +1038,11 @@ int run_full_lists(Workspace *w, const CallScoring &cs, const uint8_t *seqs_a,
     if (timing) AS_HIP(hipEventRecord(w->ev[9], stream));
   }
   if (c.n_long16 > 0) {
-    if ((rc = grow((void **)&w->bnd_long16, &w->bnd_long16_cap,
-                   c.long16_bnd_total > 0 ? c.long16_bnd_total : 1, sizeof(uint2))))
+    if ((rc = ws_grow(w, (void **)&w->bnd_long16, &w->bnd_long16_cap,
+                      c.long16_bnd_total > 0 ? c.long16_bnd_total : 1, sizeof(uint2))))
       return rc;
-    if ((rc = grow((void **)&w->flags16, &w->flags16_cap, c.n_long16_tasks, sizeof(int32_t)))) return rc;
-    AS_HIP(hipMemsetAsync(w->flags16, 0, sizeof(int32_t) * (size_t)c.n_long16_tasks, stream));
+    if ((rc = ws_grow(w, (void **)&w->flags16, &w->flags16_cap, c.n_long16_tasks, sizeof(int32_t)))) return rc;
+    if ((rc = fill_async(w->flags16, c.n_long16_tasks, 0, stream))) return rc;
     int64_t grid = (int64_t)long_dp_i16_blocks_per_cu() * w->num_cu;
     if (grid > c.n_long16_tasks) grid = c.n_long16_tasks;
     Long16Args l16;
@@ -1034,7 +1085,7 @@ int run_full_lists(Workspace *w, const CallScoring &cs, const uint8_t *seqs_a,
     const int64_t need_waves = ((int64_t)c2.n_rerun32 + kGroupsPerWave - 1) / kGroupsPerWave;
     if (grid > need_waves) grid = need_waves;
     // re-run pairs fit one 16-bit stripe, hence one 32-bit stripe: no boundary buffer
-    if ((rc = grow((void **)&w->bnd, &w->bnd_cap, grid * kGroupsPerWave * 2, sizeof(int2)))) return rc;
+    if ((rc = ws_grow(w, (void **)&w->bnd, &w->bnd_cap, grid * kGroupsPerWave * 2, sizeof(int2)))) return rc;
     args.items = w->rerun;
     args.n_items = &w->ctr->n_rerun32;
     args.next = &w->ctr->next_rerun32;
@@ -1086,6 +1137,79 @@ int check_band_scoring(const CallScoring &cs) {
 
 using namespace asmi;
 
+namespace asmi {
+namespace {
+
+// Steps 1-4 of the full DP on a workspace whose lists hold n_pairs items.
+int align_full(Workspace *w, const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t *seqs_b,
+               const int64_t *offs_b, int64_t n_pairs, const as_scoring *scoring, const CallScoring &cs,
+               int32_t *scores_out, hipStream_t stream, bool timing) {
+  int rc;
+  AS_HIP(hipMemcpyAsync(w->subst, scoring->subst, (size_t)cs.asz * cs.asz, hipMemcpyHostToDevice, stream));
+  if ((rc = fill_async((int32_t *)w->ctr, (int64_t)(sizeof(Counters) / sizeof(int32_t)), 0, stream))) return rc;
+  memset(&g_last_timing, 0, sizeof(g_last_timing));
+  if (timing) AS_HIP(hipEventRecord(w->ev[0], stream));
+  const RouteParams rp = route_params(cs, n_pairs);
+  if ((rc = launch_classify(w, rp, offs_a, offs_b, nullptr, n_pairs, scores_out, stream))) return rc;
+  if (timing) AS_HIP(hipEventRecord(w->ev[1], stream));
+  Counters c;
+  if ((rc = read_counters(w, stream, &c))) return rc;
+  g_last_timing.cells = (int64_t)c.cells;
+  if (timing) g_last_timing.classify_ms = elapsed(w->ev[0], w->ev[1]);
+  if ((rc = status_to_code(c.status))) return rc;
+  return run_full_lists(w, cs, seqs_a, seqs_b, scores_out, stream, timing, c);
+}
+
+// ---- the no-allocation entry point's scratch ----
+// One static array per device (the code object's copy on that device); its
+// device address comes from hipGetSymbolAddress once per device, and only
+// that address is ever handed to kernels or copies.
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[AS_NOALLOC_SCRATCH_BYTES];
+void *g_scratch_ptr[kMaxDevices] = {};
+Counters g_noalloc_host_ctr;  // counter read-back target (host, static)
+
+int scratch_address(int dev, char **out) {
+  if (dev < 0 || dev >= kMaxDevices) return AS_ERR_ARG;
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return AS_ERR_HIP;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = (char *)g_scratch_ptr[dev];
+  return AS_OK;
+}
+
+// Carve a no-allocation workspace out of the device's scratch array: the
+// counters, the sigma matrix and the five work lists of n_pairs items; the
+// rest is the pool for the boundary buffers run_full_lists sizes later.
+int noalloc_workspace(Workspace *w, int dev, int64_t n_pairs) {
+  char *base = nullptr;
+  int rc;
+  if ((rc = scratch_address(dev, &base))) return rc;
+  hipDeviceProp_t prop;
+  AS_HIP(hipGetDeviceProperties(&prop, dev));
+  w->device = dev;
+  w->num_cu = prop.multiProcessorCount;
+  w->noalloc = true;
+  w->pool = base;
+  w->pool_left = AS_NOALLOC_SCRATCH_BYTES;
+  w->host_ctr = &g_noalloc_host_ctr;
+  int64_t cap_ctr = 0, cap_subst = 0;
+  if ((rc = ws_grow(w, (void **)&w->ctr, &cap_ctr, 1, sizeof(Counters)))) return rc;
+  if ((rc = ws_grow(w, (void **)&w->subst, &cap_subst, 32 * 32, 1))) return rc;
+  if ((rc = ws_grow(w, (void **)&w->items, &w->items_cap, n_pairs + kGroupsPerWave * kLenBins, sizeof(PairDesc))))
+    return rc;
+  if ((rc = ws_grow(w, (void **)&w->items16, &w->items16_cap, n_pairs, sizeof(PairDesc)))) return rc;
+  if ((rc = ws_grow(w, (void **)&w->rerun, &w->rerun_cap, n_pairs, sizeof(PairDesc)))) return rc;
+  if ((rc = ws_grow(w, (void **)&w->items_long, &w->items_long_cap, n_pairs, sizeof(LongItem)))) return rc;
+  if ((rc = ws_grow(w, (void **)&w->items_long16, &w->items_long16_cap, n_pairs, sizeof(LongItem)))) return rc;
+  return AS_OK;
+}
+
+}  // namespace
+}  // namespace asmi
+
 extern "C" int as_align_batch(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t *seqs_b,
                               const int64_t *offs_b, int64_t n_pairs, const as_scoring *scoring,
                               int32_t mode, int32_t *scores_out, void *stream_ptr) {
@@ -1100,23 +1224,29 @@ extern "C" int as_align_batch(const uint8_t *seqs_a, const int64_t *offs_a, cons
   std::lock_guard<std::mutex> guard(g_lock);
   Workspace *w = nullptr;
   if ((rc = get_workspace(&w))) return rc;
-  hipStream_t stream = (hipStream_t)stream_ptr;
   if ((rc = lists_capacity(w, n_pairs))) return rc;
+  return align_full(w, seqs_a, offs_a, seqs_b, offs_b, n_pairs, scoring, cs, scores_out,
+                    (hipStream_t)stream_ptr, g_timing);
+}
 
-  AS_HIP(hipMemcpyAsync(w->subst, scoring->subst, (size_t)cs.asz * cs.asz, hipMemcpyHostToDevice, stream));
-  AS_HIP(hipMemsetAsync(w->ctr, 0, sizeof(Counters), stream));
-  const bool timing = g_timing;
-  memset(&g_last_timing, 0, sizeof(g_last_timing));
-  if (timing) AS_HIP(hipEventRecord(w->ev[0], stream));
-  const RouteParams rp = route_params(cs, n_pairs);
-  if ((rc = launch_classify(w, rp, offs_a, offs_b, nullptr, n_pairs, scores_out, stream))) return rc;
-  if (timing) AS_HIP(hipEventRecord(w->ev[1], stream));
-  Counters c;
-  if ((rc = read_counters(w, stream, &c))) return rc;
-  g_last_timing.cells = (int64_t)c.cells;
-  if (timing) g_last_timing.classify_ms = elapsed(w->ev[0], w->ev[1]);
-  if ((rc = status_to_code(c.status))) return rc;
-  return run_full_lists(w, cs, seqs_a, seqs_b, scores_out, stream, timing, c);
+extern "C" int as_align_batch_noalloc(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t *seqs_b,
+                                      const int64_t *offs_b, int64_t n_pairs, const as_scoring *scoring,
+                                      int32_t mode, int32_t *scores_out, void *stream_ptr) {
+  if (!scoring || !offs_a || !offs_b || !seqs_a || !seqs_b || !scores_out || !scoring->subst)
+    return AS_ERR_NULL;
+  if (n_pairs < 0 || n_pairs >= ((int64_t)1 << 31) - 1) return AS_ERR_ARG;
+  CallScoring cs;
+  int rc = check_scoring(scoring, mode, &cs);
+  if (rc) return rc;
+  if (n_pairs == 0) return AS_OK;
+
+  std::lock_guard<std::mutex> guard(g_lock);
+  int dev = 0;
+  AS_HIP(hipGetDevice(&dev));
+  Workspace w;  // no events, no side streams: timing stays off
+  if ((rc = noalloc_workspace(&w, dev, n_pairs))) return rc;
+  return align_full(&w, seqs_a, offs_a, seqs_b, offs_b, n_pairs, scoring, cs, scores_out,
+                    (hipStream_t)stream_ptr, false);
 }
 
 // One round's class launches of one kernel family (packed or 32-bit), largest
@@ -1653,6 +1783,7 @@ extern "C" const char *as_strerror(int code) {
     case AS_ERR_RANGE: return "a score could leave the 32-bit range";
     case AS_ERR_HIP: return "a HIP runtime call failed or a device-side wait stalled";
     case AS_ERR_ARG: return "an argument is out of range";
+    case AS_ERR_SCRATCH: return "the batch needs more scratch than the no-allocation entry point's static array";
     default: return "unknown error";
   }
 }
