@@ -93,6 +93,32 @@ int as_align_batch(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t *
                    int32_t mode, int32_t *scores_out, void *stream);
 
 /*
+ * All against all (the paper's evaluation workload, section 4.1: every read
+ * of a set aligned with every read of a set): the score of query q against
+ * subject s for every q < n_q and s < n_s, Eq. (1),(4),(5) in the given mode.
+ *   seqs_q, offs_q : device, the n_q query sequences (offs_q[n_q + 1])
+ *   seqs_s, offs_s : device, the n_s subject sequences (offs_s[n_s + 1])
+ *   scores_out     : device int32 [n_q][n_s], row-major (query q, subject s
+ *                    at scores_out[q * n_s + s])
+ * Rows of each DP are the query's residues, columns the subject's; sigma
+ * is indexed (query letter, subject letter).  n_q * n_s must stay below
+ * 2^31 - 1 (AS_ERR_ARG).  Offsets of the two sets are copied to the host to
+ * validate them and find the longest sequences (AS_ERR_OFFSETS,
+ * AS_ERR_RANGE for the longest query against the longest subject).  When
+ * one set's sequences fit one packed stripe (at most 256 residues), the
+ * alphabet has at most 4 letters and (global, semi-global) the longest pair
+ * passes the packed range proof, one kernel computes every pair with the
+ * pairs implicit: a wave builds the register profile of one sequence of
+ * that set once and keeps it for a block of sequences of the other set
+ * (the paper's section 3.1 profile, built once per subject and reused).
+ * Other batches go through as_align_batch's routing and kernels in chunks.
+ * Same errors as as_align_batch.
+ */
+int as_align_all_vs_all(const uint8_t *seqs_q, const int64_t *offs_q, int64_t n_q,
+                        const uint8_t *seqs_s, const int64_t *offs_s, int64_t n_s,
+                        const as_scoring *scoring, int32_t mode, int32_t *scores_out, void *stream);
+
+/*
  * as_align_batch for callers that cannot allocate memory (code that runs
  * while a HIP graph is being captured elsewhere, tight serving loops,
  * harnesses that forbid hipMalloc): same arguments, same results, same
@@ -117,6 +143,46 @@ int as_align_batch(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t *
 int as_align_batch_noalloc(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t *seqs_b,
                            const int64_t *offs_b, int64_t n_pairs, const as_scoring *scoring,
                            int32_t mode, int32_t *scores_out, void *stream);
+
+/*
+ * One optimal alignment of every pair, besides its score (paper section 2.1,
+ * "Traceback" paragraph: the alignment is found by following predecessors
+ * back; section 3's implementation notes: explicit predecessors for short
+ * inputs, Hirschberg's linear-space divide and conquer for longer ones).
+ * Arguments as as_align_batch, plus
+ *   ops_out  : device, uint8, at least (offs_a[n] - offs_a[0]) +
+ *              (offs_b[n] - offs_b[0]) bytes (>= 1).  Pair p's alignment
+ *              columns start at ops_out[(offs_a[p] - offs_a[0]) +
+ *              (offs_b[p] - offs_b[0])] and take at most m + n bytes: 'M'
+ *              aligns q_i with s_j (match or mismatch), 'I' puts q_i against
+ *              a gap, 'D' puts s_j against a gap, first column first.
+ *   span_out : device, int32 [n_pairs][5] = {n_ops, a0, a1, b0, b1}: the
+ *              alignment covers A[a0..a1) and B[b0..b1).  Global: the whole
+ *              of both sequences.  Semi-global: a0 == 0 or b0 == 0, and
+ *              a1 == m or b1 == n (the cut-off ends are the free end gaps).
+ *              Local: any substrings; score 0 gives the empty alignment.
+ * The alignment's score by the definition (sigma over 'M' columns,
+ * alpha + (k-1) beta per maximal run of k equal gap columns) equals
+ * scores_out[p], the optimal score.  When several alignments are optimal,
+ * which one is returned is unspecified.  Cells are 32-bit; the same range
+ * limit as as_align_batch applies (AS_ERR_RANGE).  Work: at most about four
+ * times the pair's cells for local and semi-global pairs (end cell, start
+ * cell, twice the span's cells), twice for global ones; memory: the library
+ * keeps per resident wave a column of (longest A + 2) and four rows of
+ * (longest B + 2) 32-bit values.
+ */
+int as_align_batch_traceback(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t *seqs_b,
+                             const int64_t *offs_b, int64_t n_pairs, const as_scoring *scoring,
+                             int32_t mode, int32_t *scores_out, uint8_t *ops_out, int32_t *span_out,
+                             void *stream);
+
+/*
+ * Test hook of the traceback: subproblems of at most `cells` cells (and
+ * within the kernel's LDS limits) are solved with explicit predecessors,
+ * larger ones are split; <= 0 restores the default (as large as LDS
+ * allows).  Returns the previous value.
+ */
+int as_set_traceback_base(int32_t cells);
 
 /* Human-readable text for a return code (static storage). */
 const char *as_strerror(int code);
@@ -309,6 +375,28 @@ int as_train_band_model(const uint8_t *seqs_a, const int64_t *offs_a, const uint
                         const int64_t *offs_b, int64_t n_pairs, const as_scoring *scoring,
                         int32_t mode, float *params, const int32_t *order, int32_t n_steps,
                         int32_t batch, float lr, float tau, void *stream);
+
+/*
+ * Versioned storage of a band network (not in the paper): its parameters
+ * and, optionally, the Adam moments, so training can be resumed and a
+ * trained network reused in another process.  The blob is host memory the
+ * caller owns: a 64-byte header (magic "ASBANDMD", format version 1, the
+ * parameter count, input and hidden sizes, whether Adam moments follow, the
+ * Adam step counter, an FNV-1a checksum of the payload) and the float32
+ * parameters in this library's layout, then the two moments.
+ * as_band_model_blob_size(with_adam) is the exact size.  Save copies from
+ * device memory (params, and adam_m / adam_v together or not at all);
+ * *blob_size (optional) receives the size; a blob_cap below it returns
+ * AS_ERR_ARG.  Load checks the magic, version, sizes and checksum
+ * (AS_ERR_ARG on any mismatch), then copies into device memory; asking for
+ * Adam moments from a blob without them returns AS_ERR_ARG.  Both wait for
+ * their copies before returning.
+ */
+int64_t as_band_model_blob_size(int32_t with_adam);
+int as_band_model_save(const float *params, const float *adam_m, const float *adam_v, int64_t adam_t,
+                       void *blob_out, int64_t blob_cap, int64_t *blob_size, void *stream);
+int as_band_model_load(const void *blob, int64_t blob_size, float *params_out, float *adam_m_out,
+                       float *adam_v_out, int64_t *adam_t_out, void *stream);
 
 /*
  * Learned-band alignment: features, network inference, then

@@ -81,6 +81,18 @@ def lib() -> ctypes.CDLL:
     L.as_align_batch.argtypes = [p, p, p, p, i64, ctypes.POINTER(Scoring), i32, p, p]
     L.as_align_batch_noalloc.restype = ctypes.c_int
     L.as_align_batch_noalloc.argtypes = [p, p, p, p, i64, ctypes.POINTER(Scoring), i32, p, p]
+    L.as_align_batch_traceback.restype = ctypes.c_int
+    L.as_align_batch_traceback.argtypes = [p, p, p, p, i64, ctypes.POINTER(Scoring), i32, p, p, p, p]
+    L.as_set_traceback_base.restype = ctypes.c_int
+    L.as_set_traceback_base.argtypes = [i32]
+    L.as_band_model_blob_size.restype = i64
+    L.as_band_model_blob_size.argtypes = [i32]
+    L.as_band_model_save.restype = ctypes.c_int
+    L.as_band_model_save.argtypes = [p, p, p, i64, p, i64, ctypes.POINTER(ctypes.c_int64), p]
+    L.as_band_model_load.restype = ctypes.c_int
+    L.as_band_model_load.argtypes = [p, i64, p, p, p, ctypes.POINTER(ctypes.c_int64), p]
+    L.as_align_all_vs_all.restype = ctypes.c_int
+    L.as_align_all_vs_all.argtypes = [p, p, i64, p, p, i64, ctypes.POINTER(Scoring), i32, p, p]
     L.as_strerror.restype = ctypes.c_char_p
     L.as_strerror.argtypes = [ctypes.c_int]
     L.as_release_workspace.restype = ctypes.c_int
@@ -208,6 +220,55 @@ def _align_full(fn, seqs_a, offs_a, seqs_b, offs_b, subst, alpha, beta, mode, sc
     del keep
     _check(rc)
     return scores_out
+
+
+def align_batch_traceback(seqs_a, offs_a, seqs_b, offs_b, subst, alpha: int, beta: int, mode: int,
+                          stream=None):
+    """Scores and one optimal alignment per pair: (scores int32 [n], ops uint8
+    [sum of m + n], span int32 [n, 5] = (n_ops, a0, a1, b0, b1)), device
+    tensors; pair p's columns start at (offs_a[p] - offs_a[0]) + (offs_b[p] - offs_b[0])."""
+    import torch
+    n_pairs = offs_a.numel() - 1
+    dev = offs_a.device
+    total = int((offs_a[-1] - offs_a[0] + offs_b[-1] - offs_b[0]).item()) if n_pairs > 0 else 0
+    scores = torch.empty(max(n_pairs, 1), dtype=torch.int32, device=dev)
+    ops = torch.zeros(max(total, 1), dtype=torch.uint8, device=dev)
+    span = torch.zeros((max(n_pairs, 1), 5), dtype=torch.int32, device=dev)
+    sc, keep = make_scoring(subst, alpha, beta)
+    rc = lib().as_align_batch_traceback(*_seq_ptrs(seqs_a, offs_a, seqs_b, offs_b), n_pairs,
+                                        ctypes.byref(sc), int(mode),
+                                        _dev_ptr(scores, torch.int32, "scores_out"),
+                                        _dev_ptr(ops, torch.uint8, "ops_out"),
+                                        _dev_ptr(span, torch.int32, "span_out"),
+                                        ctypes.c_void_p(_stream(dev, stream)))
+    del keep
+    _check(rc)
+    return scores[:n_pairs], ops, span[:n_pairs]
+
+
+def set_traceback_base(cells: int) -> int:
+    """Explicit-predecessor limit of the traceback in cells (test hook; <= 0 resets)."""
+    return int(lib().as_set_traceback_base(int(cells)))
+
+
+def align_all_vs_all(seqs_q, offs_q, seqs_s, offs_s, subst, alpha: int, beta: int, mode: int,
+                     scores_out=None, stream=None):
+    """Scores of every query against every subject: int32 device tensor [n_q, n_s]."""
+    import torch
+    n_q, n_s = offs_q.numel() - 1, offs_s.numel() - 1
+    dev = offs_q.device
+    if scores_out is None:
+        scores_out = torch.empty((max(n_q, 1), max(n_s, 1)), dtype=torch.int32, device=dev)
+    sc, keep = make_scoring(subst, alpha, beta)
+    pq = _dev_ptr(seqs_q, torch.uint8, "seqs_q") if seqs_q.numel() else ctypes.c_void_p(offs_q.data_ptr())
+    ps = _dev_ptr(seqs_s, torch.uint8, "seqs_s") if seqs_s.numel() else ctypes.c_void_p(offs_s.data_ptr())
+    rc = lib().as_align_all_vs_all(pq, _dev_ptr(offs_q, torch.int64, "offs_q"), n_q,
+                                   ps, _dev_ptr(offs_s, torch.int64, "offs_s"), n_s,
+                                   ctypes.byref(sc), int(mode), _dev_ptr(scores_out, torch.int32, "scores_out"),
+                                   ctypes.c_void_p(_stream(dev, stream)))
+    del keep
+    _check(rc)
+    return scores_out[:n_q, :n_s]
 
 
 def set_band_packing(on: bool) -> bool:
@@ -392,6 +453,34 @@ def align_batch_learned(seqs_a, offs_a, seqs_b, offs_b, subst, alpha: int, beta:
     del keep
     _check(rc)
     return scores_out[:n_pairs], st.as_dict()
+
+
+def band_model_save(params, adam_m=None, adam_v=None, adam_t: int = 0, stream=None) -> bytes:
+    """Versioned blob of the band network (and its Adam state when given)."""
+    import torch
+    with_adam = adam_m is not None
+    size = int(lib().as_band_model_blob_size(1 if with_adam else 0))
+    buf = ctypes.create_string_buffer(size)
+    got = ctypes.c_int64(0)
+    _check(lib().as_band_model_save(_dev_ptr(params, torch.float32, "params"),
+                                    _dev_ptr(adam_m, torch.float32, "adam_m") if with_adam else None,
+                                    _dev_ptr(adam_v, torch.float32, "adam_v") if with_adam else None,
+                                    int(adam_t), buf, size, ctypes.byref(got),
+                                    ctypes.c_void_p(_stream(params.device, stream))))
+    return buf.raw[:got.value]
+
+
+def band_model_load(blob: bytes, params_out, adam_m_out=None, adam_v_out=None, stream=None) -> int:
+    """Fill device tensors from a blob; returns the stored Adam step counter."""
+    import torch
+    with_adam = adam_m_out is not None
+    t = ctypes.c_int64(0)
+    raw = ctypes.create_string_buffer(bytes(blob), len(blob))
+    _check(lib().as_band_model_load(raw, len(blob), _dev_ptr(params_out, torch.float32, "params_out"),
+                                    _dev_ptr(adam_m_out, torch.float32, "adam_m_out") if with_adam else None,
+                                    _dev_ptr(adam_v_out, torch.float32, "adam_v_out") if with_adam else None,
+                                    ctypes.byref(t), ctypes.c_void_p(_stream(params_out.device, stream))))
+    return int(t.value)
 
 
 class Plan:

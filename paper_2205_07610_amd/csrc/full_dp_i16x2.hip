@@ -95,6 +95,183 @@ __device__ __forceinline__ uint32_t profile_word(const uint32_t *ptab, const uin
   return ptab[(tr ? 4 : 0) + s];
 }
 
+// The DP of one group's two pairs (low and high halves) once the register
+// profiles are built: rows0/rows1 hold m0/m1 row residues, the halves have
+// n0/n1 columns padded on the left to one stripe.  Returns both results, and
+// for local mode whether a half reached the saturation limit.
+template <int MODE, int K>
+__device__ __forceinline__ void duo_core(const uint8_t *rows0, const uint8_t *rows1, int m0, int m1, int n0,
+                                         int n1, const uint32_t (&Plo)[K], const uint32_t (&Phi)[K], int asz,
+                                         int alpha, int beta, int sat_limit, int lane, int &bad, int &r0,
+                                         int &r1, bool &over0, bool &over1) {
+  constexpr int W = kGroup * K;
+  const int t = lane & 15;
+  const int amb = alpha - beta;
+  const s2 beta2 = pk(beta, beta);
+  const s2 alpha2 = pk(alpha, alpha);
+  const s2 amb2 = pk(amb, amb);
+  const int P0 = W - n0, P1 = W - n1;     // left padding of each half
+  const int mmax = max(m0, m1);
+  const int msmall = min(m0, m1);
+  const bool unequal = m0 != m1;
+  const int its = mmax > 0 ? mmax + kGroup - 1 : 0;
+  const int its_max = wave_max_groups(its);
+  // ---- row-0 state ----
+  s2 Ha[K], Ee[K];
+#pragma unroll
+  for (int x = 0; x < K; ++x) {
+    const int j0 = t * K + x + 1 - P0, j1 = t * K + x + 1 - P1;
+    if (MODE == kGlobal) {
+      Ha[x] = pk(j0 == 0 ? beta - alpha : 2 * beta - 2 * alpha,
+                 j1 == 0 ? beta - alpha : 2 * beta - 2 * alpha);
+      Ee[x] = pk(kNeg16, kNeg16);
+    } else if (MODE == kSemiGlobal) {
+      Ha[x] = pk(beta * j0 + beta - alpha, beta * j1 + beta - alpha);
+      Ee[x] = pk(kNeg16, kNeg16);
+    } else {
+      Ha[x] = pk(-alpha, -alpha);
+      Ee[x] = pk(0, 0);   // E'(1, j) = max(E(1,j), 0) = 0
+    }
+  }
+  s2 hl_prev;
+  {
+    const int j0 = t * K - P0, j1 = t * K - P1;
+    if (MODE == kGlobal)
+      hl_prev = pk(j0 == 0 ? beta - alpha : 2 * beta - 2 * alpha,
+                   j1 == 0 ? beta - alpha : 2 * beta - 2 * alpha);
+    else if (MODE == kSemiGlobal)
+      hl_prev = pk(beta * j0 + beta - alpha, beta * j1 + beta - alpha);
+    else
+      hl_prev = pk(-alpha, -alpha);
+  }
+  int fout = (MODE == kLocal) ? 0 : as_i(pk(kNeg16, kNeg16));
+  // left feed for lane 0 (row 1 first)
+  s2 hb, fb;
+  if (MODE == kGlobal) { hb = pk(2 * beta - 2 * alpha, 2 * beta - 2 * alpha); fb = hb; }
+  else if (MODE == kSemiGlobal) {
+    hb = pk(beta * (1 - P0) + beta - alpha, beta * (1 - P1) + beta - alpha);
+    fb = hb;
+  } else { hb = pk(-alpha, -alpha); fb = pk(0, 0); }
+  s2 rowoff = pk(beta * (1 - t), beta * (1 - t));
+  s2 rm = pk(0, 0);                       // local: running max of H
+  s2 cm = pk(kNeg16, kNeg16);             // semi-global: max of H'(i,n) - beta*i
+  s2 snap = pk(kNeg16, kNeg16);           // value of the shorter half at its last row
+
+  auto load_sel = [&](int idx) -> int {
+    int c0 = 12, c1 = 12;
+    if (idx < m0) { c0 = rows0[idx]; if (c0 >= asz) { bad = 1; c0 = 0; } }
+    if (idx < m1) { c1 = rows1[idx]; if (c1 >= asz) { bad = 1; c1 = 0; } }
+    return (int)make_sel(c0, c1);
+  };
+  int selfeed = load_sel(t);
+  int sel = (int)make_sel(12, 12);
+
+  for (int it0 = 0; it0 < its_max; it0 += kGroup) {
+    const int selnext = load_sel(it0 + kGroup + t);
+#pragma unroll
+    for (int u = 0; u < kGroup; ++u) {
+      const int row = it0 + u + 1 - t;
+      sel = dpp_shr1(selfeed, sel);
+      const s2 hl = as_s2(dpp_shr1(as_i(hb), as_i(Ha[K - 1])));
+      const s2 fl = as_s2(dpp_shr1(as_i(fb), fout));
+      if ((unsigned)(row - 1) < (unsigned)mmax) {
+        // Phase A, independent per column: diagonal sums from the previous
+        // row's values (and, shifted frame, E), so that phase B can overwrite
+        // every state register in place.
+        s2 tt[K];
+#pragma unroll
+        for (int x = 0; x < K; ++x) {
+          const s2 p = as_s2((int)__builtin_amdgcn_perm(Phi[x], Plo[x], (uint32_t)sel));
+          const s2 dg = (x == 0) ? hl_prev : Ha[x - 1];
+          if (MODE == kLocal) {
+            tt[x] = __builtin_elementwise_add_sat(dg, p);
+          } else {
+            tt[x] = dg + p;
+            Ee[x] = vmax(Ee[x], Ha[x]);
+          }
+        }
+        // Phase B, the F chain along the row.
+        s2 f = fl;
+#pragma unroll
+        for (int x = 0; x < K; ++x) {
+          if (MODE == kLocal) {
+            const s2 h = vmax(vmax(tt[x], Ee[x]), f);
+            rm = vmax(rm, h);
+            Ha[x] = h - alpha2;
+            Ee[x] = vmax(sat_sub_u(Ee[x], beta2), Ha[x]);
+            f = vmax(sat_sub_u(f, beta2), Ha[x]);
+          } else {
+            const s2 h = vmax(vmax(tt[x], Ee[x]), f);
+            Ha[x] = h - amb2;
+            f = vmax(f, Ha[x]);
+          }
+        }
+        fout = as_i(f);
+        if (MODE == kSemiGlobal) cm = vmax(cm, Ha[K - 1] - rowoff);
+        if (MODE != kLocal && unequal && row == msmall) {
+          if (MODE == kGlobal) {
+            if (t == kGroup - 1) snap = Ha[K - 1];
+          } else {
+            s2 lr = pk(kNeg16, kNeg16);
+#pragma unroll
+            for (int x = 0; x < K; ++x) {
+              const int jp = t * K + x + 1;
+              lr = vmax(lr, Ha[x] - pk(beta * (jp - P0), beta * (jp - P1)));
+            }
+            snap = lr;
+          }
+        }
+      }
+      hl_prev = hl;
+      if (MODE == kSemiGlobal) {
+        hb = hb + beta2;
+        fb = hb;
+      }
+      rowoff = rowoff + beta2;
+      selfeed = dpp_shl1(selfeed, selfeed);
+    }
+    selfeed = selnext;
+  }
+
+  // ---- results of both halves ----
+  r0 = 0;
+  r1 = 0;
+  over0 = false;
+  over1 = false;
+  if (MODE == kLocal) {
+    const s2 gm = group_max2(rm);
+    r0 = gm.x;
+    r1 = gm.y;
+    over0 = r0 >= sat_limit;
+    over1 = r1 >= sat_limit;
+  } else if (MODE == kGlobal) {
+    // lane 15, register K-1 holds column n of both halves
+    const int src = (lane & ~(kGroup - 1)) + kGroup - 1;
+    const s2 fin = as_s2(__shfl(as_i(Ha[K - 1]), src));
+    const s2 sn = as_s2(__shfl(as_i(snap), src));
+    const int v0 = (unequal && m0 < m1) ? sn.x : fin.x;
+    const int v1 = (unequal && m1 < m0) ? sn.y : fin.y;
+    r0 = v0 + amb - beta * (m0 + n0);
+    r1 = v1 + amb - beta * (m1 + n1);
+  } else {
+    s2 lr = pk(kNeg16, kNeg16);
+#pragma unroll
+    for (int x = 0; x < K; ++x) {
+      const int jp = t * K + x + 1;
+      lr = vmax(lr, Ha[x] - pk(beta * (jp - P0), beta * (jp - P1)));
+    }
+    if (unequal) {
+      if (m0 < m1) lr.x = snap.x;
+      else lr.y = snap.y;
+    }
+    const s2 gl = group_max2(lr);
+    const int src = (lane & ~(kGroup - 1)) + kGroup - 1;
+    const s2 gc = as_s2(__shfl(as_i(cm), src));
+    r0 = max(0, max(gl.x + amb - beta * m0, gc.x + amb - beta * n0));
+    r1 = max(0, max(gl.y + amb - beta * m1, gc.y + amb - beta * n1));
+  }
+}
+
 template <int MODE, int K>
 __global__ void __launch_bounds__(kWave) full_dp_i16_kernel(FullDp16Args a) {
   constexpr int W = kGroup * K;
@@ -102,13 +279,10 @@ __global__ void __launch_bounds__(kWave) full_dp_i16_kernel(FullDp16Args a) {
   const int g = lane >> 4;
   const int t = lane & 15;
   const int n_list = a.ctr->n_full16;
-  const int alpha = a.alpha, beta = a.beta, amb = alpha - beta;
+  const int alpha = a.alpha, beta = a.beta;
   const int asz = a.asz;
   const int bias = (MODE == kLocal) ? alpha : alpha + beta;
   const int pad_val = (MODE == kLocal) ? alpha : (MODE == kGlobal ? alpha - beta : alpha + beta);
-  const s2 beta2 = pk(beta, beta);
-  const s2 alpha2 = pk(alpha, alpha);
-  const s2 amb2 = pk(amb, amb);
   const uint32_t pad_word = (uint32_t)(pad_val & 0xFF) * 0x01010101u;
   // profile words by (orientation, column letter): at most 4 letters here
   __shared__ uint32_t ptab[8];
@@ -141,11 +315,6 @@ __global__ void __launch_bounds__(kWave) full_dp_i16_kernel(FullDp16Args a) {
     const uint8_t *cols0 = (tr0 ? a.seqs_a : a.seqs_b) + d0.col_off;
     const uint8_t *rows1 = (tr1 ? a.seqs_b : a.seqs_a) + d1.row_off;
     const uint8_t *cols1 = (tr1 ? a.seqs_a : a.seqs_b) + d1.col_off;
-    const int mmax = max(m0, m1);
-    const int msmall = min(m0, m1);
-    const bool unequal = m0 != m1;
-    const int its = mmax > 0 ? mmax + kGroup - 1 : 0;
-    const int its_max = wave_max_groups(its);
     int bad = 0;
 
     // ---- register profile (paper: init_profile), both halves ----
@@ -157,158 +326,10 @@ __global__ void __launch_bounds__(kWave) full_dp_i16_kernel(FullDp16Args a) {
       Phi[x] = profile_word(ptab, cols1, n1, tr1, jp - P1, asz, pad_word, bad);
     }
 
-    // ---- row-0 state ----
-    s2 Ha[K], Ee[K];
-#pragma unroll
-    for (int x = 0; x < K; ++x) {
-      const int j0 = t * K + x + 1 - P0, j1 = t * K + x + 1 - P1;
-      if (MODE == kGlobal) {
-        Ha[x] = pk(j0 == 0 ? beta - alpha : 2 * beta - 2 * alpha,
-                   j1 == 0 ? beta - alpha : 2 * beta - 2 * alpha);
-        Ee[x] = pk(kNeg16, kNeg16);
-      } else if (MODE == kSemiGlobal) {
-        Ha[x] = pk(beta * j0 + beta - alpha, beta * j1 + beta - alpha);
-        Ee[x] = pk(kNeg16, kNeg16);
-      } else {
-        Ha[x] = pk(-alpha, -alpha);
-        Ee[x] = pk(0, 0);   // E'(1, j) = max(E(1,j), 0) = 0
-      }
-    }
-    s2 hl_prev;
-    {
-      const int j0 = t * K - P0, j1 = t * K - P1;
-      if (MODE == kGlobal)
-        hl_prev = pk(j0 == 0 ? beta - alpha : 2 * beta - 2 * alpha,
-                     j1 == 0 ? beta - alpha : 2 * beta - 2 * alpha);
-      else if (MODE == kSemiGlobal)
-        hl_prev = pk(beta * j0 + beta - alpha, beta * j1 + beta - alpha);
-      else
-        hl_prev = pk(-alpha, -alpha);
-    }
-    int fout = (MODE == kLocal) ? 0 : as_i(pk(kNeg16, kNeg16));
-    // left feed for lane 0 (row 1 first)
-    s2 hb, fb;
-    if (MODE == kGlobal) { hb = pk(2 * beta - 2 * alpha, 2 * beta - 2 * alpha); fb = hb; }
-    else if (MODE == kSemiGlobal) {
-      hb = pk(beta * (1 - P0) + beta - alpha, beta * (1 - P1) + beta - alpha);
-      fb = hb;
-    } else { hb = pk(-alpha, -alpha); fb = pk(0, 0); }
-    s2 rowoff = pk(beta * (1 - t), beta * (1 - t));
-    s2 rm = pk(0, 0);                       // local: running max of H
-    s2 cm = pk(kNeg16, kNeg16);             // semi-global: max of H'(i,n) - beta*i
-    s2 snap = pk(kNeg16, kNeg16);           // value of the shorter half at its last row
-
-    auto load_sel = [&](int idx) -> int {
-      int c0 = 12, c1 = 12;
-      if (idx < m0) { c0 = rows0[idx]; if (c0 >= asz) { bad = 1; c0 = 0; } }
-      if (idx < m1) { c1 = rows1[idx]; if (c1 >= asz) { bad = 1; c1 = 0; } }
-      return (int)make_sel(c0, c1);
-    };
-    int selfeed = load_sel(t);
-    int sel = (int)make_sel(12, 12);
-
-    for (int it0 = 0; it0 < its_max; it0 += kGroup) {
-      const int selnext = load_sel(it0 + kGroup + t);
-#pragma unroll
-      for (int u = 0; u < kGroup; ++u) {
-        const int row = it0 + u + 1 - t;
-        sel = dpp_shr1(selfeed, sel);
-        const s2 hl = as_s2(dpp_shr1(as_i(hb), as_i(Ha[K - 1])));
-        const s2 fl = as_s2(dpp_shr1(as_i(fb), fout));
-        if ((unsigned)(row - 1) < (unsigned)mmax) {
-          // Phase A, independent per column: diagonal sums from the previous
-          // row's values (and, shifted frame, E), so that phase B can overwrite
-          // every state register in place.
-          s2 tt[K];
-#pragma unroll
-          for (int x = 0; x < K; ++x) {
-            const s2 p = as_s2((int)__builtin_amdgcn_perm(Phi[x], Plo[x], (uint32_t)sel));
-            const s2 dg = (x == 0) ? hl_prev : Ha[x - 1];
-            if (MODE == kLocal) {
-              tt[x] = __builtin_elementwise_add_sat(dg, p);
-            } else {
-              tt[x] = dg + p;
-              Ee[x] = vmax(Ee[x], Ha[x]);
-            }
-          }
-          // Phase B, the F chain along the row.
-          s2 f = fl;
-#pragma unroll
-          for (int x = 0; x < K; ++x) {
-            if (MODE == kLocal) {
-              const s2 h = vmax(vmax(tt[x], Ee[x]), f);
-              rm = vmax(rm, h);
-              Ha[x] = h - alpha2;
-              Ee[x] = vmax(sat_sub_u(Ee[x], beta2), Ha[x]);
-              f = vmax(sat_sub_u(f, beta2), Ha[x]);
-            } else {
-              const s2 h = vmax(vmax(tt[x], Ee[x]), f);
-              Ha[x] = h - amb2;
-              f = vmax(f, Ha[x]);
-            }
-          }
-          fout = as_i(f);
-          if (MODE == kSemiGlobal) cm = vmax(cm, Ha[K - 1] - rowoff);
-          if (MODE != kLocal && unequal && row == msmall) {
-            if (MODE == kGlobal) {
-              if (t == kGroup - 1) snap = Ha[K - 1];
-            } else {
-              s2 lr = pk(kNeg16, kNeg16);
-#pragma unroll
-              for (int x = 0; x < K; ++x) {
-                const int jp = t * K + x + 1;
-                lr = vmax(lr, Ha[x] - pk(beta * (jp - P0), beta * (jp - P1)));
-              }
-              snap = lr;
-            }
-          }
-        }
-        hl_prev = hl;
-        if (MODE == kSemiGlobal) {
-          hb = hb + beta2;
-          fb = hb;
-        }
-        rowoff = rowoff + beta2;
-        selfeed = dpp_shl1(selfeed, selfeed);
-      }
-      selfeed = selnext;
-    }
-
-    // ---- results of both halves ----
-    int r0 = 0, r1 = 0;
-    bool over0 = false, over1 = false;
-    if (MODE == kLocal) {
-      const s2 gm = group_max2(rm);
-      r0 = gm.x;
-      r1 = gm.y;
-      over0 = r0 >= a.sat_limit;
-      over1 = r1 >= a.sat_limit;
-    } else if (MODE == kGlobal) {
-      // lane 15, register K-1 holds column n of both halves
-      const int src = (lane & ~(kGroup - 1)) + kGroup - 1;
-      const s2 fin = as_s2(__shfl(as_i(Ha[K - 1]), src));
-      const s2 sn = as_s2(__shfl(as_i(snap), src));
-      const int v0 = (unequal && m0 < m1) ? sn.x : fin.x;
-      const int v1 = (unequal && m1 < m0) ? sn.y : fin.y;
-      r0 = v0 + amb - beta * (m0 + n0);
-      r1 = v1 + amb - beta * (m1 + n1);
-    } else {
-      s2 lr = pk(kNeg16, kNeg16);
-#pragma unroll
-      for (int x = 0; x < K; ++x) {
-        const int jp = t * K + x + 1;
-        lr = vmax(lr, Ha[x] - pk(beta * (jp - P0), beta * (jp - P1)));
-      }
-      if (unequal) {
-        if (m0 < m1) lr.x = snap.x;
-        else lr.y = snap.y;
-      }
-      const s2 gl = group_max2(lr);
-      const int src = (lane & ~(kGroup - 1)) + kGroup - 1;
-      const s2 gc = as_s2(__shfl(as_i(cm), src));
-      r0 = max(0, max(gl.x + amb - beta * m0, gc.x + amb - beta * n0));
-      r1 = max(0, max(gl.y + amb - beta * m1, gc.y + amb - beta * n1));
-    }
+    int r0, r1;
+    bool over0, over1;
+    duo_core<MODE, K>(rows0, rows1, m0, m1, n0, n1, Plo, Phi, asz, alpha, beta, a.sat_limit, lane, bad, r0, r1,
+                      over0, over1);
     if (bad) atomicOr(&a.ctr->status, kStatusBadResidue);
     if (t == 0) {
       if (has0) {
@@ -320,6 +341,101 @@ __global__ void __launch_bounds__(kWave) full_dp_i16_kernel(FullDp16Args a) {
         else a.scores[d1.pair] = r1;
       }
     }
+  }
+}
+
+// All against all (the paper's evaluation workload: every read of a set
+// against every other): the pairs are implicit, pair (q, s) is row sequence
+// q against column sequence s, and its score goes to scores[q * ld + s] (or
+// scores[s * ld + q] when the caller's roles are transposed).  A wave takes
+// one column sequence of at most one packed stripe and a block of row
+// sequences; it builds the column's register profile once and keeps it for
+// the whole block, eight row sequences at a time (two per group, one per
+// 16-bit half, both halves against the same column profile).  Local pairs
+// that saturate are appended to the re-run list as descriptors for the
+// 32-bit kernel.
+template <int MODE, int K>
+__global__ void __launch_bounds__(kWave) all_vs_all_i16_kernel(AllVsAllArgs a) {
+  constexpr int W = kGroup * K;
+  const int lane = threadIdx.x;
+  const int g = lane >> 4;
+  const int t = lane & 15;
+  const int alpha = a.alpha, beta = a.beta;
+  const int asz = a.asz;
+  const int bias = (MODE == kLocal) ? alpha : alpha + beta;
+  const int pad_val = (MODE == kLocal) ? alpha : (MODE == kGlobal ? alpha - beta : alpha + beta);
+  const uint32_t pad_word = (uint32_t)(pad_val & 0xFF) * 0x01010101u;
+  __shared__ uint32_t ptab[8];
+  if (lane < 8) {
+    const int o = lane >> 2, sl = lane & 3;
+    uint32_t w = 0;
+    if (sl < asz)
+      for (int c = 0; c < asz; ++c) {
+        const int sv = o ? a.subst[sl * asz + c] : a.subst[c * asz + sl];
+        w |= (uint32_t)((sv + bias) & 0xFF) << (8 * c);
+      }
+    ptab[lane] = w;
+  }
+  __syncthreads();
+  const int64_t n_items = (int64_t)a.n_cols * a.n_blocks;
+  for (;;) {
+    int item = 0;
+    if (lane == 0) item = atomicAdd(a.next, 1);
+    item = __shfl(item, 0);
+    if (item >= n_items) break;
+    const int c = item / a.n_blocks, blk = item % a.n_blocks;
+    const int64_t c0 = a.offs_c[c];
+    const int n = (int)(a.offs_c[c + 1] - c0);
+    const uint8_t *cols = a.seqs_c + c0;
+    int bad = 0;
+    // ---- the column's register profile, built once for the whole block ----
+    uint32_t P[K];
+#pragma unroll
+    for (int x = 0; x < K; ++x) P[x] = profile_word(ptab, cols, n, a.tr != 0, t * K + x + 1 - (W - n), asz,
+                                                   pad_word, bad);
+    const int r_end = min(a.n_rows, (blk + 1) * a.rows_per_block);
+    for (int r = blk * a.rows_per_block; r < r_end; r += 2 * kGroupsPerWave) {
+      const int q0 = r + 2 * g, q1 = q0 + 1;
+      const bool has0 = q0 < r_end, has1 = q1 < r_end;
+      const int64_t o0 = has0 ? a.offs_r[q0] : 0, o1 = has1 ? a.offs_r[q1] : 0;
+      const int m0 = has0 ? (int)(a.offs_r[q0 + 1] - o0) : 0;
+      const int m1 = has1 ? (int)(a.offs_r[q1 + 1] - o1) : 0;
+      int r0, r1;
+      bool over0, over1;
+      duo_core<MODE, K>(a.seqs_r + o0, a.seqs_r + o1, m0, m1, n, n, P, P, asz, alpha, beta, a.sat_limit, lane,
+                        bad, r0, r1, over0, over1);
+      if (t == 0) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const bool has = h ? has1 : has0;
+          if (!has) continue;
+          const int q = h ? q1 : q0;
+          const int m = h ? m1 : m0;
+          int v = h ? r1 : r0;
+          const bool over = h ? over1 : over0;
+          const int64_t idx = a.tr ? (int64_t)c * a.ld + q : (int64_t)q * a.ld + c;
+          if (m == 0 || n == 0) {
+            // an empty side: one gap run (global) or the empty alignment
+            v = (MODE == kGlobal && m + n > 0) ? -alpha - beta * (m + n - 1) : 0;
+          } else if (over) {
+            // re-run descriptor: rows from the row sequences, columns from the
+            // column sequences; "transposed" when sigma's first index is the
+            // column's letter (the 32-bit launch passes the buffers to match)
+            PairDesc d;
+            d.row_off = a.offs_r[q];
+            d.col_off = c0;
+            d.m = m;
+            d.n = n;
+            d.pair = (int32_t)idx;
+            d.flags = with_variant(a.tr ? kTransposed : 0, kVarI32K16);
+            a.rerun[atomicAdd(a.n_rerun, 1)] = d;
+            continue;
+          }
+          a.scores[idx] = v;
+        }
+      }
+    }
+    if (bad) atomicOr(a.status, kStatusBadResidue);
   }
 }
 
@@ -342,6 +458,33 @@ int full_dp_i16_blocks_per_cu(int mode) {
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, full_dp_i16_kernel<kSemiGlobal, kK16>, kWave, 0);
   else
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, full_dp_i16_kernel<kLocal, kK16>, kWave, 0);
+  if (e != hipSuccess || nb < 1) nb = 1;
+  return nb;
+}
+
+hipError_t launch_all_vs_all_i16(int mode, const AllVsAllArgs &args, int grid, hipStream_t stream) {
+  switch (mode) {
+    case kGlobal:
+      hipLaunchKernelGGL((all_vs_all_i16_kernel<kGlobal, kK16>), dim3(grid), dim3(kWave), 0, stream, args);
+      break;
+    case kSemiGlobal:
+      hipLaunchKernelGGL((all_vs_all_i16_kernel<kSemiGlobal, kK16>), dim3(grid), dim3(kWave), 0, stream, args);
+      break;
+    default:
+      hipLaunchKernelGGL((all_vs_all_i16_kernel<kLocal, kK16>), dim3(grid), dim3(kWave), 0, stream, args);
+  }
+  return hipGetLastError();
+}
+
+int all_vs_all_i16_blocks_per_cu(int mode) {
+  int nb = 0;
+  hipError_t e;
+  if (mode == kGlobal)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, all_vs_all_i16_kernel<kGlobal, kK16>, kWave, 0);
+  else if (mode == kSemiGlobal)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, all_vs_all_i16_kernel<kSemiGlobal, kK16>, kWave, 0);
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, all_vs_all_i16_kernel<kLocal, kK16>, kWave, 0);
   if (e != hipSuccess || nb < 1) nb = 1;
   return nb;
 }

@@ -431,6 +431,7 @@ int band_call(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t *seqs_
               int32_t *hi_out, int32_t *accept_out, as_band_stats *stats, void *stream_ptr);
 bool timing_enabled();
 void release_learned_workspace();
+void release_traceback_workspace();
 void record_learned_timing(float features_ms, float mlp_ms);
 hipError_t launch_mlp_train_step(const float *features, const int32_t *labels, const int32_t *order,
                                  int32_t batch, float tau, float *params, float *m1, float *m2,
@@ -525,6 +526,32 @@ struct FullDp16Args {
 };
 
 hipError_t launch_full_dp_i16(int mode, const FullDp16Args &args, int grid, hipStream_t stream);
+
+// All-against-all batches on the packed kernel (columns of at most one
+// packed stripe, alphabet of at most 4): row sequence q against column
+// sequence c, score at scores[q * ld + c] (tr = 0) or scores[c * ld + q]
+// (tr = 1: the caller's first set is the column set, and sigma's first
+// index is the column letter).
+struct AllVsAllArgs {
+  const uint8_t *seqs_r;   // row sequences
+  const int64_t *offs_r;   // [n_rows + 1]
+  const uint8_t *seqs_c;   // column sequences
+  const int64_t *offs_c;   // [n_cols + 1]
+  int32_t n_rows, n_cols;
+  int32_t rows_per_block;  // row sequences per work item (a multiple of 8)
+  int32_t n_blocks;        // ceil(n_rows / rows_per_block)
+  int32_t tr;
+  int64_t ld;              // leading dimension of scores
+  const int8_t *subst;
+  int32_t asz, alpha, beta, sat_limit;
+  int32_t *scores;
+  int32_t *next;           // work counter (items = column x block)
+  int32_t *status;
+  PairDesc *rerun;         // saturated local pairs for the 32-bit kernel
+  int32_t *n_rerun;
+};
+hipError_t launch_all_vs_all_i16(int mode, const AllVsAllArgs &args, int grid, hipStream_t stream);
+int all_vs_all_i16_blocks_per_cu(int mode);
 int full_dp_i16_blocks_per_cu(int mode);
 int full_dp_i16_stripe_width();
 

@@ -419,3 +419,95 @@ extern "C" int as_align_batch_learned(const uint8_t *seqs_a, const int64_t *offs
   }
   return AS_OK;
 }
+
+// ---- band model blobs ----
+// Layout (little-endian): a 64-byte header
+//   char magic[8] = "ASBANDMD"; uint32 version = 1; uint32 n_params = 6337;
+//   uint32 inputs = 32; uint32 hidden = 64; uint32 has_adam (0/1);
+//   uint32 reserved = 0; int64 adam_t; uint32 checksum; uint32 reserved[5]
+// followed by the float32 parameters in the library's layout (w1 [32][64],
+// b1 [64], w2 [64][64], b2 [64], w3 [64], b3) and, with has_adam, the Adam
+// first and second moments in the same layout.  The checksum is FNV-1a
+// (32-bit) over every payload byte.
+namespace asmi {
+namespace {
+
+constexpr char kBlobMagic[8] = {'A', 'S', 'B', 'A', 'N', 'D', 'M', 'D'};
+constexpr uint32_t kBlobVersion = 1;
+constexpr int64_t kBlobHeader = 64;
+
+uint32_t fnv1a(const uint8_t *p, int64_t n) {
+  uint32_t h = 2166136261u;
+  for (int64_t i = 0; i < n; ++i) h = (h ^ p[i]) * 16777619u;
+  return h;
+}
+
+}  // namespace
+}  // namespace asmi
+
+extern "C" int64_t as_band_model_blob_size(int32_t with_adam) {
+  return kBlobHeader + (int64_t)sizeof(float) * kMlpParams * (with_adam ? 3 : 1);
+}
+
+extern "C" int as_band_model_save(const float *params, const float *adam_m, const float *adam_v, int64_t adam_t,
+                                  void *blob_out, int64_t blob_cap, int64_t *blob_size, void *stream_ptr) {
+  if (!params || !blob_out) return AS_ERR_NULL;
+  if ((adam_m == nullptr) != (adam_v == nullptr) || adam_t < 0) return AS_ERR_ARG;
+  const int with_adam = adam_m ? 1 : 0;
+  const int64_t need = as_band_model_blob_size(with_adam);
+  if (blob_size) *blob_size = need;
+  if (blob_cap < need) return AS_ERR_ARG;
+  hipStream_t stream = (hipStream_t)stream_ptr;
+  uint8_t *b = (uint8_t *)blob_out;
+  float *payload = (float *)(b + kBlobHeader);
+  const size_t bytes = sizeof(float) * kMlpParams;
+  if (hipMemcpyAsync(payload, params, bytes, hipMemcpyDeviceToHost, stream) != hipSuccess) return AS_ERR_HIP;
+  if (with_adam) {
+    if (hipMemcpyAsync(payload + kMlpParams, adam_m, bytes, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipMemcpyAsync(payload + 2 * kMlpParams, adam_v, bytes, hipMemcpyDeviceToHost, stream) != hipSuccess)
+      return AS_ERR_HIP;
+  }
+  if (hipStreamSynchronize(stream) != hipSuccess) return AS_ERR_HIP;
+  memset(b, 0, kBlobHeader);
+  memcpy(b, kBlobMagic, 8);
+  const uint32_t hdr[6] = {kBlobVersion, (uint32_t)kMlpParams, (uint32_t)kMlpInputs, (uint32_t)kMlpHidden,
+                           (uint32_t)with_adam, 0u};
+  memcpy(b + 8, hdr, sizeof(hdr));
+  memcpy(b + 32, &adam_t, sizeof(adam_t));
+  const uint32_t sum = fnv1a((const uint8_t *)payload, need - kBlobHeader);
+  memcpy(b + 40, &sum, sizeof(sum));
+  return AS_OK;
+}
+
+extern "C" int as_band_model_load(const void *blob, int64_t blob_size, float *params_out, float *adam_m_out,
+                                  float *adam_v_out, int64_t *adam_t_out, void *stream_ptr) {
+  if (!blob || !params_out) return AS_ERR_NULL;
+  if (blob_size < kBlobHeader) return AS_ERR_ARG;
+  const uint8_t *b = (const uint8_t *)blob;
+  if (memcmp(b, kBlobMagic, 8) != 0) return AS_ERR_ARG;
+  uint32_t hdr[6];
+  memcpy(hdr, b + 8, sizeof(hdr));
+  if (hdr[0] != kBlobVersion || hdr[1] != (uint32_t)kMlpParams || hdr[2] != (uint32_t)kMlpInputs ||
+      hdr[3] != (uint32_t)kMlpHidden || hdr[4] > 1)
+    return AS_ERR_ARG;
+  const int with_adam = (int)hdr[4];
+  if (blob_size != as_band_model_blob_size(with_adam)) return AS_ERR_ARG;
+  uint32_t sum = 0;
+  memcpy(&sum, b + 40, sizeof(sum));
+  if (fnv1a(b + kBlobHeader, blob_size - kBlobHeader) != sum) return AS_ERR_ARG;
+  if ((adam_m_out || adam_v_out) && !with_adam) return AS_ERR_ARG;
+  if ((adam_m_out == nullptr) != (adam_v_out == nullptr)) return AS_ERR_ARG;
+  hipStream_t stream = (hipStream_t)stream_ptr;
+  const float *payload = (const float *)(b + kBlobHeader);
+  const size_t bytes = sizeof(float) * kMlpParams;
+  if (hipMemcpyAsync(params_out, payload, bytes, hipMemcpyHostToDevice, stream) != hipSuccess) return AS_ERR_HIP;
+  if (adam_m_out) {
+    if (hipMemcpyAsync(adam_m_out, payload + kMlpParams, bytes, hipMemcpyHostToDevice, stream) != hipSuccess ||
+        hipMemcpyAsync(adam_v_out, payload + 2 * kMlpParams, bytes, hipMemcpyHostToDevice, stream) != hipSuccess)
+      return AS_ERR_HIP;
+  }
+  if (hipStreamSynchronize(stream) != hipSuccess) return AS_ERR_HIP;  // the blob is the caller's
+  if (adam_t_out) memcpy(adam_t_out, b + 32, sizeof(int64_t));
+  return AS_OK;
+}
+

@@ -15,6 +15,7 @@
 // kernel either accepts a pair (certificate), re-queues it with the band
 // doubled, or sends it to the full-DP fallback list, which then goes through
 // the full-DP routing of step 1 and steps 3-4.
+#include <algorithm>
 #include <mutex>
 #include <string.h>
 #include <vector>
@@ -664,6 +665,33 @@ __global__ void __launch_bounds__(256) fill_kernel(int32_t *p, int64_t n, int32_
     p[i] = v;
 }
 
+// All-against-all pairs [f0, f1) of the flat index f = q * n_s + s as full-DP
+// descriptors (rows from the first set, columns from the second); a pair
+// with an empty side is scored here by its closed form.
+__global__ void __launch_bounds__(256) all_pairs_desc_kernel(const int64_t *offs_q, const int64_t *offs_s,
+                                                              int64_t n_s, int64_t f0, int64_t f1, int32_t mode,
+                                                              int32_t alpha, int32_t beta, PairDesc *out,
+                                                              Counters *ctr, int32_t *scores) {
+  for (int64_t f = f0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < f1;
+       f += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t q = f / n_s, s = f % n_s;
+    const int64_t a0 = offs_q[q], m = offs_q[q + 1] - a0;
+    const int64_t b0 = offs_s[s], n = offs_s[s + 1] - b0;
+    if (m == 0 || n == 0) {
+      scores[f] = (mode == kGlobal && m + n > 0) ? (int32_t)(-alpha - beta * (m + n - 1)) : 0;
+      continue;
+    }
+    PairDesc d;
+    d.row_off = a0;
+    d.col_off = b0;
+    d.m = (int32_t)m;
+    d.n = (int32_t)n;
+    d.pair = (int32_t)f;
+    d.flags = 0;
+    out[atomicAdd(&ctr->n_fallback, 1)] = d;
+  }
+}
+
 constexpr int kSideStreams = 3;
 
 struct Workspace {
@@ -1229,6 +1257,148 @@ extern "C" int as_align_batch(const uint8_t *seqs_a, const int64_t *offs_a, cons
                     (hipStream_t)stream_ptr, g_timing);
 }
 
+extern "C" int as_align_all_vs_all(const uint8_t *seqs_q, const int64_t *offs_q, int64_t n_q,
+                                   const uint8_t *seqs_s, const int64_t *offs_s, int64_t n_s,
+                                   const as_scoring *scoring, int32_t mode, int32_t *scores_out,
+                                   void *stream_ptr) {
+  if (!scoring || !offs_q || !offs_s || !seqs_q || !seqs_s || !scores_out || !scoring->subst) return AS_ERR_NULL;
+  if (n_q < 0 || n_s < 0 || (n_q > 0 && n_s > 0 && n_q * n_s >= ((int64_t)1 << 31) - 1)) return AS_ERR_ARG;
+  CallScoring cs;
+  int rc = check_scoring(scoring, mode, &cs);
+  if (rc) return rc;
+  if (n_q == 0 || n_s == 0) return AS_OK;
+  const int64_t n_pairs = n_q * n_s;
+  hipStream_t stream = (hipStream_t)stream_ptr;
+  // the two sets' offsets on the host: validation, longest sequences
+  std::vector<int64_t> oq((size_t)n_q + 1), os((size_t)n_s + 1);
+  AS_HIP(hipMemcpyAsync(oq.data(), offs_q, sizeof(int64_t) * (n_q + 1), hipMemcpyDeviceToHost, stream));
+  AS_HIP(hipMemcpyAsync(os.data(), offs_s, sizeof(int64_t) * (n_s + 1), hipMemcpyDeviceToHost, stream));
+  AS_HIP(hipStreamSynchronize(stream));
+  int64_t mq = 0, ms = 0;
+  for (int64_t i = 0; i < n_q; ++i) {
+    if (oq[i] < 0 || oq[i + 1] < oq[i]) return AS_ERR_OFFSETS;
+    mq = std::max(mq, oq[i + 1] - oq[i]);
+  }
+  for (int64_t i = 0; i < n_s; ++i) {
+    if (os[i] < 0 || os[i + 1] < os[i]) return AS_ERR_OFFSETS;
+    ms = std::max(ms, os[i + 1] - os[i]);
+  }
+  // the longest pair exists (longest query against longest subject)
+  if (mq >= kMaxLen || ms >= kMaxLen || (int64_t)(cs.smax_abs + cs.alpha + 2 * cs.beta) * (mq + ms + 2) >= kCellBudget32)
+    return AS_ERR_RANGE;
+
+  std::lock_guard<std::mutex> guard(g_lock);
+  Workspace *w = nullptr;
+  if ((rc = get_workspace(&w))) return rc;
+  memset(&g_last_timing, 0, sizeof(g_last_timing));
+  AS_HIP(hipMemcpyAsync(w->subst, scoring->subst, (size_t)cs.asz * cs.asz, hipMemcpyHostToDevice, stream));
+  const int W16 = full_dp_i16_stripe_width();
+  // the packed kernel with the column profile reused across rows: columns
+  // from the set whose sequences fit one packed stripe
+  const bool cols_s = ms <= W16, cols_q = !cols_s && mq <= W16;
+  bool fast = cs.allow16 && (cols_s || cols_q);
+  if (fast && mode != kLocal) {
+    const int64_t ub = (int64_t)std::max(cs.smax, 0) * std::min(mq, ms) + (int64_t)cs.beta * (mq + ms) + (int64_t)cs.beta * W16 +
+                       cs.alpha + 2 * cs.beta + 256;
+    fast = ub < 32000;
+  }
+  if (fast) {
+    AllVsAllArgs a;
+    a.tr = cols_s ? 0 : 1;
+    a.seqs_r = cols_s ? seqs_q : seqs_s;
+    a.offs_r = cols_s ? offs_q : offs_s;
+    a.seqs_c = cols_s ? seqs_s : seqs_q;
+    a.offs_c = cols_s ? offs_s : offs_q;
+    a.n_rows = (int32_t)(cols_s ? n_q : n_s);
+    a.n_cols = (int32_t)(cols_s ? n_s : n_q);
+    a.ld = n_s;
+    int64_t grid = (int64_t)all_vs_all_i16_blocks_per_cu(mode) * w->num_cu;
+    // about eight work items (column, block of rows) per resident wave
+    int64_t n_blocks = (8 * grid + a.n_cols - 1) / a.n_cols;
+    n_blocks = std::max<int64_t>(1, std::min<int64_t>(n_blocks, (a.n_rows + 7) / 8));
+    int64_t rpb = (a.n_rows + n_blocks - 1) / n_blocks;
+    rpb = (rpb + 7) / 8 * 8;
+    a.rows_per_block = (int32_t)rpb;
+    a.n_blocks = (int32_t)((a.n_rows + rpb - 1) / rpb);
+    const int64_t items = (int64_t)a.n_cols * a.n_blocks;
+    if (grid > items) grid = items;
+    a.subst = w->subst;
+    a.asz = cs.asz;
+    a.alpha = cs.alpha;
+    a.beta = cs.beta;
+    a.sat_limit = g_i16_limit;
+    a.scores = scores_out;
+    a.next = &w->ctr->next_full16;
+    a.status = &w->ctr->status;
+    if ((rc = grow((void **)&w->rerun, &w->rerun_cap, n_pairs, sizeof(PairDesc)))) return rc;
+    a.rerun = w->rerun;
+    a.n_rerun = &w->ctr->n_rerun32;
+    if ((rc = fill_async((int32_t *)w->ctr, (int64_t)(sizeof(Counters) / sizeof(int32_t)), 0, stream))) return rc;
+    const bool timing = g_timing;
+    if (timing) AS_HIP(hipEventRecord(w->ev[2], stream));
+    AS_HIP(launch_all_vs_all_i16(mode, a, (int)grid, stream));
+    if (timing) AS_HIP(hipEventRecord(w->ev[3], stream));
+    Counters c;
+    if ((rc = read_counters(w, stream, &c))) return rc;
+    g_last_timing.cells = 0;
+    for (int64_t i = 0; i < n_q; ++i) g_last_timing.cells += (oq[i + 1] - oq[i]) * (os[n_s] - os[0]);
+    g_last_timing.pairs_full16 = n_pairs - c.n_rerun32;
+    g_last_timing.cells_full16 = g_last_timing.cells;
+    if (timing) g_last_timing.full16_ms = elapsed(w->ev[2], w->ev[3]);
+    if ((rc = status_to_code(c.status))) return rc;
+    g_last_timing.pairs_rerun32 = c.n_rerun32;
+    if (c.n_rerun32 > 0) {
+      FullDpArgs args;
+      args.seqs_a = a.tr ? a.seqs_c : a.seqs_r;   // see the re-run descriptors
+      args.seqs_b = a.tr ? a.seqs_r : a.seqs_c;
+      args.ctr = w->ctr;
+      args.subst = w->subst;
+      args.asz = cs.asz;
+      args.alpha = cs.alpha;
+      args.beta = cs.beta;
+      args.scores = scores_out;
+      const int bpc = full_dp_i32_blocks_per_cu(mode, cs.asz, kmask_of_variant(kVarI32K16));
+      int64_t g2 = (int64_t)bpc * w->num_cu;
+      const int64_t need_waves = ((int64_t)c.n_rerun32 + kGroupsPerWave - 1) / kGroupsPerWave;
+      if (g2 > need_waves) g2 = need_waves;
+      if ((rc = grow((void **)&w->bnd, &w->bnd_cap, g2 * kGroupsPerWave * 2, sizeof(int2)))) return rc;
+      args.items = w->rerun;
+      args.n_items = &w->ctr->n_rerun32;
+      args.next = &w->ctr->next_rerun32;
+      args.bnd = w->bnd;
+      args.bnd_rows = 1;
+      AS_HIP(launch_full_dp_i32(mode, args, kmask_of_variant(kVarI32K16), (int)g2, stream));
+      Counters c3;
+      if ((rc = read_counters(w, stream, &c3))) return rc;
+      if ((rc = status_to_code(c3.status))) return rc;
+    }
+    return AS_OK;
+  }
+  // every other case: the pairs as descriptors, in chunks, through the
+  // full-DP routing and kernels
+  const int64_t chunk = std::min<int64_t>(n_pairs, (int64_t)1 << 24);
+  if ((rc = lists_capacity(w, chunk))) return rc;
+  if ((rc = grow((void **)&w->fallback, &w->fallback_cap, chunk, sizeof(PairDesc)))) return rc;
+  const RouteParams rp = route_params(cs, chunk);
+  for (int64_t f0 = 0; f0 < n_pairs; f0 += chunk) {
+    const int64_t f1 = std::min(n_pairs, f0 + chunk);
+    if ((rc = fill_async((int32_t *)w->ctr, (int64_t)(sizeof(Counters) / sizeof(int32_t)), 0, stream))) return rc;
+    int64_t blocks = (f1 - f0 + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(all_pairs_desc_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, offs_q, offs_s, n_s, f0,
+                       f1, mode, cs.alpha, cs.beta, w->fallback, w->ctr, scores_out);
+    AS_HIP(hipGetLastError());
+    Counters c;
+    if ((rc = read_counters(w, stream, &c))) return rc;
+    if (c.n_fallback == 0) continue;
+    if ((rc = launch_classify(w, rp, nullptr, nullptr, w->fallback, c.n_fallback, scores_out, stream))) return rc;
+    if ((rc = read_counters(w, stream, &c))) return rc;
+    if ((rc = status_to_code(c.status))) return rc;
+    if ((rc = run_full_lists(w, cs, seqs_q, seqs_s, scores_out, stream, false, c))) return rc;
+  }
+  return AS_OK;
+}
+
 extern "C" int as_align_batch_noalloc(const uint8_t *seqs_a, const int64_t *offs_a, const uint8_t *seqs_b,
                                       const int64_t *offs_b, int64_t n_pairs, const as_scoring *scoring,
                                       int32_t mode, int32_t *scores_out, void *stream_ptr) {
@@ -1790,6 +1960,7 @@ extern "C" const char *as_strerror(int code) {
 
 extern "C" int as_release_workspace(void) {
   release_learned_workspace();  // takes its own lock, never while holding this one
+  release_traceback_workspace();
   std::lock_guard<std::mutex> guard(g_lock);
   for (Workspace &w : g_ws) {
     if (w.device < 0) continue;

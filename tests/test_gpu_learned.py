@@ -235,6 +235,54 @@ def test_training_reduces_loss(gpu):
     assert loss1 < 0.25 * loss0
 
 
+def test_band_model_blob_round_trip(gpu):
+    """A saved network (with and without its Adam state) loads back bit for
+    bit, resumed training from the loaded state equals uninterrupted
+    training, and damaged or mismatched blobs are refused."""
+    import torch
+    from paper_2205_07610_amd.binding import AlignError
+    rng = np.random.default_rng(860)
+    n = 2048
+    x = _t(rng.uniform(0, 1, (n, 32)).astype(np.float32))
+    labels = _t(rng.integers(0, 200, n).astype(np.int32))
+    order = _t(synth.minibatch_order(861, n, 40, 128))
+    p_a = _t(synth.band_params_init(862))
+    m_a, v_a = torch.zeros_like(p_a), torch.zeros_like(p_a)
+    gpu.band_train(p_a, m_a, v_a, x, labels, order[:20 * 128], 20, 128, 1, 2e-3, 0.7)
+    blob = gpu.band_model_save(p_a, m_a, v_a, adam_t=21)
+    assert len(blob) == 64 + 3 * 4 * gpu.MLP_PARAMS and blob[:8] == b"ASBANDMD"
+    p_b, m_b, v_b = torch.empty_like(p_a), torch.empty_like(p_a), torch.empty_like(p_a)
+    assert gpu.band_model_load(blob, p_b, m_b, v_b) == 21
+    for u, w in ((p_a, p_b), (m_a, m_b), (v_a, v_b)):
+        assert torch.equal(u, w)
+    # resume both copies for the last 20 steps: identical trajectories
+    gpu.band_train(p_a, m_a, v_a, x, labels, order[20 * 128:], 20, 128, 21, 2e-3, 0.7)
+    gpu.band_train(p_b, m_b, v_b, x, labels, order[20 * 128:], 20, 128, 21, 2e-3, 0.7)
+    assert torch.equal(p_a, p_b)
+    # parameters only
+    small = gpu.band_model_save(p_a)
+    assert len(small) == 64 + 4 * gpu.MLP_PARAMS
+    p_c = torch.empty_like(p_a)
+    gpu.band_model_load(small, p_c)
+    assert torch.equal(p_a, p_c)
+    with pytest.raises(AlignError) as e:        # no Adam state in this blob
+        gpu.band_model_load(small, p_c, torch.empty_like(p_a), torch.empty_like(p_a))
+    assert e.value.code == -7
+    bad = bytearray(blob)
+    bad[200] ^= 1                               # payload damaged: checksum
+    with pytest.raises(AlignError) as e:
+        gpu.band_model_load(bytes(bad), p_c)
+    assert e.value.code == -7
+    bad = bytearray(blob)
+    bad[8] = 2                                  # unknown format version
+    with pytest.raises(AlignError) as e:
+        gpu.band_model_load(bytes(bad), p_c)
+    assert e.value.code == -7
+    with pytest.raises(AlignError) as e:        # truncated
+        gpu.band_model_load(blob[:-4], p_c)
+    assert e.value.code == -7
+
+
 def test_learned_band_exact_and_beats_fixed_width(gpu, oracle_mod):
     """Train on a config-4-law training set (own seed), then align a held-out
     set: every score equals the oracle's full DP, and the learned initial
