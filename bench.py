@@ -120,6 +120,24 @@ def traffic_for(kernel: str):
     return rec.get("bytes_per_unit")
 
 
+def valu_for(kernel: str):
+    """Measured VALU issue and busy fractions of the kernel's roofline unit
+    from the committed rocprofv3 PMC summary (pmc_valu), if it was taken on
+    the current kernel and routing sources and on this workload; else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_valu_{WORKLOAD_NAME['name']}.json")
+    if kernel not in KERNEL_SOURCES or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_sha") != source_sha(KERNEL_SOURCES[kernel]):
+        return None
+    from paper_2205_07610_amd.pmc_traffic import routing_sha
+    if rec.get("routing_sha") != routing_sha():
+        return None
+    return {k: rec[k] for k in ("issue_frac", "busy_frac", "lane_util", "lane_insts_per_cell",
+                                "lds_insts_per_cell") if k in rec}
+
+
 def cpu_baseline(batch, seconds: float, gpu_scores):
     """Time the CPU oracle on a bounded sample of the same batch; also count
     GPU/oracle mismatches on that sample."""
@@ -128,7 +146,9 @@ def cpu_baseline(batch, seconds: float, gpu_scores):
     threads = oracle.default_threads()
     rng = np.random.default_rng(12345)
     order = rng.permutation(batch.n_pairs)
-    chunk = 4096
+    # about 2e10 cells per chunk (a few seconds on the host), 16..4096 pairs
+    avg_cells = max(batch.cells() / max(batch.n_pairs, 1), 1.0)
+    chunk = int(min(4096, max(16, 2e10 / avg_cells)))
     done_cells = 0
     done_pairs = 0
     mismatches = 0
@@ -167,6 +187,7 @@ def roofline(kernel_name, kernel_ms, ops, packed):
         "frac": round(achieved / peak, 4),
         "kernel_ms": round(kernel_ms, 4),
         "traffic": traffic_for(kernel_name) if kernel_name in KERNEL_SOURCES else None,
+        "valu_measured": valu_for(kernel_name),
     }
 
 
@@ -181,14 +202,28 @@ def timed(step, steps, warmup, binding, torch):
     t0 = time.perf_counter()
     for _ in range(steps):
         st = step()
+        # every library call waits for its own status word, so the host clock
+        # after a call also closes that step's GPU work
         tm = binding.last_timing()
+        tm["wall_ms"] = (time.perf_counter() - t0) * 1e3
         if isinstance(st, dict):
             tm.update({"stats": st})
         phases.append(tm)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     binding.enable_timing(False)
+    ends = [p["wall_ms"] for p in phases]
+    for i, p in enumerate(phases):
+        p["step_ms"] = ends[i] - (ends[i - 1] if i else 0.0)
     return (t1 - t0) * 1e3 / steps, phases
+
+
+def decile_median(phases):
+    """Mean of the 5th and 6th deciles of the per-step times (the paper's
+    median of repeated runs)."""
+    import numpy as np
+    t = np.sort(np.array([p["step_ms"] for p in phases]))
+    return float(np.mean(np.quantile(t, [0.5, 0.6], method="lower"))) if len(t) > 1 else float(t[0])
 
 
 def mean_phases(phases, names):
@@ -353,7 +388,7 @@ def main():
         tune_s = time.perf_counter() - t0
         log(f"table {table.tolist()} ({tune_s:.1f} s); automatic-table eager step {auto_ms:.3f} ms")
         plan = binding.Plan(sa, oa, sb, ob, *args_sc, scores_out=out)
-        plan_ms, _ = timed(plan.run, args.steps, args.warmup, binding, torch)
+        plan_ms, plan_phases = timed(plan.run, args.steps, args.warmup, binding, torch)
         plan_scores = out.cpu().numpy()
         log(f"graph replay: {plan_ms:.3f} ms/step")
         bins = sorted(set(int(x) for x in np.nonzero(gtab.max(axis=1) > 0)[0]))
@@ -442,6 +477,8 @@ def main():
         dom = max(full_names, key=lambda k: avg[k])
         roof = phase_roofline(full_phases, dom, OPS_PER_CELL[batch.mode])
         dtype = "i16x2" if dom in PACKED_PHASES else "i32"
+        per_kernel = {k.replace("_ms", ""): phase_roofline(full_phases, k, OPS_PER_CELL[batch.mode])
+                      for k in ("full32_ms", "full16_ms", "long_ms", "long16_ms") if full_avg[k] > 0}
 
     result = {
         "metric": METRIC,
@@ -464,6 +501,10 @@ def main():
         "phases_ms": {k: round(v, 4) for k, v in avg.items()},
         "roofline": roof,
     }
+    step_phases = phases if learned else plan_phases if graph_info is not None else full_phases
+    result["ms_per_step_decile_median"] = round(decile_median(step_phases), 4)
+    if not learned:
+        result["roofline_per_kernel"] = per_kernel
     if graph_info is not None:
         result["graph"] = graph_info
         result["value_note"] = ("whole step = one graph replay; phases and roofline from the eager "
