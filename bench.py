@@ -395,7 +395,7 @@ def main():
         graph_info = {"table": table.tolist(), "autotune_s": round(tune_s, 2),
                       "gcups_per_bin_variant": {str(b): [round(float(v), 1) for v in gtab[b]]
                                                 for b in bins},
-                      "variant_names": ["packed16", "k8", "k16", "k32", "wavefront"],
+                      "variant_names": ["packed16", "k8", "k16", "k32", "wavefront", "packed_lds"],
                       "eager_automatic_table_ms": round(auto_ms, 4)}
     log(f"full DP: warmup {args.warmup}, {args.steps} steps")
     full_ms, full_phases = timed(full_step, args.steps, args.warmup, binding, torch)
@@ -424,6 +424,12 @@ def main():
         gpu_scores = out_l.cpu().numpy()
         mism_full = int(np.count_nonzero(gpu_scores != full_scores))
         log(f"learned band: {ms_per_step:.3f} ms/step, mismatches vs full DP {mism_full}")
+        # the same call without the chunked overlap of features and banded rounds
+        prev_chunks = binding.set_learned_chunks(1)
+        unchunked_ms, _ = timed(learned_step, args.steps, args.warmup, binding, torch)
+        binding.set_learned_chunks(prev_chunks)
+        unchunked_mism = int(np.count_nonzero(out_l.cpu().numpy() != full_scores))
+        log(f"learned band, one chunk: {unchunked_ms:.3f} ms/step")
         # the banded phase splits into the packed 16-bit and the 32-bit kernel,
         # each with its own cells, time and peak
         opc = OPS_PER_CELL[batch.mode]
@@ -479,6 +485,24 @@ def main():
         dtype = "i16x2" if dom in PACKED_PHASES else "i32"
         per_kernel = {k.replace("_ms", ""): phase_roofline(full_phases, k, OPS_PER_CELL[batch.mode])
                       for k in ("full32_ms", "full16_ms", "long_ms", "long16_ms") if full_avg[k] > 0}
+        cell_type = int(full_phases[-1].get("full16_cell_type", 0)) if full_avg["full16_ms"] > 0 else 0
+        if dom == "full16_ms" and cell_type:
+            dtype = "f16x2"
+        if full_avg["full16_ms"] > 0:
+            # the packed kernel's cell types side by side (same batch, eager)
+            alt = {}
+            for hmode, label in ((0, "int16"), (1, "fp16_when_admissible")):
+                prev_h = binding.set_half_cells(hmode)
+                ms_h, ph_h = timed(full_step, args.steps, args.warmup, binding, torch)
+                binding.set_half_cells(prev_h)
+                alt[label] = {"ms_per_step": round(ms_h, 4),
+                              "full16_ms": round(mean_phases(ph_h, ["full16_ms"])["full16_ms"], 4),
+                              "cell_type": int(ph_h[-1]["full16_cell_type"]),
+                              "pairs_full16": int(ph_h[-1]["pairs_full16"]),
+                              "mismatches_vs_default": int(np.count_nonzero(out.cpu().numpy() != full_scores))}
+                log(f"packed cells {label}: {ms_h:.3f} ms/step, packed kernel {alt[label]['full16_ms']:.3f} ms")
+            per_kernel["full16"]["cell_type"] = cell_type
+            per_kernel["full16"]["cell_types_compared"] = alt
 
     result = {
         "metric": METRIC,
@@ -521,6 +545,9 @@ def main():
             "roofline_per_kernel": fr,
         }
         result["speedup_vs_full_dp"] = round(full_ms / ms_per_step, 3)
+        result["learned_one_chunk"] = {"ms_per_step": round(unchunked_ms, 4),
+                                       "mismatches_vs_full_dp": unchunked_mism,
+                                       "note": "features of chunk k + 1 not overlapped with chunk k's rounds"}
         result["mismatches_vs_full_dp"] = mism_full
         result["band_stats"] = {k: stats[k] for k in ("rounds", "accepted", "fallback", "band_cells",
                                                       "band16_cells", "fallback_cells", "dp_cells")}

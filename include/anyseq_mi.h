@@ -222,6 +222,8 @@ typedef struct {
     int64_t cells_long;
     int64_t pairs_long16;
     int64_t cells_long16;
+    int64_t full16_cell_type; /* cells of the packed full-DP kernel: 0 int16, 1 FP16 with FP8 E4M3
+                                 profile bytes, 2 FP16 with FP8 E5M2 profile bytes */
 } as_timing;
 
 /*
@@ -410,6 +412,15 @@ int as_align_batch_learned(const uint8_t *seqs_a, const int64_t *offs_a, const u
                            int32_t *scores_out, as_band_stats *stats, void *stream);
 
 /*
+ * Chunks of a large as_align_batch_learned call (default 4; 1 turns the
+ * overlap off): the batch is cut into up to `chunks` parts of at least
+ * 2^17 pairs; chunk 0's features and widths are computed first, then chunk
+ * k + 1's on a library side stream while chunk k's banded rounds run on the
+ * caller's stream.  Results do not depend on it.  Returns the previous value.
+ */
+int as_set_learned_chunks(int32_t chunks);
+
+/*
  * Full-DP kernel variants per length bin (batching runtime; not in the
  * paper).  Bin b holds the pairs whose longer sequence has at most 64 << b
  * residues (b = 0..AS_LEN_BINS-1, the last bin everything longer).  Within
@@ -418,12 +429,21 @@ int as_align_batch_learned(const uint8_t *seqs_a, const int64_t *offs_a, const u
  *   AS_VARIANT_AUTO       automatic: packed 16-bit when the shorter side has
  *                         at most 256 residues and the range is proven (or
  *                         local), the wavefront for at least 2048 rows and
- *                         more than 1024 columns, else 32-bit with K = 16;
+ *                         more than one wavefront stripe (1024 columns; 512
+ *                         for alphabets of more than 4 letters), else
+ *                         AS_VARIANT_PACKED_LDS for local pairs whose
+ *                         sigma + alpha fits a byte and 32-bit with K = 16
+ *                         for the others;
  *   AS_VARIANT_PACKED16   packed 16-bit kernel (two pairs per lane group);
  *   AS_VARIANT_K8/K16/K32 32-bit stripe kernel with 8/16/32 columns per lane;
- *   AS_VARIANT_WAVEFRONT  multi-wave wavefront (1024-column stripes).
+ *   AS_VARIANT_WAVEFRONT  multi-wave wavefront;
+ *   AS_VARIANT_PACKED_LDS local mode: packed 16-bit cells in 128-column
+ *                         stripes, two pairs per lane group, int8 profiles
+ *                         of any alphabet in LDS; a pair whose 16-bit maximum
+ *                         saturates is recomputed with 32-bit cells.
  * A pair the bin's variant cannot serve (packed: range or width; wavefront:
- * at most 1024 columns) takes the automatic rule.  Every variant computes
+ * at most one stripe of columns; packed LDS: other modes) takes the
+ * automatic rule.  Every variant computes
  * the same exact scores; the table only changes speed.  Tables are kept per
  * mode for the process.
  */
@@ -434,7 +454,8 @@ int as_align_batch_learned(const uint8_t *seqs_a, const int64_t *offs_a, const u
 #define AS_VARIANT_K16 2
 #define AS_VARIANT_K32 3
 #define AS_VARIANT_WAVEFRONT 4
-#define AS_VARIANTS 5
+#define AS_VARIANT_PACKED_LDS 5
+#define AS_VARIANTS 6
 
 /* Set the table of a mode (HOST int8 [AS_LEN_BINS]; NULL: all automatic). */
 int as_set_variants(int32_t mode, const int8_t *table);
@@ -499,6 +520,27 @@ int as_set_band_packing(int32_t on);
  * Returns the previous threshold.
  */
 int as_set_i16_limit(int32_t limit);
+
+/*
+ * Cell type of the packed full-DP kernel (section 3.2: two alignments per
+ * 32-bit register; the paper packs two FP16 values).  FP16 holds integers
+ * exactly only up to 2048 in magnitude, so FP16 cells are used only for
+ * calls whose sigma + bias and padding values all lie in 0..16 (bias =
+ * alpha for local, alpha + beta otherwise), and under them the packed
+ * kernel takes only global and semi-global pairs with
+ * sigma_max*256 + beta*(rows + 512) + alpha + 2*beta + 16 < 1984 (the
+ * others take the 32-bit kernels); local pairs whose FP16 maximum reaches
+ * 1984 are recomputed with 32-bit cells.  Scores are identical under every
+ * setting.
+ *   mode 0: int16 cells always.
+ *   mode 1: FP16 cells for every call that admits them.
+ *   mode 2 (default, any other value): FP16 cells for local calls whose
+ *           profile values are exact in FP8 E5M2 (0..8, 10, 12, 14, 16) and
+ *           whose maxima cannot reach 1984 (sigma_max*256 + alpha + 16 <
+ *           1984), int16 otherwise.
+ * Applies to calls and plans made after it.  Returns the previous mode.
+ */
+int as_set_half_cells(int mode);
 
 /* Enable (1) or disable (0) phase timing.  Returns the previous setting. */
 int as_enable_timing(int on);

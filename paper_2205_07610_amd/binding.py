@@ -43,7 +43,7 @@ class Timing(ctypes.Structure):
                 ("pairs_fallback", ctypes.c_int64), ("cells", ctypes.c_int64),
                 ("cells_full32", ctypes.c_int64), ("cells_full16", ctypes.c_int64),
                 ("cells_long", ctypes.c_int64), ("pairs_long16", ctypes.c_int64),
-                ("cells_long16", ctypes.c_int64)]
+                ("cells_long16", ctypes.c_int64), ("full16_cell_type", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -93,6 +93,8 @@ def lib() -> ctypes.CDLL:
     L.as_band_model_load.argtypes = [p, i64, p, p, p, ctypes.POINTER(ctypes.c_int64), p]
     L.as_align_all_vs_all.restype = ctypes.c_int
     L.as_align_all_vs_all.argtypes = [p, p, i64, p, p, i64, ctypes.POINTER(Scoring), i32, p, p]
+    L.as_set_learned_chunks.restype = ctypes.c_int
+    L.as_set_learned_chunks.argtypes = [i32]
     L.as_strerror.restype = ctypes.c_char_p
     L.as_strerror.argtypes = [ctypes.c_int]
     L.as_release_workspace.restype = ctypes.c_int
@@ -138,6 +140,8 @@ def lib() -> ctypes.CDLL:
     L.as_autotune.argtypes = [p, p, p, p, i64, ctypes.POINTER(Scoring), i32, i32, p, p, p]
     L.as_set_i16_limit.restype = ctypes.c_int
     L.as_set_i16_limit.argtypes = [ctypes.c_int32]
+    L.as_set_half_cells.restype = ctypes.c_int
+    L.as_set_half_cells.argtypes = [ctypes.c_int]
     L.as_enable_timing.restype = ctypes.c_int
     L.as_enable_timing.argtypes = [ctypes.c_int]
     L.as_last_timing.restype = ctypes.c_int
@@ -276,9 +280,21 @@ def set_band_packing(on: bool) -> bool:
     return bool(lib().as_set_band_packing(1 if on else 0))
 
 
+def set_learned_chunks(chunks: int) -> int:
+    """Chunks of a large learned call (features of the next chunk overlap the
+    current chunk's banded rounds); returns the previous value."""
+    return int(lib().as_set_learned_chunks(int(chunks)))
+
+
 def set_i16_limit(limit: int) -> int:
     """Saturation threshold of the 16-bit local path (test hook; <= 0 resets)."""
     return int(lib().as_set_i16_limit(int(limit)))
+
+
+def set_half_cells(mode: int) -> int:
+    """Cell type of the packed full-DP kernel: 0 int16, 1 FP16 whenever the
+    scoring admits it, 2 automatic (the default).  Returns the previous mode."""
+    return int(lib().as_set_half_cells(int(mode)))
 
 
 def _seq_ptrs(seqs_a, offs_a, seqs_b, offs_b):
@@ -524,7 +540,8 @@ class Plan:
 
 
 LEN_BINS = 12
-VARIANTS = {"auto": -1, "packed16": 0, "k8": 1, "k16": 2, "k32": 3, "wavefront": 4}
+VARIANTS = {"auto": -1, "packed16": 0, "k8": 1, "k16": 2, "k32": 3, "wavefront": 4, "packed_lds": 5}
+N_VARIANTS = 6
 
 
 def set_variants(mode: int, table=None):
@@ -546,19 +563,19 @@ def get_variants(mode: int) -> np.ndarray:
 
 def autotune(seqs_a, offs_a, seqs_b, offs_b, subst, alpha: int, beta: int, mode: int,
              sample_pairs: int = 8192, stream=None):
-    """Run the autotuner; returns (table int8 [12], gcups float [12, 5])."""
+    """Run the autotuner; returns (table int8 [12], gcups float [12, N_VARIANTS])."""
     import torch
     n_pairs = offs_a.numel() - 1
     dev = offs_a.device
     sc, keep = make_scoring(subst, alpha, beta)
-    g = np.zeros(LEN_BINS * 5, dtype=np.float32)
+    g = np.zeros(LEN_BINS * N_VARIANTS, dtype=np.float32)
     t = np.zeros(LEN_BINS, dtype=np.int8)
     rc = lib().as_autotune(*_seq_ptrs(seqs_a, offs_a, seqs_b, offs_b), n_pairs, ctypes.byref(sc),
                            int(mode), int(sample_pairs), g.ctypes.data_as(ctypes.c_void_p),
                            t.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(_stream(dev, stream)))
     del keep
     _check(rc)
-    return t, g.reshape(LEN_BINS, 5)
+    return t, g.reshape(LEN_BINS, N_VARIANTS)
 
 
 def enable_timing(on: bool = True) -> bool:

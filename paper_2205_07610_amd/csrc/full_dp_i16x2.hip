@@ -30,6 +30,18 @@
 //    priori bound keeps every shifted cell inside int16; local cells are
 //    bounded below by -alpha and are added with signed saturation, so a
 //    pair whose maximum reaches 32767 is re-queued for the 32-bit kernel.
+//  * Half precision (the paper's own choice of packed type, selectable per
+//    call): the same recurrences on pairs of FP16 values.  Profile bytes are
+//    FP8 E4M3 codes of sigma + bias (exact for the integers 0..16), turned
+//    into a pair of halves by one packed conversion after the v_perm; the
+//    clamped local updates take a max with 0 instead of an unsigned
+//    saturating subtract.  Integers are exact in FP16 up to 2048 in
+//    magnitude: global and semi-global pairs come here only under a priori
+//    bounds below that, and a local pair whose maximum reaches the
+//    threshold (at most 2048 - 64, so every value before it was exact) is
+//    re-run with 32 bits like a saturated int16 pair.
+#include <type_traits>
+
 #include "internal.h"
 
 namespace asmi {
@@ -68,20 +80,74 @@ __device__ __forceinline__ s2 group_max2(s2 v) {
   v = vmax(v, as_s2(__shfl_xor(as_i(v), 1, 16)));
   return v;
 }
+// Half-precision pairs (the paper's section 3.2 arithmetic: two alignments
+// in one register of two FP16 values).  Cells hold integers; they stay exact
+// while every value is within +-2048 (11 significant bits), which the
+// routing proves a priori for every pair it gives this variant.
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ int as_i(h2 v) { return __builtin_bit_cast(int, v); }
+// IEEE maximum (no NaN canonicalisation; two nested ones fuse into one
+// v_pk_maximum3_f16)
+__device__ __forceinline__ h2 vmax(h2 a, h2 b) { return __builtin_elementwise_maximum(a, b); }
+template <typename V> __device__ __forceinline__ V as_v(int v) { return __builtin_bit_cast(V, v); }
+template <typename V> __device__ __forceinline__ V pkv(int lo, int hi) {
+  V r;
+  r.x = lo;
+  r.y = hi;
+  return r;
+}
+__device__ __forceinline__ int toi(short v) { return v; }
+__device__ __forceinline__ int toi(_Float16 v) { return (int)v; }
+// max(a - b, 0) for a >= 0 (E and F of local cells, clamped at 0)
+__device__ __forceinline__ s2 clamp_sub(s2 a, s2 b) { return sat_sub_u(a, b); }
+__device__ __forceinline__ h2 clamp_sub(h2 a, h2 b) { return vmax(a - b, pkv<h2>(0, 0)); }
+// diagonal sum of local cells: signed saturation detects overflow of int16
+// cells; half cells are proven in range, so a plain add
+__device__ __forceinline__ s2 add_diag(s2 a, s2 b) { return __builtin_elementwise_add_sat(a, b); }
+__device__ __forceinline__ h2 add_diag(h2 a, h2 b) { return a + b; }
+__device__ __forceinline__ h2 group_max2(h2 v) {
+  v = vmax(v, as_v<h2>(__shfl_xor(as_i(v), 8, 16)));
+  v = vmax(v, as_v<h2>(__shfl_xor(as_i(v), 4, 16)));
+  v = vmax(v, as_v<h2>(__shfl_xor(as_i(v), 2, 16)));
+  v = vmax(v, as_v<h2>(__shfl_xor(as_i(v), 1, 16)));
+  return v;
+}
+
+// Profile bytes by cell type (kCellI16, kCellF16E4M3, kCellF16E5M2).
+template <int CELL>
+__host__ __device__ inline uint32_t profile_byte(int v) {
+  return CELL == kCellF16E4M3 ? fp8_e4m3(v) : (CELL == kCellF16E5M2 ? fp8_e5m2(v) : (uint32_t)(v & 0xFF));
+}
+
+// Scores of a cell pair from the two halves' profile words and the
+// selector.  int16: v_perm_b32 zero-extends the two selected bytes into the
+// 16-bit halves.  E5M2: v_perm puts each byte in the upper byte of its half
+// (lower byte zero), which is the FP16 value.  E4M3: v_perm puts the bytes
+// in bytes 0 and 1 and one packed conversion makes two halves of them.
+// v_perm selector for the row residues of both halves: it picks letter c0
+// of the low half's word (source bytes 0..3) and letter c1 of the high
+// half's word (source bytes 4..7) into the byte positions the cell type
+// needs, every other byte zero.  A residue code of 12 ("no row") selects
+// the constant 0 byte.
+template <int CELL>
+__device__ __forceinline__ uint32_t make_sel(int c0, int c1) {
+  const uint32_t s0 = (c0 == 12) ? 0x0Cu : (uint32_t)c0;
+  const uint32_t s1 = (c1 == 12) ? 0x0Cu : (uint32_t)(4 + c1);
+  if (CELL == kCellF16E4M3) return s0 | (s1 << 8) | 0x0C0C0000u;
+  if (CELL == kCellF16E5M2) return 0x0Cu | (s0 << 8) | 0x0C0000u | (s1 << 24);
+  return s0 | 0x0C00u | (s1 << 16) | 0x0C000000u;
+}
+template <int CELL, typename V>
+__device__ __forceinline__ V profile_pair(uint32_t phi, uint32_t plo, uint32_t sel) {
+  const int b = (int)__builtin_amdgcn_perm(phi, plo, sel);
+  if constexpr (CELL == kCellF16E4M3) return __builtin_amdgcn_cvt_scalef32_pk_f16_fp8(b, 1.0f, false);
+  else return as_v<V>(b);
+}
+
 __device__ __forceinline__ int wave_max_groups(int v) {
   v = max(v, __shfl_xor(v, 16));
   v = max(v, __shfl_xor(v, 32));
   return v;
-}
-
-// v_perm selector for the row residues of both halves: byte 0 picks letter
-// c0 of the low half's word (source bytes 0..3), byte 2 letter c1 of the
-// high half's word (source bytes 4..7), bytes 1 and 3 are zero.  A residue
-// code of 12 ("no row") selects the constant 0 byte.
-__device__ __forceinline__ uint32_t make_sel(int c0, int c1) {
-  const uint32_t s0 = (c0 == 12) ? 0x0Cu : (uint32_t)c0;
-  const uint32_t s1 = (c1 == 12) ? 0x0Cu : (uint32_t)(4 + c1);
-  return s0 | 0x0C00u | (s1 << 16) | 0x0C000000u;
 }
 
 // Profile word of column j: byte c = sigma(c, s_j) + bias for the row
@@ -99,17 +165,18 @@ __device__ __forceinline__ uint32_t profile_word(const uint32_t *ptab, const uin
 // profiles are built: rows0/rows1 hold m0/m1 row residues, the halves have
 // n0/n1 columns padded on the left to one stripe.  Returns both results, and
 // for local mode whether a half reached the saturation limit.
-template <int MODE, int K>
+template <int MODE, int K, int CELL = kCellI16>
 __device__ __forceinline__ void duo_core(const uint8_t *rows0, const uint8_t *rows1, int m0, int m1, int n0,
                                          int n1, const uint32_t (&Plo)[K], const uint32_t (&Phi)[K], int asz,
                                          int alpha, int beta, int sat_limit, int lane, int &bad, int &r0,
                                          int &r1, bool &over0, bool &over1) {
   constexpr int W = kGroup * K;
+  using V = typename std::conditional<CELL != kCellI16, h2, s2>::type;
   const int t = lane & 15;
   const int amb = alpha - beta;
-  const s2 beta2 = pk(beta, beta);
-  const s2 alpha2 = pk(alpha, alpha);
-  const s2 amb2 = pk(amb, amb);
+  const V beta2 = pkv<V>(beta, beta);
+  const V alpha2 = pkv<V>(alpha, alpha);
+  const V amb2 = pkv<V>(amb, amb);
   const int P0 = W - n0, P1 = W - n1;     // left padding of each half
   const int mmax = max(m0, m1);
   const int msmall = min(m0, m1);
@@ -117,54 +184,54 @@ __device__ __forceinline__ void duo_core(const uint8_t *rows0, const uint8_t *ro
   const int its = mmax > 0 ? mmax + kGroup - 1 : 0;
   const int its_max = wave_max_groups(its);
   // ---- row-0 state ----
-  s2 Ha[K], Ee[K];
+  V Ha[K], Ee[K];
 #pragma unroll
   for (int x = 0; x < K; ++x) {
     const int j0 = t * K + x + 1 - P0, j1 = t * K + x + 1 - P1;
     if (MODE == kGlobal) {
-      Ha[x] = pk(j0 == 0 ? beta - alpha : 2 * beta - 2 * alpha,
+      Ha[x] = pkv<V>(j0 == 0 ? beta - alpha : 2 * beta - 2 * alpha,
                  j1 == 0 ? beta - alpha : 2 * beta - 2 * alpha);
-      Ee[x] = pk(kNeg16, kNeg16);
+      Ee[x] = pkv<V>(kNeg16, kNeg16);
     } else if (MODE == kSemiGlobal) {
-      Ha[x] = pk(beta * j0 + beta - alpha, beta * j1 + beta - alpha);
-      Ee[x] = pk(kNeg16, kNeg16);
+      Ha[x] = pkv<V>(beta * j0 + beta - alpha, beta * j1 + beta - alpha);
+      Ee[x] = pkv<V>(kNeg16, kNeg16);
     } else {
-      Ha[x] = pk(-alpha, -alpha);
-      Ee[x] = pk(0, 0);   // E'(1, j) = max(E(1,j), 0) = 0
+      Ha[x] = pkv<V>(-alpha, -alpha);
+      Ee[x] = pkv<V>(0, 0);   // E'(1, j) = max(E(1,j), 0) = 0
     }
   }
-  s2 hl_prev;
+  V hl_prev;
   {
     const int j0 = t * K - P0, j1 = t * K - P1;
     if (MODE == kGlobal)
-      hl_prev = pk(j0 == 0 ? beta - alpha : 2 * beta - 2 * alpha,
+      hl_prev = pkv<V>(j0 == 0 ? beta - alpha : 2 * beta - 2 * alpha,
                    j1 == 0 ? beta - alpha : 2 * beta - 2 * alpha);
     else if (MODE == kSemiGlobal)
-      hl_prev = pk(beta * j0 + beta - alpha, beta * j1 + beta - alpha);
+      hl_prev = pkv<V>(beta * j0 + beta - alpha, beta * j1 + beta - alpha);
     else
-      hl_prev = pk(-alpha, -alpha);
+      hl_prev = pkv<V>(-alpha, -alpha);
   }
-  int fout = (MODE == kLocal) ? 0 : as_i(pk(kNeg16, kNeg16));
+  int fout = (MODE == kLocal) ? 0 : as_i(pkv<V>(kNeg16, kNeg16));
   // left feed for lane 0 (row 1 first)
-  s2 hb, fb;
-  if (MODE == kGlobal) { hb = pk(2 * beta - 2 * alpha, 2 * beta - 2 * alpha); fb = hb; }
+  V hb, fb;
+  if (MODE == kGlobal) { hb = pkv<V>(2 * beta - 2 * alpha, 2 * beta - 2 * alpha); fb = hb; }
   else if (MODE == kSemiGlobal) {
-    hb = pk(beta * (1 - P0) + beta - alpha, beta * (1 - P1) + beta - alpha);
+    hb = pkv<V>(beta * (1 - P0) + beta - alpha, beta * (1 - P1) + beta - alpha);
     fb = hb;
-  } else { hb = pk(-alpha, -alpha); fb = pk(0, 0); }
-  s2 rowoff = pk(beta * (1 - t), beta * (1 - t));
-  s2 rm = pk(0, 0);                       // local: running max of H
-  s2 cm = pk(kNeg16, kNeg16);             // semi-global: max of H'(i,n) - beta*i
-  s2 snap = pk(kNeg16, kNeg16);           // value of the shorter half at its last row
+  } else { hb = pkv<V>(-alpha, -alpha); fb = pkv<V>(0, 0); }
+  V rowoff = pkv<V>(beta * (1 - t), beta * (1 - t));
+  V rm = pkv<V>(0, 0);                       // local: running max of H
+  V cm = pkv<V>(kNeg16, kNeg16);             // semi-global: max of H'(i,n) - beta*i
+  V snap = pkv<V>(kNeg16, kNeg16);           // value of the shorter half at its last row
 
   auto load_sel = [&](int idx) -> int {
     int c0 = 12, c1 = 12;
     if (idx < m0) { c0 = rows0[idx]; if (c0 >= asz) { bad = 1; c0 = 0; } }
     if (idx < m1) { c1 = rows1[idx]; if (c1 >= asz) { bad = 1; c1 = 0; } }
-    return (int)make_sel(c0, c1);
+    return (int)make_sel<CELL>(c0, c1);
   };
   int selfeed = load_sel(t);
-  int sel = (int)make_sel(12, 12);
+  int sel = (int)make_sel<CELL>(12, 12);
 
   for (int it0 = 0; it0 < its_max; it0 += kGroup) {
     const int selnext = load_sel(it0 + kGroup + t);
@@ -172,36 +239,36 @@ __device__ __forceinline__ void duo_core(const uint8_t *rows0, const uint8_t *ro
     for (int u = 0; u < kGroup; ++u) {
       const int row = it0 + u + 1 - t;
       sel = dpp_shr1(selfeed, sel);
-      const s2 hl = as_s2(dpp_shr1(as_i(hb), as_i(Ha[K - 1])));
-      const s2 fl = as_s2(dpp_shr1(as_i(fb), fout));
+      const V hl = as_v<V>(dpp_shr1(as_i(hb), as_i(Ha[K - 1])));
+      const V fl = as_v<V>(dpp_shr1(as_i(fb), fout));
       if ((unsigned)(row - 1) < (unsigned)mmax) {
         // Phase A, independent per column: diagonal sums from the previous
         // row's values (and, shifted frame, E), so that phase B can overwrite
         // every state register in place.
-        s2 tt[K];
+        V tt[K];
 #pragma unroll
         for (int x = 0; x < K; ++x) {
-          const s2 p = as_s2((int)__builtin_amdgcn_perm(Phi[x], Plo[x], (uint32_t)sel));
-          const s2 dg = (x == 0) ? hl_prev : Ha[x - 1];
+          const V p = profile_pair<CELL, V>(Phi[x], Plo[x], (uint32_t)sel);
+          const V dg = (x == 0) ? hl_prev : Ha[x - 1];
           if (MODE == kLocal) {
-            tt[x] = __builtin_elementwise_add_sat(dg, p);
+            tt[x] = add_diag(dg, p);
           } else {
             tt[x] = dg + p;
             Ee[x] = vmax(Ee[x], Ha[x]);
           }
         }
         // Phase B, the F chain along the row.
-        s2 f = fl;
+        V f = fl;
 #pragma unroll
         for (int x = 0; x < K; ++x) {
           if (MODE == kLocal) {
-            const s2 h = vmax(vmax(tt[x], Ee[x]), f);
+            const V h = vmax(vmax(tt[x], Ee[x]), f);
             rm = vmax(rm, h);
             Ha[x] = h - alpha2;
-            Ee[x] = vmax(sat_sub_u(Ee[x], beta2), Ha[x]);
-            f = vmax(sat_sub_u(f, beta2), Ha[x]);
+            Ee[x] = vmax(clamp_sub(Ee[x], beta2), Ha[x]);
+            f = vmax(clamp_sub(f, beta2), Ha[x]);
           } else {
-            const s2 h = vmax(vmax(tt[x], Ee[x]), f);
+            const V h = vmax(vmax(tt[x], Ee[x]), f);
             Ha[x] = h - amb2;
             f = vmax(f, Ha[x]);
           }
@@ -212,11 +279,11 @@ __device__ __forceinline__ void duo_core(const uint8_t *rows0, const uint8_t *ro
           if (MODE == kGlobal) {
             if (t == kGroup - 1) snap = Ha[K - 1];
           } else {
-            s2 lr = pk(kNeg16, kNeg16);
+            V lr = pkv<V>(kNeg16, kNeg16);
 #pragma unroll
             for (int x = 0; x < K; ++x) {
               const int jp = t * K + x + 1;
-              lr = vmax(lr, Ha[x] - pk(beta * (jp - P0), beta * (jp - P1)));
+              lr = vmax(lr, Ha[x] - pkv<V>(beta * (jp - P0), beta * (jp - P1)));
             }
             snap = lr;
           }
@@ -239,40 +306,40 @@ __device__ __forceinline__ void duo_core(const uint8_t *rows0, const uint8_t *ro
   over0 = false;
   over1 = false;
   if (MODE == kLocal) {
-    const s2 gm = group_max2(rm);
-    r0 = gm.x;
-    r1 = gm.y;
+    const V gm = group_max2(rm);
+    r0 = toi(gm.x);
+    r1 = toi(gm.y);
     over0 = r0 >= sat_limit;
     over1 = r1 >= sat_limit;
   } else if (MODE == kGlobal) {
     // lane 15, register K-1 holds column n of both halves
     const int src = (lane & ~(kGroup - 1)) + kGroup - 1;
-    const s2 fin = as_s2(__shfl(as_i(Ha[K - 1]), src));
-    const s2 sn = as_s2(__shfl(as_i(snap), src));
-    const int v0 = (unequal && m0 < m1) ? sn.x : fin.x;
-    const int v1 = (unequal && m1 < m0) ? sn.y : fin.y;
+    const V fin = as_v<V>(__shfl(as_i(Ha[K - 1]), src));
+    const V sn = as_v<V>(__shfl(as_i(snap), src));
+    const int v0 = toi((unequal && m0 < m1) ? sn.x : fin.x);
+    const int v1 = toi((unequal && m1 < m0) ? sn.y : fin.y);
     r0 = v0 + amb - beta * (m0 + n0);
     r1 = v1 + amb - beta * (m1 + n1);
   } else {
-    s2 lr = pk(kNeg16, kNeg16);
+    V lr = pkv<V>(kNeg16, kNeg16);
 #pragma unroll
     for (int x = 0; x < K; ++x) {
       const int jp = t * K + x + 1;
-      lr = vmax(lr, Ha[x] - pk(beta * (jp - P0), beta * (jp - P1)));
+      lr = vmax(lr, Ha[x] - pkv<V>(beta * (jp - P0), beta * (jp - P1)));
     }
     if (unequal) {
       if (m0 < m1) lr.x = snap.x;
       else lr.y = snap.y;
     }
-    const s2 gl = group_max2(lr);
+    const V gl = group_max2(lr);
     const int src = (lane & ~(kGroup - 1)) + kGroup - 1;
-    const s2 gc = as_s2(__shfl(as_i(cm), src));
-    r0 = max(0, max(gl.x + amb - beta * m0, gc.x + amb - beta * n0));
-    r1 = max(0, max(gl.y + amb - beta * m1, gc.y + amb - beta * n1));
+    const V gc = as_v<V>(__shfl(as_i(cm), src));
+    r0 = max(0, max(toi(gl.x) + amb - beta * m0, toi(gc.x) + amb - beta * n0));
+    r1 = max(0, max(toi(gl.y) + amb - beta * m1, toi(gc.y) + amb - beta * n1));
   }
 }
 
-template <int MODE, int K>
+template <int MODE, int K, int CELL>
 __global__ void __launch_bounds__(kWave) full_dp_i16_kernel(FullDp16Args a) {
   constexpr int W = kGroup * K;
   const int lane = threadIdx.x;
@@ -283,7 +350,9 @@ __global__ void __launch_bounds__(kWave) full_dp_i16_kernel(FullDp16Args a) {
   const int asz = a.asz;
   const int bias = (MODE == kLocal) ? alpha : alpha + beta;
   const int pad_val = (MODE == kLocal) ? alpha : (MODE == kGlobal ? alpha - beta : alpha + beta);
-  const uint32_t pad_word = (uint32_t)(pad_val & 0xFF) * 0x01010101u;
+  // int16: sigma + bias as an unsigned byte; FP16: its FP8 E4M3 code (the
+  // routing admits the FP16 cells only when every such value is in 0..16)
+  const uint32_t pad_word = profile_byte<CELL>(pad_val) * 0x01010101u;
   // profile words by (orientation, column letter): at most 4 letters here
   __shared__ uint32_t ptab[8];
   if (lane < 8) {
@@ -292,7 +361,7 @@ __global__ void __launch_bounds__(kWave) full_dp_i16_kernel(FullDp16Args a) {
     if (sl < asz)
       for (int c = 0; c < asz; ++c) {
         const int sv = o ? a.subst[sl * asz + c] : a.subst[c * asz + sl];
-        w |= (uint32_t)((sv + bias) & 0xFF) << (8 * c);
+        w |= profile_byte<CELL>(sv + bias) << (8 * c);
       }
     ptab[lane] = w;
   }
@@ -328,8 +397,8 @@ __global__ void __launch_bounds__(kWave) full_dp_i16_kernel(FullDp16Args a) {
 
     int r0, r1;
     bool over0, over1;
-    duo_core<MODE, K>(rows0, rows1, m0, m1, n0, n1, Plo, Phi, asz, alpha, beta, a.sat_limit, lane, bad, r0, r1,
-                      over0, over1);
+    duo_core<MODE, K, CELL>(rows0, rows1, m0, m1, n0, n1, Plo, Phi, asz, alpha, beta, a.sat_limit, lane, bad,
+                           r0, r1, over0, over1);
     if (bad) atomicOr(&a.ctr->status, kStatusBadResidue);
     if (t == 0) {
       if (has0) {
@@ -441,7 +510,12 @@ __global__ void __launch_bounds__(kWave) all_vs_all_i16_kernel(AllVsAllArgs a) {
 
 template <int MODE>
 hipError_t launch_mode(const FullDp16Args &args, int grid, hipStream_t stream) {
-  hipLaunchKernelGGL((full_dp_i16_kernel<MODE, kK16>), dim3(grid), dim3(kWave), 0, stream, args);
+  if (args.half == kCellF16E5M2)
+    hipLaunchKernelGGL((full_dp_i16_kernel<MODE, kK16, kCellF16E5M2>), dim3(grid), dim3(kWave), 0, stream, args);
+  else if (args.half == kCellF16E4M3)
+    hipLaunchKernelGGL((full_dp_i16_kernel<MODE, kK16, kCellF16E4M3>), dim3(grid), dim3(kWave), 0, stream, args);
+  else
+    hipLaunchKernelGGL((full_dp_i16_kernel<MODE, kK16, kCellI16>), dim3(grid), dim3(kWave), 0, stream, args);
   return hipGetLastError();
 }
 
@@ -453,11 +527,11 @@ int full_dp_i16_blocks_per_cu(int mode) {
   int nb = 0;
   hipError_t e;
   if (mode == kGlobal)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, full_dp_i16_kernel<kGlobal, kK16>, kWave, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, full_dp_i16_kernel<kGlobal, kK16, kCellI16>, kWave, 0);
   else if (mode == kSemiGlobal)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, full_dp_i16_kernel<kSemiGlobal, kK16>, kWave, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, full_dp_i16_kernel<kSemiGlobal, kK16, kCellI16>, kWave, 0);
   else
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, full_dp_i16_kernel<kLocal, kK16>, kWave, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, full_dp_i16_kernel<kLocal, kK16, kCellI16>, kWave, 0);
   if (e != hipSuccess || nb < 1) nb = 1;
   return nb;
 }

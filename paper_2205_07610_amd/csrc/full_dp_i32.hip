@@ -56,6 +56,29 @@ __device__ __forceinline__ int dpp_shl1(int old, int src) {
 }
 __device__ __forceinline__ int imax3(int a, int b, int c) { return max(max(a, b), c); }
 
+// Packed 16-bit helpers of the kVarP16 variant (two pairs per register).
+typedef short s2 __attribute__((ext_vector_type(2)));
+typedef unsigned short u2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ int as_i(s2 v) { return __builtin_bit_cast(int, v); }
+__device__ __forceinline__ s2 as_s2(int v) { return __builtin_bit_cast(s2, v); }
+__device__ __forceinline__ s2 pk(int lo, int hi) {
+  s2 r;
+  r.x = (short)lo;
+  r.y = (short)hi;
+  return r;
+}
+__device__ __forceinline__ s2 vmax(s2 a, s2 b) { return __builtin_elementwise_max(a, b); }
+__device__ __forceinline__ s2 sat_sub_u(s2 a, s2 b) {
+  return __builtin_bit_cast(s2, __builtin_elementwise_sub_sat(__builtin_bit_cast(u2, a), __builtin_bit_cast(u2, b)));
+}
+__device__ __forceinline__ s2 group_max2(s2 v) {
+  v = vmax(v, as_s2(__shfl_xor(as_i(v), 8, 16)));
+  v = vmax(v, as_s2(__shfl_xor(as_i(v), 4, 16)));
+  v = vmax(v, as_s2(__shfl_xor(as_i(v), 2, 16)));
+  v = vmax(v, as_s2(__shfl_xor(as_i(v), 1, 16)));
+  return v;
+}
+
 __device__ __forceinline__ int group_max(int v) {
   v = max(v, __shfl_xor(v, 8, 16));
   v = max(v, __shfl_xor(v, 4, 16));
@@ -259,48 +282,248 @@ __device__ __forceinline__ void align_quad(const FullDpArgs &a, int8_t *prof, in
   }
 }
 
-// Persistent kernel over a quad-aligned list.  KMASK is the set of variants
-// the list may hold (bit 0: K = 8, bit 1: K = 16, bit 2: K = 32); a
-// single-variant instantiation has no dispatch and the register footprint
-// of that variant alone, the mixed one sizes registers and LDS for the
-// widest.
+// kVarP16 (local mode only): the pairs d0 and d1 of one group in the low and
+// high 16-bit halves of every register, K = 8 columns per lane, stripes of
+// 128 columns.  Each half has its own int8 profile in LDS (asz + 1 rows of
+// sigma + alpha per column; row asz is 0, the score of rows past a half's
+// length, which only lowers cells), read with one 8-byte load per half and
+// step; one v_perm_b32 per cell pair zero-extends the two halves' bytes
+// into a packed pair.  The recurrences are those of the packed local kernel
+// (full_dp_i16x2.hip): H - alpha stored, E and F clamped at 0 by unsigned
+// saturating subtraction, signed saturating diagonal sums; a half whose
+// maximum reaches sat_limit is queued for the 32-bit re-run.  Padding
+// columns (left of stripe 0) score sigma = 0, which reproduces the boundary
+// column H(i, 0) = 0; the stripes past a half's own count score 0 for every
+// letter.  The boundary column carries both halves' (H - alpha, F) packed.
+template <int MODE>
+__device__ __forceinline__ void align_octet(const FullDpArgs &a, int8_t *prof, int2 *slot, PairDesc d0, bool has0,
+                                            PairDesc d1, bool has1, int t) {
+  if constexpr (MODE != kLocal) {
+    return;
+  } else {
+    constexpr int K = 8;
+    constexpr int W = kGroup * K;
+    const int asz = a.asz;
+    const int alpha = a.alpha, beta = a.beta;
+    const s2 alpha2 = pk(alpha, alpha), beta2 = pk(beta, beta);
+    const int m0 = has0 ? d0.m : 0, m1 = has1 ? d1.m : 0;
+    const int n0 = has0 ? d0.n : 0, n1 = has1 ? d1.n : 0;
+    const int S0 = (n0 + W - 1) / W, S1 = (n1 + W - 1) / W;
+    const int pad0 = S0 * W - n0, pad1 = S1 * W - n1;
+    const bool tr0 = (d0.flags & kTransposed) != 0, tr1 = (d1.flags & kTransposed) != 0;
+    const uint8_t *rows0 = (tr0 ? a.seqs_b : a.seqs_a) + d0.row_off;
+    const uint8_t *cols0 = (tr0 ? a.seqs_a : a.seqs_b) + d0.col_off;
+    const uint8_t *rows1 = (tr1 ? a.seqs_b : a.seqs_a) + d1.row_off;
+    const uint8_t *cols1 = (tr1 ? a.seqs_a : a.seqs_b) + d1.col_off;
+    const int S = max(S0, S1);
+    const int S_max = wave_max_groups(S);
+    const int mmax = max(m0, m1);
+    int8_t *prof0 = prof, *prof1 = prof + (asz + 1) * W;
+    s2 rm = pk(0, 0);
+    int bad = 0;
+    for (int s = 0; s < S_max; ++s) {
+      const bool on = s < S;
+      const int m_s = on ? mmax : 0;
+      const int jp0 = s * W + t * K;
+      // ---- the two profiles of this lane's K columns ----
+      if (on) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int n = h ? n1 : n0, pad = h ? pad1 : pad0, Sh = h ? S1 : S0;
+          const uint8_t *cols = h ? cols1 : cols0;
+          const bool tr = h ? tr1 : tr0;
+          int8_t *pp = (h ? prof1 : prof0) + t * K;
+#pragma unroll
+          for (int x = 0; x < K; ++x) {
+            const int j = jp0 + x + 1 - pad;  // real column, 1-based
+            int c = -1;                       // -1: padding column (sigma 0), -2: past the half's stripes
+            if (s >= Sh) c = -2;
+            else if (j >= 1 && j <= n) {
+              c = cols[j - 1];
+              if (c >= asz) { bad = 1; c = 0; }
+            }
+            for (int r = 0; r < asz; ++r) {
+              int v = 0;
+              if (c >= 0) v = (tr ? a.subst[c * asz + r] : a.subst[r * asz + c]) + alpha;
+              else if (c == -1) v = alpha;
+              pp[r * W + x] = (int8_t)v;
+            }
+            pp[asz * W + x] = 0;
+          }
+        }
+      }
+      // ---- row-0 state (local: H(0, j) - alpha = -alpha, E' = 0) ----
+      s2 Ha[K], Ee[K];
+#pragma unroll
+      for (int x = 0; x < K; ++x) {
+        Ha[x] = pk(-alpha, -alpha);
+        Ee[x] = pk(0, 0);
+      }
+      s2 hl_prev = pk(-alpha, -alpha);
+      int hout = as_i(Ha[K - 1]);
+      int fout = 0;
+      const bool import = s > 0;
+      const bool export_ = on && (s + 1 < S);
+      const int2 *bin = slot + (int64_t)(s & 1) * a.bnd_rows;
+      int2 *bout = slot + (int64_t)((s + 1) & 1) * a.bnd_rows;
+      const int its = m_s > 0 ? m_s + kGroup - 1 : 0;
+      const int its_max = wave_max_groups(its);
+      const int hb = as_i(pk(-alpha, -alpha)), fb = 0;  // stripe 0's left boundary
+      // feeds: the row letters of both halves (q0 | q1 << 8) and the imported
+      // boundary, lane t holding step t of the chunk
+      auto row_pair = [&](int qi) {
+        int q0 = asz, q1 = asz;
+        if (qi < m0) { q0 = rows0[qi]; if (q0 >= asz) { bad = 1; q0 = 0; } }
+        if (qi < m1) { q1 = rows1[qi]; if (q1 >= asz) { bad = 1; q1 = 0; } }
+        return q0 | (q1 << 8);
+      };
+      int qfeed = 0, hfeed = 0, ffeed = 0, qc = 0;
+      if (t < m_s) qfeed = row_pair(t);
+      if (import && t + 1 <= m_s) {
+        const int2 v = bin[t + 1];
+        hfeed = v.x;
+        ffeed = v.y;
+      }
+      for (int it0 = 0; it0 < its_max; it0 += kGroup) {
+        int qnext = 0, hnext = 0, fnext = 0;
+        {
+          const int qi = it0 + kGroup + t;
+          if (qi < m_s) qnext = row_pair(qi);
+          const int bi = it0 + kGroup + 1 + t;
+          if (import && bi <= m_s) {
+            const int2 v = bin[bi];
+            hnext = v.x;
+            fnext = v.y;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) {
+          const int row = it0 + u + 1 - t;
+          qc = dpp_shr1(qfeed, qc);
+          const s2 hl = as_s2(dpp_shr1(import ? hfeed : hb, hout));
+          const int fl = dpp_shr1(import ? ffeed : fb, fout);
+          if ((unsigned)(row - 1) < (unsigned)m_s) {
+            const int2 w0 = *(const int2 *)(prof0 + (qc & 0xFF) * W + t * K);
+            const int2 w1 = *(const int2 *)(prof1 + (qc >> 8) * W + t * K);
+            s2 tt[K];
+#pragma unroll
+            for (int x = 0; x < K; ++x) {
+              // bytes x & 3 of the two halves' words, zero-extended into a packed pair
+              const uint32_t sel = (uint32_t)(x & 3) | 0x0C00u | ((uint32_t)(4 + (x & 3)) << 16) | 0x0C000000u;
+              const s2 p = as_s2((int)__builtin_amdgcn_perm((uint32_t)(x < 4 ? w1.x : w1.y),
+                                                            (uint32_t)(x < 4 ? w0.x : w0.y), sel));
+              const s2 dg = (x == 0) ? hl_prev : Ha[x - 1];
+              tt[x] = __builtin_elementwise_add_sat(dg, p);
+            }
+            s2 f = as_s2(fl);
+#pragma unroll
+            for (int x = 0; x < K; ++x) {
+              const s2 h = vmax(vmax(tt[x], Ee[x]), f);
+              rm = vmax(rm, h);
+              Ha[x] = h - alpha2;
+              Ee[x] = vmax(sat_sub_u(Ee[x], beta2), Ha[x]);
+              f = vmax(sat_sub_u(f, beta2), Ha[x]);
+            }
+            hout = as_i(Ha[K - 1]);
+            fout = as_i(f);
+            if (export_ && t == kGroup - 1) bout[row] = make_int2(hout, fout);
+          }
+          hl_prev = hl;
+          qfeed = dpp_shl1(qfeed, qfeed);
+          if (import) {
+            hfeed = dpp_shl1(hfeed, hfeed);
+            ffeed = dpp_shl1(ffeed, ffeed);
+          }
+        }
+        qfeed = qnext;
+        hfeed = hnext;
+        ffeed = fnext;
+      }
+      if (s + 1 < S_max) __threadfence();  // boundary writes visible to the next stripe's loads
+    }
+    const s2 gm = group_max2(rm);
+    if (bad) atomicOr(&a.ctr->status, kStatusBadResidue);
+    if (t == 0) {
+      if (has0) {
+        if (gm.x >= a.sat_limit) a.rerun[atomicAdd(a.n_rerun, 1)] = d0;
+        else a.scores[d0.pair] = gm.x;
+      }
+      if (has1) {
+        if (gm.y >= a.sat_limit) a.rerun[atomicAdd(a.n_rerun, 1)] = d1;
+        else a.scores[d1.pair] = gm.y;
+      }
+    }
+  }
+}
+
+// Persistent kernel over the 32-bit list, claimed in units of kClaim32
+// items.  KMASK is the set of variants the list may hold (bit 0: K = 8,
+// bit 1: K = 16, bit 2: K = 32, bit 3: packed kVarP16); a single-variant
+// instantiation has no dispatch and the register footprint of that variant
+// alone, the mixed ones size registers and LDS for the widest.  A unit of a
+// 32-bit variant is two quads (one item per group each, run one after the
+// other); a kVarP16 unit is one octet (two items per group, run together).
 template <int MODE, int KMASK>
 __global__ void __launch_bounds__(kWave) full_dp_i32_kernel(FullDpArgs a) {
   constexpr int KMAX = (KMASK & 4) ? 32 : ((KMASK & 2) ? 16 : 8);
+  constexpr bool HAS32 = (KMASK & 7) != 0, HASP = (KMASK & 8) != 0;
   extern __shared__ __align__(16) int8_t lds[];
   const int lane = threadIdx.x;
   const int g = lane >> 4;
   const int t = lane & 15;
   int8_t *prof = lds + g * a.asz * (kGroup * KMAX);
+  int8_t *prof_p = lds + g * 2 * (a.asz + 1) * (kGroup * 8);
   const int n_items = *a.n_items;
   int2 *slot = a.bnd + ((int64_t)blockIdx.x * kGroupsPerWave + g) * 2 * a.bnd_rows;
   for (;;) {
     int base = 0;
-    if (lane == 0) base = atomicAdd(a.next, kGroupsPerWave);
+    if (lane == 0) base = atomicAdd(a.next, kClaim32);
     base = __shfl(base, 0);
     if (base >= n_items) break;
-    const int item = base + g;
-    PairDesc d{0, 0, 0, 0, -1, 0};
-    if (item < n_items) d = a.items[item];
-    const bool has = item < n_items && d.pair >= 0;  // padding slots carry pair -1
-    if constexpr (KMASK == 1) {
-      align_quad<MODE, 8>(a, prof, slot, d, has, t);
-    } else if constexpr (KMASK == 2) {
-      align_quad<MODE, 16>(a, prof, slot, d, has, t);
-    } else if constexpr (KMASK == 4) {
-      align_quad<MODE, 32>(a, prof, slot, d, has, t);
+    // the unit's variant (units never mix variants)
+    int kv = 0;
+    if (lane == 0) kv = variant_of(a.items[base].flags);
+    kv = __shfl(kv, 0);
+    bool octet = false;
+    if constexpr (HASP) octet = !HAS32 || kv == kVarP16;
+    if (octet) {
+      if constexpr (HASP) {
+        const int i0 = base + 2 * g, i1 = i0 + 1;
+        PairDesc d0{0, 0, 0, 0, -1, 0}, d1{0, 0, 0, 0, -1, 0};
+        if (i0 < n_items) d0 = a.items[i0];
+        if (i1 < n_items) d1 = a.items[i1];
+        align_octet<MODE>(a, prof_p, slot, d0, i0 < n_items && d0.pair >= 0, d1, i1 < n_items && d1.pair >= 0, t);
+      }
     } else {
-      // the quad's variant (uniform: quads never mix variants)
-      const int kv = __shfl(variant_of(d.flags), 0);
-      if (kv == kVarI32K8) align_quad<MODE, 8>(a, prof, slot, d, has, t);
-      else if (kv == kVarI32K32) align_quad<MODE, 32>(a, prof, slot, d, has, t);
-      else align_quad<MODE, 16>(a, prof, slot, d, has, t);
+      if constexpr (HAS32) {
+        for (int q = 0; q < kClaim32 / kGroupsPerWave; ++q) {
+          const int item = base + q * kGroupsPerWave + g;
+          PairDesc d{0, 0, 0, 0, -1, 0};
+          if (item < n_items) d = a.items[item];
+          const bool has = item < n_items && d.pair >= 0;  // padding slots carry pair -1
+          if constexpr ((KMASK & 7) == 1) {
+            align_quad<MODE, 8>(a, prof, slot, d, has, t);
+          } else if constexpr ((KMASK & 7) == 2) {
+            align_quad<MODE, 16>(a, prof, slot, d, has, t);
+          } else if constexpr ((KMASK & 7) == 4) {
+            align_quad<MODE, 32>(a, prof, slot, d, has, t);
+          } else {
+            if (kv == kVarI32K8) align_quad<MODE, 8>(a, prof, slot, d, has, t);
+            else if (kv == kVarI32K32) align_quad<MODE, 32>(a, prof, slot, d, has, t);
+            else align_quad<MODE, 16>(a, prof, slot, d, has, t);
+          }
+        }
+      }
     }
   }
 }
 
-// The instantiation covering a set of variants: one of them alone, or all.
-int kmask_instance(int kmask) { return (kmask == 1 || kmask == 2 || kmask == 4) ? kmask : 7; }
+// The instantiation covering a set of variants: one of them alone, all
+// 32-bit ones, or everything.
+int kmask_instance(int kmask) {
+  if (kmask == 1 || kmask == 2 || kmask == 4 || kmask == 8) return kmask;
+  return (kmask & 8) ? 15 : 7;
+}
 
 template <int MODE>
 hipError_t launch_mode(const FullDpArgs &args, int kmask, int grid, hipStream_t stream) {
@@ -309,6 +532,8 @@ hipError_t launch_mode(const FullDpArgs &args, int kmask, int grid, hipStream_t 
     case 1: hipLaunchKernelGGL((full_dp_i32_kernel<MODE, 1>), dim3(grid), dim3(kWave), lds, stream, args); break;
     case 2: hipLaunchKernelGGL((full_dp_i32_kernel<MODE, 2>), dim3(grid), dim3(kWave), lds, stream, args); break;
     case 4: hipLaunchKernelGGL((full_dp_i32_kernel<MODE, 4>), dim3(grid), dim3(kWave), lds, stream, args); break;
+    case 8: hipLaunchKernelGGL((full_dp_i32_kernel<MODE, 8>), dim3(grid), dim3(kWave), lds, stream, args); break;
+    case 15: hipLaunchKernelGGL((full_dp_i32_kernel<MODE, 15>), dim3(grid), dim3(kWave), lds, stream, args); break;
     default: hipLaunchKernelGGL((full_dp_i32_kernel<MODE, 7>), dim3(grid), dim3(kWave), lds, stream, args); break;
   }
   return hipGetLastError();
@@ -329,6 +554,8 @@ int occupancy_mode(int kmask, size_t lds) {
     case 1: return occupancy<MODE, 1>(lds);
     case 2: return occupancy<MODE, 2>(lds);
     case 4: return occupancy<MODE, 4>(lds);
+    case 8: return occupancy<MODE, 8>(lds);
+    case 15: return occupancy<MODE, 15>(lds);
     default: return occupancy<MODE, 7>(lds);
   }
 }
@@ -338,7 +565,12 @@ int occupancy_mode(int kmask, size_t lds) {
 size_t full_dp_i32_lds_bytes(int asz, int kmask) {
   const int inst = kmask_instance(kmask);
   const int kmax = (inst & 4) ? 32 : ((inst & 2) ? 16 : 8);
-  return (size_t)kGroupsPerWave * asz * kGroup * kmax;
+  size_t bytes = (inst & 7) ? (size_t)kGroupsPerWave * asz * kGroup * kmax : 0;
+  if (inst & 8) {  // two profiles of asz + 1 rows per group, 128 columns
+    const size_t p = (size_t)kGroupsPerWave * 2 * (asz + 1) * kGroup * 8;
+    bytes = bytes > p ? bytes : p;
+  }
+  return bytes;
 }
 int full_dp_i32_stripe_width(int k) { return kGroup * k; }
 

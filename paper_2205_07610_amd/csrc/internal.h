@@ -40,17 +40,54 @@ constexpr int32_t kTransposed = 1;
 // the packed 16-bit kernel, the 32-bit stripe kernel with K = 8, 16 or 32
 // columns per lane, and the multi-wave wavefront.  Bits 8..15 of
 // PairDesc::flags carry the variant of a 32-bit list item.
+// kVarP16 (local mode): the 32-bit list's multi-stripe kernel with packed
+// 16-bit cells, two pairs per group, int8 profiles of any alphabet in LDS,
+// K = 8 columns per lane.
 enum Variant : int32_t {
   kVarI16 = 0,
   kVarI32K8 = 1,
   kVarI32K16 = 2,
   kVarI32K32 = 3,
   kVarLong = 4,
-  kNumVariants = 5
+  kVarP16 = 5,
+  kNumVariants = 6
 };
 __host__ __device__ inline int variant_of(int32_t flags) { return (flags >> 8) & 0xFF; }
 __host__ __device__ inline int32_t with_variant(int32_t flags, int v) { return (flags & ~0xFF00) | (v << 8); }
-__host__ __device__ inline int variant_k(int v) { return v == kVarI32K8 ? 8 : (v == kVarI32K32 ? 32 : 16); }
+__host__ __device__ inline int variant_k(int v) {
+  return (v == kVarI32K8 || v == kVarP16) ? 8 : (v == kVarI32K32 ? 32 : 16);
+}
+// Waves claim the 32-bit list in units of 8 items: two quads (one item per
+// group each) or one octet of kVarP16 items (two per group); its length
+// bins are padded to whole units.
+constexpr int kClaim32 = 8;
+// FP16 cells hold integers exactly up to 2048 in magnitude; the packed
+// kernel keeps every value below this when it runs them
+constexpr int kHalfLimit = 2048 - 64;
+// Cell types of the packed full-DP kernel: int16 pairs, or FP16 pairs whose
+// profile bytes are FP8 E4M3 codes (exact for the integers 0..16, one packed
+// conversion per cell pair) or FP8 E5M2 codes (the upper byte of an FP16
+// value, so v_perm alone builds the pair; exact for 0..8, 10, 12, 14, 16).
+constexpr int kCellI16 = 0, kCellF16E4M3 = 1, kCellF16E5M2 = 2;
+
+// FP8 E4M3 code (bias 7, 3 mantissa bits) of an integer 0..16
+__host__ __device__ inline uint32_t fp8_e4m3(int v) {
+  if (v <= 0) return 0u;
+  int e = 0;
+  while ((2 << e) <= v) ++e;
+  const int mant = ((v << 3) >> e) & 7;
+  return (uint32_t)(((e + 7) << 3) | mant);
+}
+// FP8 E5M2 code (bias 15, 2 mantissa bits: the upper byte of the FP16
+// value) of an integer 0..16 that it holds exactly
+__host__ __device__ inline uint32_t fp8_e5m2(int v) {
+  if (v <= 0) return 0u;
+  int e = 0;
+  while ((2 << e) <= v) ++e;
+  const int mant = ((v << 2) >> e) & 3;
+  return (uint32_t)(((e + 15) << 2) | mant);
+}
+__host__ __device__ inline bool e5m2_exact(int v) { return v >= 0 && v <= 16 && (v <= 8 || v % 2 == 0); }
 
 // Length bins: bin b holds pairs whose longer sequence has at most 64 << b
 // residues (the last bin everything longer).
@@ -104,7 +141,7 @@ struct Counters {
   int32_t n_long16;      // pairs queued for the packed wavefront (consecutive pairs form duos)
   int32_t n_long16_tasks;  // their stripes (one task per duo stripe)
   int32_t next_long16;   // ticket counter of the packed wavefront kernel
-  int32_t pad_long16_;
+  int32_t n_full32_pairs; // pairs in the 32-bit list (n_full32 less each bin's padding)
   long long long16_bnd_total;  // uint2 entries of all packed wavefront boundary columns
   long long long_bnd_total;  // int2 entries of all wavefront boundary columns
   // banded path: lists per round parity and lane-width class
@@ -433,6 +470,8 @@ bool timing_enabled();
 void release_learned_workspace();
 void release_traceback_workspace();
 void record_learned_timing(float features_ms, float mlp_ms);
+void get_last_timing(as_timing *t);   // the timing record of the last call (no lock)
+void set_last_timing(const as_timing &t);
 hipError_t launch_mlp_train_step(const float *features, const int32_t *labels, const int32_t *order,
                                  int32_t batch, float tau, float *params, float *m1, float *m2,
                                  float *partials, float *grads_out, float lr, float c1, float c2,
@@ -490,7 +529,7 @@ __host__ __device__ inline bool long16_range_ok(int64_t m, int64_t n, int smax_p
   return ub < 32000 && lb < 32000;
 }
 int long_dp_i32_blocks_per_cu(int mode, int asz);
-int long_dp_i32_stripe_width();
+int long_dp_i32_stripe_width(int asz);  // 64 K columns, K = 16 (alphabets <= 4) or 8
 size_t long_dp_i32_lds_bytes(int asz);
 
 struct FullDpArgs {
@@ -507,6 +546,9 @@ struct FullDpArgs {
   int32_t *scores;
   int2 *bnd;            // boundary columns, one slot per group: 2 * bnd_rows int2
   int64_t bnd_rows;     // rows per boundary buffer (>= max_rows_multi + 1)
+  PairDesc *rerun;      // kVarP16: pairs whose 16-bit maximum saturates (32-bit re-run)
+  int32_t *n_rerun;
+  int32_t sat_limit;
 };
 
 // Arguments of the packed 16-bit kernel: two pairs per 16-lane group, one in
@@ -523,6 +565,7 @@ struct FullDp16Args {
   int32_t beta;
   int32_t sat_limit;       // local: a 16-bit maximum >= this is re-run with 32 bits
   int32_t *scores;
+  int32_t half;            // cell type: kCellI16, or FP16 cells (values within +-2048)
 };
 
 hipError_t launch_full_dp_i16(int mode, const FullDp16Args &args, int grid, hipStream_t stream);
@@ -565,7 +608,7 @@ int full_dp_i32_blocks_per_cu(int mode, int asz, int kmask);
 int full_dp_i32_stripe_width(int k);
 size_t full_dp_i32_lds_bytes(int asz, int kmask);
 __host__ __device__ inline int kmask_of_variant(int v) {
-  return v == kVarI32K8 ? 1 : (v == kVarI32K32 ? 4 : 2);
+  return v == kVarI32K8 ? 1 : (v == kVarI32K32 ? 4 : (v == kVarP16 ? 8 : 2));
 }
 
 }  // namespace asmi

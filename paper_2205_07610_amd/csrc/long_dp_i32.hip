@@ -30,7 +30,6 @@ namespace asmi {
 namespace {
 
 constexpr int kKL = 16;              // columns per lane
-constexpr int kWL = kWave * kKL;     // columns per stripe
 constexpr int kChunk = 16;           // rows per feed refill / publication
 constexpr unsigned kSpinLimit = 1u << 25;
 
@@ -194,16 +193,26 @@ __global__ void __launch_bounds__(kWave) long_dp_i32_kernel(LongDpArgs a) {
         const int fl = wave_shr1(import ? ffeed : fb, fout);
         if ((unsigned)(row - 1) < (unsigned)m) {
           const int8_t *pp = prof + qc * W + t * K;
-          int4 pw[K / 16];
+          int pw[K / 4];
+          if constexpr (K % 16 == 0) {
 #pragma unroll
-          for (int v = 0; v < K / 16; ++v) pw[v] = *(const int4 *)(pp + 16 * v);
+            for (int v = 0; v < K / 16; ++v) {
+              const int4 q = *(const int4 *)(pp + 16 * v);
+              pw[4 * v] = q.x;
+              pw[4 * v + 1] = q.y;
+              pw[4 * v + 2] = q.z;
+              pw[4 * v + 3] = q.w;
+            }
+          } else {
+            static_assert(K == 8, "K is 8 or a multiple of 16");
+            const int2 q = *(const int2 *)pp;
+            pw[0] = q.x;
+            pw[1] = q.y;
+          }
           int tt[K];
 #pragma unroll
           for (int x = 0; x < K; ++x) {
-            const int word = (x & 15) >> 2;
-            const int w32 = word == 0 ? pw[x >> 4].x : word == 1 ? pw[x >> 4].y
-                          : word == 2 ? pw[x >> 4].z : pw[x >> 4].w;
-            const int sc = (int)(int8_t)(w32 >> (8 * (x & 3)));
+            const int sc = (int)(int8_t)(pw[x >> 2] >> (8 * (x & 3)));
             tt[x] = ((x == 0) ? hl_prev : Ha[x - 1]) + sc;
             if (MODE != kLocal) Ee[x] = max(Ee[x], Ha[x]);
           }
@@ -284,30 +293,45 @@ __global__ void __launch_bounds__(kWave) long_dp_i32_kernel(LongDpArgs a) {
   }
 }
 
+// Alphabets of more than four letters take 512-column stripes (K = 8): the
+// int8 profile of a stripe is asz x 64 K bytes of LDS per wave, and at 1024
+// columns a 20-letter profile (20 KB) would hold a CU to 8 waves.
+constexpr int kKLBig = 8;
+constexpr int stripe_k(int asz) { return asz > 4 ? kKLBig : kKL; }
+
 template <int MODE>
 hipError_t launch_mode(const LongDpArgs &args, int grid, hipStream_t stream) {
-  hipLaunchKernelGGL((long_dp_i32_kernel<MODE, kKL>), dim3(grid), dim3(kWave),
-                     long_dp_i32_lds_bytes(args.asz), stream, args);
+  if (stripe_k(args.asz) == kKLBig)
+    hipLaunchKernelGGL((long_dp_i32_kernel<MODE, kKLBig>), dim3(grid), dim3(kWave),
+                       long_dp_i32_lds_bytes(args.asz), stream, args);
+  else
+    hipLaunchKernelGGL((long_dp_i32_kernel<MODE, kKL>), dim3(grid), dim3(kWave),
+                       long_dp_i32_lds_bytes(args.asz), stream, args);
   return hipGetLastError();
+}
+
+template <int MODE>
+int occupancy(int asz, size_t lds) {
+  int nb = 0;
+  hipError_t e;
+  if (stripe_k(asz) == kKLBig)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, long_dp_i32_kernel<MODE, kKLBig>, kWave, lds);
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, long_dp_i32_kernel<MODE, kKL>, kWave, lds);
+  if (e != hipSuccess || nb < 1) nb = 1;
+  return nb;
 }
 
 }  // namespace
 
-size_t long_dp_i32_lds_bytes(int asz) { return (size_t)asz * kWL; }
-int long_dp_i32_stripe_width() { return kWL; }
+size_t long_dp_i32_lds_bytes(int asz) { return (size_t)asz * kWave * stripe_k(asz); }
+int long_dp_i32_stripe_width(int asz) { return kWave * stripe_k(asz); }
 
 int long_dp_i32_blocks_per_cu(int mode, int asz) {
-  int nb = 0;
   const size_t lds = long_dp_i32_lds_bytes(asz);
-  hipError_t e;
-  if (mode == kGlobal)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, long_dp_i32_kernel<kGlobal, kKL>, kWave, lds);
-  else if (mode == kSemiGlobal)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, long_dp_i32_kernel<kSemiGlobal, kKL>, kWave, lds);
-  else
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, long_dp_i32_kernel<kLocal, kKL>, kWave, lds);
-  if (e != hipSuccess || nb < 1) nb = 1;
-  return nb;
+  if (mode == kGlobal) return occupancy<kGlobal>(asz, lds);
+  if (mode == kSemiGlobal) return occupancy<kSemiGlobal>(asz, lds);
+  return occupancy<kLocal>(asz, lds);
 }
 
 hipError_t launch_long_dp_i32(int mode, const LongDpArgs &args, int grid, hipStream_t stream) {

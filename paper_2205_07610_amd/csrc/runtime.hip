@@ -35,6 +35,8 @@ struct RouteParams {
   int32_t mode, alpha, beta, smax_abs, smax_pos;
   int32_t drop16;         // max(0, -(sigma_min + 2 beta)): the banded int16 range proof
   int32_t allow16;        // the scoring fits the packed kernel's byte profile
+  int32_t allowP16;       // local mode, sigma + alpha fits a byte: the packed LDS-profile variant
+  int32_t half;           // the packed kernel runs FP16 cells (range bound below 2048)
   int32_t long_w;         // stripe width of the wavefront kernel
   int32_t long_min_rows;  // automatic routing: rows needed for the wavefront
   int32_t long16;         // global range-proven wavefront pairs may take the packed wavefront
@@ -79,13 +81,23 @@ __device__ int route_pair(const RouteParams &c, int64_t a0, int64_t m, int64_t b
   if (c.only_bin >= 0 && bin != c.only_bin) return -1;
   if (c.sample_stride[bin] > 1 && p % c.sample_stride[bin] != 0) return -1;
   const int v = c.var_of_bin[bin];
-  if (v == kVarI32K8 || v == kVarI32K16 || v == kVarI32K32) {
+  if (v == kVarI32K8 || v == kVarI32K16 || v == kVarI32K32 || (v == kVarP16 && c.allowP16)) {
     fill_desc(d, orient_rows_b(m, n, kGroup * variant_k(v)), a0, m, b0, n, p, v);
     return kList32;
   }
   const bool tr = orient_rows_b(m, n, kGroup * 16);
   fill_desc(d, tr, a0, m, b0, n, p, kVarI32K16);
-  if ((v < 0 || v == kVarI16) && c.allow16 && d.n <= kGroup * 16) {
+  if ((v < 0 || v == kVarI16) && c.allow16 && d.n <= kGroup * 16 && c.half) {
+    // FP16 cells: local maxima are checked at run time against a threshold
+    // below 2048; global and semi-global cells stay below
+    // sigma_max*256 + beta*(rows + 512) + alpha + 2 beta + 16, a bound that
+    // grows with the rows only, so it also covers the rows one pair of a
+    // group runs past its own end while its partner continues
+    if (c.mode == kLocal) return kList16;
+    const int64_t ub = (int64_t)c.smax_pos * (kGroup * 16) + (int64_t)c.beta * (d.m + 2 * kGroup * 16) +
+                       c.alpha + 2 * c.beta + 16;
+    if (ub < kHalfLimit) return kList16;
+  } else if ((v < 0 || v == kVarI16) && c.allow16 && d.n <= kGroup * 16) {
     if (c.mode == kLocal) return kList16;
     // shifted-frame cells stay below sigma_max*min(m,n) + beta*(m+n), plus
     // the profile byte and the padding offset beta*256
@@ -99,6 +111,8 @@ __device__ int route_pair(const RouteParams &c, int64_t a0, int64_t m, int64_t b
       return kListLong16;
     if (v == kVarLong || d.m >= c.long_min_rows) return kListLong;
   }
+  if (c.allowP16)  // local pairs of the 32-bit list: packed cells, LDS profiles
+    fill_desc(d, orient_rows_b(m, n, kGroup * variant_k(kVarP16)), a0, m, b0, n, p, kVarP16);
   return kList32;
 }
 
@@ -232,7 +246,10 @@ __global__ void __launch_bounds__(256) route_count_kernel(RouteParams c, const i
     if (cost_list(l) >= 0) atomicAdd(&ccnt[cost_list(l) * RC + bin * kCostClasses + cost_class(d, bin, l)], 1);
     if (l == kList32) {
       ctr->bin_var32[bin] = variant_of(d.flags);  // the same for every pair of the bin
-      if (d.n > kGroup * variant_k(variant_of(d.flags))) atomicMax(&ctr->max_rows_multi, d.m);
+      // boundary rows: multi-stripe items, and every packed item (its group
+      // partner may have more stripes, and the group exports the longer half's rows)
+      if (d.n > kGroup * variant_k(variant_of(d.flags)) || variant_of(d.flags) == kVarP16)
+        atomicMax(&ctr->max_rows_multi, d.m);
     }
   }
   atomicAdd(&cells_sh, cells);
@@ -251,8 +268,8 @@ __global__ void __launch_bounds__(256) route_count_kernel(RouteParams c, const i
 }
 
 // Step 2 of 3 (one thread): list offsets of every bin, longest bins first;
-// 32-bit bins are padded to whole quads (a wave never mixes variants) with
-// items of pair -1.  Capacities (0 = unchecked) guard a planned replay: a
+// 32-bit bins are padded to whole claims of kClaim32 items (a wave never
+// mixes variants) with items of pair -1.  Capacities (0 = unchecked) guard a planned replay: a
 // batch that would overflow the plan's boundary buffer is refused.
 __global__ void __launch_bounds__(kWave) route_scan_kernel(Counters *ctr, PairDesc *items32,
                                                             int64_t bnd_rows_cap) {
@@ -260,6 +277,7 @@ __global__ void __launch_bounds__(kWave) route_scan_kernel(Counters *ctr, PairDe
   if (blockIdx.x != 0) return;
   const int lane = threadIdx.x;
   int kmask = 0;
+  int real32 = 0;
   for (int l = 0; l < kLists; ++l) {
     int base = 0;
     for (int b = kLenBins - 1; b >= 0; --b) {
@@ -281,7 +299,8 @@ __global__ void __launch_bounds__(kWave) route_scan_kernel(Counters *ctr, PairDe
         ctr->cost_base[cl][b][2 * lane + 1] = first + c0;
       }
       if (l == kList32 && cnt > 0) {
-        const int padded = (cnt + kGroupsPerWave - 1) / kGroupsPerWave * kGroupsPerWave;
+        real32 += cnt;
+        const int padded = (cnt + kClaim32 - 1) / kClaim32 * kClaim32;
         const int v = ctr->bin_var32[b];
         if (lane < padded - cnt) {
           PairDesc d{0, 0, 0, 0, -1, with_variant(0, v)};
@@ -294,7 +313,10 @@ __global__ void __launch_bounds__(kWave) route_scan_kernel(Counters *ctr, PairDe
     }
     if (lane == 0) {
       if (l == kList16) ctr->n_full16 = base;
-      else if (l == kList32) ctr->n_full32 = base;
+      else if (l == kList32) {
+        ctr->n_full32 = base;
+        ctr->n_full32_pairs = real32;
+      }
       else if (l == kListLong) ctr->n_long = base;
       else ctr->n_long16 = base;
     }
@@ -303,7 +325,7 @@ __global__ void __launch_bounds__(kWave) route_scan_kernel(Counters *ctr, PairDe
   ctr->kmask32 = kmask;
   if (bnd_rows_cap > 0 && ctr->n_full32 > 0 && (int64_t)ctr->max_rows_multi + 1 > bnd_rows_cap) {
     atomicOr(&ctr->status, kStatusPlan);
-    ctr->n_full32 = ctr->n_full16 = ctr->n_long = ctr->n_long16 = 0;
+    ctr->n_full32 = ctr->n_full32_pairs = ctr->n_full16 = ctr->n_long = ctr->n_long16 = 0;
   }
 }
 
@@ -751,6 +773,7 @@ int8_t g_variants[3][kLenBins] = {{-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -
                                   {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1},
                                   {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1}};
 int32_t g_i16_limit = 32767;
+int g_half_cells = 2;   // packed kernel's FP16 cells: 0 never, 1 when admissible, 2 automatic
 as_timing g_last_timing;
 
 std::mutex g_lock;
@@ -867,6 +890,7 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
 
 struct CallScoring {
   int asz, alpha, beta, mode, smin, smax, smax_abs, allow16;
+  int half;   // the packed kernel runs FP16 cells for this call
 };
 
 // Host-side checks of the scoring scheme; fills cs.
@@ -894,7 +918,28 @@ int check_scoring(const as_scoring *scoring, int32_t mode, CallScoring *cs) {
   // The packed kernel keeps sigma + bias as unsigned bytes in registers, one
   // byte per letter of an alphabet of at most four.
   cs->allow16 = (asz <= 4 && smin + bias >= 0 && smax + bias <= 255) ? 1 : 0;
+  // FP16 cells take their profile bytes (sigma + bias and the padding
+  // value) as FP8 codes: E5M2 when every one is exact in it, else E4M3,
+  // exact for all integers 0..16.  Automatic selection takes them for local
+  // calls with E5M2 bytes whose maxima cannot reach the FP16 threshold
+  // (sigma_max * 256 + alpha + 16 below it), where they need fewer VALU
+  // instructions per cell than int16 and never add a re-run.
+  const int pad = (mode == kLocal) ? alpha : (mode == kGlobal ? alpha - beta : alpha + beta);
+  bool e5 = e5m2_exact(pad);
+  for (int i = 0; i < asz * asz; ++i) e5 = e5 && e5m2_exact(scoring->subst[i] + bias);
+  const bool h_ok = cs->allow16 && smax + bias <= 16 && pad <= 16;
+  const int smax_pos = smax > 0 ? smax : 0;
+  const bool want = g_half_cells == 1 ||
+                    (g_half_cells == 2 && mode == kLocal && e5 && smax_pos * 256 + alpha + 16 < kHalfLimit);
+  cs->half = (want && h_ok) ? (e5 ? kCellF16E5M2 : kCellF16E4M3) : kCellI16;
   return AS_OK;
+}
+
+// Local re-run threshold of the packed kernel: the int16 limit, and for
+// FP16 cells at most kHalfLimit (the scores of a step are at most 16, so a
+// maximum first reaching the threshold is still exact).
+int32_t packed_sat_limit(const CallScoring &cs) {
+  return (cs.half && cs.mode == kLocal && g_i16_limit > kHalfLimit) ? kHalfLimit : g_i16_limit;
 }
 
 int classify_blocks(int64_t n) {
@@ -913,7 +958,9 @@ RouteParams route_params(const CallScoring &cs, int64_t n_pairs) {
   rp.smax_pos = cs.smax > 0 ? cs.smax : 0;
   rp.drop16 = cs.smin + 2 * cs.beta < 0 ? -(cs.smin + 2 * cs.beta) : 0;
   rp.allow16 = cs.allow16;
-  rp.long_w = long_dp_i32_stripe_width();
+  rp.allowP16 = (cs.mode == kLocal && cs.smin + cs.alpha >= 0 && cs.smax + cs.alpha <= 255) ? 1 : 0;
+  rp.half = cs.half;
+  rp.long_w = long_dp_i32_stripe_width(cs.asz);
   rp.long_min_rows = 2048;
   rp.long16 = 1;
   rp.only_bin = -1;
@@ -944,7 +991,7 @@ int launch_classify(Workspace *w, const RouteParams &rp, const int64_t *offs_a, 
 int lists_capacity(Workspace *w, int64_t n_pairs) {
   int rc;
   // the 32-bit list pads each length bin to whole quads
-  if ((rc = grow((void **)&w->items, &w->items_cap, n_pairs + kGroupsPerWave * kLenBins, sizeof(PairDesc))))
+  if ((rc = grow((void **)&w->items, &w->items_cap, n_pairs + kClaim32 * kLenBins, sizeof(PairDesc))))
     return rc;
   if ((rc = grow((void **)&w->items16, &w->items16_cap, n_pairs, sizeof(PairDesc)))) return rc;
   if ((rc = grow((void **)&w->rerun, &w->rerun_cap, n_pairs, sizeof(PairDesc)))) return rc;
@@ -967,7 +1014,7 @@ int run_full_lists(Workspace *w, const CallScoring &cs, const uint8_t *seqs_a,
   }
   if (c.n_long > 0) {
     hipLaunchKernelGGL(long_prep_kernel, dim3(1), dim3(256), 0, stream, w->items_long, w->ctr,
-                       long_dp_i32_stripe_width(), mode, scores_out, (int64_t)0, (int64_t)0);
+                       long_dp_i32_stripe_width(asz), mode, scores_out, (int64_t)0, (int64_t)0);
     AS_HIP(hipGetLastError());
   }
   if (c.n_long > 0 || c.n_long16 > 0)
@@ -1001,8 +1048,9 @@ int run_full_lists(Workspace *w, const CallScoring &cs, const uint8_t *seqs_a,
     a16.asz = asz;
     a16.alpha = cs.alpha;
     a16.beta = cs.beta;
-    a16.sat_limit = g_i16_limit;
+    a16.sat_limit = packed_sat_limit(cs);
     a16.scores = scores_out;
+    a16.half = cs.half;
     if (timing) AS_HIP(hipEventRecord(w->ev[2], stream));
     AS_HIP(launch_full_dp_i16(mode, a16, (int)grid, stream));
     if (timing) AS_HIP(hipEventRecord(w->ev[3], stream));
@@ -1016,6 +1064,9 @@ int run_full_lists(Workspace *w, const CallScoring &cs, const uint8_t *seqs_a,
   args.alpha = cs.alpha;
   args.beta = cs.beta;
   args.scores = scores_out;
+  args.rerun = w->rerun;
+  args.n_rerun = &w->ctr->n_rerun32;
+  args.sat_limit = g_i16_limit;
   if (c.n_full32 > 0) {
     const int bpc = full_dp_i32_blocks_per_cu(mode, asz, c.kmask32);
     int64_t grid = (int64_t)bpc * w->num_cu;
@@ -1094,8 +1145,9 @@ int run_full_lists(Workspace *w, const CallScoring &cs, const uint8_t *seqs_a,
   g_last_timing.pairs_long16 += c.n_long16;
   g_last_timing.cells_long16 = (int64_t)c2.route_cells[kListLong16];
   if (timing && c.n_long16 > 0) g_last_timing.long16_ms += elapsed(w->ev[14], w->ev[15]);
-  g_last_timing.pairs_full32 += c.n_full32;
+  g_last_timing.pairs_full32 += c.n_full32_pairs;
   g_last_timing.pairs_full16 += c.n_full16;
+  if (c.n_full16 > 0) g_last_timing.full16_cell_type = cs.half;
   g_last_timing.pairs_long += c.n_long;
   g_last_timing.cells_full32 = (int64_t)c2.route_cells[kList32];
   g_last_timing.cells_full16 = (int64_t)c2.route_cells[kList16];
@@ -1112,13 +1164,21 @@ int run_full_lists(Workspace *w, const CallScoring &cs, const uint8_t *seqs_a,
     int64_t grid = (int64_t)bpc * w->num_cu;
     const int64_t need_waves = ((int64_t)c2.n_rerun32 + kGroupsPerWave - 1) / kGroupsPerWave;
     if (grid > need_waves) grid = need_waves;
-    // re-run pairs fit one 16-bit stripe, hence one 32-bit stripe: no boundary buffer
-    if ((rc = ws_grow(w, (void **)&w->bnd, &w->bnd_cap, grid * kGroupsPerWave * 2, sizeof(int2)))) return rc;
+    // re-run pairs of the packed full DP fit one 32-bit stripe; those of the
+    // packed LDS variant (local mode) may span several stripes, with at most
+    // max_rows_multi rows
+    const int64_t rr = (mode == kLocal && c.max_rows_multi > 0) ? (int64_t)c.max_rows_multi + 1 : 1;
+    if (w->noalloc) {
+      const int64_t per_wave = (int64_t)kGroupsPerWave * 2 * rr * (int64_t)sizeof(int2);
+      const int64_t fit = std::max((w->bnd_cap * (int64_t)sizeof(int2)) / per_wave, w->pool_left / per_wave);
+      if (grid > fit) grid = fit > 0 ? fit : 1;
+    }
+    if ((rc = ws_grow(w, (void **)&w->bnd, &w->bnd_cap, grid * kGroupsPerWave * 2 * rr, sizeof(int2)))) return rc;
     args.items = w->rerun;
     args.n_items = &w->ctr->n_rerun32;
     args.next = &w->ctr->next_rerun32;
     args.bnd = w->bnd;
-    args.bnd_rows = 1;
+    args.bnd_rows = rr;
     if (timing) AS_HIP(hipEventRecord(w->ev[6], stream));
     AS_HIP(launch_full_dp_i32(mode, args, kmask_of_variant(kVarI32K16), (int)grid, stream));
     if (timing) AS_HIP(hipEventRecord(w->ev[7], stream));
@@ -1226,7 +1286,7 @@ int noalloc_workspace(Workspace *w, int dev, int64_t n_pairs) {
   int64_t cap_ctr = 0, cap_subst = 0;
   if ((rc = ws_grow(w, (void **)&w->ctr, &cap_ctr, 1, sizeof(Counters)))) return rc;
   if ((rc = ws_grow(w, (void **)&w->subst, &cap_subst, 32 * 32, 1))) return rc;
-  if ((rc = ws_grow(w, (void **)&w->items, &w->items_cap, n_pairs + kGroupsPerWave * kLenBins, sizeof(PairDesc))))
+  if ((rc = ws_grow(w, (void **)&w->items, &w->items_cap, n_pairs + kClaim32 * kLenBins, sizeof(PairDesc))))
     return rc;
   if ((rc = ws_grow(w, (void **)&w->items16, &w->items16_cap, n_pairs, sizeof(PairDesc)))) return rc;
   if ((rc = ws_grow(w, (void **)&w->rerun, &w->rerun_cap, n_pairs, sizeof(PairDesc)))) return rc;
@@ -1357,6 +1417,9 @@ extern "C" int as_align_all_vs_all(const uint8_t *seqs_q, const int64_t *offs_q,
       args.alpha = cs.alpha;
       args.beta = cs.beta;
       args.scores = scores_out;
+      args.rerun = nullptr;   // the re-run list holds 32-bit items only
+      args.n_rerun = nullptr;
+      args.sat_limit = 0;
       const int bpc = full_dp_i32_blocks_per_cu(mode, cs.asz, kmask_of_variant(kVarI32K16));
       int64_t g2 = (int64_t)bpc * w->num_cu;
       const int64_t need_waves = ((int64_t)c.n_rerun32 + kGroupsPerWave - 1) / kGroupsPerWave;
@@ -1645,6 +1708,9 @@ void asmi::record_learned_timing(float features_ms, float mlp_ms) {
   g_last_timing.mlp_ms = mlp_ms;
 }
 
+void asmi::get_last_timing(as_timing *t) { *t = g_last_timing; }
+void asmi::set_last_timing(const as_timing &t) { g_last_timing = t; }
+
 // ---------------------------------------------------------------- plans
 //
 // A plan is one batch (its pointers, scoring and mode fixed) made
@@ -1684,7 +1750,7 @@ int enqueue_plan(PlanImpl &P, hipStream_t stream) {
   int rc = launch_classify(w, P.rp, P.offs_a, P.offs_b, nullptr, P.n_pairs, P.scores, stream, P.bnd_rows);
   if (rc) return rc;
   hipLaunchKernelGGL(long_prep_kernel, dim3(1), dim3(256), 0, stream, w->items_long, w->ctr,
-                     long_dp_i32_stripe_width(), mode, P.scores, P.bnd_long_cap, P.flags_cap);
+                     long_dp_i32_stripe_width(cs.asz), mode, P.scores, P.bnd_long_cap, P.flags_cap);
   AS_HIP(hipGetLastError());
   hipLaunchKernelGGL(fill_kernel, dim3(64), dim3(256), 0, stream, w->flags, P.flags_cap, 0);
   AS_HIP(hipGetLastError());
@@ -1699,8 +1765,9 @@ int enqueue_plan(PlanImpl &P, hipStream_t stream) {
     a16.asz = cs.asz;
     a16.alpha = cs.alpha;
     a16.beta = cs.beta;
-    a16.sat_limit = g_i16_limit;
+    a16.sat_limit = packed_sat_limit(cs);
     a16.scores = P.scores;
+    a16.half = cs.half;
     AS_HIP(launch_full_dp_i16(mode, a16, full_dp_i16_blocks_per_cu(mode) * w->num_cu, stream));
   }
   FullDpArgs args;
@@ -1712,6 +1779,9 @@ int enqueue_plan(PlanImpl &P, hipStream_t stream) {
   args.alpha = cs.alpha;
   args.beta = cs.beta;
   args.scores = P.scores;
+  args.rerun = w->rerun;
+  args.n_rerun = &w->ctr->n_rerun32;
+  args.sat_limit = g_i16_limit;
   args.items = w->items;
   args.n_items = &w->ctr->n_full32;
   args.next = &w->ctr->next_full32;
@@ -1732,11 +1802,11 @@ int enqueue_plan(PlanImpl &P, hipStream_t stream) {
   la.bnd = w->bnd_long;
   la.flags = w->flags;
   AS_HIP(launch_long_dp_i32(mode, la, long_dp_i32_blocks_per_cu(mode, cs.asz) * w->num_cu, stream));
-  if (cs.allow16) {
+  if (cs.allow16 || mode == kLocal) {  // saturated packed pairs (16-bit list or kVarP16)
     args.items = w->rerun;
     args.n_items = &w->ctr->n_rerun32;
     args.next = &w->ctr->next_rerun32;
-    args.bnd_rows = 1;
+    args.bnd_rows = P.bnd_rows;   // kVarP16 re-runs may span several stripes
     const int grid_r = full_dp_i32_blocks_per_cu(mode, cs.asz, kmask_of_variant(kVarI32K16)) * w->num_cu;
     AS_HIP(launch_full_dp_i32(mode, args, kmask_of_variant(kVarI32K16), grid_r, stream));
   }
@@ -1793,7 +1863,7 @@ extern "C" int as_plan_create(const uint8_t *seqs_a, const int64_t *offs_a, cons
   if (hipMemsetAsync(w->ctr, 0, sizeof(Counters), stream) != hipSuccess) return fail(AS_ERR_HIP);
   if ((rc = launch_classify(w, P->rp, offs_a, offs_b, nullptr, n_pairs, scores_out, stream))) return fail(rc);
   hipLaunchKernelGGL(long_prep_kernel, dim3(1), dim3(256), 0, stream, w->items_long, w->ctr,
-                     long_dp_i32_stripe_width(), mode, scores_out, (int64_t)0, (int64_t)0);
+                     long_dp_i32_stripe_width(cs.asz), mode, scores_out, (int64_t)0, (int64_t)0);
   if (hipGetLastError() != hipSuccess) return fail(AS_ERR_HIP);
   Counters c;
   if ((rc = read_counters(w, stream, &c))) return fail(rc);
@@ -1905,7 +1975,8 @@ extern "C" int as_autotune(const uint8_t *seqs_a, const int64_t *offs_a, const u
       int best_v = -1;
       for (int v = 0; v < kNumVariants; ++v) {
         if (v == kVarI16 && !cs.allow16) continue;
-        if (v == kVarLong && ((int64_t)64 << b) <= long_dp_i32_stripe_width()) continue;
+        if (v == kVarP16 && !rp.allowP16) continue;
+        if (v == kVarLong && ((int64_t)64 << b) <= long_dp_i32_stripe_width(cs.asz)) continue;
         RouteParams t = rp;
         t.only_bin = b;
         t.var_of_bin[b] = (int8_t)v;
@@ -1977,6 +2048,13 @@ extern "C" int as_set_band_packing(int32_t on) {
   std::lock_guard<std::mutex> guard(g_lock);
   const int prev = g_band16 ? 1 : 0;
   g_band16 = on != 0;
+  return prev;
+}
+
+extern "C" int as_set_half_cells(int mode) {
+  std::lock_guard<std::mutex> guard(g_lock);
+  const int prev = g_half_cells;
+  g_half_cells = (mode == 0 || mode == 1) ? mode : 2;
   return prev;
 }
 

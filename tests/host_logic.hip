@@ -4,6 +4,7 @@
 //   r m n W smax_pos drop alpha beta  -> band16_range_ok, band16_bias, ub, lb
 //   c                                 -> packed and 32-bit class widths
 //   p m n w smax_pos drop alpha beta  -> band_route (packed flag, class, width)
+//   f v                               -> FP8 E4M3 code, E5M2 code, E5M2 exactness
 #include <cstdio>
 #include <cstring>
 
@@ -34,6 +35,10 @@ int main() {
       bool packed = false;
       const int c = band_route(m, n, w, true, sp, dr, a, b, &packed);
       printf("%d %d %d\n", (int)packed, c, c < 0 ? 0 : (packed ? band16_class_width(c) : band_class_width(c)));
+    } else if (!strcmp(cmd, "f")) {
+      int v;
+      if (scanf("%d", &v) != 1) return 2;
+      printf("%u %u %d\n", fp8_e4m3(v), fp8_e5m2(v), (int)e5m2_exact(v));
     } else {
       return 3;
     }

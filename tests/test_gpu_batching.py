@@ -109,7 +109,7 @@ def test_autotune_then_exact(gpu, oracle_mod):
     _say(f"autotune table {table.tolist()}")
     for bb in present:
         _say(f"  bin {bb} (<= {64 << bb}): GCUPS {np.round(g[bb], 1).tolist()} -> {table[bb]}")
-        assert 0 <= table[bb] < 5
+        assert 0 <= table[bb] < gpu.N_VARIANTS
         assert g[bb].max() > 0
     got = gpu.align_batch(*dev, b.subst, b.alpha, b.beta, b.mode).cpu().numpy()
     idx = np.random.default_rng(921).choice(b.n_pairs, 400, replace=False)

@@ -138,6 +138,41 @@ def test_error_codes(gpu):
     assert out.cpu().tolist() == [10, 10]
 
 
+def test_packed_lds_local(gpu, oracle_mod):
+    """Local pairs of the 32-bit list on packed 16-bit cells with LDS profiles:
+    protein pairs of config 3's shapes and DNA pairs wider than one packed
+    stripe, two pairs per lane group with unequal lengths and stripe counts,
+    then the same batch with the saturation threshold lowered from the host
+    so that most pairs are recomputed with 32-bit cells."""
+    rng = np.random.default_rng(560)
+    c3 = synth.config3(n_pairs=1 << 16, n_long=0)
+    idx = np.sort(rng.choice(c3.n_pairs, 1500, replace=False))
+    b = c3.subset(idx)
+    gpu.enable_timing(True)
+    try:
+        _check(gpu, oracle_mod, b, "protein local, packed LDS")
+        tm = gpu.last_timing()
+    finally:
+        gpu.enable_timing(False)
+    assert tm["pairs_full32"] == b.n_pairs and tm["pairs_rerun32"] == 0
+    prev = gpu.set_i16_limit(40)
+    try:
+        _check(gpu, oracle_mod, b.subset(np.arange(400)), "protein local, forced re-run")
+    finally:
+        gpu.set_i16_limit(prev)
+    pairs = []
+    for k in range(160):
+        m, n = (int(x) for x in rng.integers(1, 1500, size=2))
+        a = rng.integers(0, 4, size=m).astype(np.uint8)
+        if k % 2:
+            s_, _ = synth.mutate(rng, a, np.array([0, m]), 0.05, 0.02, 0.02, 4)
+            s_ = s_[:n] if len(s_) >= n else np.concatenate([s_, rng.integers(0, 4, n - len(s_)).astype(np.uint8)])
+        else:
+            s_ = rng.integers(0, 4, size=n).astype(np.uint8)
+        pairs.append((a, s_))
+    _check(gpu, oracle_mod, synth.from_pairs("dna local", pairs, DNA, 5, 2, 2), "DNA local, mixed routes")
+
+
 def test_range_refusal(gpu):
     """AS_ERR_RANGE: a pair whose cells could leave the 32-bit budget is
     refused before any DP runs (|sigma|max + alpha + 2 beta) * (m + n + 2)

@@ -119,3 +119,24 @@ def test_class_ladders_and_routing(host):
         else:
             assert 2 * W < n
     assert routed > 100
+
+
+def test_fp8_profile_codes(host):
+    """The packed kernel's FP16 cells read profile bytes as FP8 codes.  E4M3
+    codes of 0..16 decode (sign 0, 4-bit exponent with bias 7, 3-bit
+    mantissa) to the integer itself; E5M2 codes shifted into the upper byte
+    of a 16-bit word are the IEEE half of the integer (decoded by numpy),
+    for exactly the integers the exactness test admits."""
+    got = [tuple(int(x) for x in line.split()) for line in host([f"f {v}" for v in range(17)])]
+    for v, (e4, e5, ex) in enumerate(got):
+        if v == 0:
+            assert e4 == 0 and e5 == 0
+        else:
+            e, m = e4 >> 3, e4 & 7
+            assert e4 < 128 and 2.0 ** (e - 7) * (1 + m / 8) == v, (v, e4)
+        half = float(np.array([e5 << 8], dtype=np.uint16).view(np.float16)[0])
+        want_exact = float(np.float16(v)) == v and (np.array([np.float16(v)]).view(np.uint16)[0] & 0xFF) == 0
+        assert bool(ex) == bool(want_exact), (v, ex)
+        if ex:
+            assert half == v, (v, e5, half)
+    assert [v for v, g in enumerate(got) if g[2]] == [0, 1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16]
