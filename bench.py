@@ -424,12 +424,6 @@ def main():
         gpu_scores = out_l.cpu().numpy()
         mism_full = int(np.count_nonzero(gpu_scores != full_scores))
         log(f"learned band: {ms_per_step:.3f} ms/step, mismatches vs full DP {mism_full}")
-        # the same call without the chunked overlap of features and banded rounds
-        prev_chunks = binding.set_learned_chunks(1)
-        unchunked_ms, _ = timed(learned_step, args.steps, args.warmup, binding, torch)
-        binding.set_learned_chunks(prev_chunks)
-        unchunked_mism = int(np.count_nonzero(out_l.cpu().numpy() != full_scores))
-        log(f"learned band, one chunk: {unchunked_ms:.3f} ms/step")
         # the banded phase splits into the packed 16-bit and the 32-bit kernel,
         # each with its own cells, time and peak
         opc = OPS_PER_CELL[batch.mode]
@@ -545,9 +539,6 @@ def main():
             "roofline_per_kernel": fr,
         }
         result["speedup_vs_full_dp"] = round(full_ms / ms_per_step, 3)
-        result["learned_one_chunk"] = {"ms_per_step": round(unchunked_ms, 4),
-                                       "mismatches_vs_full_dp": unchunked_mism,
-                                       "note": "features of chunk k + 1 not overlapped with chunk k's rounds"}
         result["mismatches_vs_full_dp"] = mism_full
         result["band_stats"] = {k: stats[k] for k in ("rounds", "accepted", "fallback", "band_cells",
                                                       "band16_cells", "fallback_cells", "dp_cells")}

@@ -412,15 +412,6 @@ int as_align_batch_learned(const uint8_t *seqs_a, const int64_t *offs_a, const u
                            int32_t *scores_out, as_band_stats *stats, void *stream);
 
 /*
- * Chunks of a large as_align_batch_learned call (default 4; 1 turns the
- * overlap off): the batch is cut into up to `chunks` parts of at least
- * 2^17 pairs; chunk 0's features and widths are computed first, then chunk
- * k + 1's on a library side stream while chunk k's banded rounds run on the
- * caller's stream.  Results do not depend on it.  Returns the previous value.
- */
-int as_set_learned_chunks(int32_t chunks);
-
-/*
  * Full-DP kernel variants per length bin (batching runtime; not in the
  * paper).  Bin b holds the pairs whose longer sequence has at most 64 << b
  * residues (b = 0..AS_LEN_BINS-1, the last bin everything longer).  Within

@@ -93,8 +93,6 @@ def lib() -> ctypes.CDLL:
     L.as_band_model_load.argtypes = [p, i64, p, p, p, ctypes.POINTER(ctypes.c_int64), p]
     L.as_align_all_vs_all.restype = ctypes.c_int
     L.as_align_all_vs_all.argtypes = [p, p, i64, p, p, i64, ctypes.POINTER(Scoring), i32, p, p]
-    L.as_set_learned_chunks.restype = ctypes.c_int
-    L.as_set_learned_chunks.argtypes = [i32]
     L.as_strerror.restype = ctypes.c_char_p
     L.as_strerror.argtypes = [ctypes.c_int]
     L.as_release_workspace.restype = ctypes.c_int
@@ -278,12 +276,6 @@ def align_all_vs_all(seqs_q, offs_q, seqs_s, offs_s, subst, alpha: int, beta: in
 def set_band_packing(on: bool) -> bool:
     """Packed 16-bit banded kernel for eligible global pairs (default on)."""
     return bool(lib().as_set_band_packing(1 if on else 0))
-
-
-def set_learned_chunks(chunks: int) -> int:
-    """Chunks of a large learned call (features of the next chunk overlap the
-    current chunk's banded rounds); returns the previous value."""
-    return int(lib().as_set_learned_chunks(int(chunks)))
 
 
 def set_i16_limit(limit: int) -> int:

@@ -178,6 +178,32 @@ __device__ __forceinline__ void align_quad(const FullDpArgs &a, int8_t *prof, in
       }
       if (MODE == kSemiGlobal) rowoff = beta * (1 - t);
 
+      // profile words of a lane's row letter (always a letter of the
+      // alphabet, so the read stays inside the profile); the letter and
+      // words of step u + 1 are fetched during step u, so the LDS latency
+      // overlaps a step's arithmetic
+      auto load_prof = [&](int q, int (&w)[K / 4]) {
+        const int8_t *pp = prof + q * W + t * K;
+        if constexpr (K % 16 == 0) {
+#pragma unroll
+          for (int v = 0; v < K / 16; ++v) {
+            const int4 r = *(const int4 *)(pp + 16 * v);
+            w[4 * v] = r.x;
+            w[4 * v + 1] = r.y;
+            w[4 * v + 2] = r.z;
+            w[4 * v + 3] = r.w;
+          }
+        } else {
+          static_assert(K == 8, "K is 8, 16 or 32");
+          const int2 r = *(const int2 *)pp;
+          w[0] = r.x;
+          w[1] = r.y;
+        }
+      };
+      qc = dpp_shr1(qfeed, qc);
+      int pw[K / 4];
+      load_prof(qc, pw);
+
       for (int it0 = 0; it0 < its_max; it0 += kGroup) {
         int qnext = 0, hnext = 0, fnext = 0;
         {
@@ -189,29 +215,15 @@ __device__ __forceinline__ void align_quad(const FullDpArgs &a, int8_t *prof, in
 #pragma unroll
         for (int u = 0; u < kGroup; ++u) {
           const int row = it0 + u + 1 - t;
-          qc = dpp_shr1(qfeed, qc);
+          const int qf_next = (u == kGroup - 1) ? qnext : dpp_shl1(qfeed, qfeed);
+          const int qc_next = dpp_shr1(qf_next, qc);
+          int pw_next[K / 4];
+          load_prof(qc_next, pw_next);
           const int hsrc = import ? hfeed : hb;
           const int fsrc = import ? ffeed : fb;
           const int hl = dpp_shr1(hsrc, hout);
           const int fl = dpp_shr1(fsrc, fout);
           if ((unsigned)(row - 1) < (unsigned)m_s) {
-            const int8_t *pp = prof + qc * W + t * K;
-            int pw[K / 4];
-            if constexpr (K % 16 == 0) {
-#pragma unroll
-              for (int v = 0; v < K / 16; ++v) {
-                const int4 q = *(const int4 *)(pp + 16 * v);
-                pw[4 * v] = q.x;
-                pw[4 * v + 1] = q.y;
-                pw[4 * v + 2] = q.z;
-                pw[4 * v + 3] = q.w;
-              }
-            } else {
-              static_assert(K == 8, "K is 8, 16 or 32");
-              const int2 q = *(const int2 *)pp;
-              pw[0] = q.x;
-              pw[1] = q.y;
-            }
             int dg = hl_prev;
             int f = fl;
 #pragma unroll
@@ -241,7 +253,10 @@ __device__ __forceinline__ void align_quad(const FullDpArgs &a, int8_t *prof, in
           }
           hl_prev = hl;
           if (MODE == kSemiGlobal) { hb += beta; fb = hb; rowoff += beta; }
-          qfeed = dpp_shl1(qfeed, qfeed);
+          qfeed = qf_next;
+          qc = qc_next;
+#pragma unroll
+          for (int v = 0; v < K / 4; ++v) pw[v] = pw_next[v];
           if (import) { hfeed = dpp_shl1(hfeed, hfeed); ffeed = dpp_shl1(ffeed, ffeed); }
         }
         qfeed = qnext;
@@ -384,6 +399,12 @@ __device__ __forceinline__ void align_octet(const FullDpArgs &a, int8_t *prof, i
         hfeed = v.x;
         ffeed = v.y;
       }
+      // The row letters and profile words of step u + 1 are fetched during
+      // step u, so the LDS latency overlaps a step's arithmetic.  Letters are
+      // always 0..asz (asz: the zero row), so the reads stay in the profiles.
+      qc = dpp_shr1(qfeed, qc);
+      int2 w0 = *(const int2 *)(prof0 + (qc & 0xFF) * W + t * K);
+      int2 w1 = *(const int2 *)(prof1 + (qc >> 8) * W + t * K);
       for (int it0 = 0; it0 < its_max; it0 += kGroup) {
         int qnext = 0, hnext = 0, fnext = 0;
         {
@@ -399,12 +420,13 @@ __device__ __forceinline__ void align_octet(const FullDpArgs &a, int8_t *prof, i
 #pragma unroll
         for (int u = 0; u < kGroup; ++u) {
           const int row = it0 + u + 1 - t;
-          qc = dpp_shr1(qfeed, qc);
+          const int qf_next = (u == kGroup - 1) ? qnext : dpp_shl1(qfeed, qfeed);
+          const int qc_next = dpp_shr1(qf_next, qc);
+          const int2 w0n = *(const int2 *)(prof0 + (qc_next & 0xFF) * W + t * K);
+          const int2 w1n = *(const int2 *)(prof1 + (qc_next >> 8) * W + t * K);
           const s2 hl = as_s2(dpp_shr1(import ? hfeed : hb, hout));
           const int fl = dpp_shr1(import ? ffeed : fb, fout);
           if ((unsigned)(row - 1) < (unsigned)m_s) {
-            const int2 w0 = *(const int2 *)(prof0 + (qc & 0xFF) * W + t * K);
-            const int2 w1 = *(const int2 *)(prof1 + (qc >> 8) * W + t * K);
             s2 tt[K];
 #pragma unroll
             for (int x = 0; x < K; ++x) {
@@ -429,7 +451,10 @@ __device__ __forceinline__ void align_octet(const FullDpArgs &a, int8_t *prof, i
             if (export_ && t == kGroup - 1) bout[row] = make_int2(hout, fout);
           }
           hl_prev = hl;
-          qfeed = dpp_shl1(qfeed, qfeed);
+          qfeed = qf_next;
+          qc = qc_next;
+          w0 = w0n;
+          w1 = w1n;
           if (import) {
             hfeed = dpp_shl1(hfeed, hfeed);
             ffeed = dpp_shl1(ffeed, ffeed);

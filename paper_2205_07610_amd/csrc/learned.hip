@@ -12,7 +12,6 @@
 // score grows and the bound shrinks as the band widens), so this finds the
 // smallest accepted w.  Every round is one exact-band launch over the pairs
 // still searching.
-#include <algorithm>
 #include <math.h>
 #include <mutex>
 #include <string.h>
@@ -34,9 +33,6 @@ struct LabelState {
   int32_t cap;  // largest half-width whose band fits the widest class
   int32_t pad;
 };
-
-constexpr int kLearnedMaxChunks = 8;
-constexpr int64_t kLearnedChunkMin = 1 << 17;  // pairs per chunk at least
 
 struct LearnedWs {
   int device = -1;
@@ -60,16 +56,10 @@ struct LearnedWs {
   int32_t *dstat = nullptr;    // device: [0] status bits, [1] counter
   int32_t *hstat = nullptr;    // pinned copy
   hipEvent_t ev[4] = {};
-  // learned calls in chunks: the next chunk's features and widths are
-  // computed on a side stream (default priority) while the banded rounds of
-  // the current chunk run on the caller's stream
-  hipStream_t side = nullptr;
-  hipEvent_t chunk_ev[kLearnedMaxChunks + 1] = {};
 };
 
 std::mutex g_llock;
 std::vector<LearnedWs> g_lws;
-int g_learned_chunks = 4;  // chunks of a large learned call (1: no overlap)
 
 #define LS_HIP(call)                             \
   do {                                           \
@@ -90,8 +80,6 @@ int get_lws(LearnedWs **out) {
     LS_HIP(hipMalloc(&w.partials, sizeof(float) * kMlpMaxParts * kMlpPartialStride));
     LS_HIP(hipMalloc(&w.adam, sizeof(float) * 2 * kMlpParams));
     for (auto &e : w.ev) LS_HIP(hipEventCreate(&e));
-    LS_HIP(hipStreamCreateWithFlags(&w.side, hipStreamNonBlocking));
-    for (auto &e : w.chunk_ev) LS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     w.device = dev;
   }
   *out = &w;
@@ -313,9 +301,6 @@ void release_learned_workspace() {
     if (w.hstat) (void)hipHostFree(w.hstat);
     for (auto &e : w.ev)
       if (e) (void)hipEventDestroy(e);
-    for (auto &e : w.chunk_ev)
-      if (e) (void)hipEventDestroy(e);
-    if (w.side) (void)hipStreamDestroy(w.side);
     w = LearnedWs();
   }
   (void)hipSetDevice(cur);
@@ -417,92 +402,22 @@ extern "C" int as_align_batch_learned(const uint8_t *seqs_a, const int64_t *offs
   if ((rc = grow(&w->features, &w->features_cap, n_pairs * kMlpInputs))) return rc;
   if ((rc = grow(&w->w, &w->w_cap, n_pairs))) return rc;
   const bool timing = timing_enabled();
-  // chunks: the features and widths of chunk k + 1 are computed on the side
-  // stream while chunk k's banded rounds run on the caller's stream (the
-  // feature kernel waits on LDS and memory, the banded kernel on VALU)
-  int chunks = (int)std::min<int64_t>(g_learned_chunks, n_pairs / kLearnedChunkMin);
-  chunks = std::max(1, std::min(chunks, kLearnedMaxChunks));
-  auto lo = [&](int k) { return n_pairs * k / chunks; };
-  LS_HIP(hipMemsetAsync(w->dstat, 0, 2 * sizeof(int32_t), stream));
   if (timing) LS_HIP(hipEventRecord(w->ev[0], stream));
-  auto widths = [&](int k, hipStream_t st) -> int {
-    const int64_t p0 = lo(k), n = lo(k + 1) - p0;
-    LS_HIP(launch_features(seqs_a, offs_a + p0, seqs_b, offs_b + p0, n, w->features + p0 * kMlpInputs, w->dstat,
-                           w->num_cu, st));
-    LS_HIP(launch_mlp_predict(params, w->features + p0 * kMlpInputs, n, w->w + p0, nullptr, w->num_cu, st));
-    return AS_OK;
-  };
-  if ((rc = widths(0, stream))) return rc;
+  if ((rc = features_impl(w, seqs_a, offs_a, seqs_b, offs_b, n_pairs, w->features, stream))) return rc;
+  if (timing) LS_HIP(hipEventRecord(w->ev[1], stream));
+  LS_HIP(launch_mlp_predict(params, w->features, n_pairs, w->w, nullptr, w->num_cu, stream));
   if (timing) LS_HIP(hipEventRecord(w->ev[2], stream));
-  LS_HIP(hipEventRecord(w->chunk_ev[0], stream));  // the status word is clear
-  as_timing acc;
-  memset(&acc, 0, sizeof(acc));
-  as_band_stats st_acc;
-  memset(&st_acc, 0, sizeof(st_acc));
-  for (int k = 0; k < chunks; ++k) {
-    if (k + 1 < chunks) {
-      LS_HIP(hipStreamWaitEvent(w->side, w->chunk_ev[0], 0));
-      if ((rc = widths(k + 1, w->side))) return rc;
-      LS_HIP(hipEventRecord(w->chunk_ev[k + 1], w->side));
-    }
-    if (k > 0) LS_HIP(hipStreamWaitEvent(stream, w->chunk_ev[k], 0));
-    const int64_t p0 = lo(k), n = lo(k + 1) - p0;
-    as_band_stats st;
-    rc = band_call(seqs_a, offs_a + p0, seqs_b, offs_b + p0, n, scoring, mode, w->w + p0, max_rounds, 0, 0,
-                   scores_out + p0, nullptr, nullptr, nullptr, &st, stream);
-    if (rc) {
-      (void)hipStreamSynchronize(w->side);
-      return rc;
-    }
-    as_timing t;
-    get_last_timing(&t);
-    acc.classify_ms += t.classify_ms;
-    acc.band_ms += t.band_ms;
-    acc.band16_ms += t.band16_ms;
-    acc.full32_ms += t.full32_ms;
-    acc.full16_ms += t.full16_ms;
-    acc.rerun32_ms += t.rerun32_ms;
-    acc.long_ms += t.long_ms;
-    acc.long16_ms += t.long16_ms;
-    acc.pairs_full32 += t.pairs_full32;
-    acc.pairs_full16 += t.pairs_full16;
-    acc.pairs_rerun32 += t.pairs_rerun32;
-    acc.pairs_long += t.pairs_long;
-    acc.pairs_long16 += t.pairs_long16;
-    acc.pairs_fallback += t.pairs_fallback;
-    acc.cells += t.cells;
-    acc.cells_full32 += t.cells_full32;
-    acc.cells_full16 += t.cells_full16;
-    acc.cells_long += t.cells_long;
-    acc.cells_long16 += t.cells_long16;
-    st_acc.rounds = std::max(st_acc.rounds, st.rounds);
-    for (int r = 0; r < 8; ++r) st_acc.accepted[r] += st.accepted[r];
-    st_acc.fallback += st.fallback;
-    st_acc.band_cells += st.band_cells;
-    st_acc.cells += st.cells;
-    st_acc.fallback_cells += st.fallback_cells;
-    st_acc.band16_cells += st.band16_cells;
-  }
-  // the feature kernels' status (bad residues are also caught by the banded path)
-  if ((rc = read_stat(w, stream))) return rc;
-  if ((rc = stat_code(w->hstat[0]))) return rc;
-  if (stats) *stats = st_acc;
+  rc = band_call(seqs_a, offs_a, seqs_b, offs_b, n_pairs, scoring, mode, w->w, max_rounds, 0, 0, scores_out,
+                 nullptr, nullptr, nullptr, stats, stream);
+  if (rc) return rc;
   if (timing) {
-    float f = 0.f;
+    float f = 0.f, m = 0.f;
     LS_HIP(hipEventSynchronize(w->ev[2]));
-    (void)hipEventElapsedTime(&f, w->ev[0], w->ev[2]);
-    acc.features_ms = f;  // the first chunk's features and widths (the part not overlapped)
-    acc.mlp_ms = 0.f;
+    (void)hipEventElapsedTime(&f, w->ev[0], w->ev[1]);
+    (void)hipEventElapsedTime(&m, w->ev[1], w->ev[2]);
+    record_learned_timing(f, m);
   }
-  set_last_timing(acc);
   return AS_OK;
-}
-
-extern "C" int as_set_learned_chunks(int32_t chunks) {
-  std::lock_guard<std::mutex> guard(g_llock);
-  const int prev = g_learned_chunks;
-  g_learned_chunks = chunks < 1 ? 1 : (chunks > kLearnedMaxChunks ? kLearnedMaxChunks : chunks);
-  return prev;
 }
 
 // ---- band model blobs ----

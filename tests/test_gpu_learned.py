@@ -234,33 +234,6 @@ def test_training_reduces_loss(gpu):
     _say(f"training: pinball {loss0:.3f} -> {loss1:.3f}")
     assert loss1 < 0.25 * loss0
 
-
-def test_learned_chunks_equal_one_call(gpu, oracle_mod):
-    """A batch large enough for the chunked learned call (features of the
-    next chunk on the side stream): the same scores with 1, 2 and 4 chunks,
-    and a sample of them equal to the oracle."""
-    import torch
-    b = synth.config4_like(300_000, 870, min_len=200, max_len=600, max_div=0.15)
-    dev = gpu.to_device(b)
-    params = _t(synth.band_params_init(871, b3=4.0))
-    outs = {}
-    prev = gpu.set_learned_chunks(1)
-    try:
-        for c in (1, 2, 4):
-            gpu.set_learned_chunks(c)
-            got, st = gpu.align_batch_learned(*dev, b.subst, b.alpha, b.beta, b.mode, params)
-            outs[c] = got.cpu().numpy()
-            _say(f"learned, {c} chunks: {st}")
-    finally:
-        gpu.set_learned_chunks(prev)
-    assert np.array_equal(outs[1], outs[2]) and np.array_equal(outs[1], outs[4])
-    idx = np.sort(np.random.default_rng(872).choice(b.n_pairs, 3000, replace=False))
-    sub = b.subset(idx)
-    want = oracle_mod.align_batch(sub.seqs_a, sub.offs_a, sub.seqs_b, sub.offs_b, sub.subst, sub.alpha,
-                                  sub.beta, sub.mode)
-    np.testing.assert_array_equal(outs[4][idx].astype(np.int64), want)
-
-
 def test_band_model_blob_round_trip(gpu):
     """A saved network (with and without its Adam state) loads back bit for
     bit, resumed training from the loaded state equals uninterrupted
