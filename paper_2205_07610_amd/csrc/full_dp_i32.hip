@@ -56,6 +56,17 @@ __device__ __forceinline__ int dpp_shl1(int old, int src) {
 }
 __device__ __forceinline__ int imax3(int a, int b, int c) { return max(max(a, b), c); }
 
+// LDS bytes of the profiles of a variant set (an instantiation's KMASK):
+// four groups of asz rows of 16 K columns for the 32-bit variants, four
+// groups of two (asz + 1)-row profiles of 128 columns for kVarP16; the mixed
+// sets take the larger.
+__host__ __device__ constexpr size_t full_dp_i32_profile_bytes(int asz, int inst) {
+  const size_t kmax = (inst & 4) ? 32 : ((inst & 2) ? 16 : 8);
+  const size_t b32 = (inst & 7) ? (size_t)kGroupsPerWave * asz * kGroup * kmax : 0;
+  const size_t bp = (inst & 8) ? (size_t)kGroupsPerWave * 2 * (asz + 1) * kGroup * 8 : 0;
+  return ((b32 > bp ? b32 : bp) + 15) / 16 * 16;
+}
+
 // Packed 16-bit helpers of the kVarP16 variant (two pairs per register).
 typedef short s2 __attribute__((ext_vector_type(2)));
 typedef unsigned short u2 __attribute__((ext_vector_type(2)));
@@ -93,15 +104,31 @@ __device__ __forceinline__ int wave_max_groups(int v) {
   return v;
 }
 
+// Profile bytes of one lane's K columns for rows 0..asz-1: row r, column x
+// holds tb[c[x] * asz + r], where tb is the workgroup's LDS score table of
+// the pair's orientation (column letter c, row letter r; c == asz is a
+// padding column, c == asz + 1 a column past the pair's stripes).  Four
+// columns go out as one 32-bit LDS store.
+template <int K>
+__device__ __forceinline__ void write_profile(int8_t *pp, int W, const int8_t *tb, const int (&c)[K], int asz) {
+  for (int r = 0; r < asz; ++r) {
+#pragma unroll
+    for (int x4 = 0; x4 < K / 4; ++x4) {
+      uint32_t w = 0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) w |= (uint32_t)(uint8_t)tb[c[4 * x4 + b] * asz + r] << (8 * b);
+      *(uint32_t *)(pp + r * W + 4 * x4) = w;
+    }
+  }
+}
+
 // One quad of items (one per group) with K columns per lane.
 template <int MODE, int K>
-__device__ __forceinline__ void align_quad(const FullDpArgs &a, int8_t *prof, int2 *slot, PairDesc d,
-                                           bool has, int t) {
+__device__ __forceinline__ void align_quad(const FullDpArgs &a, int8_t *prof, const int8_t *stab, int2 *slot,
+                                           PairDesc d, bool has, int t) {
   constexpr int W = kGroup * K;
   const int asz = a.asz;
   const int alpha = a.alpha, beta = a.beta;
-  // Profile bias: the value added to the stored diagonal (see header).
-  const int bias = (MODE == kLocal) ? alpha : alpha + beta;
   const int amb = alpha - beta;
   {
     const int m = has ? d.m : 0;
@@ -121,20 +148,17 @@ __device__ __forceinline__ void align_quad(const FullDpArgs &a, int8_t *prof, in
       const int jp0 = s * W + t * K;   // padded column of x = 0 is jp0 + 1
       // ---- scoring profile for this lane's K columns (paper: init_profile) ----
       if (on) {
+        int cc[K];  // column codes: a letter, or asz for a padding column (sigma 0, see header)
 #pragma unroll
         for (int x = 0; x < K; ++x) {
           const int j = jp0 + x + 1 - pad;  // real column, 1-based
-          int c = -1;
+          cc[x] = asz;
           if (j >= 1 && j <= n) {
-            c = cols[j - 1];
-            if (c >= asz) { bad = 1; c = 0; }
-          }
-          for (int r = 0; r < asz; ++r) {
-            int sv = 0;  // padding columns score 0 (see header)
-            if (c >= 0) sv = tr ? a.subst[c * asz + r] : a.subst[r * asz + c];
-            prof[r * W + t * K + x] = (int8_t)(sv + bias);
+            cc[x] = cols[j - 1];
+            if (cc[x] >= asz) { bad = 1; cc[x] = 0; }
           }
         }
+        write_profile<K>(prof + t * K, W, stab + (tr ? (asz + 2) * asz : 0), cc, asz);
       }
       // ---- row-0 state ----
       int Ha[K], Ee[K];
@@ -205,16 +229,20 @@ __device__ __forceinline__ void align_quad(const FullDpArgs &a, int8_t *prof, in
       load_prof(qc, pw);
 
       for (int it0 = 0; it0 < its_max; it0 += kGroup) {
+        // the next chunk's feed; the residue is checked only where it is
+        // used (the chunk's last step), so the load's latency overlaps the
+        // chunk instead of stalling its start
         int qnext = 0, hnext = 0, fnext = 0;
         {
           const int qi = it0 + kGroup + t;
-          if (qi < m_s) { qnext = rows[qi]; if (qnext >= asz) { bad = 1; qnext = 0; } }
+          if (qi < m_s) qnext = rows[qi];
           const int bi = it0 + kGroup + 1 + t;
           if (import && bi <= m_s) { const int2 v = bin[bi]; hnext = v.x; fnext = v.y; }
         }
 #pragma unroll
         for (int u = 0; u < kGroup; ++u) {
           const int row = it0 + u + 1 - t;
+          if (u == kGroup - 1 && qnext >= asz) { bad = 1; qnext = 0; }
           const int qf_next = (u == kGroup - 1) ? qnext : dpp_shl1(qfeed, qfeed);
           const int qc_next = dpp_shr1(qf_next, qc);
           int pw_next[K / 4];
@@ -311,8 +339,8 @@ __device__ __forceinline__ void align_quad(const FullDpArgs &a, int8_t *prof, in
 // column H(i, 0) = 0; the stripes past a half's own count score 0 for every
 // letter.  The boundary column carries both halves' (H - alpha, F) packed.
 template <int MODE>
-__device__ __forceinline__ void align_octet(const FullDpArgs &a, int8_t *prof, int2 *slot, PairDesc d0, bool has0,
-                                            PairDesc d1, bool has1, int t) {
+__device__ __forceinline__ void align_octet(const FullDpArgs &a, int8_t *prof, const int8_t *stab, int2 *slot,
+                                            PairDesc d0, bool has0, PairDesc d1, bool has1, int t) {
   if constexpr (MODE != kLocal) {
     return;
   } else {
@@ -348,23 +376,21 @@ __device__ __forceinline__ void align_octet(const FullDpArgs &a, int8_t *prof, i
           const uint8_t *cols = h ? cols1 : cols0;
           const bool tr = h ? tr1 : tr0;
           int8_t *pp = (h ? prof1 : prof0) + t * K;
+          // column codes: a letter, asz for a padding column (sigma 0), asz + 1
+          // past the half's stripes (score 0)
+          int cc[K];
 #pragma unroll
           for (int x = 0; x < K; ++x) {
             const int j = jp0 + x + 1 - pad;  // real column, 1-based
-            int c = -1;                       // -1: padding column (sigma 0), -2: past the half's stripes
-            if (s >= Sh) c = -2;
-            else if (j >= 1 && j <= n) {
-              c = cols[j - 1];
-              if (c >= asz) { bad = 1; c = 0; }
+            cc[x] = (s >= Sh) ? asz + 1 : asz;
+            if (s < Sh && j >= 1 && j <= n) {
+              cc[x] = cols[j - 1];
+              if (cc[x] >= asz) { bad = 1; cc[x] = 0; }
             }
-            for (int r = 0; r < asz; ++r) {
-              int v = 0;
-              if (c >= 0) v = (tr ? a.subst[c * asz + r] : a.subst[r * asz + c]) + alpha;
-              else if (c == -1) v = alpha;
-              pp[r * W + x] = (int8_t)v;
-            }
-            pp[asz * W + x] = 0;
           }
+          write_profile<K>(pp, W, stab + (tr ? (asz + 2) * asz : 0), cc, asz);
+#pragma unroll
+          for (int x4 = 0; x4 < K / 4; ++x4) *(uint32_t *)(pp + asz * W + 4 * x4) = 0u;  // the no-row row
         }
       }
       // ---- row-0 state (local: H(0, j) - alpha = -alpha, E' = 0) ----
@@ -385,15 +411,17 @@ __device__ __forceinline__ void align_octet(const FullDpArgs &a, int8_t *prof, i
       const int its_max = wave_max_groups(its);
       const int hb = as_i(pk(-alpha, -alpha)), fb = 0;  // stripe 0's left boundary
       // feeds: the row letters of both halves (q0 | q1 << 8) and the imported
-      // boundary, lane t holding step t of the chunk
-      auto row_pair = [&](int qi) {
-        int q0 = asz, q1 = asz;
-        if (qi < m0) { q0 = rows0[qi]; if (q0 >= asz) { bad = 1; q0 = 0; } }
-        if (qi < m1) { q1 = rows1[qi]; if (q1 >= asz) { bad = 1; q1 = 0; } }
+      // boundary, lane t holding step t of the chunk.  The residue bytes are
+      // loaded a chunk ahead (-1: past the half's rows) and checked and
+      // packed only where used, so the loads overlap the chunk.
+      auto pack_rows = [&](int r0, int r1) {
+        int q0 = r0 < 0 ? asz : r0, q1 = r1 < 0 ? asz : r1;
+        if (r0 >= asz) { bad = 1; q0 = 0; }
+        if (r1 >= asz) { bad = 1; q1 = 0; }
         return q0 | (q1 << 8);
       };
       int qfeed = 0, hfeed = 0, ffeed = 0, qc = 0;
-      if (t < m_s) qfeed = row_pair(t);
+      if (t < m_s) qfeed = pack_rows(t < m0 ? (int)rows0[t] : -1, t < m1 ? (int)rows1[t] : -1);
       if (import && t + 1 <= m_s) {
         const int2 v = bin[t + 1];
         hfeed = v.x;
@@ -407,9 +435,10 @@ __device__ __forceinline__ void align_octet(const FullDpArgs &a, int8_t *prof, i
       int2 w1 = *(const int2 *)(prof1 + (qc >> 8) * W + t * K);
       for (int it0 = 0; it0 < its_max; it0 += kGroup) {
         int qnext = 0, hnext = 0, fnext = 0;
+        const int qi = it0 + kGroup + t;
+        const int nr0 = (qi < m_s && qi < m0) ? (int)rows0[qi] : -1;
+        const int nr1 = (qi < m_s && qi < m1) ? (int)rows1[qi] : -1;
         {
-          const int qi = it0 + kGroup + t;
-          if (qi < m_s) qnext = row_pair(qi);
           const int bi = it0 + kGroup + 1 + t;
           if (import && bi <= m_s) {
             const int2 v = bin[bi];
@@ -420,6 +449,7 @@ __device__ __forceinline__ void align_octet(const FullDpArgs &a, int8_t *prof, i
 #pragma unroll
         for (int u = 0; u < kGroup; ++u) {
           const int row = it0 + u + 1 - t;
+          if (u == kGroup - 1 && qi < m_s) qnext = pack_rows(nr0, nr1);
           const int qf_next = (u == kGroup - 1) ? qnext : dpp_shl1(qfeed, qfeed);
           const int qc_next = dpp_shr1(qf_next, qc);
           const int2 w0n = *(const int2 *)(prof0 + (qc_next & 0xFF) * W + t * K);
@@ -498,6 +528,23 @@ __global__ void __launch_bounds__(kWave) full_dp_i32_kernel(FullDpArgs a) {
   const int t = lane & 15;
   int8_t *prof = lds + g * a.asz * (kGroup * KMAX);
   int8_t *prof_p = lds + g * 2 * (a.asz + 1) * (kGroup * 8);
+  // Score table after the profiles, filled once per workgroup: orientation o
+  // (1: the pair is transposed), column code c, row letter r ->
+  // sigma(r, c) + bias (o = 0) or sigma(c, r) + bias (o = 1) for letters,
+  // the bias for c = asz (padding column, sigma 0), 0 for c = asz + 1.
+  int8_t *stab = lds + full_dp_i32_profile_bytes(a.asz, KMASK);
+  {
+    const int asz = a.asz, tn = (asz + 2) * asz;
+    const int bias = (MODE == kLocal) ? a.alpha : a.alpha + a.beta;
+    for (int i = lane; i < 2 * tn; i += kWave) {
+      const int o = i >= tn ? 1 : 0, k = i - o * tn, c = k / asz, r = k - c * asz;
+      int v = 0;
+      if (c < asz) v = (o ? a.subst[c * asz + r] : a.subst[r * asz + c]) + bias;
+      else if (c == asz) v = bias;
+      stab[i] = (int8_t)v;
+    }
+    __syncthreads();
+  }
   const int n_items = *a.n_items;
   int2 *slot = a.bnd + ((int64_t)blockIdx.x * kGroupsPerWave + g) * 2 * a.bnd_rows;
   for (;;) {
@@ -517,7 +564,8 @@ __global__ void __launch_bounds__(kWave) full_dp_i32_kernel(FullDpArgs a) {
         PairDesc d0{0, 0, 0, 0, -1, 0}, d1{0, 0, 0, 0, -1, 0};
         if (i0 < n_items) d0 = a.items[i0];
         if (i1 < n_items) d1 = a.items[i1];
-        align_octet<MODE>(a, prof_p, slot, d0, i0 < n_items && d0.pair >= 0, d1, i1 < n_items && d1.pair >= 0, t);
+        align_octet<MODE>(a, prof_p, stab, slot, d0, i0 < n_items && d0.pair >= 0, d1,
+                          i1 < n_items && d1.pair >= 0, t);
       }
     } else {
       if constexpr (HAS32) {
@@ -527,15 +575,15 @@ __global__ void __launch_bounds__(kWave) full_dp_i32_kernel(FullDpArgs a) {
           if (item < n_items) d = a.items[item];
           const bool has = item < n_items && d.pair >= 0;  // padding slots carry pair -1
           if constexpr ((KMASK & 7) == 1) {
-            align_quad<MODE, 8>(a, prof, slot, d, has, t);
+            align_quad<MODE, 8>(a, prof, stab, slot, d, has, t);
           } else if constexpr ((KMASK & 7) == 2) {
-            align_quad<MODE, 16>(a, prof, slot, d, has, t);
+            align_quad<MODE, 16>(a, prof, stab, slot, d, has, t);
           } else if constexpr ((KMASK & 7) == 4) {
-            align_quad<MODE, 32>(a, prof, slot, d, has, t);
+            align_quad<MODE, 32>(a, prof, stab, slot, d, has, t);
           } else {
-            if (kv == kVarI32K8) align_quad<MODE, 8>(a, prof, slot, d, has, t);
-            else if (kv == kVarI32K32) align_quad<MODE, 32>(a, prof, slot, d, has, t);
-            else align_quad<MODE, 16>(a, prof, slot, d, has, t);
+            if (kv == kVarI32K8) align_quad<MODE, 8>(a, prof, stab, slot, d, has, t);
+            else if (kv == kVarI32K32) align_quad<MODE, 32>(a, prof, stab, slot, d, has, t);
+            else align_quad<MODE, 16>(a, prof, stab, slot, d, has, t);
           }
         }
       }
@@ -588,14 +636,9 @@ int occupancy_mode(int kmask, size_t lds) {
 }  // namespace
 
 size_t full_dp_i32_lds_bytes(int asz, int kmask) {
-  const int inst = kmask_instance(kmask);
-  const int kmax = (inst & 4) ? 32 : ((inst & 2) ? 16 : 8);
-  size_t bytes = (inst & 7) ? (size_t)kGroupsPerWave * asz * kGroup * kmax : 0;
-  if (inst & 8) {  // two profiles of asz + 1 rows per group, 128 columns
-    const size_t p = (size_t)kGroupsPerWave * 2 * (asz + 1) * kGroup * 8;
-    bytes = bytes > p ? bytes : p;
-  }
-  return bytes;
+  // profiles, then the score table (two orientations of (asz + 2) x asz bytes)
+  const size_t tab = ((size_t)2 * (asz + 2) * asz + 15) / 16 * 16;
+  return full_dp_i32_profile_bytes(asz, kmask_instance(kmask)) + tab;
 }
 int full_dp_i32_stripe_width(int k) { return kGroup * k; }
 

@@ -173,7 +173,7 @@ __global__ void __launch_bounds__(kWave) long_dp_i32_kernel(LongDpArgs a) {
       if (t < kChunk) {
         const int qi = it0 + t;
         q = 0;
-        if (qi < m) { q = rows[qi]; if (q >= asz) { bad = 1; q = 0; } }
+        if (qi < m) q = rows[qi];  // checked where it is used
         if (import && qi + 1 <= m) {
           const int2 v = load_bnd(bin + qi + 1);
           h = v.x;
@@ -202,6 +202,7 @@ __global__ void __launch_bounds__(kWave) long_dp_i32_kernel(LongDpArgs a) {
       }
     };
     load_feed(0, qfeed, hfeed, ffeed);
+    if (qfeed >= asz) { bad = 1; qfeed = 0; }
     for (int it0 = 0; it0 < its; it0 += kChunk) {
       int qnext = 0, hnext = 0, fnext = 0;
       if (it0 + kChunk < its) load_feed(it0 + kChunk, qnext, hnext, fnext);
@@ -248,6 +249,7 @@ __global__ void __launch_bounds__(kWave) long_dp_i32_kernel(LongDpArgs a) {
         hfeed = wave_shl1(hfeed, hfeed);
         ffeed = wave_shl1(ffeed, ffeed);
       }
+      if (qnext >= asz) { bad = 1; qnext = 0; }
       qfeed = qnext;
       hfeed = hnext;
       ffeed = fnext;
