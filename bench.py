@@ -331,6 +331,9 @@ def main():
     ap.add_argument("--workload", default="c4", help="c4 (default), c0, c1, c2, c3, c3long")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cell-compare", action="store_true",
+                    help="skip the side-by-side timing of the packed kernel's cell types (counter runs "
+                         "that attribute the largest launch to the timed step)")
     ap.add_argument("--tau", type=float, default=TRAIN["tau"], help="pinball quantile of the band network")
     ap.add_argument("--train-steps", type=int, default=TRAIN["steps"])
     ap.add_argument("--lr", type=float, default=TRAIN["lr"])
@@ -483,6 +486,8 @@ def main():
         if dom == "full16_ms" and cell_type:
             dtype = "f16x2"
         if full_avg["full16_ms"] > 0:
+            per_kernel["full16"]["cell_type"] = cell_type
+        if full_avg["full16_ms"] > 0 and not args.no_cell_compare:
             # the packed kernel's cell types side by side (same batch, eager)
             alt = {}
             for hmode, label in ((0, "int16"), (1, "fp16_when_admissible")):
@@ -495,7 +500,6 @@ def main():
                               "pairs_full16": int(ph_h[-1]["pairs_full16"]),
                               "mismatches_vs_default": int(np.count_nonzero(out.cpu().numpy() != full_scores))}
                 log(f"packed cells {label}: {ms_h:.3f} ms/step, packed kernel {alt[label]['full16_ms']:.3f} ms")
-            per_kernel["full16"]["cell_type"] = cell_type
             per_kernel["full16"]["cell_types_compared"] = alt
 
     result = {
