@@ -236,13 +236,23 @@ PHASE_CELLS = {"full32_ms": "cells_full32", "full16_ms": "cells_full16", "long_m
 PACKED_PHASES = ("full16_ms", "long16_ms")
 
 
+def packed_phase(phases, name):
+    """True when the phase's kernel computes packed 16-bit cells: the packed
+    kernels, and the 32-bit list when it ran only its packed LDS-profile
+    variant (variant bit 3)."""
+    return name in PACKED_PHASES or (name == "full32_ms" and phases[-1].get("full32_variants") == 8)
+
+
 def phase_roofline(phases, name, ops_per_cell):
-    """Roofline of one full-DP phase: its own cells x ops per cell / its time."""
+    """Roofline of one full-DP phase: its own cells x ops per cell / its time,
+    against the peak of the arithmetic the phase's kernel ran."""
     ms = sum(p[name] for p in phases) / len(phases)
     cells = phases[-1][PHASE_CELLS[name]] if name in PHASE_CELLS else 0
-    r = roofline(name.replace("_ms", ""), ms, cells * ops_per_cell, name in PACKED_PHASES)
+    r = roofline(name.replace("_ms", ""), ms, cells * ops_per_cell, packed_phase(phases, name))
     r["cells"] = cells
     r["ops_per_cell"] = ops_per_cell
+    if name == "full32_ms":
+        r["variants"] = int(phases[-1].get("full32_variants", 0))
     return r
 
 
@@ -479,7 +489,7 @@ def main():
             ms_per_step, gpu_scores = plan_ms, plan_scores
         dom = max(full_names, key=lambda k: avg[k])
         roof = phase_roofline(full_phases, dom, OPS_PER_CELL[batch.mode])
-        dtype = "i16x2" if dom in PACKED_PHASES else "i32"
+        dtype = "i16x2" if packed_phase(full_phases, dom) else "i32"
         per_kernel = {k.replace("_ms", ""): phase_roofline(full_phases, k, OPS_PER_CELL[batch.mode])
                       for k in ("full32_ms", "full16_ms", "long_ms", "long16_ms") if full_avg[k] > 0}
         cell_type = int(full_phases[-1].get("full16_cell_type", 0)) if full_avg["full16_ms"] > 0 else 0

@@ -224,6 +224,8 @@ typedef struct {
     int64_t cells_long16;
     int64_t full16_cell_type; /* cells of the packed full-DP kernel: 0 int16, 1 FP16 with FP8 E4M3
                                  profile bytes, 2 FP16 with FP8 E5M2 profile bytes */
+    int64_t full32_variants;  /* variants the 32-bit list ran: bit 0 K = 8, bit 1 K = 16, bit 2 K = 32,
+                                 bit 3 the packed int16 LDS-profile variant (two local pairs per group) */
 } as_timing;
 
 /*

@@ -43,7 +43,8 @@ class Timing(ctypes.Structure):
                 ("pairs_fallback", ctypes.c_int64), ("cells", ctypes.c_int64),
                 ("cells_full32", ctypes.c_int64), ("cells_full16", ctypes.c_int64),
                 ("cells_long", ctypes.c_int64), ("pairs_long16", ctypes.c_int64),
-                ("cells_long16", ctypes.c_int64), ("full16_cell_type", ctypes.c_int64)]
+                ("cells_long16", ctypes.c_int64), ("full16_cell_type", ctypes.c_int64),
+                ("full32_variants", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

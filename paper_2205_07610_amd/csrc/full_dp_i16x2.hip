@@ -423,7 +423,7 @@ __global__ void __launch_bounds__(kWave) full_dp_i16_kernel(FullDp16Args a) {
 // 16-bit half, both halves against the same column profile).  Local pairs
 // that saturate are appended to the re-run list as descriptors for the
 // 32-bit kernel.
-template <int MODE, int K>
+template <int MODE, int K, int CELL>
 __global__ void __launch_bounds__(kWave) all_vs_all_i16_kernel(AllVsAllArgs a) {
   constexpr int W = kGroup * K;
   const int lane = threadIdx.x;
@@ -433,7 +433,7 @@ __global__ void __launch_bounds__(kWave) all_vs_all_i16_kernel(AllVsAllArgs a) {
   const int asz = a.asz;
   const int bias = (MODE == kLocal) ? alpha : alpha + beta;
   const int pad_val = (MODE == kLocal) ? alpha : (MODE == kGlobal ? alpha - beta : alpha + beta);
-  const uint32_t pad_word = (uint32_t)(pad_val & 0xFF) * 0x01010101u;
+  const uint32_t pad_word = profile_byte<CELL>(pad_val) * 0x01010101u;
   __shared__ uint32_t ptab[8];
   if (lane < 8) {
     const int o = lane >> 2, sl = lane & 3;
@@ -441,7 +441,7 @@ __global__ void __launch_bounds__(kWave) all_vs_all_i16_kernel(AllVsAllArgs a) {
     if (sl < asz)
       for (int c = 0; c < asz; ++c) {
         const int sv = o ? a.subst[sl * asz + c] : a.subst[c * asz + sl];
-        w |= (uint32_t)((sv + bias) & 0xFF) << (8 * c);
+        w |= profile_byte<CELL>(sv + bias) << (8 * c);
       }
     ptab[lane] = w;
   }
@@ -471,8 +471,8 @@ __global__ void __launch_bounds__(kWave) all_vs_all_i16_kernel(AllVsAllArgs a) {
       const int m1 = has1 ? (int)(a.offs_r[q1 + 1] - o1) : 0;
       int r0, r1;
       bool over0, over1;
-      duo_core<MODE, K>(a.seqs_r + o0, a.seqs_r + o1, m0, m1, n, n, P, P, asz, alpha, beta, a.sat_limit, lane,
-                        bad, r0, r1, over0, over1);
+      duo_core<MODE, K, CELL>(a.seqs_r + o0, a.seqs_r + o1, m0, m1, n, n, P, P, asz, alpha, beta, a.sat_limit,
+                              lane, bad, r0, r1, over0, over1);
       if (t == 0) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -536,29 +536,34 @@ int full_dp_i16_blocks_per_cu(int mode) {
   return nb;
 }
 
+template <int MODE>
+hipError_t launch_avsa_mode(const AllVsAllArgs &args, int grid, hipStream_t stream) {
+  if (args.half == kCellF16E5M2)
+    hipLaunchKernelGGL((all_vs_all_i16_kernel<MODE, kK16, kCellF16E5M2>), dim3(grid), dim3(kWave), 0, stream, args);
+  else if (args.half == kCellF16E4M3)
+    hipLaunchKernelGGL((all_vs_all_i16_kernel<MODE, kK16, kCellF16E4M3>), dim3(grid), dim3(kWave), 0, stream, args);
+  else
+    hipLaunchKernelGGL((all_vs_all_i16_kernel<MODE, kK16, kCellI16>), dim3(grid), dim3(kWave), 0, stream, args);
+  return hipGetLastError();
+}
+
 hipError_t launch_all_vs_all_i16(int mode, const AllVsAllArgs &args, int grid, hipStream_t stream) {
   switch (mode) {
-    case kGlobal:
-      hipLaunchKernelGGL((all_vs_all_i16_kernel<kGlobal, kK16>), dim3(grid), dim3(kWave), 0, stream, args);
-      break;
-    case kSemiGlobal:
-      hipLaunchKernelGGL((all_vs_all_i16_kernel<kSemiGlobal, kK16>), dim3(grid), dim3(kWave), 0, stream, args);
-      break;
-    default:
-      hipLaunchKernelGGL((all_vs_all_i16_kernel<kLocal, kK16>), dim3(grid), dim3(kWave), 0, stream, args);
+    case kGlobal: return launch_avsa_mode<kGlobal>(args, grid, stream);
+    case kSemiGlobal: return launch_avsa_mode<kSemiGlobal>(args, grid, stream);
+    default: return launch_avsa_mode<kLocal>(args, grid, stream);
   }
-  return hipGetLastError();
 }
 
 int all_vs_all_i16_blocks_per_cu(int mode) {
   int nb = 0;
   hipError_t e;
   if (mode == kGlobal)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, all_vs_all_i16_kernel<kGlobal, kK16>, kWave, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, all_vs_all_i16_kernel<kGlobal, kK16, kCellI16>, kWave, 0);
   else if (mode == kSemiGlobal)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, all_vs_all_i16_kernel<kSemiGlobal, kK16>, kWave, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, all_vs_all_i16_kernel<kSemiGlobal, kK16, kCellI16>, kWave, 0);
   else
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, all_vs_all_i16_kernel<kLocal, kK16>, kWave, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, all_vs_all_i16_kernel<kLocal, kK16, kCellI16>, kWave, 0);
   if (e != hipSuccess || nb < 1) nb = 1;
   return nb;
 }

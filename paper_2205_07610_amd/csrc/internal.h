@@ -592,6 +592,7 @@ struct AllVsAllArgs {
   int32_t *status;
   PairDesc *rerun;         // saturated local pairs for the 32-bit kernel
   int32_t *n_rerun;
+  int32_t half;            // cell type (kCellI16, or FP16 cells: values within +-2048)
 };
 hipError_t launch_all_vs_all_i16(int mode, const AllVsAllArgs &args, int grid, hipStream_t stream);
 int all_vs_all_i16_blocks_per_cu(int mode);

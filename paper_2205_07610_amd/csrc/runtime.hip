@@ -1146,6 +1146,7 @@ int run_full_lists(Workspace *w, const CallScoring &cs, const uint8_t *seqs_a,
   g_last_timing.cells_long16 = (int64_t)c2.route_cells[kListLong16];
   if (timing && c.n_long16 > 0) g_last_timing.long16_ms += elapsed(w->ev[14], w->ev[15]);
   g_last_timing.pairs_full32 += c.n_full32_pairs;
+  if (c.n_full32 > 0) g_last_timing.full32_variants |= c.kmask32;
   g_last_timing.pairs_full16 += c.n_full16;
   if (c.n_full16 > 0) g_last_timing.full16_cell_type = cs.half;
   g_last_timing.pairs_long += c.n_long;
@@ -1386,7 +1387,16 @@ extern "C" int as_align_all_vs_all(const uint8_t *seqs_q, const int64_t *offs_q,
     a.asz = cs.asz;
     a.alpha = cs.alpha;
     a.beta = cs.beta;
-    a.sat_limit = g_i16_limit;
+    // FP16 cells when the call admits them: local pairs check their maxima at
+    // run time; global and semi-global ones need the row bound of the packed
+    // kernel's routing for the longest row sequence
+    const int64_t rows_max = cols_s ? mq : ms;
+    a.half = cs.half;
+    if (cs.half && mode != kLocal &&
+        (int64_t)std::max(cs.smax, 0) * W16 + (int64_t)cs.beta * (rows_max + 2 * W16) + cs.alpha + 2 * cs.beta +
+                16 >= kHalfLimit)
+      a.half = kCellI16;
+    a.sat_limit = a.half ? packed_sat_limit(cs) : g_i16_limit;
     a.scores = scores_out;
     a.next = &w->ctr->next_full16;
     a.status = &w->ctr->status;
@@ -1403,6 +1413,7 @@ extern "C" int as_align_all_vs_all(const uint8_t *seqs_q, const int64_t *offs_q,
     g_last_timing.cells = 0;
     for (int64_t i = 0; i < n_q; ++i) g_last_timing.cells += (oq[i + 1] - oq[i]) * (os[n_s] - os[0]);
     g_last_timing.pairs_full16 = n_pairs - c.n_rerun32;
+    g_last_timing.full16_cell_type = a.half;
     g_last_timing.cells_full16 = g_last_timing.cells;
     if (timing) g_last_timing.full16_ms = elapsed(w->ev[2], w->ev[3]);
     if ((rc = status_to_code(c.status))) return rc;

@@ -143,3 +143,31 @@ def test_all_vs_all_errors(gpu):
     assert e.value.code == -3
     out = gpu.align_all_vs_all(seq, ok, seq, ok, DNA, 5, 2, 2)
     assert out.cpu().tolist() == [[10, 10], [10, 10]]
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_half_cells(gpu, oracle_mod, mode):
+    """FP16 cells in the all-against-all packed kernel (forced where the
+    scoring admits them): DNA scoring takes E4M3 profile bytes in global and
+    semi-global mode and E5M2 in local mode (rows of at most 200 residues
+    keep global and semi-global cells under the FP16 row bound); then local
+    with the re-run threshold lowered from the host."""
+    rng = np.random.default_rng(1150 + mode)
+    Q = _set(rng, 37, 0, 200)
+    S = _set(rng, 29, 0, 256, base=Q, related=0.5)
+    prev = gpu.set_half_cells(1)
+    prev_t = gpu.enable_timing(True)
+    try:
+        _check(gpu, oracle_mod, Q, S, DNA, 5, 2, mode, "half cells")
+        t = gpu.last_timing()
+        assert t["full16_cell_type"] == (2 if mode == 2 else 1), t["full16_cell_type"]
+        if mode == 2:
+            prev_l = gpu.set_i16_limit(60)
+            try:
+                _check(gpu, oracle_mod, Q, S, DNA, 5, 2, mode, "half cells, forced re-run")
+                assert gpu.last_timing()["pairs_full16"] < len(Q) * len(S)
+            finally:
+                gpu.set_i16_limit(prev_l)
+    finally:
+        gpu.enable_timing(prev_t)
+        gpu.set_half_cells(prev)
