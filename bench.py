@@ -256,34 +256,6 @@ def phase_roofline(phases, name, ops_per_cell):
     return r
 
 
-def own_label_cells(batch, labels, band_wide):
-    """DP cells if every pair were banded at its own label: the smallest
-    lane width holding the label's band, packed widths first where the
-    library would use them (global mode, range proof, at most 3/4 of the
-    row), else 32-bit widths (less than half the row), else the full DP."""
-    import numpy as np
-    la, lb = batch.lens_a.astype(np.int64), batch.lens_b.astype(np.int64)
-    rows, cols, dn = np.minimum(la, lb), np.maximum(la, lb), np.abs(la - lb)
-    need = dn + 2 * labels.astype(np.int64) + 1
-    smax_pos = max(int(batch.subst.max()), 0)
-    drop = max(0, -(int(batch.subst.min()) + 2 * batch.beta))
-    cells = la * lb
-    chosen = np.zeros(len(la), dtype=bool)
-    ok_label = labels < band_wide
-    if batch.mode == 0:
-        for W in (80, 96, 112, 128, 160, 192, 224, 256, 320, 384, 448, 512, 640, 768, 896, 1024, 1280, 1536):
-            ub = smax_pos * rows + batch.beta * (la + lb + W) + batch.alpha + 2 * batch.beta + 256
-            lo = drop * rows + 3 * (batch.alpha - batch.beta) + 256
-            ok = ok_label & ~chosen & (need <= W) & (4 * W <= 3 * cols) & (ub + lo < 65000) & (lo < 32000)
-            cells = np.where(ok, rows * W, cells)
-            chosen |= ok
-    for W in (64, 128, 192, 256, 384, 512, 768, 1024, 1280, 1536):
-        ok = ok_label & ~chosen & (need <= W) & (2 * W < cols)
-        cells = np.where(ok, rows * W, cells)
-        chosen |= ok
-    return int(cells.sum())
-
-
 def train_band_model(binding, torch, synth):
     """Labels and training on the training set; returns params and a summary."""
     t0 = time.perf_counter()
@@ -300,12 +272,15 @@ def train_band_model(binding, torch, synth):
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
     # diagnostics on the training set: DP cells of the learned path against
-    # the cells of each pair's own label (its smallest accepted band), both
-    # in the kernel's band widths
+    # those of the same certified path started from each pair's own label
+    # (its smallest accepted band), both as the library routes and counts them
     import numpy as np
-    labels = binding.band_labels(*dev, train.subst, train.alpha, train.beta, train.mode).cpu().numpy()
+    labels_t = binding.band_labels(*dev, train.subst, train.alpha, train.beta, train.mode)
+    labels = labels_t.cpu().numpy()
     _, st = binding.align_batch_learned(*dev, train.subst, train.alpha, train.beta, train.mode, params)
-    ideal = own_label_cells(train, labels, binding.BAND_WIDE)
+    _, st_own = binding.align_batch_band(*dev, train.subst, train.alpha, train.beta, train.mode,
+                                         labels_t.to(torch.int32))
+    ideal = st_own["dp_cells"]
     # the fixed-band comparison: the constant initial half-width that makes
     # the certified banded path fastest on the training set
     fixed = {}
@@ -332,13 +307,139 @@ def train_band_model(binding, torch, synth):
                     "fixed_w0_train_ms": fixed, "fixed_w0_best": best_w0}
 
 
+# The paper's evaluation shape (section 4.1): 3536 short reads aligned all
+# against all, global mode with linear gaps (+2/-1, every gap residue costs
+# 1), score only; and its traceback columns on pairs of the same reads.
+PAPER_WORKLOADS = {"avsa125": 125, "avsa512": 512, "tb125": 125, "tb512": 512}
+PAPER_READS = 3536
+PAPER_GCUPS = {"avsa125": {"MI100": 2909, "A100": 2459}, "avsa512": {"MI100": 3754, "A100": 3268}}
+
+
+def paper_workload(args, binding, torch, synth):
+    """All-against-all score-only batches of the paper's read shapes, or the
+    traceback of 2^20 (125 bp) / 2^17 (512 bp) pairs of the same reads."""
+    import numpy as np
+    L = PAPER_WORKLOADS[args.workload]
+    subst, alpha, beta, mode = synth.dna_subst(2, -1), 1, 1, 0
+    seqs, offs = synth.read_set(PAPER_READS, L, 1005 if L == 125 else 1006)
+    n = PAPER_READS
+    lens = np.diff(offs)
+    sq, oq = torch.from_numpy(seqs).cuda(), torch.from_numpy(offs).cuda()
+    traceback = args.workload.startswith("tb")
+    if traceback:
+        n_pairs = args.pairs or ((1 << 20) if L == 125 else (1 << 17))
+        rng = np.random.default_rng(1007)
+        qi, si = rng.integers(0, n, size=n_pairs), rng.integers(0, n, size=n_pairs)
+        batch = synth.from_pairs(f"tb{L}", [(seqs[offs[q]:offs[q + 1]], seqs[offs[t]:offs[t + 1]])
+                                            for q, t in zip(qi, si)], subst, alpha, beta, mode)
+        cells = batch.cells()
+        sa, oa, sb, ob = binding.to_device(batch)
+        desc = f"traceback of {n_pairs} pairs of {L} bp reads, global linear gaps (+2/-1, gap 1)"
+        res = {}
+
+        def step():
+            res["out"] = binding.align_batch_traceback(sa, oa, sb, ob, subst, alpha, beta, mode)
+    else:
+        n_pairs = n * n
+        cells = int(lens.sum()) ** 2
+        out = torch.empty((n, n), dtype=torch.int32, device="cuda")
+        desc = f"{n} reads of {L} bp all against all ({n_pairs} pairs), global linear gaps (+2/-1, gap 1)"
+
+        def step():
+            binding.align_all_vs_all(sq, oq, sq, oq, subst, alpha, beta, mode, scores_out=out)
+    log(f"{args.workload}: warmup {args.warmup}, {args.steps} steps")
+    ms, phases = timed(step, args.steps, args.warmup, binding, torch)
+    log(f"{args.workload}: {ms:.3f} ms/step")
+    names = ["full32_ms", "full16_ms", "rerun32_ms", "long_ms", "long16_ms", "classify_ms"]
+    avg = mean_phases(phases, names)
+    per_kernel = {k.replace("_ms", ""): phase_roofline(phases, k, OPS_PER_CELL[mode])
+                  for k in ("full32_ms", "full16_ms", "long_ms", "long16_ms") if avg[k] > 0}
+    result = {
+        "metric": METRIC,
+        "value": round(cells / (ms * 1e-3) / 1e9, 2),
+        "unit": "GCUPS",
+        "pairs_per_s": round(n_pairs / (ms * 1e-3), 1),
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "ms_per_step_decile_median": round(decile_median(phases), 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "data": "synthetic",
+        "config": {"workload": desc, "name": args.workload, "n_pairs": n_pairs, "cells": cells,
+                   "mode": "global", "method": "traceback" if traceback else "all against all"},
+        "phases_ms": {k: round(v, 4) for k, v in avg.items()},
+        "paper_gcups_context": PAPER_GCUPS.get(args.workload),
+    }
+    if traceback:
+        result["dtype"] = "i32"
+        result["roofline"] = None
+        result["roofline_note"] = ("one wave per pair, Myers-Miller split with 64-lane wavefront passes; "
+                                   "no per-kernel cell count is reported for it")
+    elif per_kernel:
+        dom = max(per_kernel, key=lambda k: per_kernel[k]["kernel_ms"])
+        result["roofline"] = per_kernel[dom]
+        result["roofline_per_kernel"] = per_kernel
+        cell_type = int(phases[-1].get("full16_cell_type", 0))
+        result["dtype"] = ("f16x2" if cell_type else "i16x2") if dom == "full16" else "i32"
+        if dom == "full16":
+            per_kernel["full16"]["cell_type"] = cell_type
+            if not args.no_cell_compare:
+                alt = {}
+                for hmode, label in ((0, "int16"), (1, "fp16_when_admissible")):
+                    prev_h = binding.set_half_cells(hmode)
+                    ms_h, ph_h = timed(step, args.steps, args.warmup, binding, torch)
+                    binding.set_half_cells(prev_h)
+                    alt[label] = {"ms_per_step": round(ms_h, 4),
+                                  "full16_ms": round(mean_phases(ph_h, ["full16_ms"])["full16_ms"], 4),
+                                  "cell_type": int(ph_h[-1]["full16_cell_type"])}
+                    log(f"cells {label}: {ms_h:.3f} ms/step")
+                per_kernel["full16"]["cell_types_compared"] = alt
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = oracle.default_threads()
+        rng = np.random.default_rng(12345)
+        if traceback:
+            sc, ops, span = (x.cpu().numpy() for x in res["out"])
+            k = min(n_pairs, 20000)
+            idx = np.sort(rng.choice(n_pairs, k, replace=False))
+            sub = batch.subset(idx)
+            t1 = time.perf_counter()
+            want = oracle.traceback_batch(sub.seqs_a, sub.offs_a, sub.seqs_b, sub.offs_b, subst, alpha, beta,
+                                          mode, threads)[0]
+            el = time.perf_counter() - t1
+            # every alignment of the sample is rescored from its columns
+            full_got = oracle.alignment_score_batch(batch.seqs_a, batch.offs_a, batch.seqs_b, batch.offs_b,
+                                                    subst, alpha, beta, mode, ops, span)
+            mism = int(np.count_nonzero(sc[idx].astype(np.int64) != want)) + \
+                int(np.count_nonzero(full_got[idx] != want))
+            sample = f"{k} random pairs of the batch, oracle traceback (GPU scores and alignments checked)"
+        else:
+            got = out.cpu().numpy()
+            k = 20000 if L == 125 else 4000
+            qi, si = rng.integers(0, n, size=k), rng.integers(0, n, size=k)
+            sub = synth.from_pairs("sample", [(seqs[offs[q]:offs[q + 1]], seqs[offs[t]:offs[t + 1]])
+                                              for q, t in zip(qi, si)], subst, alpha, beta, mode)
+            t1 = time.perf_counter()
+            want = oracle.align_batch(sub.seqs_a, sub.offs_a, sub.seqs_b, sub.offs_b, subst, alpha, beta, mode,
+                                      threads)
+            el = time.perf_counter() - t1
+            mism = int(np.count_nonzero(got[qi, si].astype(np.int64) != want))
+            sample = f"{k} random (query, subject) pairs of the matrix"
+        result["cpu_baseline"] = {"value": round(sub.cells() / el / 1e9, 4), "unit": "GCUPS", "cores": threads,
+                                  "kind": "oracle", "sample": f"{sample} ({sub.cells():.3e} cells, {el:.1f} s, "
+                                                              f"scalar int64 C, {threads} threads)"}
+        result["mismatches"] = {"checked_pairs": k, "mismatches": mism}
+    return result
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--pairs", type=int, default=None)
-    ap.add_argument("--workload", default="c4", help="c4 (default), c0, c1, c2, c3, c3long")
+    ap.add_argument("--workload", default="c4",
+                    help="c4 (default), c0, c1, c2, c3, c3long; the paper's shapes: avsa125, avsa512 "
+                         "(all against all), tb125, tb512 (traceback)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cell-compare", action="store_true",
@@ -374,6 +475,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.workload in PAPER_WORKLOADS:
+        print(json.dumps(paper_workload(args, binding, torch, synth)), flush=True)
+        return
     learned = args.workload == "c4"
     train_info = None
     if learned:

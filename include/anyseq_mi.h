@@ -530,7 +530,9 @@ int as_set_i16_limit(int32_t limit);
  *   mode 2 (default, any other value): FP16 cells for local calls whose
  *           profile values are exact in FP8 E5M2 (0..8, 10, 12, 14, 16) and
  *           whose maxima cannot reach 1984 (sigma_max*256 + alpha + 16 <
- *           1984), int16 otherwise.
+ *           1984), int16 otherwise; as_align_all_vs_all also takes them for
+ *           global and semi-global calls with E5M2-exact values whose
+ *           longest row sequence satisfies the bound above.
  * Applies to calls and plans made after it.  Returns the previous mode.
  */
 int as_set_half_cells(int mode);

@@ -48,6 +48,7 @@ namespace asmi {
 namespace {
 
 constexpr int kK16 = 16;
+constexpr int kK8 = 8;
 constexpr int kW16 = kGroup * kK16;
 constexpr short kNeg16 = -16384;
 
@@ -536,15 +537,22 @@ int full_dp_i16_blocks_per_cu(int mode) {
   return nb;
 }
 
+template <int MODE, int K>
+hipError_t launch_avsa_k(const AllVsAllArgs &args, int grid, hipStream_t stream) {
+  if (args.half == kCellF16E5M2)
+    hipLaunchKernelGGL((all_vs_all_i16_kernel<MODE, K, kCellF16E5M2>), dim3(grid), dim3(kWave), 0, stream, args);
+  else if (args.half == kCellF16E4M3)
+    hipLaunchKernelGGL((all_vs_all_i16_kernel<MODE, K, kCellF16E4M3>), dim3(grid), dim3(kWave), 0, stream, args);
+  else
+    hipLaunchKernelGGL((all_vs_all_i16_kernel<MODE, K, kCellI16>), dim3(grid), dim3(kWave), 0, stream, args);
+  return hipGetLastError();
+}
+
+// Column sequences of at most 128 residues take 128-column stripes (K = 8):
+// half the padding of the 256-column stripe for the paper's 125-bp reads.
 template <int MODE>
 hipError_t launch_avsa_mode(const AllVsAllArgs &args, int grid, hipStream_t stream) {
-  if (args.half == kCellF16E5M2)
-    hipLaunchKernelGGL((all_vs_all_i16_kernel<MODE, kK16, kCellF16E5M2>), dim3(grid), dim3(kWave), 0, stream, args);
-  else if (args.half == kCellF16E4M3)
-    hipLaunchKernelGGL((all_vs_all_i16_kernel<MODE, kK16, kCellF16E4M3>), dim3(grid), dim3(kWave), 0, stream, args);
-  else
-    hipLaunchKernelGGL((all_vs_all_i16_kernel<MODE, kK16, kCellI16>), dim3(grid), dim3(kWave), 0, stream, args);
-  return hipGetLastError();
+  return args.k8 ? launch_avsa_k<MODE, kK8>(args, grid, stream) : launch_avsa_k<MODE, kK16>(args, grid, stream);
 }
 
 hipError_t launch_all_vs_all_i16(int mode, const AllVsAllArgs &args, int grid, hipStream_t stream) {
@@ -555,18 +563,21 @@ hipError_t launch_all_vs_all_i16(int mode, const AllVsAllArgs &args, int grid, h
   }
 }
 
-int all_vs_all_i16_blocks_per_cu(int mode) {
+template <int K>
+int avsa_occupancy(int mode) {
   int nb = 0;
   hipError_t e;
   if (mode == kGlobal)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, all_vs_all_i16_kernel<kGlobal, kK16, kCellI16>, kWave, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, all_vs_all_i16_kernel<kGlobal, K, kCellI16>, kWave, 0);
   else if (mode == kSemiGlobal)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, all_vs_all_i16_kernel<kSemiGlobal, kK16, kCellI16>, kWave, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, all_vs_all_i16_kernel<kSemiGlobal, K, kCellI16>, kWave, 0);
   else
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, all_vs_all_i16_kernel<kLocal, kK16, kCellI16>, kWave, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, all_vs_all_i16_kernel<kLocal, K, kCellI16>, kWave, 0);
   if (e != hipSuccess || nb < 1) nb = 1;
   return nb;
 }
+
+int all_vs_all_i16_blocks_per_cu(int mode, bool k8) { return k8 ? avsa_occupancy<kK8>(mode) : avsa_occupancy<kK16>(mode); }
 
 hipError_t launch_full_dp_i16(int mode, const FullDp16Args &args, int grid, hipStream_t stream) {
   switch (mode) {

@@ -593,9 +593,10 @@ struct AllVsAllArgs {
   PairDesc *rerun;         // saturated local pairs for the 32-bit kernel
   int32_t *n_rerun;
   int32_t half;            // cell type (kCellI16, or FP16 cells: values within +-2048)
+  int32_t k8;              // columns of at most 128 residues: 128-column stripes
 };
 hipError_t launch_all_vs_all_i16(int mode, const AllVsAllArgs &args, int grid, hipStream_t stream);
-int all_vs_all_i16_blocks_per_cu(int mode);
+int all_vs_all_i16_blocks_per_cu(int mode, bool k8);
 int full_dp_i16_blocks_per_cu(int mode);
 int full_dp_i16_stripe_width();
 

@@ -890,7 +890,8 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
 
 struct CallScoring {
   int asz, alpha, beta, mode, smin, smax, smax_abs, allow16;
-  int half;   // the packed kernel runs FP16 cells for this call
+  int half;       // the packed kernel runs FP16 cells for this call
+  int half_adm;   // the FP16 cell type the scoring admits (kCellI16: none)
 };
 
 // Host-side checks of the scoring scheme; fills cs.
@@ -931,7 +932,8 @@ int check_scoring(const as_scoring *scoring, int32_t mode, CallScoring *cs) {
   const int smax_pos = smax > 0 ? smax : 0;
   const bool want = g_half_cells == 1 ||
                     (g_half_cells == 2 && mode == kLocal && e5 && smax_pos * 256 + alpha + 16 < kHalfLimit);
-  cs->half = (want && h_ok) ? (e5 ? kCellF16E5M2 : kCellF16E4M3) : kCellI16;
+  cs->half_adm = h_ok ? (e5 ? kCellF16E5M2 : kCellF16E4M3) : kCellI16;
+  cs->half = want ? cs->half_adm : kCellI16;
   return AS_OK;
 }
 
@@ -1143,16 +1145,16 @@ int run_full_lists(Workspace *w, const CallScoring &cs, const uint8_t *seqs_a,
   Counters c2;
   if ((rc = read_counters(w, stream, &c2))) return rc;
   g_last_timing.pairs_long16 += c.n_long16;
-  g_last_timing.cells_long16 = (int64_t)c2.route_cells[kListLong16];
+  g_last_timing.cells_long16 += (int64_t)c2.route_cells[kListLong16];
   if (timing && c.n_long16 > 0) g_last_timing.long16_ms += elapsed(w->ev[14], w->ev[15]);
   g_last_timing.pairs_full32 += c.n_full32_pairs;
   if (c.n_full32 > 0) g_last_timing.full32_variants |= c.kmask32;
   g_last_timing.pairs_full16 += c.n_full16;
   if (c.n_full16 > 0) g_last_timing.full16_cell_type = cs.half;
   g_last_timing.pairs_long += c.n_long;
-  g_last_timing.cells_full32 = (int64_t)c2.route_cells[kList32];
-  g_last_timing.cells_full16 = (int64_t)c2.route_cells[kList16];
-  g_last_timing.cells_long = (int64_t)c2.route_cells[kListLong];
+  g_last_timing.cells_full32 += (int64_t)c2.route_cells[kList32];
+  g_last_timing.cells_full16 += (int64_t)c2.route_cells[kList16];
+  g_last_timing.cells_long += (int64_t)c2.route_cells[kListLong];
   if (timing && c.n_full16 > 0) g_last_timing.full16_ms += elapsed(w->ev[2], w->ev[3]);
   if (timing && c.n_full32 > 0) g_last_timing.full32_ms += elapsed(w->ev[4], w->ev[5]);
   if (timing && c.n_long > 0) g_last_timing.long_ms += elapsed(w->ev[8], w->ev[9]);
@@ -1373,7 +1375,8 @@ extern "C" int as_align_all_vs_all(const uint8_t *seqs_q, const int64_t *offs_q,
     a.n_rows = (int32_t)(cols_s ? n_q : n_s);
     a.n_cols = (int32_t)(cols_s ? n_s : n_q);
     a.ld = n_s;
-    int64_t grid = (int64_t)all_vs_all_i16_blocks_per_cu(mode) * w->num_cu;
+    a.k8 = (cols_s ? ms : mq) <= W16 / 2 ? 1 : 0;
+    int64_t grid = (int64_t)all_vs_all_i16_blocks_per_cu(mode, a.k8 != 0) * w->num_cu;
     // about eight work items (column, block of rows) per resident wave
     int64_t n_blocks = (8 * grid + a.n_cols - 1) / a.n_cols;
     n_blocks = std::max<int64_t>(1, std::min<int64_t>(n_blocks, (a.n_rows + 7) / 8));
@@ -1389,9 +1392,13 @@ extern "C" int as_align_all_vs_all(const uint8_t *seqs_q, const int64_t *offs_q,
     a.beta = cs.beta;
     // FP16 cells when the call admits them: local pairs check their maxima at
     // run time; global and semi-global ones need the row bound of the packed
-    // kernel's routing for the longest row sequence
+    // kernel's routing for the longest row sequence.  Every pair of the call
+    // shares that bound, so the automatic choice also takes FP16 cells for
+    // global and semi-global calls with E5M2-exact scores (no pair is sent
+    // elsewhere by it).
     const int64_t rows_max = cols_s ? mq : ms;
     a.half = cs.half;
+    if (a.half == kCellI16 && g_half_cells == 2 && cs.half_adm == kCellF16E5M2 && mode != kLocal) a.half = kCellF16E5M2;
     if (cs.half && mode != kLocal &&
         (int64_t)std::max(cs.smax, 0) * W16 + (int64_t)cs.beta * (rows_max + 2 * W16) + cs.alpha + 2 * cs.beta +
                 16 >= kHalfLimit)
@@ -1468,7 +1475,7 @@ extern "C" int as_align_all_vs_all(const uint8_t *seqs_q, const int64_t *offs_q,
     if ((rc = launch_classify(w, rp, nullptr, nullptr, w->fallback, c.n_fallback, scores_out, stream))) return rc;
     if ((rc = read_counters(w, stream, &c))) return rc;
     if ((rc = status_to_code(c.status))) return rc;
-    if ((rc = run_full_lists(w, cs, seqs_q, seqs_s, scores_out, stream, false, c))) return rc;
+    if ((rc = run_full_lists(w, cs, seqs_q, seqs_s, scores_out, stream, g_timing, c))) return rc;
   }
   return AS_OK;
 }

@@ -329,6 +329,21 @@ def config4_training(n_pairs: int = 200_000, seed: int = 2004) -> Batch:
     return b
 
 
+def read_set(n_reads: int, length: int, seed: int) -> tuple[np.ndarray, np.ndarray]:
+    """n_reads DNA reads of `length` residues (CSR), drawn at uniform
+    positions of a seeded uniform random genome of 2^24 residues, with 0.5%
+    substitution errors: a stand-in for the paper's simulated short reads of
+    one chromosome aligned all against all (section 4.1), which are not
+    available here."""
+    rng = np.random.default_rng(seed)
+    genome = rng.integers(0, 4, size=1 << 24, dtype=np.uint8)
+    starts = rng.integers(0, len(genome) - length + 1, size=n_reads)
+    seqs = genome[starts[:, None] + np.arange(length)[None, :]].reshape(-1)
+    offs = np.arange(n_reads + 1, dtype=np.int64) * length
+    seqs, offs = mutate(rng, seqs, offs, 0.005, 0.0, 0.0, 4)
+    return seqs.astype(np.uint8), offs
+
+
 def random_small(rng: np.random.Generator, n_pairs: int, max_len: int, asz: int = 4,
                  related: float = 0.5) -> tuple[np.ndarray, np.ndarray, np.ndarray, np.ndarray]:
     """Mixed small pairs for edge-case tests: lengths U[0, max_len], about

@@ -171,3 +171,24 @@ def test_half_cells(gpu, oracle_mod, mode):
     finally:
         gpu.enable_timing(prev_t)
         gpu.set_half_cells(prev)
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_short_columns_128(gpu, oracle_mod, mode):
+    """Column sequences of at most 128 residues take 128-column stripes:
+    subjects of 0..128 against queries of any length (int16 and FP16
+    cells), and the transposed case with queries of 1..128 against long
+    subjects."""
+    rng = np.random.default_rng(1160 + mode)
+    Q = _set(rng, 35, 0, 300)
+    S = _set(rng, 31, 0, 128, base=Q, related=0.4)
+    S[4] = np.zeros(0, np.uint8)
+    _check(gpu, oracle_mod, Q, S, DNA, 5, 2, mode, "columns <= 128")
+    prev = gpu.set_half_cells(1)
+    try:
+        _check(gpu, oracle_mod, Q[:20], S, synth.dna_subst(1, -1), 3, 1, mode, "columns <= 128, FP16")
+    finally:
+        gpu.set_half_cells(prev)
+    Q2 = _set(rng, 19, 1, 128)
+    S2 = _set(rng, 13, 300, 900, base=Q2, related=0.3)
+    _check(gpu, oracle_mod, Q2, S2, DNA, 5, 2, mode, "queries <= 128 transposed")
