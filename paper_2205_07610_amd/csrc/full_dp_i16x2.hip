@@ -49,6 +49,7 @@ namespace {
 
 constexpr int kK16 = 16;
 constexpr int kK8 = 8;
+constexpr int kK32 = 32;
 constexpr int kW16 = kGroup * kK16;
 constexpr short kNeg16 = -16384;
 
@@ -497,7 +498,7 @@ __global__ void __launch_bounds__(kWave) all_vs_all_i16_kernel(AllVsAllArgs a) {
             d.m = m;
             d.n = n;
             d.pair = (int32_t)idx;
-            d.flags = with_variant(a.tr ? kTransposed : 0, kVarI32K16);
+            d.flags = with_variant(a.tr ? kTransposed : 0, K > 16 ? kVarI32K32 : kVarI32K16);
             a.rerun[atomicAdd(a.n_rerun, 1)] = d;
             continue;
           }
@@ -549,10 +550,13 @@ hipError_t launch_avsa_k(const AllVsAllArgs &args, int grid, hipStream_t stream)
 }
 
 // Column sequences of at most 128 residues take 128-column stripes (K = 8):
-// half the padding of the 256-column stripe for the paper's 125-bp reads.
+// half the padding of the 256-column stripe for the paper's 125-bp reads;
+// columns of 257..512 residues take 512-column stripes (K = 32).
 template <int MODE>
 hipError_t launch_avsa_mode(const AllVsAllArgs &args, int grid, hipStream_t stream) {
-  return args.k8 ? launch_avsa_k<MODE, kK8>(args, grid, stream) : launch_avsa_k<MODE, kK16>(args, grid, stream);
+  if (args.kcols == 8) return launch_avsa_k<MODE, kK8>(args, grid, stream);
+  if (args.kcols == 32) return launch_avsa_k<MODE, kK32>(args, grid, stream);
+  return launch_avsa_k<MODE, kK16>(args, grid, stream);
 }
 
 hipError_t launch_all_vs_all_i16(int mode, const AllVsAllArgs &args, int grid, hipStream_t stream) {
@@ -577,7 +581,9 @@ int avsa_occupancy(int mode) {
   return nb;
 }
 
-int all_vs_all_i16_blocks_per_cu(int mode, bool k8) { return k8 ? avsa_occupancy<kK8>(mode) : avsa_occupancy<kK16>(mode); }
+int all_vs_all_i16_blocks_per_cu(int mode, int kcols) {
+  return kcols == 8 ? avsa_occupancy<kK8>(mode) : (kcols == 32 ? avsa_occupancy<kK32>(mode) : avsa_occupancy<kK16>(mode));
+}
 
 hipError_t launch_full_dp_i16(int mode, const FullDp16Args &args, int grid, hipStream_t stream) {
   switch (mode) {

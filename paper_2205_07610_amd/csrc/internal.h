@@ -593,10 +593,12 @@ struct AllVsAllArgs {
   PairDesc *rerun;         // saturated local pairs for the 32-bit kernel
   int32_t *n_rerun;
   int32_t half;            // cell type (kCellI16, or FP16 cells: values within +-2048)
-  int32_t k8;              // columns of at most 128 residues: 128-column stripes
+  int32_t kcols;           // columns per lane: 8, 16 or 32 (stripes of 128, 256 or 512 columns)
 };
+// Longest column sequence the all-against-all packed kernel takes.
+constexpr int kAvsaMaxCols = 512;
 hipError_t launch_all_vs_all_i16(int mode, const AllVsAllArgs &args, int grid, hipStream_t stream);
-int all_vs_all_i16_blocks_per_cu(int mode, bool k8);
+int all_vs_all_i16_blocks_per_cu(int mode, int kcols);
 int full_dp_i16_blocks_per_cu(int mode);
 int full_dp_i16_stripe_width();
 

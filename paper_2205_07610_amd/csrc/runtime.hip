@@ -1355,14 +1355,23 @@ extern "C" int as_align_all_vs_all(const uint8_t *seqs_q, const int64_t *offs_q,
   if ((rc = get_workspace(&w))) return rc;
   memset(&g_last_timing, 0, sizeof(g_last_timing));
   AS_HIP(hipMemcpyAsync(w->subst, scoring->subst, (size_t)cs.asz * cs.asz, hipMemcpyHostToDevice, stream));
-  const int W16 = full_dp_i16_stripe_width();
-  // the packed kernel with the column profile reused across rows: columns
-  // from the set whose sequences fit one packed stripe
-  const bool cols_s = ms <= W16, cols_q = !cols_s && mq <= W16;
+  // the packed kernel with the column profile reused across rows: the
+  // columns from a set whose longest sequence fits a packed stripe of 128,
+  // 256 or 512 columns (K = 8, 16, 32 per lane), the one with fewer steps
+  // (columns x stripe width x the other set's rows + 15 per sequence)
+  const auto stripe_w = [](int64_t L) -> double { return L <= 128 ? 128.0 : (L <= 256 ? 256.0 : 512.0); };
+  const double rows_q = (double)(oq[n_q] - oq[0]) + 15.0 * n_q, rows_s = (double)(os[n_s] - os[0]) + 15.0 * n_s;
+  const double cost_s = ms <= kAvsaMaxCols ? (double)n_s * stripe_w(ms) * rows_q : 1e300;
+  const double cost_q = mq <= kAvsaMaxCols ? (double)n_q * stripe_w(mq) * rows_s : 1e300;
+  const bool cols_s = ms <= kAvsaMaxCols && cost_s <= cost_q;
+  const bool cols_q = !cols_s && mq <= kAvsaMaxCols;
+  const int64_t col_max = cols_s ? ms : mq;
+  const int kcols = col_max <= 128 ? 8 : (col_max <= 256 ? 16 : 32);
+  const int Wc = kGroup * kcols;
   bool fast = cs.allow16 && (cols_s || cols_q);
   if (fast && mode != kLocal) {
-    const int64_t ub = (int64_t)std::max(cs.smax, 0) * std::min(mq, ms) + (int64_t)cs.beta * (mq + ms) + (int64_t)cs.beta * W16 +
-                       cs.alpha + 2 * cs.beta + 256;
+    const int64_t ub = (int64_t)std::max(cs.smax, 0) * std::min(mq, ms) + (int64_t)cs.beta * (mq + ms) +
+                       (int64_t)cs.beta * Wc + cs.alpha + 2 * cs.beta + 256;
     fast = ub < 32000;
   }
   if (fast) {
@@ -1375,8 +1384,8 @@ extern "C" int as_align_all_vs_all(const uint8_t *seqs_q, const int64_t *offs_q,
     a.n_rows = (int32_t)(cols_s ? n_q : n_s);
     a.n_cols = (int32_t)(cols_s ? n_s : n_q);
     a.ld = n_s;
-    a.k8 = (cols_s ? ms : mq) <= W16 / 2 ? 1 : 0;
-    int64_t grid = (int64_t)all_vs_all_i16_blocks_per_cu(mode, a.k8 != 0) * w->num_cu;
+    a.kcols = kcols;
+    int64_t grid = (int64_t)all_vs_all_i16_blocks_per_cu(mode, kcols) * w->num_cu;
     // about eight work items (column, block of rows) per resident wave
     int64_t n_blocks = (8 * grid + a.n_cols - 1) / a.n_cols;
     n_blocks = std::max<int64_t>(1, std::min<int64_t>(n_blocks, (a.n_rows + 7) / 8));
@@ -1399,9 +1408,9 @@ extern "C" int as_align_all_vs_all(const uint8_t *seqs_q, const int64_t *offs_q,
     const int64_t rows_max = cols_s ? mq : ms;
     a.half = cs.half;
     if (a.half == kCellI16 && g_half_cells == 2 && cs.half_adm == kCellF16E5M2 && mode != kLocal) a.half = kCellF16E5M2;
-    if (cs.half && mode != kLocal &&
-        (int64_t)std::max(cs.smax, 0) * W16 + (int64_t)cs.beta * (rows_max + 2 * W16) + cs.alpha + 2 * cs.beta +
-                16 >= kHalfLimit)
+    if (a.half != kCellI16 && mode != kLocal &&
+        (int64_t)std::max(cs.smax, 0) * Wc + (int64_t)cs.beta * (rows_max + 2 * Wc) + cs.alpha + 2 * cs.beta + 16 >=
+            kHalfLimit)
       a.half = kCellI16;
     a.sat_limit = a.half ? packed_sat_limit(cs) : g_i16_limit;
     a.scores = scores_out;
@@ -1438,7 +1447,9 @@ extern "C" int as_align_all_vs_all(const uint8_t *seqs_q, const int64_t *offs_q,
       args.rerun = nullptr;   // the re-run list holds 32-bit items only
       args.n_rerun = nullptr;
       args.sat_limit = 0;
-      const int bpc = full_dp_i32_blocks_per_cu(mode, cs.asz, kmask_of_variant(kVarI32K16));
+      // re-run items are single-stripe: 256 columns, or 512 for the widest packed stripes
+      const int rv = kcols == 32 ? kVarI32K32 : kVarI32K16;
+      const int bpc = full_dp_i32_blocks_per_cu(mode, cs.asz, kmask_of_variant(rv));
       int64_t g2 = (int64_t)bpc * w->num_cu;
       const int64_t need_waves = ((int64_t)c.n_rerun32 + kGroupsPerWave - 1) / kGroupsPerWave;
       if (g2 > need_waves) g2 = need_waves;
@@ -1448,7 +1459,7 @@ extern "C" int as_align_all_vs_all(const uint8_t *seqs_q, const int64_t *offs_q,
       args.next = &w->ctr->next_rerun32;
       args.bnd = w->bnd;
       args.bnd_rows = 1;
-      AS_HIP(launch_full_dp_i32(mode, args, kmask_of_variant(kVarI32K16), (int)g2, stream));
+      AS_HIP(launch_full_dp_i32(mode, args, kmask_of_variant(rv), (int)g2, stream));
       Counters c3;
       if ((rc = read_counters(w, stream, &c3))) return rc;
       if ((rc = status_to_code(c3.status))) return rc;

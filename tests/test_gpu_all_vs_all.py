@@ -192,3 +192,23 @@ def test_short_columns_128(gpu, oracle_mod, mode):
     Q2 = _set(rng, 19, 1, 128)
     S2 = _set(rng, 13, 300, 900, base=Q2, related=0.3)
     _check(gpu, oracle_mod, Q2, S2, DNA, 5, 2, mode, "queries <= 128 transposed")
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_columns_512(gpu, oracle_mod, mode):
+    """The shorter set's sequences of 257..512 residues take 512-column
+    stripes (K = 32), either set as columns; local pairs forced to the
+    32-bit re-run keep their 512 columns in one stripe."""
+    rng = np.random.default_rng(1170 + mode)
+    Q = _set(rng, 23, 300, 700)
+    S = _set(rng, 17, 257, 512, base=Q, related=0.5)
+    _check(gpu, oracle_mod, Q, S, DNA, 5, 2, mode, "columns <= 512")
+    Q2 = _set(rng, 15, 100, 512)
+    S2 = _set(rng, 21, 513, 800, base=Q2, related=0.3)
+    _check(gpu, oracle_mod, Q2, S2, DNA, 5, 2, mode, "queries as columns")
+    if mode == 2:
+        prev = gpu.set_i16_limit(60)
+        try:
+            _check(gpu, oracle_mod, Q, S, DNA, 5, 2, mode, "columns <= 512, forced re-run")
+        finally:
+            gpu.set_i16_limit(prev)
