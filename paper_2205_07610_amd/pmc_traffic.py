@@ -41,7 +41,9 @@ GROUPS = {
                "paper_2205_07610_amd/csrc/long_dp_i16x2.hip", "largest"),
     "full32": (lambda k: k.startswith("full_dp_i32_kernel"),
                "paper_2205_07610_amd/csrc/full_dp_i32.hip", "largest"),
-    "full16": (lambda k: k.startswith("full_dp_i16_kernel"),
+    # the packed kernel, or its all-against-all form (the same source and
+    # timing phase; a workload runs one of them)
+    "full16": (lambda k: k.startswith("full_dp_i16_kernel") or k.startswith("all_vs_all_i16_kernel"),
                "paper_2205_07610_amd/csrc/full_dp_i16x2.hip", "largest"),
 }
 
@@ -96,26 +98,32 @@ def summarise(fetch_dir, write_dir, workload_name, workload_desc):
     # wavefront launch of the run, 32-bit or packed; earlier launches belong
     # to training and its diagnostics) and ends before the next call's band
     # classification (the step itself classifies once).
-    long_rows = rows_of(F, GROUPS["long"][0]) + rows_of(F, GROUPS["long16"][0])
-    after = max(long_rows, key=lambda x: x[1])[0] if long_rows else -1
-    feats = [d for d, _ in rows_of(F, GROUPS["features"][0]) if d > after]
-    start = feats[0] if feats else after + 1
-    classify = [d for d, _ in rows_of(F, lambda k: k.startswith("band_classify_kernel")) if d > start]
-    end = classify[1] if len(classify) > 1 else float("inf")
+    def step_window(R):
+        long_rows = rows_of(R, GROUPS["long"][0]) + rows_of(R, GROUPS["long16"][0])
+        after = max(long_rows, key=lambda x: x[1])[0] if long_rows else -1
+        feats = [d for d, _ in rows_of(R, GROUPS["features"][0]) if d > after]
+        start = feats[0] if feats else after + 1
+        classify = [d for d, _ in rows_of(R, lambda k: k.startswith("band_classify_kernel")) if d > start]
+        return start, (classify[1] if len(classify) > 1 else float("inf"))
+
+    # each pass's own window (launches after the learned step, such as the
+    # fixed-band comparison chosen by timing, may differ between the passes)
+    win_f, win_w = step_window(F), step_window(W)
     out = {}
     for g, (pred, src, unit) in GROUPS.items():
         fr, wr = rows_of(F, pred), rows_of(W, pred)
-        if not fr or len(fr) != len(wr):
+        if not fr or not wr:
             continue
         if unit == "largest":   # the full-DP step's launch is the largest of the run
             i = max(range(len(fr)), key=lambda k: fr[k][1])
-            fr, wr = [fr[i]], [wr[i]]
+            j = max(range(len(wr)), key=lambda k: wr[k][1])
+            fr, wr = [fr[i]], [wr[j]]
             note = "unit: the full-DP step's launch (largest of the run)"
         else:
-            fr = [x for x in fr if start <= x[0] < end]
-            wr = [x for x in wr if start <= x[0] < end]
+            fr = [x for x in fr if win_f[0] <= x[0] < win_f[1]]
+            wr = [x for x in wr if win_w[0] <= x[0] < win_w[1]]
             note = "unit: all launches of the one timed learned step (every class and round)"
-        if not fr:
+        if not fr or len(fr) != len(wr):
             continue
         n = len(fr)
         fb = sum(x[1] for x in fr) * 1024 * sf
