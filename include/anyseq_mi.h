@@ -456,6 +456,22 @@ int as_set_variants(int32_t mode, const int8_t *table);
 int as_get_variants(int32_t mode, int8_t *table_out);
 
 /*
+ * Persisted tables (the batching runtime's autotuner output, not in the
+ * paper): the three modes' tables as one versioned, checksummed blob of
+ * as_variant_tables_blob_size() bytes (64), host memory owned by the
+ * caller.  Layout (little-endian): char magic[8] = "ASVARTAB"; uint32
+ * version = 1, n_modes = 3, n_bins = AS_LEN_BINS, n_variants = AS_VARIANTS;
+ * int8 table[3][AS_LEN_BINS]; uint32 FNV-1a checksum of the 64 bytes with
+ * this field zero.  Save: AS_ERR_NULL, or AS_ERR_ARG when blob_size is too
+ * small.  Load: a wrong size, magic, version, dimension, checksum or entry
+ * returns AS_ERR_ARG and leaves every table as it was; otherwise all three
+ * tables are replaced.
+ */
+int64_t as_variant_tables_blob_size(void);
+int as_variant_tables_save(uint8_t *blob_out, int64_t blob_size);
+int as_variant_tables_load(const uint8_t *blob, int64_t blob_size);
+
+/*
  * Autotuner: for every length bin present in the batch, time each variant
  * on a sample of the bin's pairs (every stride-th pair: at most sample_pairs
  * pairs and about 1e11 cells; best of two runs, HIP events around the DP

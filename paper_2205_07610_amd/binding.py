@@ -141,6 +141,12 @@ def lib() -> ctypes.CDLL:
     L.as_set_i16_limit.argtypes = [ctypes.c_int32]
     L.as_set_half_cells.restype = ctypes.c_int
     L.as_set_half_cells.argtypes = [ctypes.c_int]
+    L.as_variant_tables_blob_size.restype = i64
+    L.as_variant_tables_blob_size.argtypes = []
+    L.as_variant_tables_save.restype = ctypes.c_int
+    L.as_variant_tables_save.argtypes = [p, i64]
+    L.as_variant_tables_load.restype = ctypes.c_int
+    L.as_variant_tables_load.argtypes = [p, i64]
     L.as_enable_timing.restype = ctypes.c_int
     L.as_enable_timing.argtypes = [ctypes.c_int]
     L.as_last_timing.restype = ctypes.c_int
@@ -552,6 +558,20 @@ def get_variants(mode: int) -> np.ndarray:
     t = np.zeros(LEN_BINS, dtype=np.int8)
     _check(lib().as_get_variants(int(mode), t.ctypes.data_as(ctypes.c_void_p)))
     return t
+
+
+def variant_tables_save() -> bytes:
+    """The three modes' variant tables as a versioned blob (for a file)."""
+    n = int(lib().as_variant_tables_blob_size())
+    buf = ctypes.create_string_buffer(n)
+    _check(lib().as_variant_tables_save(ctypes.cast(buf, ctypes.c_void_p), n))
+    return buf.raw
+
+
+def variant_tables_load(blob: bytes):
+    """Replace the three modes' variant tables from a saved blob."""
+    buf = ctypes.create_string_buffer(bytes(blob), len(blob))
+    _check(lib().as_variant_tables_load(ctypes.cast(buf, ctypes.c_void_p), len(blob)))
 
 
 def autotune(seqs_a, offs_a, seqs_b, offs_b, subst, alpha: int, beta: int, mode: int,

@@ -15,7 +15,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libanyseq_mi.so")
 SOURCES = ["runtime.hip", "full_dp_i32.hip", "full_dp_i16x2.hip", "long_dp_i32.hip", "long_dp_i16x2.hip",
            "band_dp_i32.hip", "band_dp_i16x2.hip", "features.hip", "mlp_bf16.hip", "learned.hip",
-           "traceback.hip"]
+           "traceback.hip", "tables.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -1,0 +1,90 @@
+// Persisted variant tables (the autotuner's result, section 11 of the
+// batching runtime; not in the paper): the three modes' per-length-bin
+// full-DP variants as one versioned, checksummed blob, so that a table tuned
+// once can be loaded by later processes instead of tuning again.
+//
+// Layout (little-endian), 64 bytes:
+//   char magic[8] = "ASVARTAB"; uint32 version = 1; uint32 n_modes = 3;
+//   uint32 n_bins = 12; uint32 n_variants = 6; int8 table[3][12];
+//   uint32 checksum (FNV-1a 32 of bytes 0..59 with the checksum field zero).
+// The tables are read and written through as_get_variants /
+// as_set_variants, so a loaded blob is validated exactly like a table set
+// directly.
+#include <string.h>
+
+#include "internal.h"
+
+namespace {
+
+constexpr int64_t kTabBlob = 64;
+constexpr int kTabModes = 3;
+constexpr uint32_t kTabVersion = 1;
+constexpr int kTabTableOff = 24;
+constexpr int kTabSumOff = kTabTableOff + kTabModes * asmi::kLenBins;  // 60
+
+uint32_t tab_fnv1a(const uint8_t *p, int64_t n) {
+  uint32_t h = 2166136261u;
+  for (int64_t i = 0; i < n; ++i) {
+    h ^= p[i];
+    h *= 16777619u;
+  }
+  return h;
+}
+
+void put_u32(uint8_t *p, uint32_t v) {
+  for (int i = 0; i < 4; ++i) p[i] = (uint8_t)(v >> (8 * i));
+}
+uint32_t get_u32(const uint8_t *p) {
+  uint32_t v = 0;
+  for (int i = 0; i < 4; ++i) v |= (uint32_t)p[i] << (8 * i);
+  return v;
+}
+
+}  // namespace
+
+static_assert(kTabSumOff + 4 == kTabBlob, "variant table blob layout");
+
+extern "C" int64_t as_variant_tables_blob_size(void) { return kTabBlob; }
+
+extern "C" int as_variant_tables_save(uint8_t *blob_out, int64_t blob_size) {
+  if (!blob_out) return AS_ERR_NULL;
+  if (blob_size < kTabBlob) return AS_ERR_ARG;
+  uint8_t b[kTabBlob];
+  memset(b, 0, sizeof(b));
+  memcpy(b, "ASVARTAB", 8);
+  put_u32(b + 8, kTabVersion);
+  put_u32(b + 12, kTabModes);
+  put_u32(b + 16, asmi::kLenBins);
+  put_u32(b + 20, asmi::kNumVariants);
+  for (int mode = 0; mode < kTabModes; ++mode) {
+    const int rc = as_get_variants(mode, (int8_t *)(b + kTabTableOff + mode * asmi::kLenBins));
+    if (rc) return rc;
+  }
+  put_u32(b + kTabSumOff, tab_fnv1a(b, kTabBlob));
+  memcpy(blob_out, b, sizeof(b));
+  return AS_OK;
+}
+
+extern "C" int as_variant_tables_load(const uint8_t *blob, int64_t blob_size) {
+  if (!blob) return AS_ERR_NULL;
+  if (blob_size != kTabBlob) return AS_ERR_ARG;
+  uint8_t b[kTabBlob];
+  memcpy(b, blob, sizeof(b));
+  if (memcmp(b, "ASVARTAB", 8) != 0 || get_u32(b + 8) != kTabVersion || get_u32(b + 12) != kTabModes ||
+      get_u32(b + 16) != (uint32_t)asmi::kLenBins || get_u32(b + 20) != (uint32_t)asmi::kNumVariants)
+    return AS_ERR_ARG;
+  const uint32_t sum = get_u32(b + kTabSumOff);
+  put_u32(b + kTabSumOff, 0);
+  if (tab_fnv1a(b, kTabBlob) != sum) return AS_ERR_ARG;
+  // every table is checked before any is set, so a bad blob changes nothing
+  for (int mode = 0; mode < kTabModes; ++mode)
+    for (int k = 0; k < asmi::kLenBins; ++k) {
+      const int v = (int8_t)b[kTabTableOff + mode * asmi::kLenBins + k];
+      if (v < -1 || v >= asmi::kNumVariants) return AS_ERR_ARG;
+    }
+  for (int mode = 0; mode < kTabModes; ++mode) {
+    const int rc = as_set_variants(mode, (const int8_t *)(b + kTabTableOff + mode * asmi::kLenBins));
+    if (rc) return rc;
+  }
+  return AS_OK;
+}

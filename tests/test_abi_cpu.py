@@ -99,3 +99,45 @@ def test_struct_layouts_match_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for field, _ in py._fields_:
             assert got[(cname, field)] == getattr(py, field).offset, (cname, field)
+
+
+def test_variant_tables_blob_round_trip(L):
+    """The persisted variant tables: a saved blob restores all three modes'
+    tables; a damaged, truncated or out-of-range blob is refused and leaves
+    the tables as they were.  Host-only (no device work)."""
+    prev = [binding.get_variants(m) for m in range(3)]
+    try:
+        tabs = [np.array([0, 1, 2, 3, 4, 5, -1, -1, 2, 2, 4, 4], np.int8),
+                np.array([-1] * 12, np.int8),
+                np.array([5, 5, 3, 3, 2, 2, 1, 1, 0, 4, 4, -1], np.int8)]
+        for m, t in enumerate(tabs):
+            binding.set_variants(m, t)
+        blob = binding.variant_tables_save()
+        assert len(blob) == 64 and blob[:8] == b"ASVARTAB"
+        for m in range(3):
+            binding.set_variants(m, None)
+        binding.variant_tables_load(blob)
+        for m, t in enumerate(tabs):
+            assert np.array_equal(binding.get_variants(m), t)
+        for m in range(3):
+            binding.set_variants(m, None)
+        bad_sum = bytearray(blob)
+        bad_sum[30] ^= 1
+        bad_entry = bytearray(blob)
+        bad_entry[24] = 9                      # variant 9 does not exist (checksum fixed below)
+        h = 2166136261
+        bad_entry[60:64] = b"\0\0\0\0"
+        for x in bytes(bad_entry):
+            h = ((h ^ x) * 16777619) & 0xFFFFFFFF
+        bad_entry[60:64] = h.to_bytes(4, "little")
+        bad_version = bytearray(blob)
+        bad_version[8] = 2
+        for bad in (bytes(bad_sum), bytes(bad_entry), bytes(bad_version), blob[:-1]):
+            with pytest.raises(binding.AlignError) as e:
+                binding.variant_tables_load(bad)
+            assert e.value.code == AS_ERR_ARG
+            for m in range(3):
+                assert np.all(binding.get_variants(m) == -1)
+    finally:
+        for m in range(3):
+            binding.set_variants(m, prev[m])
