@@ -9,8 +9,8 @@ input generator module, which holds none of the method's arithmetic.
 What it computes is the plain definition of the optimal alignment score
 (paper section 2.1, Eq. (1)-(5) and the local / global / semi-global mode
 paragraphs), written in ``oracle.c`` as a textbook row-by-row dynamic program
-in 64-bit integers.  ``band.py`` holds the banded score's acceptance bound
-and the band label, ``mlp.py`` the band network in float64, ``features.py``
+in 64-bit integers.  ``band.py`` holds the banded score's acceptance bound,
+the band label and a residue-aware (seed-chain) bound on band-leaving paths, ``mlp.py`` the band network in float64, ``features.py``
 the per-pair k-mer features.  How each function is pinned to something other
 than itself is stated in the function's docstring and in the tests under
 ``tests/test_oracle_*.py``.

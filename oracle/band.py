@@ -127,3 +127,166 @@ def band_label(q, s, subst, alpha, beta, mode, max_band: int = MAX_BAND) -> int:
         return max_band
     wa = accepted_width(q, s, subst, alpha, beta, mode)
     return wa if wa <= w_cap else max_band
+
+
+# ---- residue-aware bound on band-leaving paths (global mode) ---------------
+#
+# A study of a tighter certificate than ub_outside; the GPU library does not
+# use it.  Loss of a global path: sigma_max*(m+n)/2 - score, a sum of
+# non-negative step costs (every diagonal step loses sigma_max - sigma, every
+# gap run of L columns alpha - beta + (beta + sigma_max/2)*L, from the gap
+# cost alpha + beta*(L-1) of Eq. (4),(5)).  Costs are kept doubled so that
+# they stay integers.  Cut Q into seeds of k residues (rows r_s = s*k,
+# s < m // k).  A path's node s is its last cell in row r_s, on diagonal d;
+# between node s and node s+1 it takes k down-moves and the horizontal moves
+# of rows r_s+1 .. r_s+k.  With no gap in between, its k diagonal steps lose
+# nothing only if every pair on diagonal d scores sigma_max (the seed matches
+# exactly there) and at least delta otherwise (delta: sigma_max minus the next
+# lower score); with gaps, a net shift of t > 0 diagonals costs at least one
+# run opening plus t gap columns, a shift of t < 0 at least |t| columns (the
+# vertical run may have opened earlier), no shift at least an opening plus
+# two columns.  The least total over node sequences is a lower bound on
+# every path's loss; adding the cost of reaching diagonal e from the nodes on
+# either side of the segment where the path first gets there gives a lower
+# bound on the loss of every path that visits e.  (Seed matches bounding the
+# errors of a region are the q-gram argument used by seed heuristics for
+# exact alignment; this is a chaining form of it with the affine costs.)
+
+def _chain_costs(subst, alpha, beta):
+    sub = __import__("numpy").asarray(subst, dtype=int)
+    smax = int(sub.max())
+    lower = sub[sub < smax]
+    two_cg = 2 * beta + smax                 # doubled cost of one gap column
+    two_a0 = 2 * (alpha - beta)              # doubled cost of opening a run
+    two_delta = 2 * (smax - int(lower.max())) if lower.size else None
+    pen = two_a0 + 2 * two_cg
+    if two_delta is not None:
+        pen = min(pen, two_delta)
+    return sub, smax, two_cg, two_a0, pen
+
+
+def seed_chain_visit_bounds(q, s, subst, alpha, beta, k):
+    """Doubled lower bounds on the loss of global paths that visit each
+    diagonal e (array index e + m, e = -m .. n): (C_up, C_dn, any_fwd,
+    any_bwd), C_up valid for e > max(0, n-m) and C_dn for e < min(0, n-m);
+    any_fwd (forward chain to the last node plus the tail) and any_bwd
+    (backward chain from the first node) bound the loss of every path.
+    Needs 0 <= beta <= alpha and k >= 1."""
+    import numpy as np
+    sub, smax, cg, a0, pen = _chain_costs(subst, alpha, beta)
+    q = np.asarray(q, dtype=int)
+    s = np.asarray(s, dtype=int)
+    m, n = len(q), len(s)
+    big = 1 << 60
+    d = np.arange(-m, n + 1)
+    idx = np.arange(len(d))
+
+    def up(F, a):        # min over j < i of F[j] + a + cg*(i - j)
+        x = np.minimum(F + a - cg * idx, big)
+        out = np.full(len(F), big, dtype=np.int64)
+        out[1:] = np.minimum.accumulate(x[:-1])
+        return np.minimum(out + cg * idx, big)
+
+    def dn(F, a):        # min over j > i of F[j] + a + cg*(j - i)
+        x = np.minimum(F + a + cg * idx, big)
+        out = np.full(len(F), big, dtype=np.int64)
+        out[:-1] = np.minimum.accumulate(x[::-1])[::-1][1:]
+        return np.minimum(out - cg * idx, big)
+
+    nseed = m // k
+    match = np.zeros((nseed, len(d)), dtype=bool)
+    for si in range(nseed if n else 0):
+        r = si * k
+        ok = (r + d >= 0) & (r + d + k <= n)
+        good = ok.copy()
+        for t in range(k):
+            col = np.where(ok, r + d + t, 0)
+            good &= sub[q[r + t], s[col]] == smax
+        match[si] = good
+
+    def seg(F, si, a_up, a_dn):
+        stay = np.minimum(F + np.where(match[si], 0, pen), big)
+        return np.minimum(stay, np.minimum(up(F, a_up), dn(F, a_dn)))
+
+    F = [np.where(d == 0, 0, np.where(d > 0, a0 + cg * d, big)).astype(np.int64)]
+    for si in range(nseed):
+        F.append(seg(F[-1], si, a0, 0))
+    e = n - m
+    B = [None] * (nseed + 1)
+    B[nseed] = np.where(d == e, 0, np.where(d < e, a0 + cg * (e - d), cg * (d - e))).astype(np.int64)
+    for si in range(nseed - 1, -1, -1):
+        # from node diagonal x: up to x' > x costs a0 + cg*(x'-x), down cg*(x-x')
+        B[si] = seg(B[si + 1], si, 0, a0)
+
+    c_up = np.full(len(d), big, dtype=np.int64)
+    c_dn = np.full(len(d), big, dtype=np.int64)
+    for si in range(nseed + 1):
+        Fs = F[si]
+        reach_up = np.minimum(Fs, up(Fs, a0))       # at diagonal e going up
+        reach_dn = np.minimum(Fs, dn(Fs, 0))        # at diagonal e going down
+        if si == nseed:
+            back_dn = np.where(d >= e, cg * (d - e), big)
+            back_up = np.where(d <= e, np.where(d < e, a0, 0) + cg * (e - d), big)
+        else:
+            Bn = B[si + 1]
+            back_dn = np.minimum(Bn, np.minimum(up(Bn, 0), dn(Bn, 0)))
+            back_up = np.minimum(Bn, np.minimum(dn(Bn, a0), up(Bn, 0)))
+        c_up = np.minimum(c_up, np.minimum(reach_up + back_dn, big))
+        c_dn = np.minimum(c_dn, np.minimum(reach_dn + back_up, big))
+    # a path that visits e beyond the band also visits every diagonal between
+    lo0, hi0 = min(0, n - m), max(0, n - m)
+    top = idx[d > hi0]
+    if len(top):
+        c_up[top] = np.maximum.accumulate(c_up[top])
+    bot = idx[d < lo0][::-1]
+    if len(bot):
+        c_dn[bot] = np.maximum.accumulate(c_dn[bot])
+    any_fwd = int(np.min(np.minimum(F[nseed] + B[nseed], big)))
+    any_bwd = int(B[0][m])
+    return c_up, c_dn, any_fwd, any_bwd
+
+
+def seed_chain_ub_outside(q, s, subst, alpha, beta, k, lo, hi, bounds=None):
+    """Upper bound on the score of every global path that visits a diagonal
+    outside [lo, hi] (lo <= min(0, n-m), hi >= max(0, n-m)), from the seed
+    chain; None if no path can leave.  `bounds` reuses a result of
+    seed_chain_visit_bounds for the same pair."""
+    m, n = len(q), len(s)
+    c_up, c_dn = (bounds if bounds is not None else seed_chain_visit_bounds(q, s, subst, alpha, beta, k))[:2]
+    cands = []
+    if hi + 1 <= n:
+        cands.append(int(c_up[hi + 1 + m]))
+    if lo - 1 >= -m:
+        cands.append(int(c_dn[lo - 1 + m]))
+    if not cands:
+        return None
+    smax = int(__import__("numpy").asarray(subst).max())
+    return (smax * (m + n) - min(cands)) // 2
+
+
+def seed_chain_accepted_width(q, s, subst, alpha, beta, k) -> int:
+    """Smallest w >= 0 whose banded global score passes the smaller of the
+    closed-form bound and the seed-chain bound (both are sound, so either
+    accepts only exact scores)."""
+    import numpy as np
+    m, n = len(q), len(s)
+    smax = int(np.asarray(subst).max())
+    bounds = seed_chain_visit_bounds(q, s, subst, alpha, beta, k)
+
+    def ok(w):
+        lo, hi = band_limits(m, n, w)
+        ub1 = ub_outside(m, n, w, smax, alpha, beta, GLOBAL)
+        ub2 = seed_chain_ub_outside(q, s, subst, alpha, beta, k, lo, hi, bounds)
+        ub = ub1 if ub2 is None else (ub2 if ub1 is None else min(ub1, ub2))
+        return accepts(banded_pair(q, s, subst, alpha, beta, GLOBAL, w), ub)
+
+    if ok(0):
+        return 0
+    lo_w, hi_w = 0, max(m, n)
+    while hi_w - lo_w > 1:
+        mid = (lo_w + hi_w) // 2
+        if ok(mid):
+            hi_w = mid
+        else:
+            lo_w = mid
+    return hi_w
