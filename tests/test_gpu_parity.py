@@ -58,7 +58,7 @@ def test_config1_subset(gpu, oracle_mod):
 
 
 def test_config2_subset(gpu, oracle_mod):
-    _check(gpu, oracle_mod, synth.config2(n_pairs=300), "c2[300]")
+    _check(gpu, oracle_mod, synth.config2(n_pairs=2000), "c2[2000]")
 
 
 def test_config3_subset(gpu, oracle_mod):
@@ -220,6 +220,46 @@ def test_config1_full_size_sampled(gpu, oracle_mod):
     want = oracle_mod.align_batch(sub.seqs_a, sub.offs_a, sub.seqs_b, sub.offs_b, sub.subst,
                                   sub.alpha, sub.beta, sub.mode)
     assert np.array_equal(got[idx].astype(np.int64), want)
+
+
+def _full_size_sampled(gpu, oracle_mod, b, label, n_sample, seed):
+    _say(f"{label}: {b.n_pairs} pairs, {b.cells():.3g} cells, mode {b.mode}")
+    got = gpu.align(b)
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(b.n_pairs, size=n_sample, replace=False))
+    sub = b.subset(idx)
+    want = oracle_mod.align_batch(sub.seqs_a, sub.offs_a, sub.seqs_b, sub.offs_b, sub.subst,
+                                  sub.alpha, sub.beta, sub.mode)
+    bad = np.nonzero(got[idx].astype(np.int64) != want)[0]
+    assert len(bad) == 0, f"{label}: {len(bad)} of {n_sample} sampled pairs differ (first {idx[bad[0]]})"
+    return got
+
+
+def test_config2_full_size_sampled(gpu, oracle_mod):
+    """All 10^5 semi-global pairs of log-normal length (50..20,000) in the
+    benchmark's configuration; 2000 sampled pairs checked against the
+    oracle, and every score is at least the empty alignment's 0 and at most
+    sigma_max times the shorter length."""
+    b = synth.config2()
+    got = _full_size_sampled(gpu, oracle_mod, b, "c2 full", 2000, 6)
+    assert got.min() >= 0
+    assert np.all(got.astype(np.int64) <= 2 * np.minimum(b.lens_a, b.lens_b))
+
+
+def test_config3_short_full_size_sampled(gpu, oracle_mod):
+    """All 2^16 short local protein pairs (packed LDS-profile variant and
+    the 32-bit re-run); 3000 sampled pairs checked against the oracle."""
+    b = synth.config3(n_long=0)
+    got = _full_size_sampled(gpu, oracle_mod, b, "c3 short full", 3000, 7)
+    assert got.min() >= 0
+
+
+def test_config4_full_dp_sampled(gpu, oracle_mod):
+    """The full DP of all 10^6 pairs of 1-5 kb (packed wavefront, the
+    learned path's reference); 1500 sampled pairs checked against the
+    oracle."""
+    b = synth.config4()
+    _full_size_sampled(gpu, oracle_mod, b, "c4 full DP", 1500, 8)
 
 
 def test_packed16_rerun_forced(gpu, oracle_mod):
