@@ -457,15 +457,18 @@ int as_get_variants(int32_t mode, int8_t *table_out);
 
 /*
  * Persisted tables (the batching runtime's autotuner output, not in the
- * paper): the three modes' tables as one versioned, checksummed blob of
- * as_variant_tables_blob_size() bytes (64), host memory owned by the
+ * paper): the three modes' variant tables and measured cell types
+ * (as_half_cells_preference) as one versioned, checksummed blob of
+ * as_variant_tables_blob_size() bytes (68), host memory owned by the
  * caller.  Layout (little-endian): char magic[8] = "ASVARTAB"; uint32
- * version = 1, n_modes = 3, n_bins = AS_LEN_BINS, n_variants = AS_VARIANTS;
- * int8 table[3][AS_LEN_BINS]; uint32 FNV-1a checksum of the 64 bytes with
- * this field zero.  Save: AS_ERR_NULL, or AS_ERR_ARG when blob_size is too
- * small.  Load: a wrong size, magic, version, dimension, checksum or entry
- * returns AS_ERR_ARG and leaves every table as it was; otherwise all three
- * tables are replaced.
+ * version = 2, n_modes = 3, n_bins = AS_LEN_BINS, n_variants = AS_VARIANTS;
+ * int8 table[3][AS_LEN_BINS]; int8 half_pref[3]; uint8 0; uint32 FNV-1a
+ * checksum of the 68 bytes with this field zero.  A version-1 blob (64
+ * bytes: no half_pref, the checksum at byte 60) still loads and clears the
+ * measured cell types.  Save: AS_ERR_NULL, or AS_ERR_ARG when blob_size is
+ * too small.  Load: a wrong size, magic, version, dimension, checksum or
+ * entry returns AS_ERR_ARG and leaves every table as it was; otherwise all
+ * three tables and cell types are replaced.
  */
 int64_t as_variant_tables_blob_size(void);
 int as_variant_tables_save(uint8_t *blob_out, int64_t blob_size);
@@ -476,7 +479,12 @@ int as_variant_tables_load(const uint8_t *blob, int64_t blob_size);
  * on a sample of the bin's pairs (every stride-th pair: at most sample_pairs
  * pairs and about 1e11 cells; best of two runs, HIP events around the DP
  * kernels) and keep the fastest in the mode's table.  Bins without pairs
- * keep their entry.  The sample's scores go to library scratch memory.
+ * keep their entry.  Then, when the scoring admits FP16 cells
+ * (as_set_half_cells) and a sampled bin can take the packed kernel, the
+ * sampled bins run under the tuned table once with int16 and once with FP16
+ * cells (best of two each), and the faster becomes the mode's measured cell
+ * type (as_half_cells_preference).  The sample's scores go to library
+ * scratch memory.
  *   gcups_out : optional HOST float [AS_LEN_BINS * AS_VARIANTS]: measured
  *               GCUPS per (bin, variant), 0 where not measured
  *   table_out : optional HOST int8 [AS_LEN_BINS]: the resulting table
@@ -549,9 +557,22 @@ int as_set_i16_limit(int32_t limit);
  *           1984), int16 otherwise; as_align_all_vs_all also takes them for
  *           global and semi-global calls with E5M2-exact values whose
  *           longest row sequence satisfies the bound above.
+ *           A measured cell type for the mode (as_half_cells_preference,
+ *           set by as_autotune) replaces this rule for as_align_batch and
+ *           plans.
  * Applies to calls and plans made after it.  Returns the previous mode.
  */
 int as_set_half_cells(int mode);
+
+/*
+ * The automatic setting's measured cell type for a mode (batching runtime;
+ * not in the paper): -1 none (the static rule of as_set_half_cells mode 2
+ * decides), 0 int16, 1 FP16 cells where the scoring admits them.
+ * as_autotune sets it; set != 0 stores pref (-1, 0 or 1), set == 0 only
+ * reads.  Returns the previous value, or AS_ERR_ARG for a mode outside 0..2
+ * or such a pref.  Per process, for calls and plans made after it.
+ */
+int as_half_cells_preference(int32_t mode, int32_t pref, int32_t set);
 
 /* Enable (1) or disable (0) phase timing.  Returns the previous setting. */
 int as_enable_timing(int on);

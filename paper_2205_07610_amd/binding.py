@@ -141,6 +141,8 @@ def lib() -> ctypes.CDLL:
     L.as_set_i16_limit.argtypes = [ctypes.c_int32]
     L.as_set_half_cells.restype = ctypes.c_int
     L.as_set_half_cells.argtypes = [ctypes.c_int]
+    L.as_half_cells_preference.restype = ctypes.c_int
+    L.as_half_cells_preference.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     L.as_variant_tables_blob_size.restype = i64
     L.as_variant_tables_blob_size.argtypes = []
     L.as_variant_tables_save.restype = ctypes.c_int
@@ -558,6 +560,17 @@ def get_variants(mode: int) -> np.ndarray:
     t = np.zeros(LEN_BINS, dtype=np.int8)
     _check(lib().as_get_variants(int(mode), t.ctypes.data_as(ctypes.c_void_p)))
     return t
+
+
+def half_cells_preference(mode: int, pref=None) -> int:
+    """The automatic setting's measured cell type for a mode (-1 none, 0
+    int16, 1 FP16; as_autotune sets it).  With pref given, store it.
+    Returns the previous value."""
+    rc = int(lib().as_half_cells_preference(int(mode), 0 if pref is None else int(pref),
+                                             0 if pref is None else 1))
+    if rc < -1:
+        _check(rc)
+    return rc
 
 
 def variant_tables_save() -> bytes:

@@ -774,6 +774,9 @@ int8_t g_variants[3][kLenBins] = {{-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -
                                   {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1}};
 int32_t g_i16_limit = 32767;
 int g_half_cells = 2;   // packed kernel's FP16 cells: 0 never, 1 when admissible, 2 automatic
+// The automatic setting's cell type per mode as the autotuner measured it:
+// -1 not measured (the static rule decides), 0 int16, 1 FP16.
+int8_t g_half_pref[3] = {-1, -1, -1};
 as_timing g_last_timing;
 
 std::mutex g_lock;
@@ -930,8 +933,10 @@ int check_scoring(const as_scoring *scoring, int32_t mode, CallScoring *cs) {
   for (int i = 0; i < asz * asz; ++i) e5 = e5 && e5m2_exact(scoring->subst[i] + bias);
   const bool h_ok = cs->allow16 && smax + bias <= 16 && pad <= 16;
   const int smax_pos = smax > 0 ? smax : 0;
+  const int pref = g_half_pref[mode];
   const bool want = g_half_cells == 1 ||
-                    (g_half_cells == 2 && mode == kLocal && e5 && smax_pos * 256 + alpha + 16 < kHalfLimit);
+                    (g_half_cells == 2 && (pref >= 0 ? pref == 1
+                                                     : mode == kLocal && e5 && smax_pos * 256 + alpha + 16 < kHalfLimit));
   cs->half_adm = h_ok ? (e5 ? kCellF16E5M2 : kCellF16E4M3) : kCellI16;
   cs->half = want ? cs->half_adm : kCellI16;
   return AS_OK;
@@ -1992,6 +1997,7 @@ extern "C" int as_autotune(const uint8_t *seqs_a, const int64_t *offs_a, const u
     // A sample of a bin: every stride-th pair, at most sample_pairs pairs
     // and about 1e11 cells (tens of milliseconds per variant).
     const double cell_cap = 1e11;
+    int32_t strides[kLenBins] = {};  // each measured bin's sample stride (0: no pairs)
     for (int b = 0; b < kLenBins; ++b) {
       int64_t cnt = 0;
       for (int l = 0; l < 3; ++l) cnt += c0.bin_count[l][b];
@@ -2034,6 +2040,40 @@ extern "C" int as_autotune(const uint8_t *seqs_a, const int64_t *offs_a, const u
       }
       if (rc) break;
       g_variants[mode][b] = (int8_t)best_v;
+      strides[b] = (int32_t)(stride > (1 << 30) ? (1 << 30) : stride);
+    }
+    // Precision: where the scoring admits FP16 cells and the tuned table
+    // sends a bin to the packed kernel, time the sampled bins under both
+    // cell types (pairs an FP16 range bound refuses take the 32-bit kernels,
+    // which the timing includes) and keep the faster for the automatic
+    // setting.
+    bool packed_bin = false;
+    for (int b = 0; b < kLenBins; ++b)
+      packed_bin = packed_bin || (strides[b] > 0 && (g_variants[mode][b] == kVarI16 ||
+                                                     (g_variants[mode][b] < 0 && cs.allow16)));
+    if (!rc && cs.half_adm != kCellI16 && packed_bin) {
+      float ms_of[2] = {-1.f, -1.f};
+      for (int h = 0; h < 2 && !rc; ++h) {
+        CallScoring ch = cs;
+        ch.half = h ? cs.half_adm : kCellI16;
+        RouteParams t = route_params(ch, n_pairs);
+        for (int b = 0; b < kLenBins; ++b) {
+          t.var_of_bin[b] = g_variants[mode][b];
+          t.sample_stride[b] = strides[b] > 0 ? strides[b] : (1 << 30);
+        }
+        for (int rep = 0; rep < 2; ++rep) {
+          AS_HIP(hipMemsetAsync(w->ctr, 0, sizeof(Counters), stream));
+          if ((rc = launch_classify(w, t, offs_a, offs_b, nullptr, n_pairs, w->tune_scores, stream))) break;
+          Counters c;
+          if ((rc = read_counters(w, stream, &c))) break;
+          memset(&g_last_timing, 0, sizeof(g_last_timing));
+          if ((rc = run_full_lists(w, ch, seqs_a, seqs_b, w->tune_scores, stream, true, c))) break;
+          const float ms = g_last_timing.full16_ms + g_last_timing.full32_ms + g_last_timing.long_ms +
+                           g_last_timing.rerun32_ms;
+          if (ms_of[h] < 0.f || ms < ms_of[h]) ms_of[h] = ms;
+        }
+      }
+      if (!rc) g_half_pref[mode] = (int8_t)(ms_of[1] < ms_of[0] ? 1 : 0);
     }
     g_timing = timing_was;
     if (rc) return rc;
@@ -2084,6 +2124,15 @@ extern "C" int as_set_half_cells(int mode) {
   std::lock_guard<std::mutex> guard(g_lock);
   const int prev = g_half_cells;
   g_half_cells = (mode == 0 || mode == 1) ? mode : 2;
+  return prev;
+}
+
+extern "C" int as_half_cells_preference(int32_t mode, int32_t pref, int32_t set) {
+  if (mode < 0 || mode > 2) return AS_ERR_ARG;
+  if (set && (pref < -1 || pref > 1)) return AS_ERR_ARG;
+  std::lock_guard<std::mutex> guard(g_lock);
+  const int prev = g_half_pref[mode];
+  if (set) g_half_pref[mode] = (int8_t)pref;
   return prev;
 }
 

@@ -101,43 +101,78 @@ def test_struct_layouts_match_header(tmp_path):
             assert got[(cname, field)] == getattr(py, field).offset, (cname, field)
 
 
+def _fnv_fix(blob, sum_off):
+    b = bytearray(blob)
+    b[sum_off:sum_off + 4] = b"\0\0\0\0"
+    h = 2166136261
+    for x in bytes(b):
+        h = ((h ^ x) * 16777619) & 0xFFFFFFFF
+    b[sum_off:sum_off + 4] = h.to_bytes(4, "little")
+    return bytes(b)
+
+
 def test_variant_tables_blob_round_trip(L):
     """The persisted variant tables: a saved blob restores all three modes'
-    tables; a damaged, truncated or out-of-range blob is refused and leaves
-    the tables as they were.  Host-only (no device work)."""
+    tables and measured cell types; a version-1 blob (tables only) still
+    loads and clears the cell types; a damaged, truncated or out-of-range
+    blob is refused and leaves everything as it was.  Host-only (no device
+    work)."""
     prev = [binding.get_variants(m) for m in range(3)]
+    prev_h = [binding.half_cells_preference(m) for m in range(3)]
     try:
         tabs = [np.array([0, 1, 2, 3, 4, 5, -1, -1, 2, 2, 4, 4], np.int8),
                 np.array([-1] * 12, np.int8),
                 np.array([5, 5, 3, 3, 2, 2, 1, 1, 0, 4, 4, -1], np.int8)]
+        prefs = [1, -1, 0]
         for m, t in enumerate(tabs):
             binding.set_variants(m, t)
+            binding.half_cells_preference(m, prefs[m])
         blob = binding.variant_tables_save()
-        assert len(blob) == 64 and blob[:8] == b"ASVARTAB"
-        for m in range(3):
-            binding.set_variants(m, None)
+        assert len(blob) == 68 and blob[:8] == b"ASVARTAB" and blob[8] == 2
+        assert list(np.frombuffer(blob[60:63], np.int8)) == prefs and blob[63] == 0
+
+        def clear():
+            for m in range(3):
+                binding.set_variants(m, None)
+                binding.half_cells_preference(m, -1)
+
+        clear()
         binding.variant_tables_load(blob)
         for m, t in enumerate(tabs):
             assert np.array_equal(binding.get_variants(m), t)
-        for m in range(3):
-            binding.set_variants(m, None)
+            assert binding.half_cells_preference(m) == prefs[m]
+        # version 1: the same tables, no cell types, checksum at byte 60
+        v1 = bytearray(blob[:64])
+        v1[8] = 1
+        v1 = _fnv_fix(v1, 60)
+        binding.variant_tables_load(v1)
+        for m, t in enumerate(tabs):
+            assert np.array_equal(binding.get_variants(m), t)
+            assert binding.half_cells_preference(m) == -1
+        clear()
         bad_sum = bytearray(blob)
         bad_sum[30] ^= 1
         bad_entry = bytearray(blob)
-        bad_entry[24] = 9                      # variant 9 does not exist (checksum fixed below)
-        h = 2166136261
-        bad_entry[60:64] = b"\0\0\0\0"
-        for x in bytes(bad_entry):
-            h = ((h ^ x) * 16777619) & 0xFFFFFFFF
-        bad_entry[60:64] = h.to_bytes(4, "little")
+        bad_entry[24] = 9                      # variant 9 does not exist
+        bad_pref = bytearray(blob)
+        bad_pref[61] = 2                       # cell type 2 does not exist
+        bad_pad = bytearray(blob)
+        bad_pad[63] = 1
         bad_version = bytearray(blob)
-        bad_version[8] = 2
-        for bad in (bytes(bad_sum), bytes(bad_entry), bytes(bad_version), blob[:-1]):
+        bad_version[8] = 3
+        bads = [bytes(bad_sum), _fnv_fix(bad_entry, 64), _fnv_fix(bad_pref, 64), _fnv_fix(bad_pad, 64),
+                _fnv_fix(bad_version, 64), blob[:-1], _fnv_fix(bytearray(blob[:64]), 60)]
+        for bad in bads:
             with pytest.raises(binding.AlignError) as e:
                 binding.variant_tables_load(bad)
             assert e.value.code == AS_ERR_ARG
             for m in range(3):
                 assert np.all(binding.get_variants(m) == -1)
+                assert binding.half_cells_preference(m) == -1
+        for args in ((3, 0), (-1, 0), (0, 2), (0, -2)):
+            with pytest.raises(binding.AlignError):
+                binding.half_cells_preference(*args)
     finally:
         for m in range(3):
             binding.set_variants(m, prev[m])
+            binding.half_cells_preference(m, prev_h[m])

@@ -118,6 +118,53 @@ def test_autotune_then_exact(gpu, oracle_mod):
     gpu.set_variants(b.mode, None)
 
 
+def test_autotune_cell_type(gpu, oracle_mod):
+    """The autotuner's precision axis: for the local reads workload's
+    scoring (FP16 cells admitted with E5M2 bytes) and the global DNA
+    scoring (E4M3 bytes) it measures int16 against FP16 cells and stores the
+    faster for the automatic setting; calls then run that cell type, the
+    opposite one when set by hand, and every score equals the oracle's.
+    Protein scoring admits no FP16 cells and leaves the type unmeasured."""
+    prev_t = gpu.enable_timing(True)
+    exercised = 0
+    try:
+        for b, fp16 in ((synth.config1(n_pairs=20000, seed=930), 2), (synth.config0(n_pairs=3000), 1)):
+            gpu.half_cells_preference(b.mode, -1)
+            dev = gpu.to_device(b)
+            table, _ = gpu.autotune(*dev, b.subst, b.alpha, b.beta, b.mode, sample_pairs=4096)
+            pref = gpu.half_cells_preference(b.mode)
+            _say(f"{b.name}: table {table.tolist()}, measured cell type {pref}")
+            # 150- and 250-residue pairs live in bin 2; the cell type is
+            # measured only when the tuned table sends that bin to the packed
+            # full-DP kernel
+            if table[2] != 0:
+                assert pref == -1
+                gpu.set_variants(b.mode, None)
+                continue
+            assert pref in (0, 1)
+            exercised += 1
+            want = _oracle(oracle_mod, b)
+            for p in (pref, 1 - pref):
+                gpu.half_cells_preference(b.mode, p)
+                got = gpu.align_batch(*dev, b.subst, b.alpha, b.beta, b.mode).cpu().numpy()
+                t = gpu.last_timing()
+                assert t["pairs_full16"] > 0
+                assert t["full16_cell_type"] == (fp16 if p == 1 else 0), (p, t["full16_cell_type"])
+                np.testing.assert_array_equal(got.astype(np.int64), want)
+            gpu.half_cells_preference(b.mode, -1)
+            gpu.set_variants(b.mode, None)
+        assert exercised > 0
+        c3 = synth.config3(n_pairs=2000, n_long=0)
+        gpu.half_cells_preference(c3.mode, -1)
+        gpu.autotune(*gpu.to_device(c3), c3.subst, c3.alpha, c3.beta, c3.mode, sample_pairs=512)
+        assert gpu.half_cells_preference(c3.mode) == -1
+        gpu.set_variants(c3.mode, None)
+    finally:
+        gpu.enable_timing(prev_t)
+        for m in range(3):
+            gpu.half_cells_preference(m, -1)
+
+
 def test_plan_replays_match_oracle(gpu, oracle_mod):
     """A captured plan replayed several times, with eager library work and
     synchronisations between the replays; every replay equals the oracle.

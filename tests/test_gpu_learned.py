@@ -342,3 +342,35 @@ def test_features_many_pairs_per_workgroup(gpu):
     np.testing.assert_array_equal(got[idx, :30], want[:, :30])
     np.testing.assert_array_equal(got[idx, 31], want[:, 31])
     _say(f"features of {n} short pairs: {len(idx)} checked, hits in {np.count_nonzero(want[:, 31])}")
+
+
+def test_learned_full_size_sampled(gpu, oracle_mod):
+    """The benchmark's configuration: the network trained on 2*10^5 pairs of
+    the 1-5 kb law (4000 Adam steps of 1024, pinball quantile 0.7), then one
+    learned call on all 10^6 pairs of 1-5 kb.  Every score equals the full
+    DP's on the GPU, 1500 sampled scores equal the oracle's, every pair is
+    settled by the second round and none falls back to the full DP."""
+    import torch
+    train = synth.config4_training()
+    dtr = gpu.to_device(train)
+    params = _t(synth.band_params_init(2005, b3=5.0))
+    order = _t(synth.minibatch_order(2006, train.n_pairs, 4000, 1024))
+    gpu.train_band_model(*dtr, DNA, 5, 2, 0, params, order, 4000, 1024, lr=2e-3, tau=0.7)
+    torch.cuda.synchronize()
+    del dtr
+    b = synth.config4()
+    _say(f"c4 learned full: {b.n_pairs} pairs, {b.cells():.3g} cells")
+    dev = gpu.to_device(b)
+    got_t, st = gpu.align_batch_learned(*dev, DNA, 5, 2, 0, params)
+    got = got_t.cpu().numpy()
+    full = gpu.align(b)
+    _say(f"c4 learned full: rounds {st['rounds']}, accepted {st['accepted']}, fallback {st['fallback']}, "
+         f"cells {st['dp_cells'] / b.cells():.4f} of full")
+    np.testing.assert_array_equal(got.astype(np.int64), full.astype(np.int64))
+    rng = np.random.default_rng(9)
+    idx = np.sort(rng.choice(b.n_pairs, size=1500, replace=False))
+    sub = b.subset(idx)
+    want = oracle_mod.align_batch(sub.seqs_a, sub.offs_a, sub.seqs_b, sub.offs_b, sub.subst, sub.alpha,
+                                  sub.beta, sub.mode)
+    np.testing.assert_array_equal(got[idx].astype(np.int64), want)
+    assert st["fallback"] == 0 and st["rounds"] <= 2
