@@ -212,3 +212,24 @@ def test_columns_512(gpu, oracle_mod, mode):
             _check(gpu, oracle_mod, Q, S, DNA, 5, 2, mode, "columns <= 512, forced re-run")
         finally:
             gpu.set_i16_limit(prev)
+
+
+@pytest.mark.parametrize("length", [125, 512])
+def test_read_sets_full_size_sampled(gpu, oracle_mod, length):
+    """The benchmark's configuration: 3536 reads of 125 or 512 bp all
+    against all (12.5 M pairs, global, linear gaps, +2/-1) in one call; 3000
+    sampled (query, subject) scores equal the oracle's, and the matrix is
+    symmetric (the set against itself, a symmetric scoring)."""
+    import torch
+    seqs, offs = synth.read_set(3536, length, 1005 if length == 125 else 1006)
+    sq, oq = torch.from_numpy(seqs).cuda(), torch.from_numpy(offs).cuda()
+    sub = synth.dna_subst(2, -1)
+    got = gpu.align_all_vs_all(sq, oq, sq, oq, sub, 1, 1, 0).cpu().numpy()
+    _say(f"reads {length}: 3536 x 3536 scored")
+    assert np.array_equal(got, got.T)
+    rng = np.random.default_rng(9)
+    qi, si = rng.integers(0, 3536, 3000), rng.integers(0, 3536, 3000)
+    b = synth.from_pairs("sample", [(seqs[offs[q]:offs[q + 1]], seqs[offs[s]:offs[s + 1]]) for q, s in zip(qi, si)],
+                         sub, 1, 1, 0)
+    want = oracle_mod.align_batch(b.seqs_a, b.offs_a, b.seqs_b, b.offs_b, b.subst, b.alpha, b.beta, b.mode)
+    np.testing.assert_array_equal(got[qi, si].astype(np.int64), want)

@@ -157,3 +157,31 @@ def test_traceback_errors(gpu):
     o = ops.cpu().numpy()
     assert o[0:5].tobytes() == b"MMMMM" and o[10:15].tobytes() == b"MMMMM"
     assert span.cpu().tolist() == [[5, 0, 5, 0, 5], [5, 0, 5, 0, 5]]
+
+
+@pytest.mark.parametrize("length,n_pairs", [(125, 1 << 20), (512, 1 << 17)])
+def test_read_pairs_full_size_sampled(gpu, oracle_mod, length, n_pairs):
+    """The benchmark's traceback configuration: 2^20 pairs of 125 bp reads
+    or 2^17 of 512 bp (3536 reads of a seeded genome, global, linear gaps,
+    +2/-1), traced in one call; 3000 sampled pairs have the oracle's optimum
+    as their score, and their alignments rescore to it."""
+    seqs, offs = synth.read_set(3536, length, 1005 if length == 125 else 1006)
+    rng = np.random.default_rng(1007)
+    qi, si = rng.integers(0, 3536, size=n_pairs), rng.integers(0, 3536, size=n_pairs)
+    b = synth.from_pairs(f"reads {length}", [(seqs[offs[q]:offs[q + 1]], seqs[offs[t]:offs[t + 1]])
+                                              for q, t in zip(qi, si)], synth.dna_subst(2, -1), 1, 1, 0)
+    dev = gpu.to_device(b, "cuda:0")
+    sc, ops, span = gpu.align_batch_traceback(*dev, b.subst, b.alpha, b.beta, b.mode)
+    sc, ops, span = sc.cpu().numpy(), ops.cpu().numpy(), span.cpu().numpy()
+    _say(f"reads {length}: {n_pairs} pairs traced")
+    idx = np.sort(np.random.default_rng(8).choice(n_pairs, size=3000, replace=False))
+    sub = b.subset(idx)
+    want = oracle_mod.align_batch(sub.seqs_a, sub.offs_a, sub.seqs_b, sub.offs_b, sub.subst, sub.alpha,
+                                  sub.beta, sub.mode)
+    np.testing.assert_array_equal(sc[idx].astype(np.int64), want)
+    # the sampled pairs' columns, gathered from the batch's column buffer
+    col0 = (b.offs_a[:-1] - b.offs_a[0]) + (b.offs_b[:-1] - b.offs_b[0])
+    sub_ops = np.concatenate([ops[col0[p]:col0[p] + b.lens_a[p] + b.lens_b[p]] for p in idx])
+    got = oracle_mod.alignment_score_batch(sub.seqs_a, sub.offs_a, sub.seqs_b, sub.offs_b, sub.subst,
+                                           sub.alpha, sub.beta, sub.mode, sub_ops, span[idx])
+    np.testing.assert_array_equal(got, want)
