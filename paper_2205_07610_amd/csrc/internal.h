@@ -153,7 +153,7 @@ struct Counters {
   unsigned long long band_cells;  // cells computed by the banded kernels (both widths)
   unsigned long long band16_cells;  // of these, cells computed by the packed 16-bit kernel
   unsigned long long fallback_cells;  // sum of m*n over the fallback pairs
-  unsigned long long route_cells[4];  // sum of m*n per full-DP list (16-bit, 32-bit, wavefront)
+  unsigned long long route_cells[4];  // sum of m*n per full-DP list (16-bit, 32-bit, wavefront, packed wavefront)
   // length-binned lists: counts, offsets and scatter cursors per (list, bin)
   int32_t bin_count[kListSlots][kLenBins];
   int32_t bin_base[kListSlots][kLenBins];

@@ -2000,7 +2000,7 @@ extern "C" int as_autotune(const uint8_t *seqs_a, const int64_t *offs_a, const u
     int32_t strides[kLenBins] = {};  // each measured bin's sample stride (0: no pairs)
     for (int b = 0; b < kLenBins; ++b) {
       int64_t cnt = 0;
-      for (int l = 0; l < 3; ++l) cnt += c0.bin_count[l][b];
+      for (int l = 0; l < kLists; ++l) cnt += c0.bin_count[l][b];
       if (cnt == 0) continue;
       int64_t stride = cnt / sample_pairs;
       const int64_t by_cells = (int64_t)((double)c0.bin_cells[b] / cell_cap);
@@ -2026,8 +2026,9 @@ extern "C" int as_autotune(const uint8_t *seqs_a, const int64_t *offs_a, const u
           memset(&g_last_timing, 0, sizeof(g_last_timing));
           if ((rc = run_full_lists(w, cs, seqs_a, seqs_b, w->tune_scores, stream, true, c))) break;
           const float ms = g_last_timing.full16_ms + g_last_timing.full32_ms + g_last_timing.long_ms +
-                           g_last_timing.rerun32_ms;
-          cells = (double)(c.route_cells[0] + c.route_cells[1] + c.route_cells[2]);
+                           g_last_timing.long16_ms + g_last_timing.rerun32_ms;
+          cells = (double)(c.route_cells[kList16] + c.route_cells[kList32] + c.route_cells[kListLong] +
+                           c.route_cells[kListLong16]);
           if (ms_best < 0.f || ms < ms_best) ms_best = ms;
         }
         if (rc) break;
@@ -2069,7 +2070,7 @@ extern "C" int as_autotune(const uint8_t *seqs_a, const int64_t *offs_a, const u
           memset(&g_last_timing, 0, sizeof(g_last_timing));
           if ((rc = run_full_lists(w, ch, seqs_a, seqs_b, w->tune_scores, stream, true, c))) break;
           const float ms = g_last_timing.full16_ms + g_last_timing.full32_ms + g_last_timing.long_ms +
-                           g_last_timing.rerun32_ms;
+                           g_last_timing.long16_ms + g_last_timing.rerun32_ms;
           if (ms_of[h] < 0.f || ms < ms_of[h]) ms_of[h] = ms;
         }
       }

@@ -118,6 +118,27 @@ def test_autotune_then_exact(gpu, oracle_mod):
     gpu.set_variants(b.mode, None)
 
 
+def test_autotune_global_long_pairs(gpu, oracle_mod):
+    """Global pairs of 1-3 kb: the wavefront variant of their bins routes
+    them to the packed wavefront, whose time and cells the autotuner counts
+    (a measured rate above zero for that variant), and the tuned table keeps
+    the oracle's scores."""
+    b = synth.config4_like(400, 940, min_len=1000, max_len=3000)
+    dev = gpu.to_device(b)
+    table, g = gpu.autotune(*dev, b.subst, b.alpha, b.beta, b.mode, sample_pairs=256)
+    lens = np.maximum(b.lens_a, b.lens_b)
+    present = sorted({min(11, max(0, int(np.ceil(np.log2(max(x, 1) / 64))))) for x in lens if x > 0})
+    _say(f"autotune table {table.tolist()}")
+    for bb in present:
+        _say(f"  bin {bb} (<= {64 << bb}): GCUPS {np.round(g[bb], 1).tolist()} -> {table[bb]}")
+        assert np.all(np.isfinite(g[bb])) and g[bb].max() < 1e5
+        if (64 << bb) > 1024:
+            assert g[bb][gpu.VARIANTS["wavefront"]] > 0
+    got = gpu.align_batch(*dev, b.subst, b.alpha, b.beta, b.mode).cpu().numpy()
+    np.testing.assert_array_equal(got.astype(np.int64), _oracle(oracle_mod, b))
+    gpu.set_variants(b.mode, None)
+
+
 def test_autotune_cell_type(gpu, oracle_mod):
     """The autotuner's precision axis: for the local reads workload's
     scoring (FP16 cells admitted with E5M2 bytes) and the global DNA
