@@ -28,6 +28,7 @@ def gpu():
     yield binding
     for mode in (0, 1, 2):
         binding.set_variants(mode, None)
+        binding.half_cells_preference(mode, -1)  # the autotuner's measured cell types
 
 
 def _mixed_batch(seed, asz, n_pairs=700):
@@ -116,6 +117,7 @@ def test_autotune_then_exact(gpu, oracle_mod):
     sub = b.subset(np.sort(idx))
     np.testing.assert_array_equal(got[np.sort(idx)], _oracle(oracle_mod, sub))
     gpu.set_variants(b.mode, None)
+    gpu.half_cells_preference(b.mode, -1)
 
 
 def test_autotune_global_long_pairs(gpu, oracle_mod):
@@ -137,6 +139,7 @@ def test_autotune_global_long_pairs(gpu, oracle_mod):
     got = gpu.align_batch(*dev, b.subst, b.alpha, b.beta, b.mode).cpu().numpy()
     np.testing.assert_array_equal(got.astype(np.int64), _oracle(oracle_mod, b))
     gpu.set_variants(b.mode, None)
+    gpu.half_cells_preference(b.mode, -1)
 
 
 def test_autotune_cell_type(gpu, oracle_mod):
