@@ -173,6 +173,37 @@ def test_packed_lds_local(gpu, oracle_mod):
     _check(gpu, oracle_mod, synth.from_pairs("dna local", pairs, DNA, 5, 2, 2), "DNA local, mixed routes")
 
 
+def test_local_scores_beyond_int16(gpu, oracle_mod):
+    """Local DNA pairs of 300-1200 residues with match 100 (mismatch -20,
+    alpha 20, beta 5): identical and nearly identical pairs score up to
+    120,000, far past int16, so the packed LDS-profile kernel saturates on
+    its own (no lowered threshold) and the 32-bit re-run gives the exact
+    scores; unrelated pairs stay on 16-bit cells."""
+    rng = np.random.default_rng(570)
+    sub = synth.dna_subst(100, -20)
+    pairs = []
+    for k in range(120):
+        m = int(rng.integers(300, 1201))
+        a = rng.integers(0, 4, size=m).astype(np.uint8)
+        if k % 3 == 0:
+            s_ = a.copy()
+        elif k % 3 == 1:
+            s_, _ = synth.mutate(rng, a, np.array([0, m]), 0.02, 0.005, 0.005, 4)
+            s_ = s_.astype(np.uint8)
+        else:
+            s_ = rng.integers(0, 4, size=int(rng.integers(300, 1201))).astype(np.uint8)
+        pairs.append((a, s_))
+    b = synth.from_pairs("local beyond int16", pairs, sub, 20, 5, 2)
+    gpu.enable_timing(True)
+    try:
+        got = _check(gpu, oracle_mod, b, "local beyond int16")
+        tm = gpu.last_timing()
+    finally:
+        gpu.enable_timing(False)
+    assert got.max() > 32767
+    assert tm["pairs_rerun32"] >= 40
+
+
 def test_range_refusal(gpu):
     """AS_ERR_RANGE: a pair whose cells could leave the 32-bit budget is
     refused before any DP runs (|sigma|max + alpha + 2 beta) * (m + n + 2)
