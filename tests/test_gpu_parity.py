@@ -204,6 +204,28 @@ def test_local_scores_beyond_int16(gpu, oracle_mod):
     assert tm["pairs_rerun32"] >= 40
 
 
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_all_mismatch_and_very_unequal_lengths(gpu, oracle_mod, mode):
+    """Pairs with no matching letter at all (A all 0, B all 1, 1..3000
+    residues), and very unequal lengths in both orientations (1-10 residues
+    against 3000-20000, and the reverse): global scores run deep negative
+    (down to about -40,000), local and semi-global ones sit at their floors;
+    every route (packed, 32-bit stripes, wavefront) meets them."""
+    rng = np.random.default_rng(580 + mode)
+    pairs = []
+    for _ in range(60):
+        m, n = (int(x) for x in rng.integers(1, 3001, size=2))
+        pairs.append((np.zeros(m, np.uint8), np.ones(n, np.uint8)))
+    for _ in range(40):
+        short = rng.integers(0, 4, size=int(rng.integers(1, 11))).astype(np.uint8)
+        long_ = rng.integers(0, 4, size=int(rng.integers(3000, 20001))).astype(np.uint8)
+        pairs.append((short, long_) if rng.random() < 0.5 else (long_, short))
+    b = synth.from_pairs("adversarial", pairs, DNA, 5, 2, mode)
+    got = _check(gpu, oracle_mod, b, f"all-mismatch and unequal, mode {mode}")
+    if mode == 0:
+        assert got.min() < -30000
+
+
 def test_range_refusal(gpu):
     """AS_ERR_RANGE: a pair whose cells could leave the 32-bit budget is
     refused before any DP runs (|sigma|max + alpha + 2 beta) * (m + n + 2)
