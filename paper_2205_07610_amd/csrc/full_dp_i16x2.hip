@@ -425,6 +425,116 @@ __global__ void __launch_bounds__(kWave) full_dp_i16_kernel(FullDp16Args a) {
 // 16-bit half, both halves against the same column profile).  Local pairs
 // that saturate are appended to the re-run list as descriptors for the
 // 32-bit kernel.
+// Global mode, every row sequence of length m: a group's row sequences run
+// through its 16-lane pipeline back to back instead of one duo at a time,
+// so the pipeline fills and drains once per group and block, not once per
+// duo (16 steps of every m + 15).  The low halves take the group's queries
+// q0(k) = first + 8k, the high halves q0(k) + 1; virtual row v of a half is
+// row v - k m of its query k.  A lane that reaches the first row of a query
+// puts its registers (and its diagonal input) back to the row-0 values; its
+// left neighbour, one step ahead, already works on that query, and lane 0's
+// boundary column is the same for every query in global mode.  Lane 15
+// holds H'(m, n) of both halves when it finishes a query's last row.
+template <int K, int CELL>
+__device__ __forceinline__ void stream_global(const AllVsAllArgs &a, const uint32_t (&P)[K], int c, int n,
+                                              int r_begin, int r_end, int lane, int &bad) {
+  constexpr int W = kGroup * K;
+  using V = typename std::conditional<CELL != kCellI16, h2, s2>::type;
+  const int t = lane & 15, g = lane >> 4;
+  const int alpha = a.alpha, beta = a.beta, amb = alpha - beta, asz = a.asz;
+  const int m = a.eq_rows;
+  const V amb2 = pkv<V>(amb, amb);
+  const int pad = W - n;  // left padding of both halves
+  const int first = r_begin + 2 * g;
+  const int nk = first < r_end ? (r_end - first + 2 * kGroupsPerWave - 1) / (2 * kGroupsPerWave) : 0;
+  const int total = nk * m;  // virtual rows of the group's low half
+  const int its = nk > 0 ? total + kGroup - 1 : 0;
+  const int its_max = wave_max_groups(its);
+  const int neg_i = as_i(pkv<V>(kNeg16, kNeg16));
+  auto row0 = [&](int j) -> int { return j == 0 ? beta - alpha : 2 * beta - 2 * alpha; };
+  V Ha[K], Ee[K];
+#pragma unroll
+  for (int x = 0; x < K; ++x) {
+    const int v0 = row0(t * K + x + 1 - pad);
+    Ha[x] = pkv<V>(v0, v0);
+    Ee[x] = as_v<V>(neg_i);
+  }
+  const int hl0 = row0(t * K - pad);
+  V hl_prev = pkv<V>(hl0, hl0);
+  int fout = neg_i;
+  const V hb = pkv<V>(2 * beta - 2 * alpha, 2 * beta - 2 * alpha);
+  // row letters of virtual row idx (0-based) of both halves; past a half's
+  // queries the null letter (score 0), which never reaches a result
+  auto load_sel = [&](int idx) -> int {
+    int c0 = 12, c1 = 12;
+    if (idx < total) {
+      const int k = idx / m, loc = idx - k * m;
+      const int q0 = first + 2 * kGroupsPerWave * k, q1 = q0 + 1;
+      if (q0 < r_end) { c0 = a.seqs_r[a.offs_r[q0] + loc]; if (c0 >= asz) { bad = 1; c0 = 0; } }
+      if (q1 < r_end) { c1 = a.seqs_r[a.offs_r[q1] + loc]; if (c1 >= asz) { bad = 1; c1 = 0; } }
+    }
+    return (int)make_sel<CELL>(c0, c1);
+  };
+  int selfeed = load_sel(t);
+  int sel = (int)make_sel<CELL>(12, 12);
+  int lrow = 0, kq = -1;  // this lane's row within its current query, and that query
+  for (int it0 = 0; it0 < its_max; it0 += kGroup) {
+    const int selnext = load_sel(it0 + kGroup + t);
+#pragma unroll
+    for (int u = 0; u < kGroup; ++u) {
+      const int row = it0 + u + 1 - t;
+      sel = dpp_shr1(selfeed, sel);
+      const V hl = as_v<V>(dpp_shr1(as_i(hb), as_i(Ha[K - 1])));
+      const V fl = as_v<V>(dpp_shr1(as_i(hb), fout));
+      if ((unsigned)(row - 1) < (unsigned)total) {
+        if (lrow == m || lrow == 0) {  // the first row of the next query
+          lrow = 0;
+          ++kq;
+#pragma unroll
+          for (int x = 0; x < K; ++x) {
+            const int v0 = row0(t * K + x + 1 - pad);
+            Ha[x] = pkv<V>(v0, v0);
+            Ee[x] = as_v<V>(neg_i);
+          }
+          hl_prev = pkv<V>(hl0, hl0);
+        }
+        ++lrow;
+        V tt[K];
+#pragma unroll
+        for (int x = 0; x < K; ++x) {
+          const V p = profile_pair<CELL, V>(P[x], P[x], (uint32_t)sel);
+          const V dg = (x == 0) ? hl_prev : Ha[x - 1];
+          tt[x] = dg + p;
+          Ee[x] = vmax(Ee[x], Ha[x]);
+        }
+        V f = fl;
+#pragma unroll
+        for (int x = 0; x < K; ++x) {
+          const V h = vmax(vmax(tt[x], Ee[x]), f);
+          Ha[x] = h - amb2;
+          f = vmax(f, Ha[x]);
+        }
+        fout = as_i(f);
+        if (lrow == m && t == kGroup - 1) {
+          const int q0 = first + 2 * kGroupsPerWave * kq, q1 = q0 + 1;
+          const int off = amb - beta * (m + n);
+          if (q0 < r_end) {
+            const int64_t idx = a.tr ? (int64_t)c * a.ld + q0 : (int64_t)q0 * a.ld + c;
+            a.scores[idx] = toi(Ha[K - 1].x) + off;
+          }
+          if (q1 < r_end) {
+            const int64_t idx = a.tr ? (int64_t)c * a.ld + q1 : (int64_t)q1 * a.ld + c;
+            a.scores[idx] = toi(Ha[K - 1].y) + off;
+          }
+        }
+      }
+      hl_prev = hl;
+      selfeed = dpp_shl1(selfeed, selfeed);
+    }
+    selfeed = selnext;
+  }
+}
+
 template <int MODE, int K, int CELL>
 __global__ void __launch_bounds__(kWave) all_vs_all_i16_kernel(AllVsAllArgs a) {
   constexpr int W = kGroup * K;
@@ -465,6 +575,14 @@ __global__ void __launch_bounds__(kWave) all_vs_all_i16_kernel(AllVsAllArgs a) {
     for (int x = 0; x < K; ++x) P[x] = profile_word(ptab, cols, n, a.tr != 0, t * K + x + 1 - (W - n), asz,
                                                    pad_word, bad);
     const int r_end = min(a.n_rows, (blk + 1) * a.rows_per_block);
+    // (not for 512-column stripes: the extra state would push them past 256 VGPRs)
+    if constexpr (MODE == kGlobal && K <= kK16) {
+      if (a.eq_rows > 0 && n > 0) {
+        stream_global<K, CELL>(a, P, c, n, blk * a.rows_per_block, r_end, lane, bad);
+        if (bad) atomicOr(a.status, kStatusBadResidue);
+        continue;
+      }
+    }
     for (int r = blk * a.rows_per_block; r < r_end; r += 2 * kGroupsPerWave) {
       const int q0 = r + 2 * g, q1 = q0 + 1;
       const bool has0 = q0 < r_end, has1 = q1 < r_end;

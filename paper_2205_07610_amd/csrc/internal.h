@@ -594,6 +594,7 @@ struct AllVsAllArgs {
   int32_t *n_rerun;
   int32_t half;            // cell type (kCellI16, or FP16 cells: values within +-2048)
   int32_t kcols;           // columns per lane: 8, 16 or 32 (stripes of 128, 256 or 512 columns)
+  int32_t eq_rows;         // > 0: every row sequence has this length (global calls stream them)
 };
 // Longest column sequence the all-against-all packed kernel takes.
 constexpr int kAvsaMaxCols = 512;

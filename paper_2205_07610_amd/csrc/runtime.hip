@@ -1398,6 +1398,21 @@ extern "C" int as_align_all_vs_all(const uint8_t *seqs_q, const int64_t *offs_q,
     rpb = (rpb + 7) / 8 * 8;
     a.rows_per_block = (int32_t)rpb;
     a.n_blocks = (int32_t)((a.n_rows + rpb - 1) / rpb);
+    // global calls whose row sequences all have one length stream them
+    // through the kernel's pipeline (128- and 256-column stripes; the
+    // virtual row count of a group stays far inside int)
+    {
+      const std::vector<int64_t> &orow = cols_s ? oq : os;
+      int64_t lmin = orow[1] - orow[0], lmax = lmin;
+      for (int64_t i = 1; i < a.n_rows; ++i) {
+        const int64_t L = orow[i + 1] - orow[i];
+        lmin = std::min(lmin, L);
+        lmax = std::max(lmax, L);
+      }
+      a.eq_rows = (mode == kGlobal && kcols <= 16 && lmin == lmax && lmin > 0 &&
+                   (rpb / 8 + 1) * lmax < ((int64_t)1 << 30))
+                      ? (int32_t)lmax : 0;
+    }
     const int64_t items = (int64_t)a.n_cols * a.n_blocks;
     if (grid > items) grid = items;
     a.subst = w->subst;

@@ -233,3 +233,30 @@ def test_read_sets_full_size_sampled(gpu, oracle_mod, length):
                          sub, 1, 1, 0)
     want = oracle_mod.align_batch(b.seqs_a, b.offs_a, b.seqs_b, b.offs_b, b.subst, b.alpha, b.beta, b.mode)
     np.testing.assert_array_equal(got[qi, si].astype(np.int64), want)
+
+
+@pytest.mark.parametrize("m", [1, 2, 15, 16, 17, 100, 300])
+def test_equal_length_rows_streamed(gpu, oracle_mod, m):
+    """Global calls whose row sequences all have one length stream them
+    through the packed pipeline without draining it between pairs: rows of
+    m residues (a ragged count, so the last block and group run short)
+    against columns of 1-500 residues (every stripe width), in both
+    orientations, with int16 and FP16 cells; every score equals the
+    oracle's."""
+    rng = np.random.default_rng(1500 + m)
+    n_rows = 37
+    rows = [rng.integers(0, 4, size=m).astype(np.uint8) for _ in range(n_rows)]
+    for i in range(0, n_rows, 4):  # some rows related to the first column
+        rows[i] = rows[0].copy()
+    for col_max in (120, 250, 500):
+        cols = _set(rng, 13, 1, col_max, base=rows, related=0.3)
+        for hmode in (0, 1):
+            prev = gpu.set_half_cells(hmode)
+            try:
+                # rows as queries (columns are the subjects), then as subjects
+                _check(gpu, oracle_mod, rows, cols, DNA, 5, 2, 0, f"rows {m} cols {col_max} half {hmode}")
+                _check(gpu, oracle_mod, cols, rows, DNA, 5, 2, 0, f"rows {m} (transposed) cols {col_max}")
+            finally:
+                gpu.set_half_cells(prev)
+    # linear gaps with the paper's read scoring
+    _check(gpu, oracle_mod, rows, _set(rng, 9, 1, 128), synth.dna_subst(2, -1), 1, 1, 0, f"rows {m} linear")
